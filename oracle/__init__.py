@@ -1,0 +1,47 @@
+"""FP64 CPU oracle for the GEEK data pass -- TEST INFRASTRUCTURE ONLY.
+
+This package is the correctness authority for the HIP library.  It is plain,
+slow numpy written from the paper (Luo, Huang, Tung: "A Generic Distributed
+Clustering Framework for Massive Data", arXiv 2106.10515).  Only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import it; the product path (``paper_2106_10515_amd``) never imports, links or
+executes anything here, and this package never imports the product path.  The
+two share only the seeded input generators in ``workloads/``.
+
+Where a step has a plain definition (the E2LSH code, MinHash, exact-tuple
+bucketing, centroids, nearest-centre assignment, SSE) the oracle computes that
+definition directly in a stated floating-point order.  SILK is a heuristic, so
+the oracle follows Algorithm 4's steps in the paper's order.
+
+Pins (see ``tests/test_oracle_*.py``): exact rational arithmetic, closed forms
+(E2LSH collision probability, MinHash collision probability = Jaccard),
+published MurmurHash3 finalizer vectors, brute force on tiny inputs, and the
+SILK worked example (Example 2).
+
+Parity unpinned: SILK's end-to-end seed sets on hashed inputs.  The paper's
+figures carry no coordinates, so only the worked example (explicit bins) and
+invariants pin the vote / threshold / de-duplication logic; the binning of
+real buckets is checked for self-consistency only.
+"""
+
+from .lsh import (  # noqa: F401
+    code_bits,
+    codes_in_range,
+    e2lsh_codes,
+    fmix32,
+    hetero_tokens,
+    minhash_sets,
+    perm,
+)
+from .buckets import bucketize, bucketize_tables  # noqa: F401
+from .silk import majority, silk_from_bins, silk_seeds  # noqa: F401
+from .assign import (  # noqa: F401
+    assign_euclid,
+    assign_hetero,
+    assign_sig,
+    centroids,
+    euclid_dist_rows,
+    modes,
+    radius,
+    sse,
+)
