@@ -1,0 +1,281 @@
+/*
+ * geek.h -- C ABI of libgeek.so, the GEEK data pass on one AMD Instinct
+ * MI355X (gfx950) GPU.
+ *
+ * GEEK (Luo, Huang, Tung, "A Generic Distributed Clustering Framework for
+ * Massive Data", arXiv 2106.10515) clusters data in three phases: a data
+ * transformation that turns objects into buckets with LSH (Section 3.1),
+ * SILK seeding from similar buckets (Section 3.2, Algorithm 4), and a
+ * one-pass assignment of every object to its closest central vector
+ * (Section 3.3, Eq. (1)).  This library exposes four calls:
+ *
+ *   geek_hash        LSH values of every object (E2LSH codes packed into an
+ *                    exact per-table key; MinHash signatures of sets or of
+ *                    heterogeneous rows)
+ *   geek_bucketize   group objects with identical table keys into buckets
+ *   geek_silk_seeds  SILK: bins of similar buckets, majority voting, the
+ *                    seeding threshold and near-duplicate removal
+ *   geek_assign      central vectors of the seeds and the one-pass assignment
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every pointer inside a job descriptor is a DEVICE pointer unless the
+ *   field says "host".  Device buffers are allocated and freed by the caller;
+ *   the library never frees caller memory and holds no device memory between
+ *   calls.  Base pointers must be 16-byte aligned.
+ * - Each call takes an array of ``njobs`` job descriptors (host memory),
+ *   a caller-owned device workspace of at least the size that
+ *   ``geek_workspace_size`` returns for the same jobs, a device status word
+ *   ``d_status`` (int32, device) and a HIP stream (``hipStream_t`` passed as
+ *   ``void*``; NULL = the default stream).
+ * - Calls are stream-ordered and return without waiting for the GPU, except
+ *   ``geek_silk_seeds``, which synchronizes ``stream`` internally because the
+ *   sizes of its intermediate collections are only known on the device.
+ *   ``geek_hash``, ``geek_bucketize`` and ``geek_assign`` perform no host
+ *   synchronization and no device allocation.
+ * - Host-detectable errors (bad arguments, workspace too small, unsupported
+ *   sizes, launch failure) return a negative status at once and enqueue no
+ *   work.  Data-dependent errors (non-finite input, a hash code outside the
+ *   packable range, too little output capacity, no seeds, an empty set) are
+ *   written by the kernels into ``*d_status`` (first error wins; later
+ *   kernels of the same call become no-ops once it is non-zero).  The caller
+ *   zeroes ``*d_status`` before a call chain and reads it after synchronizing
+ *   the stream.
+ * - Ids are 0-based uint32.  Matrices are row-major.
+ */
+#ifndef GEEK_H
+#define GEEK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define GEEK_OK 0
+#define GEEK_ERR_ARG (-1)         /* null/misaligned pointer, inconsistent sizes */
+#define GEEK_ERR_WORKSPACE (-2)   /* ws_bytes below geek_workspace_size */
+#define GEEK_ERR_UNSUPPORTED (-3) /* a size this build does not handle */
+#define GEEK_ERR_HIP (-4)         /* HIP launch failure; see geek_last_hip_error */
+/* data-dependent, written to *d_status */
+#define GEEK_ERR_NONFINITE 1      /* NaN or Inf in a float input */
+#define GEEK_ERR_RANGE 2          /* hash code outside the packable range */
+#define GEEK_ERR_CAPACITY 3       /* output capacity too small (see `needed`) */
+#define GEEK_ERR_NO_SEEDS 4       /* SILK found no seed */
+#define GEEK_ERR_EMPTY_SET 5      /* a set (or seed) with no element */
+
+/* ---- geek_hash ----------------------------------------------------------
+ * The data transformation's LSH values (paper Section 3.1).
+ *
+ * GEEK_HASH_DENSE: E2LSH, code[i][p] = floor((a_p . x_i + b_p) / w), the form
+ *   named in the Remarks after Example 1, with a_p drawn as in Eq. (3)
+ *   (caller supplies A and b).  P = m * L projections; table l uses
+ *   projections l*m .. l*m+m-1.  The code is the value of the float64
+ *   evaluation s = sum_t a_pt * x_it accumulated for t = 0..d-1 in order,
+ *   v = s + b_p, floor(v / w): the GPU computes in float32 on the matrix
+ *   cores and recomputes every (i, p) whose float32 quotient lies within a
+ *   rigorous error bound of an integer in exactly that float64 order, so
+ *   the codes are bit-exact.  The m codes of table l and object i are
+ *   packed into a 128-bit key keys[l][i][0..3]: code j occupies bits
+ *   j*B .. j*B+B-1 (little-endian over the four words) as code + 2^(B-1),
+ *   with B = min(32, 128 / m); a code outside [-2^(B-1), 2^(B-1)) sets
+ *   GEEK_ERR_RANGE.  The packing is injective, so equal keys <=> equal code
+ *   tuples.
+ * GEEK_HASH_SETS: MinHash (Eq. (2), Algorithm 3).  sig[i][f] = min over the
+ *   tokens t of set i of pi_f(t), pi_f(t) = (a_f * fmix32(t) + b_f) mod 2^32
+ *   with a_f = mh_keys[f][0] | 1, b_f = mh_keys[f][1] and fmix32 the
+ *   MurmurHash3 32-bit finalizer (a bijection of 32-bit words).  An empty
+ *   set sets GEEK_ERR_EMPTY_SET.
+ * GEEK_HASH_HETERO: Algorithm 2.  The numeric attributes X [n][d] get
+ *   P = m * L E2LSH codes as above; categorical attribute a with value v
+ *   becomes token (a << 16) | v, numeric projection p with code c becomes
+ *   0x80000000 | (p << 16) | (c + 32768); the row's n_cat + P tokens are
+ *   then MinHashed as a set into sig [n][F].  A value or code outside 16
+ *   bits sets GEEK_ERR_RANGE.
+ */
+#define GEEK_HASH_DENSE 0
+#define GEEK_HASH_SETS 1
+#define GEEK_HASH_HETERO 2
+
+typedef struct geek_hash_job {
+  int32_t kind;             /* GEEK_HASH_* */
+  int32_t d;                /* dense/hetero: attributes per row (1..1024) */
+  int64_t n;                /* objects (0 <= n < 2^31) */
+  /* dense and the numeric part of hetero */
+  const float* X;           /* [n][ldx] float32, ldx >= d */
+  int64_t ldx;
+  const float* A;           /* [m*L][d] projection vectors */
+  const float* b;           /* [m*L] offsets in [0, w) */
+  int32_t m;                /* codes per table (dense: 1..32) */
+  int32_t L;                /* tables */
+  float w;                  /* bucket width, > 0 */
+  int32_t F;                /* sets/hetero: MinHash functions */
+  uint32_t* keys;           /* dense out: [L][n][4] packed table keys */
+  int32_t* codes;           /* optional out: [n][m*L] codes (NULL to skip) */
+  /* sets */
+  const int64_t* offsets;   /* [n+1], set i = tokens[offsets[i]..offsets[i+1]) */
+  const uint32_t* tokens;   /* [nnz] */
+  /* hetero */
+  const int32_t* cat;       /* [n][n_cat], values in [0, 65536) */
+  int32_t n_cat;
+  int32_t pad0;
+  const uint32_t* mh_keys;  /* [F][2] MinHash key words */
+  uint32_t* sig;            /* sets/hetero out: [n][F] */
+  unsigned long long* n_fixup; /* optional out (device, accumulated):
+                                  (i, p) pairs recomputed in float64 */
+} geek_hash_job;
+
+/* ---- geek_bucketize -----------------------------------------------------
+ * Buckets of every table: objects whose table key is identical share a
+ * bucket ("T[G(x_j)].push(j)" in Algorithms 2 and 3; the exact tuple of the
+ * table's hash values).  The key of (table t, object i) is the key_words
+ * uint32 words at keys + t*table_stride + i*row_stride (dense keys from
+ * geek_hash: key_words 4, table_stride n*4, row_stride 4; band b of MinHash
+ * signatures with K rows: key_words K, table_stride K, row_stride F).
+ * Output per table t, canonical: buckets ordered by their smallest member,
+ * members ascending; bucket j of table t is
+ * members[t*n + offsets[t*(n+1) + j] .. t*n + offsets[t*(n+1) + j + 1]).
+ */
+typedef struct geek_bucketize_job {
+  int64_t n;                /* objects per table (1 <= n < 2^31) */
+  int32_t T;                /* tables */
+  int32_t key_words;        /* 1..4 */
+  const uint32_t* keys;
+  int64_t table_stride;     /* in uint32 words */
+  int64_t row_stride;       /* in uint32 words */
+  uint32_t* members;        /* out [T][n] */
+  uint32_t* offsets;        /* out [T][n+1]; entries past nbuckets[t] unspecified */
+  uint32_t* nbuckets;       /* out [T] */
+  uint32_t* bucket_of;      /* optional out [T][n] */
+} geek_bucketize_job;
+
+/* ---- geek_silk_seeds ----------------------------------------------------
+ * SILK (Algorithm 4) over all buckets of all tables (the collection B, in
+ * the geek_bucketize output layout).  For each of L SILK tables, K MinHash
+ * functions over object ids (pi as in GEEK_HASH_SETS, key words
+ * silk_keys[(s*K + k)][0..1]) give every bucket the signature
+ * G(B) = (min_{x in B} pi_1(x), ..., min pi_K(x)); buckets with identical G
+ * form a bin; bins of at most one bucket are skipped; C_shared = the ids
+ * appearing in more than half of the bin's buckets (2*count > |Bin|); it
+ * joins the multiset C when |C_shared| >= delta.  Near-duplicates are then
+ * removed with one more table (key rows L*K .. L*K+K-1) over the sets of C:
+ * a bin holding one set passes it through, a bin of several sets is
+ * majority-voted and delta-filtered.  Seeds are ordered by the ascending
+ * lexicographic K-tuple of their de-duplication bin, members ascending.
+ * Output CSR: seed j = seed_members[seed_offsets[j] .. seed_offsets[j+1]).
+ * If the capacities are too small, *needed = {seeds, members} and
+ * GEEK_ERR_CAPACITY is set; no seed sets GEEK_ERR_NO_SEEDS.
+ */
+typedef struct geek_silk_job {
+  int64_t n;                /* objects */
+  int32_t T;                /* transform tables */
+  int32_t K;                /* MinHash functions per SILK table (1..4) */
+  const uint32_t* members;  /* [T][n]   (geek_bucketize output) */
+  const uint32_t* offsets;  /* [T][n+1] */
+  const uint32_t* nbuckets; /* [T] */
+  int32_t L;                /* SILK tables */
+  int32_t delta;            /* seeding threshold */
+  const uint32_t* silk_keys;/* [(L+1)*K][2] */
+  int64_t cap_k;            /* capacity of seed_offsets minus one */
+  int64_t cap_members;      /* capacity of seed_members */
+  uint32_t* seed_offsets;   /* out [cap_k+1] */
+  uint32_t* seed_members;   /* out [cap_members] */
+  uint32_t* k_out;          /* out [1] number of seeds */
+  unsigned long long* needed;   /* out [2] seeds, members needed */
+  unsigned long long* counters; /* optional out [4]: hash evaluations,
+                                   voted (bin, id) pairs, |C| before
+                                   de-duplication, multi-bucket bins */
+} geek_silk_job;
+
+/* ---- geek_assign --------------------------------------------------------
+ * Central vectors and the one-pass assignment (Section 3.3).
+ * GEEK_METRIC_EUCLID: centroid c_j = (sum over members of seed j, ascending,
+ *   of x_i, accumulated in float64 one addition at a time) / |C_j|;
+ *   ID_i = argmin_j D(i, j) with D the squared Euclidean distance evaluated
+ *   in float64 as: for t = 0..d-1, delta = x_it - c_jt, acc += delta*delta
+ *   (each operation rounded, no fused multiply-add); lowest j on ties.
+ *   The matrix cores compute an approximate D~ = |x|^2 - 2 x.c + |c|^2 in
+ *   `precision`; every j whose D~ lies within a rigorous per-row error bound
+ *   of the row minimum is re-evaluated with the float64 formula above, rows
+ *   with more than 8 such candidates are rescanned (BF16/FP8: in FP32; FP32:
+ *   in float64 over all seeds), so the assignment is exact.
+ * GEEK_METRIC_SIG: modes mode_j[f] = most frequent sig value of the members
+ *   at position f (smallest value on ties); ID_i = argmax_j #{f : sig[i][f]
+ *   == mode_j[f]} (lowest j on ties); dist = 1 - matches / F.
+ * GEEK_METRIC_HETERO: D = D_num(i, j) + gamma * #{a : cat[i][a] !=
+ *   catmode_j[a]} with D_num as for EUCLID over X and the centroid, and
+ *   catmode the per-attribute mode of the members.
+ * Outputs: assign [n]; centroids [k][d] (EUCLID, HETERO); modes [k][F]
+ *   (SIG) or [k][n_cat] (HETERO); dist [n] (optional) = D(i, ID_i);
+ *   sse [1] = sum_i dist_i in float64, sequential within consecutive blocks
+ *   of 4096 rows, then over the block sums; radius [k] (optional) = sqrt of
+ *   the largest member distance (EUCLID, HETERO: of D), 0 for empty
+ *   clusters; counters (optional) [4]: rows certified by the first pass,
+ *   rows rescanned at higher precision, rows scanned in float64, candidate
+ *   distances evaluated in float64.
+ */
+#define GEEK_METRIC_EUCLID 0
+#define GEEK_METRIC_SIG 1
+#define GEEK_METRIC_HETERO 2
+
+#define GEEK_PREC_FP32 0
+#define GEEK_PREC_BF16 1
+#define GEEK_PREC_FP8 2
+#define GEEK_PREC_BF16X3 3   /* BF16 hi/lo split, three products */
+
+typedef struct geek_assign_job {
+  int32_t metric;           /* GEEK_METRIC_* */
+  int32_t precision;        /* GEEK_PREC_* (EUCLID, HETERO) */
+  int64_t n;
+  int32_t d;                /* EUCLID/HETERO: numeric attributes (1..256) */
+  int32_t k;                /* host: number of seeds (>= 1) */
+  const float* X;           /* [n][ldx] */
+  int64_t ldx;
+  const uint32_t* sig;      /* SIG: [n][F] */
+  int32_t F;
+  int32_t n_cat;            /* HETERO */
+  const int32_t* cat;       /* HETERO: [n][n_cat] */
+  double gamma;             /* HETERO mismatch weight */
+  const uint32_t* seed_offsets; /* [k+1] */
+  const uint32_t* seed_members;
+  int32_t* assign;          /* out [n] */
+  double* centroids;        /* out [k][d] */
+  uint32_t* modes;          /* out SIG [k][F]; HETERO [k][n_cat] (as uint32) */
+  double* dist;             /* optional out [n] */
+  double* sse;              /* out [1] */
+  double* radius;           /* optional out [k] */
+  unsigned long long* counters; /* optional out [4] */
+} geek_assign_job;
+
+/* ---- entry points -------------------------------------------------------- */
+#define GEEK_OP_HASH 0
+#define GEEK_OP_BUCKETIZE 1
+#define GEEK_OP_SILK 2
+#define GEEK_OP_ASSIGN 3
+
+/* Bytes of device workspace the call `op` needs for these jobs (host). */
+int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t* bytes);
+
+int32_t geek_hash(const geek_hash_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                  int32_t* d_status, void* stream);
+int32_t geek_bucketize(const geek_bucketize_job* jobs, int32_t njobs, void* ws,
+                       size_t ws_bytes, int32_t* d_status, void* stream);
+int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                        int32_t* d_status, void* stream);
+int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                    int32_t* d_status, void* stream);
+
+/* Static description of a status code. */
+const char* geek_status_string(int32_t status);
+/* Library version string, e.g. "geek 0.1.0 gfx950". */
+const char* geek_version(void);
+/* The last HIP error message seen by this thread (empty if none). */
+const char* geek_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEEK_H */

@@ -1,0 +1,214 @@
+"""Torch-facing wrappers of the four GEEK calls.
+
+They allocate output tensors and a per-device workspace with torch, pass raw
+device pointers and torch's current HIP stream to libgeek.so, and return the
+outputs.  No arithmetic of the method happens here.  Unsigned outputs are
+returned in int32/int64 tensors holding the same bits (view them as uint32
+on the host).
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+from ._lib import GeekError
+
+_WS: dict = {}
+
+
+def _dev(t: torch.Tensor) -> torch.device:
+    if not t.is_cuda:
+        raise GeekError(L.GEEK_ERR_ARG, "input must be a GPU tensor")
+    return t.device
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A cached device buffer of at least ``nbytes`` (grown on demand)."""
+    key = str(device)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _WS.pop(key, None)
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    return buf
+
+
+def release_workspace():
+    _WS.clear()
+
+
+def stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def new_status(device) -> torch.Tensor:
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def check_status(status: torch.Tensor, where: str = "device status") -> None:
+    """Synchronizes with the stream and raises on a non-zero status word."""
+    v = int(status.item())
+    if v != 0:
+        raise GeekError(v, where)
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _run(op, fn, jobs, device, status):
+    nbytes = L.workspace_size(op, jobs)
+    ws = workspace(nbytes, device)
+    fn(jobs, ws.data_ptr(), ws.numel(), status.data_ptr(), stream_ptr(device))
+
+
+# ---------------------------------------------------------------- geek_hash
+def hash_dense(X, A, b, m, L_tables, w, want_codes=False, status=None, check=True,
+               n_fixup=None):
+    """E2LSH codes of every row of X packed into per-table 128-bit keys.
+    Returns ``(keys int32 [L, n, 4], codes int32 [n, m*L] or None)``."""
+    dev = _dev(X)
+    n, d = X.shape
+    assert X.dtype == torch.float32 and X.stride(1) == 1
+    A = A.contiguous()
+    b = b.contiguous()
+    P = m * L_tables
+    keys = torch.empty((L_tables, n, 4), dtype=torch.int32, device=dev)
+    codes = torch.empty((n, P), dtype=torch.int32, device=dev) if want_codes else None
+    status = new_status(dev) if status is None else status
+    j = L.HashJob(kind=L.GEEK_HASH_DENSE, d=d, n=n, X=_p(X), ldx=X.stride(0), A=_p(A), b=_p(b),
+                  m=m, L=L_tables, w=float(w), F=0, keys=_p(keys), codes=_p(codes),
+                  n_fixup=_p(n_fixup))
+    _run(L.GEEK_OP_HASH, L.geek_hash, [j], dev, status)
+    if check:
+        check_status(status, "geek_hash")
+    return keys, codes
+
+
+def hash_sets(offsets, tokens, mh_keys, status=None, check=True):
+    """MinHash signatures of sets.  Returns ``sig int32 [n, F]``."""
+    dev = _dev(tokens)
+    n = offsets.numel() - 1
+    F = mh_keys.shape[0]
+    sig = torch.empty((n, F), dtype=torch.int32, device=dev)
+    status = new_status(dev) if status is None else status
+    j = L.HashJob(kind=L.GEEK_HASH_SETS, n=n, F=F, offsets=_p(offsets), tokens=_p(tokens),
+                  mh_keys=_p(mh_keys), sig=_p(sig))
+    _run(L.GEEK_OP_HASH, L.geek_hash, [j], dev, status)
+    if check:
+        check_status(status, "geek_hash")
+    return sig
+
+
+def hash_hetero(X, cat, A, b, m, L_tables, w, mh_keys, status=None, check=True):
+    """MinHash signatures of heterogeneous rows (numeric attributes turned
+    into E2LSH code tokens).  Returns ``sig int32 [n, F]``."""
+    dev = _dev(X)
+    n, d = X.shape
+    F = mh_keys.shape[0]
+    sig = torch.empty((n, F), dtype=torch.int32, device=dev)
+    status = new_status(dev) if status is None else status
+    j = L.HashJob(kind=L.GEEK_HASH_HETERO, d=d, n=n, X=_p(X), ldx=X.stride(0), A=_p(A.contiguous()),
+                  b=_p(b.contiguous()), m=m, L=L_tables, w=float(w), F=F, cat=_p(cat),
+                  n_cat=cat.shape[1], mh_keys=_p(mh_keys), sig=_p(sig))
+    _run(L.GEEK_OP_HASH, L.geek_hash, [j], dev, status)
+    if check:
+        check_status(status, "geek_hash")
+    return sig
+
+
+# ---------------------------------------------------------------- geek_bucketize
+def bucketize(keys, n, T, key_words, table_stride, row_stride, want_bucket_of=True,
+              status=None, check=True):
+    """Buckets of T tables.  ``keys`` is any int32 device tensor holding the
+    key words at the given strides (in words).  Returns ``(members [T, n],
+    offsets [T, n+1], nbuckets [T], bucket_of [T, n] or None)``."""
+    dev = _dev(keys)
+    members = torch.empty((T, n), dtype=torch.int32, device=dev)
+    offsets = torch.empty((T, n + 1), dtype=torch.int32, device=dev)
+    nbuckets = torch.empty((T,), dtype=torch.int32, device=dev)
+    bucket_of = torch.empty((T, n), dtype=torch.int32, device=dev) if want_bucket_of else None
+    status = new_status(dev) if status is None else status
+    j = L.BucketizeJob(n=n, T=T, key_words=key_words, keys=_p(keys), table_stride=table_stride,
+                       row_stride=row_stride, members=_p(members), offsets=_p(offsets),
+                       nbuckets=_p(nbuckets), bucket_of=_p(bucket_of))
+    _run(L.GEEK_OP_BUCKETIZE, L.geek_bucketize, [j], dev, status)
+    if check:
+        check_status(status, "geek_bucketize")
+    return members, offsets, nbuckets, bucket_of
+
+
+# ---------------------------------------------------------------- geek_silk_seeds
+def silk_seeds(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys,
+               cap_k=None, cap_members=None, status=None, check=True):
+    """SILK seeds.  Returns ``(seed_offsets [k+1], seed_members [N_C],
+    counters [4])`` trimmed to the k seeds found."""
+    dev = _dev(members)
+    cap_k = cap_k or max(1024, n // 4)
+    cap_members = cap_members or max(4096, 2 * n)
+    so = torch.empty((cap_k + 1,), dtype=torch.int32, device=dev)
+    sm = torch.empty((cap_members,), dtype=torch.int32, device=dev)
+    k_out = torch.zeros((1,), dtype=torch.int32, device=dev)
+    needed = torch.zeros((2,), dtype=torch.int64, device=dev)
+    ctr = torch.zeros((4,), dtype=torch.int64, device=dev)
+    status = new_status(dev) if status is None else status
+    j = L.SilkJob(n=n, T=T, K=K, members=_p(members), offsets=_p(offsets), nbuckets=_p(nbuckets),
+                  L=L_silk, delta=delta, silk_keys=_p(silk_keys), cap_k=cap_k,
+                  cap_members=cap_members, seed_offsets=_p(so), seed_members=_p(sm),
+                  k_out=_p(k_out), needed=_p(needed), counters=_p(ctr))
+    _run(L.GEEK_OP_SILK, L.geek_silk_seeds, [j], dev, status)
+    if check:
+        check_status(status, "geek_silk_seeds")
+    k = int(k_out.item())
+    nm = int(so[k].item()) if k > 0 else 0
+    return so[:k + 1], sm[:nm], ctr
+
+
+# ---------------------------------------------------------------- geek_assign
+def assign_euclid(X, seed_offsets, seed_members, k, precision=L.GEEK_PREC_FP32,
+                  want_dist=True, want_radius=True, status=None, check=True):
+    """Central vectors and one-pass Euclidean assignment.  Returns a dict with
+    assign, centroids, dist, sse, radius and counters."""
+    dev = _dev(X)
+    n, d = X.shape
+    out = dict(
+        assign=torch.empty((n,), dtype=torch.int32, device=dev),
+        centroids=torch.empty((k, d), dtype=torch.float64, device=dev),
+        dist=torch.empty((n,), dtype=torch.float64, device=dev) if want_dist else None,
+        sse=torch.empty((1,), dtype=torch.float64, device=dev),
+        radius=torch.empty((k,), dtype=torch.float64, device=dev) if want_radius else None,
+        counters=torch.zeros((4,), dtype=torch.int64, device=dev),
+    )
+    status = new_status(dev) if status is None else status
+    j = L.AssignJob(metric=L.GEEK_METRIC_EUCLID, precision=precision, n=n, d=d, k=k, X=_p(X),
+                    ldx=X.stride(0), seed_offsets=_p(seed_offsets), seed_members=_p(seed_members),
+                    assign=_p(out["assign"]), centroids=_p(out["centroids"]), dist=_p(out["dist"]),
+                    sse=_p(out["sse"]), radius=_p(out["radius"]), counters=_p(out["counters"]))
+    _run(L.GEEK_OP_ASSIGN, L.geek_assign, [j], dev, status)
+    if check:
+        check_status(status, "geek_assign")
+    return out
+
+
+def assign_sig(sig, seed_offsets, seed_members, k, want_dist=True, status=None, check=True):
+    """Modes of the seeds and assignment of signature rows by match count."""
+    dev = _dev(sig)
+    n, F = sig.shape
+    out = dict(
+        assign=torch.empty((n,), dtype=torch.int32, device=dev),
+        modes=torch.empty((k, F), dtype=torch.int32, device=dev),
+        dist=torch.empty((n,), dtype=torch.float64, device=dev) if want_dist else None,
+        sse=torch.empty((1,), dtype=torch.float64, device=dev),
+        radius=torch.empty((k,), dtype=torch.float64, device=dev),
+        counters=torch.zeros((4,), dtype=torch.int64, device=dev),
+    )
+    status = new_status(dev) if status is None else status
+    j = L.AssignJob(metric=L.GEEK_METRIC_SIG, n=n, k=k, sig=_p(sig), F=F,
+                    seed_offsets=_p(seed_offsets), seed_members=_p(seed_members),
+                    assign=_p(out["assign"]), modes=_p(out["modes"]), dist=_p(out["dist"]),
+                    sse=_p(out["sse"]), radius=_p(out["radius"]), counters=_p(out["counters"]))
+    _run(L.GEEK_OP_ASSIGN, L.geek_assign, [j], dev, status)
+    if check:
+        check_status(status, "geek_assign")
+    return out

@@ -1,0 +1,212 @@
+// extern "C" entry points of libgeek.so: argument validation, workspace
+// sizing and dispatch to the kernels of hash.hip, bucketize.hip, silk.hip
+// and assign.hip.
+#include <string.h>
+
+#include <string>
+
+#include "common.hpp"
+
+namespace geek {
+
+size_t hash_ws(const geek_hash_job& J);
+int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
+size_t bucketize_ws(const geek_bucketize_job& J);
+int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, int32_t* st,
+                      hipStream_t s);
+size_t silk_ws(const geek_silk_job& J);
+int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
+size_t assign_euclid_ws(const geek_assign_job& J);
+int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st,
+                      hipStream_t s);
+size_t assign_sig_ws(const geek_assign_job& J);
+int32_t assign_sig(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
+
+static thread_local std::string g_last_err;
+
+int32_t hip_fail(hipError_t e) {
+  g_last_err = hipGetErrorString(e);
+  return GEEK_ERR_HIP;
+}
+
+static bool al16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+static bool al4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+static int32_t check_hash(const geek_hash_job& J) {
+  if (J.n < 0 || J.n >= (1ll << 31)) return GEEK_ERR_ARG;
+  if (J.kind == GEEK_HASH_DENSE || J.kind == GEEK_HASH_HETERO) {
+    if (J.n > 0 && (!J.X || !al4(J.X))) return GEEK_ERR_ARG;
+    if (!J.A || !J.b || J.d < 1 || J.ldx < J.d || J.m < 1 || J.L < 1 || !(J.w > 0.f))
+      return GEEK_ERR_ARG;
+    if (J.d > 256) return GEEK_ERR_UNSUPPORTED;
+    if (J.m > 64) return GEEK_ERR_UNSUPPORTED;
+    if ((int64_t)J.m * J.L > 65535) return GEEK_ERR_UNSUPPORTED;
+  }
+  if (J.kind == GEEK_HASH_DENSE) {
+    if (J.m > 32) return GEEK_ERR_UNSUPPORTED;  // at least 4 bits per packed code
+    if (J.n > 0 && (!J.keys || !al16(J.keys))) return GEEK_ERR_ARG;
+  } else if (J.kind == GEEK_HASH_SETS || J.kind == GEEK_HASH_HETERO) {
+    if (J.F < 1 || !J.mh_keys) return GEEK_ERR_ARG;
+    if (J.F > 512) return GEEK_ERR_UNSUPPORTED;
+    if (J.n > 0 && !J.sig) return GEEK_ERR_ARG;
+    if (J.kind == GEEK_HASH_SETS && J.n > 0 && (!J.offsets || !J.tokens)) return GEEK_ERR_ARG;
+    if (J.kind == GEEK_HASH_HETERO) {
+      if (J.n_cat < 0 || (J.n_cat > 0 && !J.cat)) return GEEK_ERR_ARG;
+      if (J.n_cat >= 32768 || J.m * J.L >= 32768) return GEEK_ERR_UNSUPPORTED;
+    }
+  } else {
+    return GEEK_ERR_ARG;
+  }
+  return GEEK_OK;
+}
+
+static int32_t check_bz(const geek_bucketize_job& J) {
+  if (J.n < 1 || J.n >= (1ll << 31) || J.T < 1 || J.T > 65535) return GEEK_ERR_ARG;
+  if (J.key_words < 1 || J.key_words > 4) return GEEK_ERR_ARG;
+  if (!J.keys || !al4(J.keys) || !J.members || !J.offsets || !J.nbuckets) return GEEK_ERR_ARG;
+  if (J.table_stride < 0 || J.row_stride < J.key_words) return GEEK_ERR_ARG;
+  return GEEK_OK;
+}
+
+static int32_t check_assign(const geek_assign_job& J) {
+  if (J.n < 1 || J.n >= (1ll << 31) || J.k < 1) return GEEK_ERR_ARG;
+  if (!J.seed_offsets || !J.seed_members || !J.assign || !J.sse) return GEEK_ERR_ARG;
+  if (J.metric == GEEK_METRIC_EUCLID || J.metric == GEEK_METRIC_HETERO) {
+    if (!J.X || !al4(J.X) || J.d < 1 || J.ldx < J.d || !J.centroids) return GEEK_ERR_ARG;
+    if (J.d > 256) return GEEK_ERR_UNSUPPORTED;
+    if (J.precision != GEEK_PREC_FP32 && J.precision != GEEK_PREC_BF16) return GEEK_ERR_UNSUPPORTED;
+    if (J.metric == GEEK_METRIC_HETERO) return GEEK_ERR_UNSUPPORTED;
+  } else if (J.metric == GEEK_METRIC_SIG) {
+    if (!J.sig || J.F < 1 || !J.modes) return GEEK_ERR_ARG;
+    if (J.F > 1024) return GEEK_ERR_UNSUPPORTED;
+  } else {
+    return GEEK_ERR_ARG;
+  }
+  return GEEK_OK;
+}
+
+}  // namespace geek
+
+using namespace geek;
+
+extern "C" {
+
+const char* geek_status_string(int32_t s) {
+  switch (s) {
+    case GEEK_OK: return "ok";
+    case GEEK_ERR_ARG: return "invalid argument";
+    case GEEK_ERR_WORKSPACE: return "workspace too small";
+    case GEEK_ERR_UNSUPPORTED: return "unsupported size";
+    case GEEK_ERR_HIP: return "HIP error";
+    case GEEK_ERR_NONFINITE: return "non-finite input";
+    case GEEK_ERR_RANGE: return "value outside the packable range";
+    case GEEK_ERR_CAPACITY: return "output capacity too small";
+    case GEEK_ERR_NO_SEEDS: return "no seeds";
+    case GEEK_ERR_EMPTY_SET: return "empty set";
+    default: return "unknown status";
+  }
+}
+
+const char* geek_version(void) { return "geek 0.1.0 gfx950"; }
+
+const char* geek_last_hip_error(void) { return g_last_err.c_str(); }
+
+int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t* bytes) {
+  if (!jobs || njobs < 1 || !bytes) return GEEK_ERR_ARG;
+  size_t tot = 0;
+  for (int j = 0; j < njobs; ++j) {
+    size_t b = 0;
+    switch (op) {
+      case GEEK_OP_HASH: {
+        const geek_hash_job& J = static_cast<const geek_hash_job*>(jobs)[j];
+        if (int32_t rc = check_hash(J)) return rc;
+        b = hash_ws(J);
+        break;
+      }
+      case GEEK_OP_BUCKETIZE: {
+        const geek_bucketize_job& J = static_cast<const geek_bucketize_job*>(jobs)[j];
+        if (int32_t rc = check_bz(J)) return rc;
+        b = bucketize_ws(J);
+        break;
+      }
+      case GEEK_OP_SILK: {
+        const geek_silk_job& J = static_cast<const geek_silk_job*>(jobs)[j];
+        b = silk_ws(J);
+        break;
+      }
+      case GEEK_OP_ASSIGN: {
+        const geek_assign_job& J = static_cast<const geek_assign_job*>(jobs)[j];
+        if (int32_t rc = check_assign(J)) return rc;
+        b = J.metric == GEEK_METRIC_SIG ? assign_sig_ws(J) : assign_euclid_ws(J);
+        break;
+      }
+      default:
+        return GEEK_ERR_ARG;
+    }
+    tot = b > tot ? b : tot;  // jobs run one after another and share the workspace
+  }
+  *bytes = tot;
+  return GEEK_OK;
+}
+
+int32_t geek_hash(const geek_hash_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                  int32_t* d_status, void* stream) {
+  if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j)
+    if (int32_t rc = check_hash(jobs[j])) return rc;
+  for (int j = 0; j < njobs; ++j) {
+    if (ws_bytes < hash_ws(jobs[j])) return GEEK_ERR_WORKSPACE;
+  }
+  for (int j = 0; j < njobs; ++j) {
+    int32_t rc = hash_run(jobs[j], ws, ws_bytes, d_status, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return GEEK_OK;
+}
+
+int32_t geek_bucketize(const geek_bucketize_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                       int32_t* d_status, void* stream) {
+  if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    if (int32_t rc = check_bz(jobs[j])) return rc;
+    if (ws_bytes < bucketize_ws(jobs[j])) return GEEK_ERR_WORKSPACE;
+    if (!ws) return GEEK_ERR_ARG;
+  }
+  for (int j = 0; j < njobs; ++j) {
+    int32_t rc = bucketize_run(jobs[j], ws, ws_bytes, d_status, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return GEEK_OK;
+}
+
+int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                        int32_t* d_status, void* stream) {
+  if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    int32_t rc = silk_run(jobs[j], ws, ws_bytes, d_status, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return GEEK_OK;
+}
+
+int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                    int32_t* d_status, void* stream) {
+  if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    if (int32_t rc = check_assign(jobs[j])) return rc;
+    const size_t need = jobs[j].metric == GEEK_METRIC_SIG ? assign_sig_ws(jobs[j])
+                                                          : assign_euclid_ws(jobs[j]);
+    if (ws_bytes < need) return GEEK_ERR_WORKSPACE;
+    if (!ws) return GEEK_ERR_ARG;
+  }
+  for (int j = 0; j < njobs; ++j) {
+    const geek_assign_job& J = jobs[j];
+    int32_t rc = J.metric == GEEK_METRIC_SIG
+                     ? assign_sig(J, ws, ws_bytes, d_status, (hipStream_t)stream)
+                     : assign_euclid(J, ws, ws_bytes, d_status, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return GEEK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,376 @@
+// LSH values of the data transformation (paper Section 3.1) on gfx950.
+//
+// Dense E2LSH: code[i][p] = floor((a_p . x_i + b_p) / w).  The projection is
+// a GEMM X[n x d] . A^T[d x P] on the float32 matrix cores; the epilogue adds
+// b, scales by 1/w, floors and certifies the result: the float32 quotient q
+// differs from the float64 reference quotient (sum over t in order, + b, / w)
+// by at most tau = c * (|a_p| |x_i| + |b_p|) / w, so when [q - tau, q + tau]
+// holds no integer the float32 floor equals the reference floor.  Otherwise
+// the pair is recomputed in float64 in exactly the reference order.  The m
+// codes of each table are then packed into a 128-bit exact key.
+//
+// MinHash of sets / heterogeneous rows: one wavefront per object; lane f
+// handles functions f, f+64, ...; the tokens of the object are loaded once
+// and broadcast, so each lane runs a plain min over the set with no
+// cross-lane reduction.
+#include <math.h>
+
+#include <type_traits>
+
+#include "common.hpp"
+
+namespace geek {
+
+constexpr int H_THREADS = 256;
+constexpr int H_BN = 128;   // points per block
+constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks)
+
+template <int DP>
+__global__ __launch_bounds__(H_THREADS) void k_e2lsh(
+    const float* __restrict__ X, int64_t ldx, int d, int64_t n, const float* __restrict__ A,
+    const float* __restrict__ bvec, const float* __restrict__ anorm, int m, int L, float w,
+    int tpc, uint32_t* __restrict__ keys, int32_t* __restrict__ codes_out,
+    unsigned long long* __restrict__ n_fixup, int32_t* st) {
+  constexpr int S = DP / 2;
+  constexpr int STR = DP + 4;
+  __shared__ __attribute__((aligned(16))) float lds_a[H_BC * STR];
+  __shared__ float lds_b[H_BC], lds_an[H_BC];
+  __shared__ int lds_code[H_BN * H_BC];
+  __shared__ uint32_t lds_flag[H_BN * H_BC / 32];  // one bit per (point, row)
+  __shared__ unsigned int lds_nfix;
+
+  const int P = m * L;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int p = lane & 31, h = lane >> 5;
+  const int64_t i0 = (int64_t)blockIdx.x * H_BN;
+  const int64_t i = i0 + wv * 32 + p;
+  const bool valid = i < n;
+  const float* xr = X + (valid ? i : 0) * ldx;
+  const bool vec4 = ((d & 3) == 0) && ((ldx & 3) == 0);
+  const float inv_w = 1.0f / w;
+  const int B = 128 / m < 32 ? 128 / m : 32;
+
+  // ---- x fragments (K index of step s for half h: h*DP/2 + s), exact |x|^2
+  float xb[S];
+#pragma unroll
+  for (int q = 0; q < S; q += 4) {
+    const int t0 = h * S + q;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+      if (vec4 && t0 + 3 < d) {
+        v = *reinterpret_cast<const float4*>(xr + t0);
+      } else {
+        v.x = t0 < d ? xr[t0] : 0.f;
+        v.y = t0 + 1 < d ? xr[t0 + 1] : 0.f;
+        v.z = t0 + 2 < d ? xr[t0 + 2] : 0.f;
+        v.w = t0 + 3 < d ? xr[t0 + 3] : 0.f;
+      }
+    }
+    xb[q] = v.x;
+    xb[q + 1] = v.y;
+    xb[q + 2] = v.z;
+    xb[q + 3] = v.w;
+  }
+  double nrm = 0.0;
+  bool finite = true;
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    finite = finite && isfinite(xb[q]);
+    nrm += (double)xb[q] * (double)xb[q];
+  }
+  if (!finite) set_status(st, GEEK_ERR_NONFINITE);
+  nrm += __shfl_xor(nrm, 32);
+  const float xn = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
+  // |q32 - q64| <= coef * (|a||x| + |b|) / w: float32 GEMM (2u per step,
+  // d+1 steps), + b, * (1/w) with 1/w rounded, float64 reference rounding.
+  const double u32 = 0x1p-24;
+  const double coef_d = ((DP + 1) * 2.0 * u32 / (1.0 - (DP + 1) * 2.0 * u32) + 6.0 * u32 +
+                         (DP + 3) * 0x1p-53) * 1.01;
+  const float coef = (float)coef_d;
+
+  if (tid == 0) lds_nfix = 0;
+  for (int tb = 0; tb < L; tb += tpc) {
+    const int ntab = (L - tb) < tpc ? (L - tb) : tpc;
+    const int p0 = tb * m;
+    const int rows_used = ntab * m;
+    __syncthreads();
+    for (int q = tid; q < H_BC * (DP / 4); q += H_THREADS) {
+      const int r = q / (DP / 4), c4 = (q % (DP / 4)) * 4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < rows_used) {
+        const float* ar = A + (int64_t)(p0 + r) * d;
+        v.x = c4 < d ? ar[c4] : 0.f;
+        v.y = c4 + 1 < d ? ar[c4 + 1] : 0.f;
+        v.z = c4 + 2 < d ? ar[c4 + 2] : 0.f;
+        v.w = c4 + 3 < d ? ar[c4 + 3] : 0.f;
+      }
+      *reinterpret_cast<float4*>(lds_a + r * STR + c4) = v;
+    }
+    if (tid < H_BC) {
+      lds_b[tid] = tid < rows_used ? bvec[p0 + tid] : 0.f;
+      lds_an[tid] = tid < rows_used ? anorm[p0 + tid] : 0.f;
+    }
+    lds_flag[tid] = 0u;  // H_THREADS == H_BN * H_BC / 32 words
+    __syncthreads();
+
+    f32x16 acc0 = {}, acc1 = {};
+    const float* a0p = lds_a + p * STR + h * S;
+    const float* a1p = a0p + 32 * STR;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0p[s], xb[s], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1p[s], xb[s], acc1, 0, 0, 0);
+    }
+    const int pl = wv * 32 + p;  // point within block
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const f32x16& acc = half ? acc1 : acc0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = half * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
+        if (row < rows_used) {
+          const float v = acc[r] + lds_b[row];
+          const float q = v * inv_w;
+          const float fq = floorf(q);
+          const float frac = q - fq;
+          const float tau = coef * __builtin_fmaf(lds_an[row], xn, fabsf(lds_b[row])) * inv_w +
+                            0x1p-22f;
+          const bool ok = frac > tau && frac < 1.0f - tau && fabsf(q) < 0x1p22f;
+          lds_code[pl * H_BC + row] = (int)fq;
+          if (!ok && valid) atomicOr(&lds_flag[pl * 2 + (row >> 5)], 1u << (row & 31));
+        }
+      }
+    }
+    __syncthreads();
+    // ---- float64 recomputation of the uncertified pairs, reference order
+    {
+      uint32_t bits = lds_flag[tid];
+      const unsigned int nf = __popc(bits);
+      while (bits) {
+        const int bb = __ffs(bits) - 1;
+        bits &= bits - 1u;
+        const int pp = tid >> 1, row = (tid & 1) * 32 + bb;
+        const int64_t ii = i0 + pp;
+        const float* xi = X + ii * ldx;
+        const float* ap = A + (int64_t)(p0 + row) * d;
+        double sacc = 0.0;
+        for (int t = 0; t < d; ++t) sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xi[t]));
+        const double v = __dadd_rn(sacc, (double)bvec[p0 + row]);
+        const double qd = v / (double)w;
+        const double fl = floor(qd);
+        const bool fits = fl >= -2147483648.0 && fl <= 2147483647.0;
+        if (!fits) set_status(st, GEEK_ERR_RANGE);
+        lds_code[pp * H_BC + row] = fits ? (int)fl : 0;
+      }
+      if (nf) atomicAdd(&lds_nfix, nf);
+    }
+    __syncthreads();
+    // ---- pack the m codes of every (table, point) into a 128-bit key
+    const int64_t np = (n - i0) < H_BN ? (n - i0) : H_BN;
+    for (int q = tid; keys && q < ntab * H_BN; q += H_THREADS) {
+      const int t = q / H_BN, pp = q % H_BN;
+      if (pp >= np) continue;
+      uint32_t kw[4] = {0u, 0u, 0u, 0u};
+      bool inr = true;
+      for (int j = 0; j < m; ++j) {
+        const int c = lds_code[pp * H_BC + t * m + j];
+        const int64_t off = (int64_t)c + (B == 32 ? 0x80000000ll : (1ll << (B - 1)));
+        inr = inr && off >= 0 && off < (B == 32 ? 0x100000000ll : (1ll << B));
+        const uint64_t f = (uint64_t)off & (B == 32 ? 0xFFFFFFFFull : ((1ull << B) - 1));
+        const int bit = j * B;
+        const int wi = bit >> 5, sh = bit & 31;
+        kw[wi] |= (uint32_t)(f << sh);
+        if (sh + B > 32 && wi < 3) kw[wi + 1] |= (uint32_t)(f >> (32 - sh));
+      }
+      if (!inr) set_status(st, GEEK_ERR_RANGE);
+      const int64_t ii = i0 + pp;
+      *reinterpret_cast<uint4*>(keys + ((int64_t)(tb + t) * n + ii) * 4) =
+          make_uint4(kw[0], kw[1], kw[2], kw[3]);
+    }
+    if (codes_out) {
+      for (int q = tid; q < H_BN * rows_used; q += H_THREADS) {
+        const int pp = q / rows_used, row = q % rows_used;
+        if (pp < np) codes_out[(i0 + pp) * P + p0 + row] = lds_code[pp * H_BC + row];
+      }
+    }
+  }
+  __syncthreads();
+  if (n_fixup && tid == 0 && lds_nfix) atomicAdd(n_fixup, (unsigned long long)lds_nfix);
+}
+
+// |a_p| rounded up (float64 sum of squares), per projection.
+__global__ void k_rownorm(const float* __restrict__ A, int P, int d, float* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P) return;
+  double s = 0.0;
+  for (int t = 0; t < d; ++t) s += (double)A[(int64_t)r * d + t] * (double)A[(int64_t)r * d + t];
+  out[r] = (float)(sqrt(s) * (1.0 + 0x1p-20));
+}
+
+__global__ void k_check_finite(const float* __restrict__ v, int64_t n, int32_t* st) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(v[i])) set_status(st, GEEK_ERR_NONFINITE);
+}
+
+// ---------------------------------------------------------------- MinHash
+// One wavefront per object.  Lane f keeps the running minimum of pi_g for
+// g = f, f + 64, ... (up to FPL functions per lane, F <= 64 * FPL).
+// `get_token` supplies token q of object i; tokens are read once per
+// wavefront (uniform address) and mixed once, then every lane applies its
+// affine maps.
+template <int FPL, class TokenFn>
+__device__ void minhash_row(int64_t i, int ntok, const TokenFn& get_token,
+                            const uint32_t* __restrict__ mh_keys, int F, uint32_t* __restrict__ sig) {
+  const int lane = threadIdx.x & 63;
+  uint32_t a[FPL], b[FPL], mn[FPL];
+#pragma unroll
+  for (int u = 0; u < FPL; ++u) {
+    const int f = lane + 64 * u;
+    a[u] = f < F ? (mh_keys[2 * f] | 1u) : 1u;
+    b[u] = f < F ? mh_keys[2 * f + 1] : 0u;
+    mn[u] = 0xFFFFFFFFu;
+  }
+  for (int q0 = 0; q0 < ntok; q0 += 64) {
+    // each lane loads and premixes one token, then they are broadcast
+    const uint32_t mine = (q0 + lane < ntok) ? fmix32(get_token(q0 + lane)) : 0u;
+    const int lim = (ntok - q0) < 64 ? (ntok - q0) : 64;
+    for (int q = 0; q < lim; ++q) {
+      const uint32_t y = __shfl(mine, q);
+#pragma unroll
+      for (int u = 0; u < FPL; ++u) {
+        const uint32_t v = perm_premixed(a[u], b[u], y);
+        mn[u] = v < mn[u] ? v : mn[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < FPL; ++u) {
+    const int f = lane + 64 * u;
+    if (f < F) sig[i * F + f] = mn[u];
+  }
+}
+
+template <int FPL>
+__global__ __launch_bounds__(256) void k_minhash_sets(const int64_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ tokens,
+                                                       int64_t n, const uint32_t* __restrict__ mh_keys,
+                                                       int F, uint32_t* __restrict__ sig, int32_t* st) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int64_t s = offsets[i], e = offsets[i + 1];
+  if (e <= s) {
+    set_status(st, GEEK_ERR_EMPTY_SET);
+    return;
+  }
+  const uint32_t* tk = tokens + s;
+  minhash_row<FPL>(i, (int)(e - s), [&](int q) { return tk[q]; }, mh_keys, F, sig);
+}
+
+// Heterogeneous rows: categorical tokens (a << 16) | v and numeric tokens
+// 0x80000000 | (p << 16) | (code + 32768), then MinHash of the token set.
+template <int FPL>
+__global__ __launch_bounds__(256) void k_minhash_hetero(const int32_t* __restrict__ cat, int n_cat,
+                                                         const int32_t* __restrict__ codes, int P,
+                                                         int64_t n, const uint32_t* __restrict__ mh_keys,
+                                                         int F, uint32_t* __restrict__ sig, int32_t* st) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const int32_t* cr = cat + i * n_cat;
+  const int32_t* co = codes + i * P;
+  auto tok = [&](int q) -> uint32_t {
+    if (q < n_cat) {
+      const int32_t v = cr[q];
+      if (v < 0 || v > 0xFFFF) set_status(st, GEEK_ERR_RANGE);
+      return ((uint32_t)q << 16) | ((uint32_t)v & 0xFFFFu);
+    }
+    const int pp = q - n_cat;
+    const int32_t c = co[pp];
+    if (c < -32768 || c > 32767) set_status(st, GEEK_ERR_RANGE);
+    return 0x80000000u | ((uint32_t)pp << 16) | ((uint32_t)(c + 32768) & 0xFFFFu);
+  };
+  minhash_row<FPL>(i, n_cat + P, tok, mh_keys, F, sig);
+}
+
+// ---------------------------------------------------------------- host side
+static int pick_dp_h(int d) { return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : d <= 256 ? 256 : 0; }
+
+size_t hash_ws(const geek_hash_job& J) {
+  Carver c(nullptr);
+  c.take<float>((size_t)J.m * J.L + 64);
+  if (J.kind == GEEK_HASH_HETERO) c.take<int32_t>((size_t)J.n * J.m * J.L);
+  c.take<unsigned long long>(1);
+  return c.used + 256;
+}
+
+static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys, int32_t* codes,
+                            unsigned long long* nfix, int32_t* st, hipStream_t s) {
+  const int P = J.m * J.L;
+  hipLaunchKernelGGL(k_rownorm, dim3(ceil_div(P, 128)), dim3(128), 0, s, J.A, P, J.d, anorm);
+  const int tpc = H_BC / J.m;  // whole tables per 64-row chunk
+  const int grid = ceil_div(J.n, H_BN);
+  if (grid == 0) return GEEK_OK;
+  switch (pick_dp_h(J.d)) {
+#define GEEK_H_CASE(DPV)                                                                        \
+  case DPV:                                                                                     \
+    hipLaunchKernelGGL((k_e2lsh<DPV>), dim3(grid), dim3(H_THREADS), 0, s, J.X, J.ldx, J.d, J.n, \
+                       J.A, J.b, anorm, J.m, J.L, J.w, tpc, keys, codes, nfix, st);             \
+    break;
+    GEEK_H_CASE(32)
+    GEEK_H_CASE(64)
+    GEEK_H_CASE(128)
+    GEEK_H_CASE(256)
+#undef GEEK_H_CASE
+    default:
+      return GEEK_ERR_UNSUPPORTED;
+  }
+  return GEEK_OK;
+}
+
+template <class Fn>
+static int32_t dispatch_fpl(int F, Fn&& fn) {
+  if (F <= 64) return fn(std::integral_constant<int, 1>{});
+  if (F <= 128) return fn(std::integral_constant<int, 2>{});
+  if (F <= 256) return fn(std::integral_constant<int, 4>{});
+  if (F <= 512) return fn(std::integral_constant<int, 8>{});
+  return GEEK_ERR_UNSUPPORTED;
+}
+
+int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s) {
+  Carver c(ws);
+  float* anorm = c.take<float>((size_t)J.m * J.L + 64);
+  int32_t* hcodes = (J.kind == GEEK_HASH_HETERO) ? c.take<int32_t>((size_t)J.n * J.m * J.L) : nullptr;
+  unsigned long long* dummy = c.take<unsigned long long>(1);
+  (void)dummy;
+  if (ws_bytes < c.used + 256) return GEEK_ERR_WORKSPACE;
+  int32_t rc = GEEK_OK;
+  if (J.kind == GEEK_HASH_DENSE) {
+    rc = launch_e2lsh(J, anorm, J.keys, J.codes, J.n_fixup, st, s);
+  } else if (J.kind == GEEK_HASH_SETS) {
+    if (J.n == 0) return GEEK_OK;
+    rc = dispatch_fpl(J.F, [&](auto fpl) {
+      hipLaunchKernelGGL((k_minhash_sets<decltype(fpl)::value>), dim3(ceil_div(J.n, 4)), dim3(256),
+                         0, s, J.offsets, J.tokens, J.n, J.mh_keys, J.F, J.sig, st);
+      return GEEK_OK;
+    });
+  } else {
+    // numeric codes without keys, then the token sets
+    uint32_t* no_keys = nullptr;
+    geek_hash_job D = J;
+    D.kind = GEEK_HASH_DENSE;
+    rc = launch_e2lsh(D, anorm, no_keys, hcodes, J.n_fixup, st, s);
+    if (rc != GEEK_OK) return rc;
+    if (J.n == 0) return GEEK_OK;
+    const int P = J.m * J.L;
+    rc = dispatch_fpl(J.F, [&](auto fpl) {
+      hipLaunchKernelGGL((k_minhash_hetero<decltype(fpl)::value>), dim3(ceil_div(J.n, 4)), dim3(256),
+                         0, s, J.cat, J.n_cat, hcodes, P, J.n, J.mh_keys, J.F, J.sig, st);
+      return GEEK_OK;
+    });
+  }
+  if (rc != GEEK_OK) return rc;
+  GEEK_LAUNCH_CHECK();
+  return GEEK_OK;
+}
+
+}  // namespace geek

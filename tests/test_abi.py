@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point that include/geek.h declares, and the ctypes job structs
+have the header's layout; argument errors are reported without a GPU."""
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2106_10515_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "geek.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\S.*?\b(geek_[a-z_]+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libgeek.so is not built (run __graft_entry__.build())")
+    lib = C.CDLL(L.LIB_PATH)
+    names = _declared()
+    assert set(names) >= set(L.EXPORTS)
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert L.version().startswith("geek")
+
+
+def test_struct_layouts_match_header(tmp_path):
+    exe = tmp_path / "abi_layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "abi_layout.c"), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    structs = {"geek_hash_job": L.HashJob, "geek_bucketize_job": L.BucketizeJob,
+               "geek_silk_job": L.SilkJob, "geek_assign_job": L.AssignJob}
+    n = 0
+    for line in out.splitlines():
+        sname, field, val = line.split()
+        cls = structs[sname]
+        if field == "sizeof":
+            assert C.sizeof(cls) == int(val), sname
+        else:
+            assert getattr(cls, field).offset == int(val), (sname, field)
+        n += 1
+    assert n > 60
+
+
+def test_argument_errors_need_no_gpu():
+    lib = L.lib()
+    nb = C.c_size_t(0)
+    bad = L.BucketizeJob(n=0, T=1, key_words=4)
+    assert lib.geek_workspace_size(L.GEEK_OP_BUCKETIZE, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_ARG
+    bad = L.AssignJob(metric=L.GEEK_METRIC_EUCLID, n=10, d=300, k=1, X=16, ldx=300,
+                      seed_offsets=16, seed_members=16, assign=16, sse=16, centroids=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_ASSIGN, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_UNSUPPORTED
+    bad = L.HashJob(kind=L.GEEK_HASH_DENSE, n=10, d=4, X=16, ldx=4, A=16, b=16, m=33, L=1, w=1.0, keys=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_HASH, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_UNSUPPORTED
+    bad = L.HashJob(kind=L.GEEK_HASH_DENSE, n=10, d=4, X=16, ldx=4, A=16, b=16, m=4, L=1, w=0.0, keys=16)
+    assert lib.geek_hash(C.byref(bad), 1, None, 0, None, None) == L.GEEK_ERR_ARG
+    assert lib.geek_status_string(L.GEEK_ERR_RANGE).decode() == "value outside the packable range"
+    ok = L.BucketizeJob(n=1000, T=3, key_words=4, keys=16, table_stride=4000, row_stride=4,
+                        members=16, offsets=16, nbuckets=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_BUCKETIZE, C.byref(ok), 1, C.byref(nb)) == 0
+    assert nb.value > 3 * 1000 * 20
+    # a too-small workspace is refused before any launch
+    assert lib.geek_bucketize(C.byref(ok), 1, C.c_void_p(256), 16, None, None) == L.GEEK_ERR_WORKSPACE

@@ -1,0 +1,99 @@
+"""GPU parity of geek_assign (Euclidean) against the FP64 oracle: centroids,
+assignments, distances and SSE bit for bit, radius to 1e-13 relative."""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import dense_mixture, e2lsh_params, key_words, planted_seeds
+from workloads.gen import STREAM_SILK
+
+from .gpu_util import announce, cuda, gpu_api
+
+pytestmark = pytest.mark.gpu
+
+PRECS = {"fp32": 0, "bf16": 1}
+
+
+def _check(api, X, so, sm, prec, name):
+    k = len(so) - 1
+    announce(f"assign {name} n={len(X)} d={X.shape[1]} k={k} prec={prec}")
+    C = oracle.centroids(X, so, sm)
+    a, dist = oracle.assign_euclid(X, C)
+    sse = oracle.sse(dist)
+    rad = oracle.radius(dist, a, k)
+    out = api.assign_euclid(cuda(X), cuda(so), cuda(sm), k, PRECS[prec])
+    assert np.array_equal(out["centroids"].cpu().numpy(), C)
+    got = out["assign"].cpu().numpy()
+    bad = np.flatnonzero(got != a)
+    assert bad.size == 0, (bad[:10], got[bad[:10]], a[bad[:10]])
+    assert np.array_equal(out["dist"].cpu().numpy(), dist)
+    assert out["sse"].item() == sse
+    np.testing.assert_allclose(out["radius"].cpu().numpy(), rad, rtol=1e-13, atol=0)
+    ctr = out["counters"].cpu().numpy()
+    assert ctr[0] + ctr[1] + ctr[2] >= len(X) and ctr[0] + ctr[2] <= len(X)
+    return ctr
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,d,clusters,per,seed", [
+    (3000, 32, 50, 32, 0),     # one centroid tile (k=50 padded to 64), ragged rows
+    (5000, 128, 300, 8, 1),    # five centroid tiles, 40 row tiles
+    (2000, 20, 40, 16, 2),     # d padded to 32
+    (1500, 256, 70, 4, 3),     # widest d
+    (777, 64, 129, 2, 4),      # k just above two tiles
+])
+def test_assign_planted(prec, n, d, clusters, per, seed):
+    api = gpu_api()
+    X, lab, _ = dense_mixture(n, d, clusters, -10, 10, 1.0, "equal", seed)
+    so, sm = planted_seeds(lab, clusters, per)
+    _check(api, X, so, sm, prec, "planted")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_assign_silk_seeds_many_per_cluster(prec):
+    # seeds from the oracle's SILK on the scaled small dense config: several
+    # seeds per cluster, so rows have many near-tied candidates
+    api = gpu_api()
+    n, d, m, L = 4000, 32, 8, 16
+    X, lab, _ = dense_mixture(n, d, 20, -10, 10, 1.0, "equal", 5)
+    w = 4.0 * np.sqrt(d)
+    A, b = e2lsh_params(m * L, d, w, 5)
+    codes = oracle.e2lsh_codes(X, A, b, w)
+    offs, mem = [0], []
+    for mm, oo, _ in oracle.bucketize_tables(codes, m, L):
+        mem.append(mm)
+        offs.extend((oo[1:].astype(np.int64) + offs[-1]).tolist())
+    keys = key_words(21 * 3, 5, STREAM_SILK)
+    so, sm, _ = oracle.silk_seeds(np.asarray(offs), np.concatenate(mem), 3, 20, 10, keys)
+    assert len(so) - 1 > 40
+    ctr = _check(api, X, so, sm, prec, "silk-seeds")
+    if prec == "bf16":
+        assert ctr[1] > 0  # the bf16 window overflowed for some rows
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_assign_ties_and_degenerate(prec):
+    api = gpu_api()
+    X, lab, _ = dense_mixture(1000, 16, 10, -10, 10, 1.0, "equal", 6)
+    # duplicated seeds (identical centroids): exact ties, lowest index wins;
+    # single-point seeds: those points are at distance 0
+    so = np.array([0, 5, 10, 11, 12, 17], dtype=np.uint32)
+    sm = np.array([1, 2, 3, 4, 5, 1, 2, 3, 4, 5, 40, 41, 1, 2, 3, 4, 5], dtype=np.uint32)
+    _check(api, X, so, sm, prec, "ties")
+    _check(api, X, np.array([0, 1000], np.uint32), np.arange(1000, dtype=np.uint32), prec, "k=1")
+    _check(api, X[:1], np.array([0, 1], np.uint32), np.array([0], np.uint32), prec, "n=1")
+
+
+def test_assign_nonfinite_input_is_reported():
+    api = gpu_api()
+    from paper_2106_10515_amd import GeekError
+
+    X, lab, _ = dense_mixture(300, 32, 3, -10, 10, 1.0, "equal", 7)
+    X[17, 5] = np.nan
+    so, sm = planted_seeds(lab, 3, 4)
+    sm = sm[~np.isin(sm, [17])] if 17 in sm else sm
+    so = np.array([0, len(sm)], np.uint32)
+    with pytest.raises(GeekError) as e:
+        api.assign_euclid(cuda(X), cuda(so), cuda(sm), 1, 0)
+    assert e.value.code == 1
