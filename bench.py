@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark of GEEK's data pass on one MI355X.
+
+Metric: points/s of hash + bucketize + assign on the dense large workload
+(n = 10,000,000 points, d = 128, a 10,000-cluster Gaussian mixture with Zipf
+cluster sizes; E2LSH with m = 10 codes x L = 32 tables, w = 8), with the
+assignment on the bfloat16 matrix cores (exact: every candidate within the
+rigorous error window is re-evaluated in float64).  The float32 matrix-core
+path is timed beside it on the same data.  SILK is not part of the metric's
+region; the assignment uses k = 10,000 planted seeds (the first 32 members of
+every planted cluster), because the literal hash width gives SILK almost
+only singleton buckets.
+
+One "step" = geek_hash + geek_bucketize + geek_assign over the whole input,
+which is resident in HBM before timing starts.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_BF16 = 2500.0   # TFLOP/s, MI355X dense bf16 matrix
+PEAK_FP32 = 157.3    # TFLOP/s, MI355X fp32 matrix
+PEAK_HBM = 8000.0    # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--clusters", type=int, default=10_000)
+    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2106_10515_amd import _lib as L
+    from paper_2106_10515_amd import api
+    from workloads import CONFIGS, dense_mixture, e2lsh_params, planted_seeds
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS["dense_large"]
+    n, d, m, Lt = args.n, cfg["d"], cfg["m"], cfg["L"]
+    w = cfg["w"] * (d ** 0.5 if args.scaled else 1.0)
+    clusters = min(args.clusters, n)
+
+    t0 = time.time()
+    X, labels, _ = dense_mixture(n, d, clusters, cfg["lo"], cfg["hi"], cfg["sigma"], cfg["sizes"],
+                                 seed=0, device=dev)
+    A, b = e2lsh_params(m * Lt, d, w, 0)
+    so, sm = planted_seeds(labels, clusters, 32)
+    k = len(so) - 1
+    Ag, bg = torch.from_numpy(A).to(dev), torch.from_numpy(b).to(dev)
+    sog = torch.from_numpy(so.view(np.int32)).to(dev)
+    smg = torch.from_numpy(sm.view(np.int32)).to(dev)
+    torch.cuda.synchronize()
+    log(f"workload ready n={n} d={d} k={k} in {time.time() - t0:.1f}s")
+
+    status = api.new_status(dev)
+    nfix = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def step(prec):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        keys, _ = api.hash_dense(X, Ag, bg, m, Lt, w, status=status, check=False, n_fixup=nfix)
+        ev[1].record()
+        mem, off, nb, bof = api.bucketize(keys, n, Lt, 4, n * 4, 4, status=status, check=False)
+        ev[2].record()
+        out = api.assign_euclid(X, sog, smg, k, prec, status=status, check=False)
+        ev[3].record()
+        return ev, out, (mem, off, nb, bof)
+
+    def run(prec, steps, warmup, profile=False):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        api.check_status(status, "warmup")
+        if profile:
+            L.geek_profile(True)
+        stage = np.zeros(3)
+        torch.cuda.synchronize()
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record()
+        evs = []
+        out = None
+        for _ in range(steps):
+            ev, out, _ = step(prec)
+            evs.append(ev)
+        t_end.record()
+        torch.cuda.synchronize()
+        api.check_status(status, "timed steps")
+        total = t_start.elapsed_time(t_end)
+        for ev in evs:
+            stage += [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+        prof = {}
+        if profile:
+            for name, kid in (("assign_scan", L.GEEK_PROF_ASSIGN_SCAN), ("e2lsh", L.GEEK_PROF_E2LSH),
+                              ("bucketize", L.GEEK_PROF_BUCKETIZE), ("assign", L.GEEK_PROF_ASSIGN),
+                              ("bz_sort", L.GEEK_PROF_BZ_SORT)):
+                ms, cnt = L.geek_profile_read(kid)
+                prof[name] = (ms / max(cnt, 1), cnt)
+            L.geek_profile(False)
+        return total / steps, stage / steps, out, prof
+
+    ms_bf16, st_bf16, out_bf16, prof_bf16 = run(L.GEEK_PREC_BF16, args.steps, args.warmup, True)
+    log(f"bf16 path {ms_bf16:.2f} ms/step stages {np.round(st_bf16, 2)}")
+    ctr_bf16 = out_bf16["counters"].cpu().numpy().tolist()
+    a_bf16 = out_bf16["assign"]
+    sse_bf16 = float(out_bf16["sse"].item())
+    ms_fp32, st_fp32, out_fp32, prof_fp32 = run(L.GEEK_PREC_FP32, args.fp32_steps, 1, True)
+    log(f"fp32 path {ms_fp32:.2f} ms/step stages {np.round(st_fp32, 2)}")
+    same = bool(torch.equal(a_bf16, out_fp32["assign"])) and sse_bf16 == float(out_fp32["sse"].item())
+
+    flops = 2.0 * n * d * k
+    scan_ms = prof_bf16["assign_scan"][0]
+    ach = flops / (scan_ms * 1e-3) / 1e12
+    scan32_ms = prof_fp32["assign_scan"][0]
+    ach32 = flops / (scan32_ms * 1e-3) / 1e12
+    hash_ms = prof_bf16["e2lsh"][0]
+    hash_tf = 2.0 * n * d * m * Lt / (hash_ms * 1e-3) / 1e12
+    bz_ms = prof_bf16["bucketize"][0]
+    bz_gbs = 28.0 * n * Lt / (bz_ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(X, A, b, w, m, Lt, so, sm, a_bf16, args.cpu_rows, n, log)
+
+    value = n / (ms_bf16 * 1e-3)
+    res = {
+        "metric": "points/s (hash+bucketize+assign), d=128 k≈1e4: BF16-MFMA vs FP32 path",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_bf16,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"dense_large: n={n} d={d} {clusters}-cluster Gaussian mixture "
+                               f"(Zipf sizes), E2LSH m={m} L={Lt} w={w:g}, k={k} planted seeds",
+                   "n": n, "d": d, "k": k, "m": m, "L": Lt, "w": w, "seeds": "planted"},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_BF16, "traffic": None,
+                     "kernel": "k_scan<ModeBF16,128>", "avg_launch_ms": scan_ms,
+                     "flop_per_launch": flops},
+        "fp32_path": {"value": n / (ms_fp32 * 1e-3), "ms_per_step": ms_fp32,
+                      "stages_ms": dict(zip(("hash", "bucketize", "assign"), st_fp32.round(3).tolist())),
+                      "scan_ms": scan32_ms, "scan_tflops": ach32, "scan_frac": ach32 / PEAK_FP32},
+        "speedup_bf16_over_fp32": ms_fp32 / ms_bf16,
+        "stages_ms": dict(zip(("hash", "bucketize", "assign"), st_bf16.round(3).tolist())),
+        "kernels": {"e2lsh_ms": hash_ms, "e2lsh_tflops": hash_tf, "e2lsh_frac_fp32": hash_tf / PEAK_FP32,
+                    "bucketize_ms": bz_ms, "bucketize_gbs_algorithmic": bz_gbs,
+                    "bz_sort_ms": prof_bf16["bz_sort"][0]},
+        "assign_counters": {"first_pass_rows": ctr_bf16[0], "rescanned_fp32": ctr_bf16[1],
+                            "full_fp64_rows": ctr_bf16[2], "fp64_candidate_evals": ctr_bf16[3]},
+        "bf16_equals_fp32": same,
+        "sse": sse_bf16,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+def cpu_baseline(X, A, b, w, m, Lt, so, sm, a_gpu, rows, n, log):
+    """The FP64 oracle on the first ``rows`` points of the same workload with
+    all k centroids (centroid cost prorated to the sample)."""
+    import numpy as np
+
+    import oracle
+
+    Xs = X[:rows].cpu().numpy()
+    t0 = time.time()
+    codes = oracle.e2lsh_codes(Xs, A, b, w)
+    oracle.bucketize_tables(codes, m, Lt)
+    t_hb = time.time() - t0
+    mem_rows = X[np.asarray(sm, dtype=np.int64)].cpu().numpy()
+    so_local = so.astype(np.int64)
+    t0 = time.time()
+    C = oracle.centroids(mem_rows, so_local, np.arange(len(sm), dtype=np.uint32))
+    t_c = time.time() - t0
+    t0 = time.time()
+    a, _ = oracle.assign_euclid(Xs, C)
+    t_a = time.time() - t0
+    agree = bool(np.array_equal(a, a_gpu[:rows].cpu().numpy()))
+    t = t_hb + t_a + t_c * rows / n
+    log(f"cpu oracle: {rows} rows hash+bucketize {t_hb:.1f}s assign {t_a:.1f}s centroids {t_c:.1f}s")
+    return {"value": rows / t, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {rows} of {n} points, all {len(so) - 1} centroids; centroid time "
+                      f"prorated by rows/n; numpy float64, single thread",
+            "seconds": t, "sample_assign_matches_gpu": agree}
+
+
+if __name__ == "__main__":
+    main()

@@ -247,6 +247,9 @@ typedef struct geek_assign_job {
   double* sse;              /* out [1] */
   double* radius;           /* optional out [k] */
   unsigned long long* counters; /* optional out [4] */
+  int64_t n_members;        /* host: seed_offsets[k], the total number of seed
+                               members (required by SIG and HETERO, which
+                               size their mode computation by it) */
 } geek_assign_job;
 
 /* ---- entry points -------------------------------------------------------- */
@@ -266,6 +269,24 @@ int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size
                         int32_t* d_status, void* stream);
 int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                     int32_t* d_status, void* stream);
+
+/* ---- profiling (opt-in) -------------------------------------------------
+ * With profiling enabled the library brackets its main kernels with HIP
+ * events recorded on the call's stream.  geek_profile(1) clears earlier
+ * records and starts recording, geek_profile(0) stops.  geek_profile_read
+ * waits for the recorded events of kernel `id` and returns their summed
+ * duration (ms) and count.  Not for use under graph capture.
+ */
+#define GEEK_PROF_E2LSH 0        /* k_e2lsh: projection GEMM + floor/pack */
+#define GEEK_PROF_BUCKETIZE 1    /* all kernels of one geek_bucketize job */
+#define GEEK_PROF_ASSIGN_SCAN 2  /* first matrix-core pass of geek_assign */
+#define GEEK_PROF_ASSIGN 3       /* all kernels of one geek_assign job */
+#define GEEK_PROF_MINHASH 4      /* MinHash kernel of geek_hash */
+#define GEEK_PROF_SILK 5         /* all kernels of one geek_silk_seeds job */
+#define GEEK_PROF_BZ_SORT 6      /* per-bin sort kernel of geek_bucketize */
+#define GEEK_PROF_COUNT 8
+int32_t geek_profile(int32_t enable);
+int32_t geek_profile_read(int32_t id, double* total_ms, int64_t* launches);
 
 /* Static description of a status code. */
 const char* geek_status_string(int32_t status);

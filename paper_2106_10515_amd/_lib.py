@@ -81,11 +81,16 @@ class AssignJob(C.Structure):
         ("sig", P), ("F", C.c_int32), ("n_cat", C.c_int32), ("cat", P), ("gamma", C.c_double),
         ("seed_offsets", P), ("seed_members", P), ("assign", P), ("centroids", P),
         ("modes", P), ("dist", P), ("sse", P), ("radius", P), ("counters", P),
+        ("n_members", C.c_int64),
     ]
 
 
 EXPORTS = ("geek_workspace_size", "geek_hash", "geek_bucketize", "geek_silk_seeds",
-           "geek_assign", "geek_status_string", "geek_version", "geek_last_hip_error")
+           "geek_assign", "geek_status_string", "geek_version", "geek_last_hip_error",
+           "geek_profile", "geek_profile_read")
+
+GEEK_PROF_E2LSH, GEEK_PROF_BUCKETIZE, GEEK_PROF_ASSIGN_SCAN, GEEK_PROF_ASSIGN = 0, 1, 2, 3
+GEEK_PROF_MINHASH, GEEK_PROF_SILK, GEEK_PROF_BZ_SORT = 4, 5, 6
 
 _LIB = None
 
@@ -108,6 +113,10 @@ def _load():
     lib.geek_status_string.restype = C.c_char_p
     lib.geek_version.restype = C.c_char_p
     lib.geek_last_hip_error.restype = C.c_char_p
+    lib.geek_profile.argtypes = [C.c_int32]
+    lib.geek_profile.restype = C.c_int32
+    lib.geek_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.geek_profile_read.restype = C.c_int32
     _LIB = lib
     return lib
 
@@ -119,6 +128,20 @@ def lib():
 
 def version() -> str:
     return _load().geek_version().decode()
+
+
+def geek_profile(enable: bool) -> None:
+    _load().geek_profile(1 if enable else 0)
+
+
+def geek_profile_read(kernel_id: int):
+    """(total milliseconds, number of launches) recorded for ``kernel_id``."""
+    ms = C.c_double(0.0)
+    cnt = C.c_int64(0)
+    rc = _load().geek_profile_read(kernel_id, C.byref(ms), C.byref(cnt))
+    if rc != GEEK_OK:
+        raise GeekError(rc, "geek_profile_read")
+    return float(ms.value), int(cnt.value)
 
 
 def workspace_size(op: int, jobs) -> int:

@@ -182,7 +182,8 @@ def assign_euclid(X, seed_offsets, seed_members, k, precision=L.GEEK_PREC_FP32,
     )
     status = new_status(dev) if status is None else status
     j = L.AssignJob(metric=L.GEEK_METRIC_EUCLID, precision=precision, n=n, d=d, k=k, X=_p(X),
-                    ldx=X.stride(0), seed_offsets=_p(seed_offsets), seed_members=_p(seed_members),
+                    ldx=X.stride(0), n_members=seed_members.numel(),
+                    seed_offsets=_p(seed_offsets), seed_members=_p(seed_members),
                     assign=_p(out["assign"]), centroids=_p(out["centroids"]), dist=_p(out["dist"]),
                     sse=_p(out["sse"]), radius=_p(out["radius"]), counters=_p(out["counters"]))
     _run(L.GEEK_OP_ASSIGN, L.geek_assign, [j], dev, status)
@@ -205,8 +206,38 @@ def assign_sig(sig, seed_offsets, seed_members, k, want_dist=True, status=None, 
     )
     status = new_status(dev) if status is None else status
     j = L.AssignJob(metric=L.GEEK_METRIC_SIG, n=n, k=k, sig=_p(sig), F=F,
+                    n_members=seed_members.numel(),
                     seed_offsets=_p(seed_offsets), seed_members=_p(seed_members),
                     assign=_p(out["assign"]), modes=_p(out["modes"]), dist=_p(out["dist"]),
+                    sse=_p(out["sse"]), radius=_p(out["radius"]), counters=_p(out["counters"]))
+    _run(L.GEEK_OP_ASSIGN, L.geek_assign, [j], dev, status)
+    if check:
+        check_status(status, "geek_assign")
+    return out
+
+
+def assign_hetero(X, cat, seed_offsets, seed_members, k, gamma=1.0, precision=L.GEEK_PREC_FP8,
+                  want_dist=True, status=None, check=True):
+    """Heterogeneous rows: numeric centroid + categorical modes; distance =
+    squared Euclidean over X + gamma * mismatching categorical attributes."""
+    dev = _dev(X)
+    n, d = X.shape
+    n_cat = cat.shape[1]
+    out = dict(
+        assign=torch.empty((n,), dtype=torch.int32, device=dev),
+        centroids=torch.empty((k, d), dtype=torch.float64, device=dev),
+        modes=torch.empty((k, n_cat), dtype=torch.int32, device=dev),
+        dist=torch.empty((n,), dtype=torch.float64, device=dev) if want_dist else None,
+        sse=torch.empty((1,), dtype=torch.float64, device=dev),
+        radius=torch.empty((k,), dtype=torch.float64, device=dev),
+        counters=torch.zeros((4,), dtype=torch.int64, device=dev),
+    )
+    status = new_status(dev) if status is None else status
+    j = L.AssignJob(metric=L.GEEK_METRIC_HETERO, precision=precision, n=n, d=d, k=k, X=_p(X),
+                    ldx=X.stride(0), n_cat=n_cat, cat=_p(cat), gamma=float(gamma),
+                    n_members=seed_members.numel(), seed_offsets=_p(seed_offsets),
+                    seed_members=_p(seed_members), assign=_p(out["assign"]),
+                    centroids=_p(out["centroids"]), modes=_p(out["modes"]), dist=_p(out["dist"]),
                     sse=_p(out["sse"]), radius=_p(out["radius"]), counters=_p(out["counters"]))
     _run(L.GEEK_OP_ASSIGN, L.geek_assign, [j], dev, status)
     if check:

@@ -3,7 +3,9 @@
 // and assign.hip.
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -23,6 +25,34 @@ size_t assign_sig_ws(const geek_assign_job& J);
 int32_t assign_sig(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
 
 static thread_local std::string g_last_err;
+
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static thread_local int g_open[GEEK_PROF_COUNT] = {-1, -1, -1, -1, -1, -1, -1, -1};
+
+void prof_begin(int id, hipStream_t s) {
+  if (!g_prof_on || id < 0 || id >= GEEK_PROF_COUNT) return;
+  ProfRec r{id, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  hipEventRecord(r.a, s);
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_open[id] = (int)g_prof.size();
+  g_prof.push_back(r);
+}
+
+void prof_end(int id, hipStream_t s) {
+  if (!g_prof_on || id < 0 || id >= GEEK_PROF_COUNT) return;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  const int k = g_open[id];
+  if (k < 0 || k >= (int)g_prof.size()) return;
+  hipEventRecord(g_prof[k].b, s);
+  g_open[id] = -1;
+}
 
 int32_t hip_fail(hipError_t e) {
   g_last_err = hipGetErrorString(e);
@@ -74,10 +104,16 @@ static int32_t check_assign(const geek_assign_job& J) {
   if (J.metric == GEEK_METRIC_EUCLID || J.metric == GEEK_METRIC_HETERO) {
     if (!J.X || !al4(J.X) || J.d < 1 || J.ldx < J.d || !J.centroids) return GEEK_ERR_ARG;
     if (J.d > 256) return GEEK_ERR_UNSUPPORTED;
-    if (J.precision != GEEK_PREC_FP32 && J.precision != GEEK_PREC_BF16) return GEEK_ERR_UNSUPPORTED;
-    if (J.metric == GEEK_METRIC_HETERO) return GEEK_ERR_UNSUPPORTED;
+    if (J.precision != GEEK_PREC_FP32 && J.precision != GEEK_PREC_BF16 && J.precision != GEEK_PREC_FP8)
+      return GEEK_ERR_UNSUPPORTED;
+    if (J.metric == GEEK_METRIC_HETERO) {
+      if (!J.cat || J.n_cat < 1 || !J.modes || J.n_members < J.k) return GEEK_ERR_ARG;
+      if (J.n_cat > 16) return GEEK_ERR_UNSUPPORTED;
+      // gamma must be finite, non-negative and exact in float32
+      if (!(J.gamma >= 0.0) || !(J.gamma < 1e30) || (double)(float)J.gamma != J.gamma) return GEEK_ERR_ARG;
+    }
   } else if (J.metric == GEEK_METRIC_SIG) {
-    if (!J.sig || J.F < 1 || !J.modes) return GEEK_ERR_ARG;
+    if (!J.sig || J.F < 1 || !J.modes || J.n_members < J.k) return GEEK_ERR_ARG;
     if (J.F > 1024) return GEEK_ERR_UNSUPPORTED;
   } else {
     return GEEK_ERR_ARG;
@@ -108,6 +144,39 @@ const char* geek_status_string(int32_t s) {
 }
 
 const char* geek_version(void) { return "geek 0.1.0 gfx950"; }
+
+int32_t geek_profile(int32_t enable) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (enable) {
+    for (auto& r : g_prof) {
+      hipEventSynchronize(r.b);
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    for (int i = 0; i < GEEK_PROF_COUNT; ++i) g_open[i] = -1;
+  }
+  g_prof_on = enable != 0;
+  return GEEK_OK;
+}
+
+int32_t geek_profile_read(int32_t id, double* total_ms, int64_t* launches) {
+  if (!total_ms || !launches) return GEEK_ERR_ARG;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& r : g_prof) {
+    if (r.id != id) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return hip_fail(hipGetLastError());
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return hip_fail(hipGetLastError());
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return GEEK_OK;
+}
 
 const char* geek_last_hip_error(void) { return g_last_err.c_str(); }
 

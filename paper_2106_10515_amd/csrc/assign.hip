@@ -15,6 +15,11 @@
 //                 Rows whose candidate window overflowed are escalated.
 //   k_fallback64  float64 distance to every centroid for the rows left.
 //   k_sse_*       SSE in fixed 4096-row blocks; radius per cluster.
+//
+// Heterogeneous rows (numeric attributes + categorical attributes) use the
+// same pipeline with D = D_num + gamma * #mismatching attributes: the
+// mismatch count is exact and added in the scan epilogue; the categorical
+// central vector is the per-attribute mode (assign_sig.hip computes modes).
 #include <math.h>
 
 #include "common.hpp"
@@ -52,78 +57,175 @@ __global__ void k_centroids(const float* __restrict__ X, int64_t ldx, int64_t n,
   C[gid] = acc / (double)(e - s);
 }
 
+// Largest |value| of a float32 matrix / float64 centroids (FP8 scaling).
+__global__ void k_absmax_x(const float* __restrict__ X, int64_t ldx, int64_t n, int d, float* __restrict__ out) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  float m = 0.f;
+  for (int64_t e = g; e < n * d; e += (int64_t)gridDim.x * blockDim.x) {
+    const float v = fabsf(X[(e / d) * ldx + (e % d)]);
+    if (v > m) m = v;  // NaN compares false and is ignored here
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
+}
+
+__global__ void k_absmax_c(const double* __restrict__ C, int64_t kd, float* __restrict__ out) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  float m = 0.f;
+  for (int64_t e = g; e < kd; e += (int64_t)gridDim.x * blockDim.x) m = fmaxf(m, (float)fabs(C[e]) * 1.0001f);
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(out, m);
+}
+
+// scale = 2^floor(log2(224 / max)), so scaled values stay inside every
+// e4m3 variant's normal range; 1 when everything is zero.
+__global__ void k_fp8_scale(const float* __restrict__ mx, const float* __restrict__ mc, float* __restrict__ scale) {
+  if (blockIdx.x || threadIdx.x) return;
+  const float m = fmaxf(*mx, *mc);
+  *scale = m > 0.f ? exp2f(floorf(log2f(224.0f / m))) : 1.0f;
+}
+
 // Matrix-core input copies of the centroids, zero-padded to [k_pad][DP];
 // padded rows get |c|^2 = +inf so they never enter a window.
-template <class CE>
+template <class M>
 __global__ void k_cprep(const double* __restrict__ C, int k, int d, int k_pad, int DP,
-                        CE* __restrict__ cl, float* __restrict__ nc, float* __restrict__ cmax) {
+                        typename M::ce* __restrict__ cl, float* __restrict__ nc, float* __restrict__ cmax,
+                        const float* __restrict__ scale_p) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k_pad) return;
+  const float sc = M::SCALED ? *scale_p : 1.0f;
   if (j >= k) {
-    for (int t = 0; t < DP; ++t) cl[(int64_t)j * DP + t] = (CE)0.0f;
-    nc[j] = INFINITY;
+    for (int t = 0; t < DP; t += M::KPER) M::store_zero(cl + (int64_t)j * DP + t);
+    if (nc) nc[j] = INFINITY;
     return;
   }
-  double s = 0.0;
-  for (int t = 0; t < DP; ++t) {
-    double c = t < d ? C[(int64_t)j * d + t] : 0.0;
-    s = __dadd_rn(s, __dmul_rn(c, c));
-    cl[(int64_t)j * DP + t] = (CE)(float)c;
+  double sq = 0.0;
+  float v[M::KPER];
+  for (int t = 0; t < DP; t += M::KPER) {
+#pragma unroll
+    for (int e = 0; e < M::KPER; ++e) {
+      const double c = t + e < d ? C[(int64_t)j * d + t + e] : 0.0;
+      sq = __dadd_rn(sq, __dmul_rn(c, c));
+      v[e] = (float)c;
+    }
+    M::store(cl + (int64_t)j * DP + t, v, sc);
   }
-  nc[j] = (float)s;
-  atomic_max_nonneg(cmax, (float)(sqrt(s) * (1.0 + 0x1p-20)));
+  if (nc) {
+    nc[j] = (float)sq;
+    atomic_max_nonneg(cmax, (float)(sqrt(sq) * (1.0 + 0x1p-20)));
+  }
 }
 
 // ---------------------------------------------------------------- modes
 struct ModeF32 {
   static constexpr int KPER = 1;  // K elements per lane per instruction
+  static constexpr bool SCALED = false;
   using ce = float;
   using frag = float;
   static constexpr double UX = 0.0;        // x is already float32
   static constexpr double UC = 0x1p-24;    // float64 -> float32 rounding
+  static constexpr double A0 = 0.0;        // absolute error per element (scaled units)
   GEEK_D static f32x16 mma(frag a, frag b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
   GEEK_D static frag load_lds(const ce* p) { return *p; }
-  GEEK_D static frag from_f32(const float* v) { return v[0]; }
+  GEEK_D static frag from_f32(const float* v, float) { return v[0]; }
+  GEEK_D static void store(ce* p, const float* v, float) { p[0] = v[0]; }
+  GEEK_D static void store_zero(ce* p) { p[0] = 0.f; }
 };
 
 struct ModeBF16 {
   static constexpr int KPER = 8;
+  static constexpr bool SCALED = false;
   using ce = __bf16;
   using frag = bf16x8;
   static constexpr double UX = 0x1p-8;  // conservative for any rounding to bf16
   static constexpr double UC = 0x1p-8;
+  static constexpr double A0 = 0.0;
   GEEK_D static f32x16 mma(frag a, frag b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
   GEEK_D static frag load_lds(const ce* p) { return *reinterpret_cast<const bf16x8*>(p); }
-  GEEK_D static frag from_f32(const float* v) {
+  GEEK_D static frag from_f32(const float* v, float) {
     frag f;
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] = (__bf16)v[e];
     return f;
   }
+  GEEK_D static void store(ce* p, const float* v, float) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) p[e] = (__bf16)v[e];
+  }
+  GEEK_D static void store_zero(ce* p) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) p[e] = (__bf16)0.0f;
+  }
 };
+
+// e4m3 inputs, scaled by a power of two into the normal range; products are
+// exact in float32.  Relative rounding 2^-3 (conservative), absolute error
+// 2^-10 per element in scaled units (half the smallest subnormal spacing of
+// either e4m3 variant).
+struct ModeFP8 {
+  static constexpr int KPER = 8;
+  static constexpr bool SCALED = true;
+  using ce = uint8_t;
+  using frag = long;
+  static constexpr double UX = 0x1p-3;
+  static constexpr double UC = 0x1p-3;
+  static constexpr double A0 = 0x1p-10;
+  GEEK_D static f32x16 mma(frag a, frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
+  }
+  GEEK_D static frag load_lds(const ce* p) { return *reinterpret_cast<const long*>(p); }
+  GEEK_D static frag from_f32(const float* v, float sc) {
+    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * sc, v[1] * sc, 0, false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2] * sc, v[3] * sc, lo, true);
+    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4] * sc, v[5] * sc, 0, false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6] * sc, v[7] * sc, hi, true);
+    return (long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+  }
+  GEEK_D static void store(ce* p, const float* v, float sc) {
+    *reinterpret_cast<long*>(p) = from_f32(v, sc);
+  }
+  GEEK_D static void store_zero(ce* p) { *reinterpret_cast<long*>(p) = 0; }
+};
+
+// Categorical part of heterogeneous rows (cat == nullptr: Euclidean only).
+struct Het {
+  const int32_t* cat;     // [n][n_cat]
+  const uint32_t* mode;   // [k][n_cat] per-attribute modes of the seeds
+  int n_cat;
+  float gamma_f;          // gamma, exactly representable in float32
+  double gamma;
+};
+constexpr int MAX_CAT = 16;
 
 GEEK_D double gamma_n(double nn, double u) { return nn * u / (1.0 - nn * u); }
 
 // Rigorous bound on |(|x|^2 + v_j) - D64(i, j)| for every j, where v_j is the
-// float32 epilogue value fma(-2, acc, |c_j|^2) and D64 the float64 reference.
+// float32 epilogue value fma(-2/s^2, acc, |c_j|^2) (+ gamma * mismatches)
+// and D64 the float64 reference.  X = |x|, cm = max |c|; the inputs are
+// rounded with relative error UX/UC and absolute error A0/s per element, so
+// |x^ - x| <= ex = UX X + A0 sqrt(DP) / s (likewise ec) and, by Cauchy-
+// Schwarz, |x^.c^ - x.c| <= ex cm + X ec + ex ec; the float32 accumulation of
+// the (exact) products adds gamma_{DP+1}(2u) |x^| |c^|.
 template <class M, int DP>
-GEEK_D float two_eps(double xn, double cm) {
+GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
   const double u32 = 0x1p-24;
-  const double ux = M::UX, uc = M::UC;
   const double g_acc = gamma_n(DP + 1, 2.0 * u32);
   const double g64 = gamma_n(DP + 2, 0x1p-53);
-  const double xc = xn * cm;
-  const double s2 = (xn + cm) * (xn + cm);
-  double eps = 2.0 * ((ux + uc + ux * uc) + g_acc * (1.0 + ux) * (1.0 + uc)) * xc  // 2 x.c
-               + (u32 + g64) * cm * cm                    // |c|^2 stored as float32
-               + u32 * (cm * cm + 2.01 * xc)              // epilogue rounding
-               + g64 * s2                                 // float64 reference rounding
-               + 4.0 * u32 * s2                           // threshold arithmetic
-               + DP * 0x1p-120;                           // flushed subnormal products
+  const double ab = M::A0 * inv_scale * sqrt((double)DP);
+  const double ex = M::UX * xn + ab, ec = M::UC * cm + ab;
+  const double dot = ex * cm + xn * ec + ex * ec + g_acc * (xn + ex) * (cm + ec);
+  const double vmax = cm * cm + 2.0 * (xn + ex) * (cm + ec) + het_max;
+  const double s2 = (xn + cm) * (xn + cm) + het_max;
+  double eps = 2.0 * dot                       // 2 x.c
+               + (u32 + g64) * cm * cm          // |c|^2 stored as float32
+               + 2.0 * u32 * vmax               // epilogue roundings
+               + g64 * s2 + 0x1p-52 * het_max   // float64 reference rounding
+               + 4.0 * u32 * s2                 // threshold arithmetic
+               + DP * 0x1p-120;                 // flushed subnormal products
   eps *= 1.01;
   return (float)(2.0 * eps * (1.0 + 0x1p-20));
 }
@@ -135,12 +237,13 @@ GEEK_D float two_eps(double xn, double cm) {
 // element e is h*DP/2 + s*KPER + e (any bijection works for a dot product
 // as long as A and B agree).  Accumulator register r of lane l holds
 // centroid row (r/4)*8 + h*4 + r%4 of point p.
-template <class M, int DP>
+template <class M, int DP, bool HET>
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n_rows,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
     const typename M::ce* __restrict__ cl, const float* __restrict__ nc, int k_pad,
-    const float* __restrict__ cmax_p, int32_t* __restrict__ rec, int32_t* st) {
+    const float* __restrict__ cmax_p, const float* __restrict__ scale_p, Het het, int k,
+    int32_t* __restrict__ rec, int32_t* st) {
   using CE = typename M::ce;
   constexpr int S = DP / 2 / M::KPER;       // MFMA steps over K
   constexpr int STR = DP + 16 / (int)sizeof(CE);  // padded LDS row (elements)
@@ -148,6 +251,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
   __shared__ float lds_nc[SCAN_BC];
   __shared__ float lds_lv[SCAN_THREADS * TCAND];
   __shared__ int lds_lj[SCAN_THREADS * TCAND];
+  __shared__ uint32_t lds_mode[HET ? SCAN_BC * MAX_CAT : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
@@ -157,7 +261,10 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
 
   const int64_t count = rows ? (int64_t)*rows_count : n_rows;
   const double cm = (double)*cmax_p;
+  const float sc = M::SCALED ? *scale_p : 1.0f;
+  const float m2s = -2.0f / (sc * sc);  // power of two: exact rescaling
   const bool vec4 = ((d & 3) == 0) && ((ldx & 3) == 0);
+  const double het_max = HET ? het.gamma * het.n_cat : 0.0;
 
   for (int64_t tile = blockIdx.x; tile * SCAN_BN < count; tile += gridDim.x) {
     const int64_t pos = tile * SCAN_BN + w * 32 + p;
@@ -195,10 +302,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
     }
     typename M::frag xb[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) xb[s] = M::from_f32(xv + s * M::KPER);
+    for (int s = 0; s < S; ++s) xb[s] = M::from_f32(xv + s * M::KPER, sc);
     if (!finite) set_status(st, GEEK_ERR_NONFINITE);
     nrm += __shfl_xor(nrm, 32);
-    const float twoeps = two_eps<M, DP>(sqrt(nrm) * (1.0 + 1e-12), cm);
+    const float twoeps = two_eps<M, DP>(sqrt(nrm) * (1.0 + 1e-12), cm, 1.0 / sc, het_max);
+    int32_t crow[HET ? MAX_CAT : 1];
+    if constexpr (HET) {
+#pragma unroll
+      for (int a = 0; a < MAX_CAT; ++a) crow[a] = (valid && a < het.n_cat) ? het.cat[i * het.n_cat + a] : 0;
+    }
 
     // thr starts at the largest finite float: padded centroids (|c|^2 = +inf)
     // and non-finite values never enter the window
@@ -217,6 +329,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
         *reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds_c + r * STR) + c * 16) = val;
       }
       if (tid < SCAN_BC) lds_nc[tid] = nc[c0 + tid];
+      if constexpr (HET) {
+        for (int q = tid; q < SCAN_BC * MAX_CAT; q += SCAN_THREADS) {
+          const int r = q / MAX_CAT, a = q % MAX_CAT;
+          lds_mode[q] = (a < het.n_cat && c0 + r < k) ? het.mode[(int64_t)(c0 + r) * het.n_cat + a] : 0u;
+        }
+      }
       __syncthreads();
 
 #pragma unroll
@@ -238,7 +356,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int row = (r >> 2) * 8 + h * 4 + (r & 3);
-            v[r] = __builtin_fmaf(-2.0f, acc[r], lds_nc[jb + row]);
+            v[r] = __builtin_fmaf(m2s, acc[r], lds_nc[jb + row]);
+            if constexpr (HET) {
+              const uint32_t* md = lds_mode + (jb + row) * MAX_CAT;
+              int mm = 0;
+#pragma unroll
+              for (int a = 0; a < MAX_CAT; ++a) mm += (a < het.n_cat && (uint32_t)crow[a] != md[a]) ? 1 : 0;
+              v[r] = v[r] + het.gamma_f * (float)mm;
+            }
             vmin = fminf(vmin, v[r]);
           }
           if (vmin <= thr) {
@@ -319,6 +444,17 @@ GEEK_D double d64(const float* __restrict__ xr, const double* __restrict__ cr, i
   return acc;
 }
 
+// D_num + gamma * mismatches, in that float64 order (reference formula).
+GEEK_D double d64h(const float* __restrict__ xr, const double* __restrict__ cr, int d, const Het& het,
+                   int64_t i, int j) {
+  const double dn = d64(xr, cr, d);
+  if (!het.cat) return dn;
+  int mm = 0;
+  for (int a = 0; a < het.n_cat; ++a)
+    mm += ((uint32_t)het.cat[i * het.n_cat + a] != het.mode[(int64_t)j * het.n_cat + a]) ? 1 : 0;
+  return __dadd_rn(dn, __dmul_rn(het.gamma, (double)mm));
+}
+
 __device__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
   // one atomic per wave
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -326,7 +462,7 @@ __device__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
 }
 
 __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
-                           const double* __restrict__ C, int k, int64_t n_rows,
+                           const double* __restrict__ C, int k, Het het, int64_t n_rows,
                            const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
                            const int32_t* __restrict__ rec, int32_t* __restrict__ assign,
                            double* __restrict__ dist, uint32_t* __restrict__ esc,
@@ -353,7 +489,7 @@ __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
         for (int q = 0; q < c; ++q) {
           const int j = rr[1 + q];
           if ((unsigned)j >= (unsigned)k) continue;
-          const double D = d64(xr, C + (int64_t)j * d, d);
+          const double D = d64h(xr, C + (int64_t)j * d, d, het, i, j);
           if (D < best || (D == best && j < bj)) {
             best = D;
             bj = j;
@@ -375,7 +511,7 @@ __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
 
 // One block per row: float64 distance to every centroid, lowest index on ties.
 __global__ __launch_bounds__(256) void k_fallback64(
-    const float* __restrict__ X, int64_t ldx, int d, const double* __restrict__ C, int k,
+    const float* __restrict__ X, int64_t ldx, int d, const double* __restrict__ C, int k, Het het,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
     int32_t* __restrict__ assign, double* __restrict__ dist, unsigned long long* __restrict__ ctr) {
   __shared__ float xs[1024];
@@ -390,7 +526,7 @@ __global__ __launch_bounds__(256) void k_fallback64(
     double best = INFINITY;
     int bj = 0x7fffffff;
     for (int j = threadIdx.x; j < k; j += blockDim.x) {
-      const double D = d64(xs, C + (int64_t)j * d, d);
+      const double D = d64h(xs, C + (int64_t)j * d, d, het, i, j);
       if (D < best) {  // j increases along this thread: strict keeps the lowest
         best = D;
         bj = j;
@@ -466,13 +602,33 @@ __global__ void k_copy_u64(const unsigned long long* a, unsigned long long* b, i
 }
 
 // ---------------------------------------------------------------- host side
+// SSE over 4096-row blocks and the per-cluster radius (sqrt of the largest
+// member distance when `take_sqrt`), shared by every metric.
+void sse_and_radius(const double* dist, const int32_t* assign, int64_t n, int k, double* sse, double* radius,
+                    int take_sqrt, double* sse_blk, hipStream_t s) {
+  const int64_t nblk = (n + SSE_BLOCK - 1) / SSE_BLOCK;
+  hipLaunchKernelGGL(k_sse_blocks, dim3(ceil_div(nblk, 64)), dim3(64), 0, s, dist, n, sse_blk);
+  hipLaunchKernelGGL(k_sse_total, dim3(1), dim3(1), 0, s, sse_blk, nblk, sse);
+  if (radius) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(ceil_div(k, 256)), dim3(256), 0, s, radius, k, 0.0);
+    hipLaunchKernelGGL(k_radius, dim3(ceil_div(n, 256)), dim3(256), 0, s, assign, dist, n, k, radius);
+    hipLaunchKernelGGL(k_sqrt_inplace, dim3(ceil_div(k, 256)), dim3(256), 0, s, radius, k, take_sqrt);
+  }
+}
+
+size_t sse_blk_words(int64_t n) { return (size_t)((n + SSE_BLOCK - 1) / SSE_BLOCK + 1); }
+
 static int pick_dp(int d) { return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : d <= 256 ? 256 : 0; }
+
+size_t modes_ws(int64_t n_members, int F, int k);
+int32_t modes_compute(const uint32_t* V, int64_t ldv, int F, int64_t n, const uint32_t* so, const uint32_t* sm,
+                      int k, int64_t NC, uint32_t* modes, void* ws, int32_t* st, hipStream_t s);
 
 struct AssignWs {
   float* cl32;
-  __bf16* cl16;
+  void* cllow;  // bf16 / fp8 copy for the first pass
   float* nc;
-  float* cmax;
+  float* cmax;   // [0] max |c|, [1] max |x_t|, [2] max |c_t|, [3] fp8 scale
   int32_t* rec;
   uint32_t* esc;
   uint32_t* fb;
@@ -480,6 +636,8 @@ struct AssignWs {
   unsigned long long* ctr;
   double* dist;
   double* sse_blk;
+  void* modes_ws;
+  size_t modes_bytes;
 };
 
 static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
@@ -487,9 +645,10 @@ static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
   const int DP = pick_dp(J.d);
   const int64_t k_pad = ((int64_t)J.k + SCAN_BC - 1) / SCAN_BC * SCAN_BC;
   out->cl32 = c.take<float>(k_pad * DP);
-  out->cl16 = c.take<__bf16>(J.precision == GEEK_PREC_BF16 ? k_pad * DP : 1);
+  const size_t low = J.precision == GEEK_PREC_BF16 ? 2 : J.precision == GEEK_PREC_FP8 ? 1 : 0;
+  out->cllow = c.take<char>(low ? k_pad * DP * low : 16);
   out->nc = c.take<float>(k_pad);
-  out->cmax = c.take<float>(1);
+  out->cmax = c.take<float>(4);
   out->rec = c.take<int32_t>(J.n * (TCAND + 1));
   out->esc = c.take<uint32_t>(J.n);
   out->fb = c.take<uint32_t>(J.n);
@@ -497,6 +656,8 @@ static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
   out->ctr = c.take<unsigned long long>(4);
   out->dist = c.take<double>(J.dist ? 1 : J.n);
   out->sse_blk = c.take<double>((J.n + SSE_BLOCK - 1) / SSE_BLOCK + 1);
+  out->modes_bytes = J.metric == GEEK_METRIC_HETERO ? modes_ws(J.n_members, J.n_cat, J.k) : 0;
+  out->modes_ws = c.take<char>(out->modes_bytes + 16);
   return c.used + 256;
 }
 
@@ -505,15 +666,17 @@ size_t assign_euclid_ws(const geek_assign_job& J) {
   return carve_assign(J, nullptr, &W);
 }
 
-template <class M>
+template <class M, bool HET>
 static void launch_scan(int DP, int grid, hipStream_t s, const geek_assign_job& J, int64_t n_rows,
-                        const uint32_t* rows, const uint32_t* rows_count,
-                        const typename M::ce* cl, const AssignWs& W, int k_pad, int32_t* st) {
+                        const uint32_t* rows, const uint32_t* rows_count, const void* cl, const AssignWs& W,
+                        int k_pad, const Het& het, int32_t* st) {
+  using CE = typename M::ce;
   switch (DP) {
-#define GEEK_SCAN_CASE(DPV)                                                                 \
-  case DPV:                                                                                 \
-    hipLaunchKernelGGL((k_scan<M, DPV>), dim3(grid), dim3(SCAN_THREADS), 0, s, J.X, J.ldx, \
-                       J.d, n_rows, rows, rows_count, cl, W.nc, k_pad, W.cmax, W.rec, st); \
+#define GEEK_SCAN_CASE(DPV)                                                                             \
+  case DPV:                                                                                             \
+    hipLaunchKernelGGL((k_scan<M, DPV, HET>), dim3(grid), dim3(SCAN_THREADS), 0, s, J.X, J.ldx, J.d,   \
+                       n_rows, rows, rows_count, static_cast<const CE*>(cl), W.nc, k_pad, W.cmax,       \
+                       W.cmax + 3, het, J.k, W.rec, st);                                                \
     break;
     GEEK_SCAN_CASE(32)
     GEEK_SCAN_CASE(64)
@@ -521,6 +684,16 @@ static void launch_scan(int DP, int grid, hipStream_t s, const geek_assign_job& 
     GEEK_SCAN_CASE(256)
 #undef GEEK_SCAN_CASE
   }
+}
+
+template <class M>
+static void scan_any(bool het_on, int DP, int grid, hipStream_t s, const geek_assign_job& J, int64_t n_rows,
+                     const uint32_t* rows, const uint32_t* rows_count, const void* cl, const AssignWs& W,
+                     int k_pad, const Het& het, int32_t* st) {
+  if (het_on)
+    launch_scan<M, true>(DP, grid, s, J, n_rows, rows, rows_count, cl, W, k_pad, het, st);
+  else
+    launch_scan<M, false>(DP, grid, s, J, n_rows, rows, rows_count, cl, W, k_pad, het, st);
 }
 
 int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st,
@@ -532,46 +705,62 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
   const int k_pad = (J.k + SCAN_BC - 1) / SCAN_BC * SCAN_BC;
   double* dist = J.dist ? J.dist : W.dist;
   const int nb_rows = ceil_div(J.n, 256);
+  const bool het_on = J.metric == GEEK_METRIC_HETERO;
+  Het het{nullptr, nullptr, 0, 0.f, 0.0};
+  if (het_on) het = Het{J.cat, J.modes, J.n_cat, (float)J.gamma, J.gamma};
 
+  prof_begin(GEEK_PROF_ASSIGN, s);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, W.counts, 4, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(W.ctr), 8, 0u);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(W.cmax), 1, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(W.cmax), 4, 0u);
   hipLaunchKernelGGL(k_centroids, dim3(ceil_div((int64_t)J.k * J.d, 256)), dim3(256), 0, s, J.X,
                      J.ldx, J.n, J.d, J.seed_offsets, J.seed_members, J.k, J.centroids, st);
-  hipLaunchKernelGGL(k_cprep<float>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k,
-                     J.d, k_pad, DP, W.cl32, W.nc, W.cmax);
-  if (J.precision == GEEK_PREC_BF16)
-    hipLaunchKernelGGL(k_cprep<__bf16>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids,
-                       J.k, J.d, k_pad, DP, W.cl16, W.nc, W.cmax);
+  if (het_on) {
+    if (int32_t rc = modes_compute(reinterpret_cast<const uint32_t*>(J.cat), J.n_cat, J.n_cat, J.n,
+                                   J.seed_offsets, J.seed_members, J.k, J.n_members, J.modes, W.modes_ws, st, s))
+      return rc;
+  }
+  hipLaunchKernelGGL(k_cprep<ModeF32>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k, J.d, k_pad,
+                     DP, W.cl32, W.nc, W.cmax, W.cmax + 3);
+  if (J.precision == GEEK_PREC_BF16) {
+    hipLaunchKernelGGL(k_cprep<ModeBF16>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k, J.d,
+                       k_pad, DP, static_cast<__bf16*>(W.cllow), nullptr, nullptr, W.cmax + 3);
+  } else if (J.precision == GEEK_PREC_FP8) {
+    hipLaunchKernelGGL(k_absmax_x, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.n, J.d, W.cmax + 1);
+    hipLaunchKernelGGL(k_absmax_c, dim3(256), dim3(256), 0, s, J.centroids, (int64_t)J.k * J.d, W.cmax + 2);
+    hipLaunchKernelGGL(k_fp8_scale, dim3(1), dim3(1), 0, s, W.cmax + 1, W.cmax + 2, W.cmax + 3);
+    hipLaunchKernelGGL(k_cprep<ModeFP8>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k, J.d,
+                       k_pad, DP, static_cast<uint8_t*>(W.cllow), nullptr, nullptr, W.cmax + 3);
+  }
   GEEK_LAUNCH_CHECK();
 
   const int grid_all = ceil_div(J.n, SCAN_BN);
   unsigned long long* ctr = W.ctr;
-  if (J.precision == GEEK_PREC_BF16) {
-    launch_scan<ModeBF16>(DP, grid_all, s, J, J.n, nullptr, nullptr, W.cl16, W, k_pad, st);
-    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids,
-                       J.k, J.n, nullptr, nullptr, W.rec, J.assign, dist, W.esc, W.counts + 0, ctr, 0);
-    // rows whose bf16 window overflowed: float32 rescan of those rows
-    launch_scan<ModeF32>(DP, 1024, s, J, 0, W.esc, W.counts + 0, W.cl32, W, k_pad, st);
-    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids,
-                       J.k, (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, dist, W.fb,
-                       W.counts + 1, ctr, 1);
+  if (J.precision == GEEK_PREC_BF16 || J.precision == GEEK_PREC_FP8) {
+    prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
+    if (J.precision == GEEK_PREC_BF16)
+      scan_any<ModeBF16>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cllow, W, k_pad, het, st);
+    else
+      scan_any<ModeFP8>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cllow, W, k_pad, het, st);
+    prof_end(GEEK_PROF_ASSIGN_SCAN, s);
+    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, J.n,
+                       nullptr, nullptr, W.rec, J.assign, dist, W.esc, W.counts + 0, ctr, 0);
+    // rows whose low-precision window overflowed: float32 rescan of those rows
+    scan_any<ModeF32>(het_on, DP, 1024, s, J, 0, W.esc, W.counts + 0, W.cl32, W, k_pad, het, st);
+    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, (int64_t)0,
+                       W.esc, W.counts + 0, W.rec, J.assign, dist, W.fb, W.counts + 1, ctr, 1);
   } else {
-    launch_scan<ModeF32>(DP, grid_all, s, J, J.n, nullptr, nullptr, W.cl32, W, k_pad, st);
-    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids,
-                       J.k, J.n, nullptr, nullptr, W.rec, J.assign, dist, W.fb, W.counts + 1, ctr, 0);
+    prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
+    scan_any<ModeF32>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cl32, W, k_pad, het, st);
+    prof_end(GEEK_PROF_ASSIGN_SCAN, s);
+    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, J.n,
+                       nullptr, nullptr, W.rec, J.assign, dist, W.fb, W.counts + 1, ctr, 0);
   }
-  hipLaunchKernelGGL(k_fallback64, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
-                     W.fb, W.counts + 1, J.assign, dist, ctr);
-  const int64_t nblk = (J.n + SSE_BLOCK - 1) / SSE_BLOCK;
-  hipLaunchKernelGGL(k_sse_blocks, dim3(ceil_div(nblk, 64)), dim3(64), 0, s, dist, J.n, W.sse_blk);
-  hipLaunchKernelGGL(k_sse_total, dim3(1), dim3(1), 0, s, W.sse_blk, nblk, J.sse);
-  if (J.radius) {
-    hipLaunchKernelGGL(k_fill_f64, dim3(ceil_div(J.k, 256)), dim3(256), 0, s, J.radius, J.k, 0.0);
-    hipLaunchKernelGGL(k_radius, dim3(nb_rows), dim3(256), 0, s, J.assign, dist, J.n, J.k, J.radius);
-    hipLaunchKernelGGL(k_sqrt_inplace, dim3(ceil_div(J.k, 256)), dim3(256), 0, s, J.radius, J.k, 1);
-  }
+  hipLaunchKernelGGL(k_fallback64, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, W.fb,
+                     W.counts + 1, J.assign, dist, ctr);
+  sse_and_radius(dist, J.assign, J.n, J.k, J.sse, J.radius, het_on ? 0 : 1, W.sse_blk, s);
   if (J.counters) hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, ctr, J.counters, 4);
+  prof_end(GEEK_PROF_ASSIGN, s);
   GEEK_LAUNCH_CHECK();
   return GEEK_OK;
 }

@@ -559,6 +559,7 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   const int nch = ceil_div(J.n, SC_CHUNK);
   BzArgs a{J.keys, J.n, J.T, J.key_words, J.table_stride, J.row_stride, nb};
   const size_t hbytes = (size_t)nbins * 4;
+  prof_begin(GEEK_PROF_BUCKETIZE, s);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, W.big_count, 4);
   hipLaunchKernelGGL(k_bin_count, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, W.counts);
   hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div((int64_t)J.T * nbins, 256)), dim3(256), 0, s, J.T,
@@ -567,8 +568,10 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   hipLaunchKernelGGL(k_bin_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, W.counts,
                      W.binstart, W.st_keys, W.st_ids);
   RunOut ro{W.st_ids, W.rec_head, W.run_len, W.run_pos};
+  prof_begin(GEEK_PROF_BZ_SORT, s);
   hipLaunchKernelGGL(k_bin_sort, dim3(nbins, J.T), dim3(BZ_THREADS), 0, s, J.n, nb, W.bintot,
                      W.binstart, W.st_keys, ro, W.big_list, W.big_count);
+  prof_end(GEEK_PROF_BZ_SORT, s);
   hipLaunchKernelGGL(k_big_sort, dim3(256), dim3(BIG_THREADS), 0, s, J.n, nb, J.key_words, W.bintot,
                      W.binstart, W.st_keys, W.st_ids, W.alt_keys, W.alt_ids, W.big_list, W.big_count);
   hipLaunchKernelGGL(k_big_runs, dim3(256), dim3(BIG_THREADS), 0, s, J.n, nb, W.bintot, W.binstart,
@@ -579,6 +582,7 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
                      W.hoff, J.offsets, J.nbuckets);
   hipLaunchKernelGGL(k_emit, dim3(ceil_div((int64_t)J.T * J.n, 256)), dim3(256), 0, s, J.n, J.T,
                      W.st_ids, W.rec_head, W.run_len, W.hoff, W.run_pos, J.members, J.bucket_of);
+  prof_end(GEEK_PROF_BUCKETIZE, s);
   GEEK_LAUNCH_CHECK();
   return GEEK_OK;
 }

@@ -74,6 +74,10 @@ struct Carver {
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Opt-in event timing of the main kernels (see geek_profile in geek.h).
+void prof_begin(int id, hipStream_t s);
+void prof_end(int id, hipStream_t s);
+
 // Records the HIP error string for geek_last_hip_error and maps to a status.
 int32_t hip_fail(hipError_t e);
 #define GEEK_LAUNCH_CHECK()                                   \

@@ -310,6 +310,7 @@ static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys
   const int tpc = H_BC / J.m;  // whole tables per 64-row chunk
   const int grid = ceil_div(J.n, H_BN);
   if (grid == 0) return GEEK_OK;
+  prof_begin(GEEK_PROF_E2LSH, s);
   switch (pick_dp_h(J.d)) {
 #define GEEK_H_CASE(DPV)                                                                        \
   case DPV:                                                                                     \
@@ -324,6 +325,7 @@ static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys
     default:
       return GEEK_ERR_UNSUPPORTED;
   }
+  prof_end(GEEK_PROF_E2LSH, s);
   return GEEK_OK;
 }
 
@@ -348,11 +350,13 @@ int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st,
     rc = launch_e2lsh(J, anorm, J.keys, J.codes, J.n_fixup, st, s);
   } else if (J.kind == GEEK_HASH_SETS) {
     if (J.n == 0) return GEEK_OK;
+    prof_begin(GEEK_PROF_MINHASH, s);
     rc = dispatch_fpl(J.F, [&](auto fpl) {
       hipLaunchKernelGGL((k_minhash_sets<decltype(fpl)::value>), dim3(ceil_div(J.n, 4)), dim3(256),
                          0, s, J.offsets, J.tokens, J.n, J.mh_keys, J.F, J.sig, st);
       return GEEK_OK;
     });
+    prof_end(GEEK_PROF_MINHASH, s);
   } else {
     // numeric codes without keys, then the token sets
     uint32_t* no_keys = nullptr;

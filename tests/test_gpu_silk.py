@@ -1,0 +1,103 @@
+"""GPU parity of geek_silk_seeds against the oracle's SILK (Algorithm 4):
+the seed sets, their order and the work counters, bit for bit."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import dense_mixture, e2lsh_params, key_words, sparse_sets
+from workloads.gen import STREAM_SILK
+
+from .gpu_util import announce, cuda, gpu_api, host_u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_buckets(codes, m, L):
+    offs, mem = [0], []
+    for mm, oo, _ in oracle.bucketize_tables(codes, m, L):
+        mem.append(mm)
+        offs.extend((oo[1:].astype(np.int64) + offs[-1]).tolist())
+    return np.asarray(offs, np.int64), np.concatenate(mem)
+
+
+def _run_dense(api, n, d, clusters, m, L, w, K, LS, delta, seed, check=True):
+    X, _, _ = dense_mixture(n, d, clusters, -10, 10, 1.0, "equal", seed)
+    A, b = e2lsh_params(m * L, d, w, seed)
+    keys = key_words((LS + 1) * K, seed, STREAM_SILK)
+    codes = oracle.e2lsh_codes(X, A, b, w)
+    offs, mem = _oracle_buckets(codes, m, L)
+    ref_o, ref_m, info = oracle.silk_seeds(offs, mem, K, LS, delta, keys)
+    announce(f"silk n={n} d={d} m={m} L={L} K={K} LS={LS} delta={delta} ref k={len(ref_o) - 1}")
+    kg, _ = api.hash_dense(cuda(X), cuda(A), cuda(b), m, L, w)
+    bm, bo, bn, _ = api.bucketize(kg, n, L, 4, n * 4, 4, want_bucket_of=False)
+    status = api.new_status("cuda")
+    so, sm, ctr = api.silk_seeds(bm, bo, bn, n, L, K, LS, delta, cuda(keys), status=status,
+                                 check=False)
+    return (ref_o, ref_m, info), (host_u32(so), host_u32(sm), ctr.cpu().numpy()), int(status.item())
+
+
+@pytest.mark.parametrize("n,d,clusters,m,L,K,LS,delta,seed", [
+    (4000, 32, 20, 8, 16, 3, 20, 10, 0),
+    (6000, 16, 40, 6, 10, 2, 8, 5, 1),
+    (3000, 32, 10, 8, 8, 4, 12, 3, 2),
+])
+def test_silk_matches_oracle(n, d, clusters, m, L, K, LS, delta, seed):
+    api = gpu_api()
+    w = 4.0 * math.sqrt(d)
+    (ro, rm, info), (go, gm, ctr), st = _run_dense(api, n, d, clusters, m, L, w, K, LS, delta, seed)
+    assert st == 0
+    assert len(ro) > 2
+    assert np.array_equal(go, ro)
+    assert np.array_equal(gm, rm)
+    assert ctr[0] == info["hash_evals"]
+    assert ctr[1] == info["pairs_voted"]
+    assert ctr[2] == info["multiset"]
+
+
+def test_silk_no_seeds_literal_width():
+    # the literal width puts almost every point alone in its bucket: no seed
+    api = gpu_api()
+    (ro, rm, info), (go, gm, ctr), st = _run_dense(api, 3000, 32, 10, 8, 16, 4.0, 3, 6, 10, 3)
+    assert len(ro) == 1
+    assert st == 4 and len(go) == 1
+
+
+def test_silk_capacity_reported():
+    api = gpu_api()
+    from paper_2106_10515_amd import GeekError
+
+    n, d, m, L, w = 3000, 32, 8, 16, 4.0 * math.sqrt(32)
+    X, _, _ = dense_mixture(n, d, 10, -10, 10, 1.0, "equal", 4)
+    A, b = e2lsh_params(m * L, d, w, 4)
+    keys = key_words(21 * 3, 4, STREAM_SILK)
+    kg, _ = api.hash_dense(cuda(X), cuda(A), cuda(b), m, L, w)
+    bm, bo, bn, _ = api.bucketize(kg, n, L, 4, n * 4, 4, want_bucket_of=False)
+    with pytest.raises(GeekError) as e:
+        api.silk_seeds(bm, bo, bn, n, L, 3, 20, 10, cuda(keys), cap_k=2, cap_members=4000)
+    assert e.value.code == 3
+
+
+def test_silk_over_minhash_bands():
+    # sets -> MinHash -> band buckets -> SILK, compared with the oracle chain
+    api = gpu_api()
+    off, tok, _ = sparse_sets(4000, vocab=20_000, clusters=30, seed=5)
+    K, Lb = 4, 16
+    mk = key_words(K * Lb, 5)
+    sig = oracle.minhash_sets(off, tok, mk)
+    offs, mem = [0], []
+    for mm, oo, _ in oracle.bucketize_tables(sig, K, Lb):
+        mem.append(mm)
+        offs.extend((oo[1:].astype(np.int64) + offs[-1]).tolist())
+    sk = key_words(21 * 3, 5, STREAM_SILK)
+    ro, rm, info = oracle.silk_seeds(np.asarray(offs), np.concatenate(mem), 3, 20, 10, sk)
+    announce(f"silk bands n=4000 ref k={len(ro) - 1}")
+    sg = api.hash_sets(cuda(off), cuda(tok), cuda(mk))
+    n = len(off) - 1
+    bm, bo, bn, _ = api.bucketize(sg, n, Lb, K, K, K * Lb, want_bucket_of=False)
+    so, sm, ctr = api.silk_seeds(bm, bo, bn, n, Lb, 3, 20, 10, cuda(sk), check=len(ro) > 1)
+    assert np.array_equal(host_u32(so), ro)
+    assert np.array_equal(host_u32(sm), rm)
