@@ -6,10 +6,13 @@
 //   k_cprep       centroid copies in the matrix-core input type (fp32 / bf16),
 //                 |c|^2 and max |c| for the error bound.
 //   k_scan<M,DP>  matrix-core tile |x|^2 - 2 x.c + |c|^2 over all centroids for
-//                 a block of rows; per row it keeps every centroid whose
-//                 approximate distance lies within 2*eps_i of the running
-//                 minimum (eps_i a rigorous bound of the approximation error),
-//                 up to TCAND candidates.
+//                 a block of rows.  Float32: per row it keeps every centroid
+//                 whose approximate distance lies within 2*eps_i of the
+//                 running minimum (eps_i a rigorous bound of the approximation
+//                 error), up to TCAND candidates.  BF16/FP8 first passes keep
+//                 only the best and second-best values (branch-free); a row
+//                 is settled when the runner-up lies beyond 2*eps_i, else it
+//                 is rescanned in float32.
 //   k_finalize    float64 distance (the reference formula, same operation
 //                 order) for each candidate; lowest index wins exact ties.
 //                 Rows whose candidate window overflowed are escalated.
@@ -29,7 +32,6 @@ namespace geek {
 constexpr int TCAND = 8;
 constexpr int SSE_BLOCK = 4096;
 constexpr int SCAN_THREADS = 256;
-constexpr int SCAN_BN = 128;  // rows per block (4 waves x 32 rows)
 constexpr int SCAN_BC = 64;   // centroids per LDS stage
 
 // ---------------------------------------------------------------- centroids
@@ -82,7 +84,15 @@ __global__ void k_absmax_c(const double* __restrict__ C, int64_t kd, float* __re
 __global__ void k_fp8_scale(const float* __restrict__ mx, const float* __restrict__ mc, float* __restrict__ scale) {
   if (blockIdx.x || threadIdx.x) return;
   const float m = fmaxf(*mx, *mc);
-  *scale = m > 0.f ? exp2f(floorf(log2f(224.0f / m))) : 1.0f;
+  // 2^e with max |value| * 2^e in [112, 224]; e is clamped at 60 for tiny
+  // data (the absolute error term covers it); data too large for a safe
+  // 2^e gets scale 0, which makes every row's bound infinite (escalation)
+  if (!(m > 0.f)) {
+    *scale = 1.0f;
+    return;
+  }
+  const float e = floorf(log2f(224.0f / m));
+  *scale = e < -60.f ? 0.0f : exp2f(fminf(e, 60.f));
 }
 
 // Matrix-core input copies of the centroids, zero-padded to [k_pad][DP];
@@ -195,6 +205,7 @@ struct ModeFP8 {
 struct Het {
   const int32_t* cat;     // [n][n_cat]
   const uint32_t* mode;   // [k][n_cat] per-attribute modes of the seeds
+  const uint32_t* mode16; // [k_pad][MAX_CAT] zero-padded copy streamed by the scan
   int n_cat;
   float gamma_f;          // gamma, exactly representable in float32
   double gamma;
@@ -220,7 +231,11 @@ GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
   const double dot = ex * cm + xn * ec + ex * ec + g_acc * (xn + ex) * (cm + ec);
   const double vmax = cm * cm + 2.0 * (xn + ex) * (cm + ec) + het_max;
   const double s2 = (xn + cm) * (xn + cm) + het_max;
+  // accumulations that could overflow float32 give no bound: rows escalate
+  if (!(4.0 * vmax < 0x1p120)) return INFINITY;
   double eps = 2.0 * dot                       // 2 x.c
+               + g_acc * cm * cm                // |c|^2 / 2 as the accumulator's start
+               + 0x1p-124 * inv_scale * inv_scale  // its float32 subnormal rounding
                + (u32 + g64) * cm * cm          // |c|^2 stored as float32
                + 2.0 * u32 * vmax               // epilogue roundings
                + g64 * s2 + 0x1p-52 * het_max   // float64 reference rounding
@@ -231,13 +246,16 @@ GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
 }
 
 // ---------------------------------------------------------------- scan
-// Block = 4 waves; wave w owns rows [w*32, w*32+32) of the block's tile.
+// Block = 4 waves; wave w owns NCB column blocks of 32 rows (points) each.
 // MFMA 32x32: A = 32 centroids (rows), B = 32 points (columns).  Lane l
-// supplies point p = l%32 and K half h = l/32; the K index of step s,
-// element e is h*DP/2 + s*KPER + e (any bijection works for a dot product
-// as long as A and B agree).  Accumulator register r of lane l holds
-// centroid row (r/4)*8 + h*4 + r%4 of point p.
-template <class M, int DP, bool HET>
+// supplies point p = l%32 of every column block and K half h = l/32; the K
+// index of step s, element e is h*DP/2 + s*KPER + e (any bijection works for
+// a dot product as long as A and B agree).  Accumulator register r of lane l
+// holds centroid row (r/4)*8 + h*4 + r%4 of point p.  Each A fragment read
+// from LDS feeds NCB MFMAs.  With NBUF = 2 the next stage of centroids is
+// in flight while the current one is consumed (LDS DMA where rows are at
+// least 64 bytes, else through registers).
+template <class M, int DP, bool HET, int NCB, int NBUF, bool T2>
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n_rows,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
@@ -245,199 +263,399 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
     const float* __restrict__ cmax_p, const float* __restrict__ scale_p, Het het, int k,
     int32_t* __restrict__ rec, int32_t* st) {
   using CE = typename M::ce;
-  constexpr int S = DP / 2 / M::KPER;       // MFMA steps over K
-  constexpr int STR = DP + 16 / (int)sizeof(CE);  // padded LDS row (elements)
-  __shared__ __attribute__((aligned(16))) CE lds_c[SCAN_BC * STR];
-  __shared__ float lds_nc[SCAN_BC];
-  __shared__ float lds_lv[SCAN_THREADS * TCAND];
-  __shared__ int lds_lj[SCAN_THREADS * TCAND];
-  __shared__ uint32_t lds_mode[HET ? SCAN_BC * MAX_CAT : 1];
+  constexpr int S = DP / 2 / M::KPER;             // MFMA steps over K
+  constexpr int CH = DP * (int)sizeof(CE) / 16;   // 16-byte chunks per centroid row
+  // DMA: stages stream global -> LDS directly (global_load_lds_dwordx4, one
+  // 16-byte chunk per lane, lane-contiguous in LDS), rows unpadded with the
+  // chunk index XOR-swizzled by the row; otherwise registers stage the copy
+  // into rows padded by 16 bytes.
+  constexpr bool DMA = NBUF == 2 && CH >= 4;
+  constexpr int STR = DMA ? DP : DP + 16 / (int)sizeof(CE);  // LDS row (elements)
+  constexpr int BN = 128 * NCB;                   // rows per tile
+  constexpr int CPT = DMA ? 1 : (SCAN_BC * CH + SCAN_THREADS - 1) / SCAN_THREADS;
+  __shared__ __attribute__((aligned(16))) CE lds_c[NBUF][SCAN_BC * STR];
+  __shared__ float lds_nc[NBUF][SCAN_BC];
+  __shared__ uint32_t lds_mode[HET ? NBUF : 1][HET ? SCAN_BC * MAX_CAT : 1];
+  __shared__ float lds_lv[T2 ? 1 : SCAN_THREADS * NCB * TCAND];
+  __shared__ int lds_lj[T2 ? 1 : SCAN_THREADS * NCB * TCAND];
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar) for LDS DMA bases
   const int p = lane & 31, h = lane >> 5;
-  float* lv = lds_lv + tid * TCAND;
-  int* lj = lds_lj + tid * TCAND;
 
   const int64_t count = rows ? (int64_t)*rows_count : n_rows;
   const double cm = (double)*cmax_p;
   const float sc = M::SCALED ? *scale_p : 1.0f;
   const float m2s = -2.0f / (sc * sc);  // power of two: exact rescaling
+  // T2 starts every accumulator at -s^2 |c_j|^2 / 2 (exact power-of-two
+  // scalings), so acc = s^2 (x.c - |c_j|^2 / 2) and v_j = m2s * acc
+  const float nc_mul = T2 ? -0.5f * sc * sc : 1.0f;
   const bool vec4 = ((d & 3) == 0) && ((ldx & 3) == 0);
   const double het_max = HET ? het.gamma * het.n_cat : 0.0;
 
-  for (int64_t tile = blockIdx.x; tile * SCAN_BN < count; tile += gridDim.x) {
-    const int64_t pos = tile * SCAN_BN + w * 32 + p;
-    const bool valid = pos < count;
-    const int64_t i = valid ? (rows ? (int64_t)rows[pos] : pos) : 0;
-    const float* xr = X + i * ldx;
+  // stage loading: registers <- global, LDS <- registers
+  constexpr int MPT = HET ? (SCAN_BC * MAX_CAT + SCAN_THREADS - 1) / SCAN_THREADS : 1;
+  uint4 stg[CPT];
+  float stg_nc = 0.f;
+  uint32_t stg_mode[MPT];
+#define GEEK_LOAD_REGS(C0)                                                                                 \
+  do {                                                                                                     \
+    _Pragma("unroll") for (int u = 0; u < CPT; ++u) {                                                     \
+      const int q = min(tid + u * SCAN_THREADS, SCAN_BC * CH - 1); /* clamped: always in bounds */        \
+      const int r = q / CH, c = q % CH;                                                                    \
+      stg[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(cl + (int64_t)((C0) + r) * DP) + \
+                                               c * 16);                                                    \
+    }                                                                                                      \
+    stg_nc = nc[(C0) + (tid & (SCAN_BC - 1))] * nc_mul;                                                    \
+    if constexpr (HET) {                                                                                   \
+      _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                                   \
+        const int q = min(tid + u * SCAN_THREADS, SCAN_BC * MAX_CAT - 1);                                  \
+        const int r = q / MAX_CAT, a = q % MAX_CAT;                                                        \
+        const bool ok = a < het.n_cat && (C0) + r < k;                                                     \
+        const uint32_t mv = het.mode[ok ? (int64_t)((C0) + r) * het.n_cat + a : 0];                        \
+        stg_mode[u] = ok ? mv : 0u;                                                                        \
+      }                                                                                                    \
+    }                                                                                                      \
+  } while (0)
+#define GEEK_STORE_LDS(B)                                                                                  \
+  do {                                                                                                     \
+    _Pragma("unroll") for (int u = 0; u < CPT; ++u) {                                                     \
+      const int q = tid + u * SCAN_THREADS;                                                                \
+      if (q < SCAN_BC * CH) {                                                                              \
+        const int r = q / CH, c = q % CH;                                                                  \
+        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds_c[B] + r * STR) + c * 16) = stg[u];          \
+      }                                                                                                    \
+    }                                                                                                      \
+    if (tid < SCAN_BC) lds_nc[B][tid] = stg_nc;                                                            \
+    if constexpr (HET) {                                                                                   \
+      _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                                   \
+        const int q = tid + u * SCAN_THREADS;                                                              \
+        if (q < SCAN_BC * MAX_CAT) lds_mode[B][q] = stg_mode[u];                                           \
+      }                                                                                                    \
+    }                                                                                                      \
+  } while (0)
+#define GEEK_DMA_STAGE(C0, B)                                                                              \
+  do {                                                                                                     \
+    _Pragma("unroll") for (int u = 0; u < CH / 4; ++u) {                                                  \
+      const int slot0 = w * (SCAN_BC * CH / 4) + u * 64; /* wave-uniform LDS chunk */                     \
+      const int slot = slot0 + lane;                                                                       \
+      const int r = slot / CH, c = (slot % CH) ^ (r & (CH - 1));                                           \
+      __builtin_amdgcn_global_load_lds(                                                                    \
+          reinterpret_cast<const char*>(cl + (int64_t)((C0) + r) * DP) + c * 16,                           \
+          reinterpret_cast<char*>(lds_c[B]) + slot0 * 16, 16, 0, 0);                                      \
+    }                                                                                                      \
+    stg_nc = nc[(C0) + (tid & (SCAN_BC - 1))] * nc_mul; /* lds_nc[B] stored from the register */        \
+    if constexpr (HET)                                                                                     \
+      __builtin_amdgcn_global_load_lds(                                                                    \
+          reinterpret_cast<const char*>(het.mode16 + (int64_t)(C0) * MAX_CAT) + (w * 64 + lane) * 16,     \
+          reinterpret_cast<char*>(lds_mode[B]) + w * 64 * 16, 16, 0, 0);                                  \
+  } while (0)
 
-    // ---- this lane's half row of x as MFMA B fragments; exact |x|^2
-    float xv[DP / 2];
+  for (int64_t tile = blockIdx.x; tile * BN < count; tile += gridDim.x) {
+    typename M::frag xb[NCB][S];
+    float twoeps[NCB];
+    int32_t crow[NCB][HET ? MAX_CAT : 1];
+    bool valid[NCB];
+    int64_t posv[NCB];
 #pragma unroll
-    for (int q = 0; q < DP / 2; q += 4) {
-      const int t0 = h * (DP / 2) + q;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (valid) {
-        if (vec4 && t0 + 3 < d) {
-          val = *reinterpret_cast<const float4*>(xr + t0);
-        } else {
-          val.x = t0 < d ? xr[t0] : 0.f;
-          val.y = t0 + 1 < d ? xr[t0 + 1] : 0.f;
-          val.z = t0 + 2 < d ? xr[t0 + 2] : 0.f;
-          val.w = t0 + 3 < d ? xr[t0 + 3] : 0.f;
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int64_t pos = tile * BN + (int64_t)w * (32 * NCB) + cb * 32 + p;
+      valid[cb] = pos < count;
+      posv[cb] = pos;
+      const int64_t i = valid[cb] ? (rows ? (int64_t)rows[pos] : pos) : 0;
+      const float* xr = X + i * ldx;
+      // this lane's half row of x as MFMA B fragments; exact |x|^2
+      float xv[DP / 2];
+#pragma unroll
+      for (int q = 0; q < DP / 2; q += 4) {
+        const int t0 = h * (DP / 2) + q;
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (valid[cb]) {
+          if (vec4 && t0 + 3 < d) {
+            val = *reinterpret_cast<const float4*>(xr + t0);
+          } else {
+            val.x = t0 < d ? xr[t0] : 0.f;
+            val.y = t0 + 1 < d ? xr[t0 + 1] : 0.f;
+            val.z = t0 + 2 < d ? xr[t0 + 2] : 0.f;
+            val.w = t0 + 3 < d ? xr[t0 + 3] : 0.f;
+          }
         }
+        xv[q] = val.x;
+        xv[q + 1] = val.y;
+        xv[q + 2] = val.z;
+        xv[q + 3] = val.w;
       }
-      xv[q] = val.x;
-      xv[q + 1] = val.y;
-      xv[q + 2] = val.z;
-      xv[q + 3] = val.w;
-    }
-    double nrm = 0.0;
-    bool finite = true;
+      double nrm = 0.0;
+      bool finite = true;
 #pragma unroll
-    for (int q = 0; q < DP / 2; ++q) {
-      finite = finite && isfinite(xv[q]);
-      nrm += (double)xv[q] * (double)xv[q];
-    }
-    typename M::frag xb[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) xb[s] = M::from_f32(xv + s * M::KPER, sc);
-    if (!finite) set_status(st, GEEK_ERR_NONFINITE);
-    nrm += __shfl_xor(nrm, 32);
-    const float twoeps = two_eps<M, DP>(sqrt(nrm) * (1.0 + 1e-12), cm, 1.0 / sc, het_max);
-    int32_t crow[HET ? MAX_CAT : 1];
-    if constexpr (HET) {
-#pragma unroll
-      for (int a = 0; a < MAX_CAT; ++a) crow[a] = (valid && a < het.n_cat) ? het.cat[i * het.n_cat + a] : 0;
-    }
-
-    // thr starts at the largest finite float: padded centroids (|c|^2 = +inf)
-    // and non-finite values never enter the window
-    float b0 = INFINITY, thr = 3.402823466e38f;
-    int cnt = 0;
-    bool ovf = false;
-
-    for (int c0 = 0; c0 < k_pad; c0 += SCAN_BC) {
-      __syncthreads();
-      // cooperative load of SCAN_BC centroid rows (16-byte chunks)
-      constexpr int CH = DP * (int)sizeof(CE) / 16;  // chunks per row
-      for (int q = tid; q < SCAN_BC * CH; q += SCAN_THREADS) {
-        const int r = q / CH, c = q % CH;
-        const uint4 val = *reinterpret_cast<const uint4*>(
-            reinterpret_cast<const char*>(cl + (int64_t)(c0 + r) * DP) + c * 16);
-        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds_c + r * STR) + c * 16) = val;
+      for (int q = 0; q < DP / 2; ++q) {
+        finite = finite && isfinite(xv[q]);
+        nrm += (double)xv[q] * (double)xv[q];
       }
-      if (tid < SCAN_BC) lds_nc[tid] = nc[c0 + tid];
+#pragma unroll
+      for (int s = 0; s < S; ++s) xb[cb][s] = M::from_f32(xv + s * M::KPER, sc);
+      if (!finite) set_status(st, GEEK_ERR_NONFINITE);
+      nrm += __shfl_xor(nrm, 32);
+      twoeps[cb] = two_eps<M, DP>(sqrt(nrm) * (1.0 + 1e-12), cm, 1.0 / sc, het_max);
       if constexpr (HET) {
-        for (int q = tid; q < SCAN_BC * MAX_CAT; q += SCAN_THREADS) {
-          const int r = q / MAX_CAT, a = q % MAX_CAT;
-          lds_mode[q] = (a < het.n_cat && c0 + r < k) ? het.mode[(int64_t)(c0 + r) * het.n_cat + a] : 0u;
-        }
-      }
-      __syncthreads();
-
 #pragma unroll
-      for (int rb = 0; rb < SCAN_BC / 32; rb += 2) {
-        f32x16 acc0 = {}, acc1 = {};
-        const CE* a0p = lds_c + (rb * 32 + p) * STR + h * (DP / 2);
-        const CE* a1p = a0p + 32 * STR;
+        for (int a = 0; a < MAX_CAT; ++a)
+          crow[cb][a] = (valid[cb] && a < het.n_cat) ? het.cat[i * het.n_cat + a] : 0;
+      }
+    }
+
+    // Window: thr starts at the largest finite float, so padded centroids
+    // (|c|^2 = +inf) and non-finite values never enter it; lost is the
+    // smallest value dropped from a full window.
+    // T2: best (a1, index j1) and second best (a2) of the values seen, in
+    // accumulator units where larger is nearer; j1 is kept relative to the
+    // current stage (the stage index is added back at the end).
+    float b0[NCB], thr[NCB], lost[NCB];
+    int cnt[NCB];
+    float a1[NCB], a2[NCB];
+    int j1[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      b0[cb] = INFINITY;
+      thr[cb] = 3.402823466e38f;
+      lost[cb] = INFINITY;
+      cnt[cb] = 0;
+      a1[cb] = -3.402823466e38f;
+      a2[cb] = -3.402823466e38f;
+      j1[cb] = 0;
+    }
+
+    __syncthreads();  // previous tile done with the LDS buffers
+    if constexpr (DMA) {
+      GEEK_DMA_STAGE(0, 0);
+      if (tid < SCAN_BC) lds_nc[0][tid] = stg_nc;
+      __builtin_amdgcn_s_waitcnt(0);
+    } else {
+      GEEK_LOAD_REGS(0);
+      GEEK_STORE_LDS(0);
+    }
+    __syncthreads();
+    int it = 0;
+    for (int c0 = 0; c0 < k_pad; c0 += SCAN_BC, ++it) {
+      const int cur = NBUF == 2 ? (it & 1) : 0;
+      const bool more = c0 + SCAN_BC < k_pad;
+      if constexpr (DMA) {
+        if (more) GEEK_DMA_STAGE(c0 + SCAN_BC, cur ^ 1);
+      } else {
+        if (NBUF == 2 && more) GEEK_LOAD_REGS(c0 + SCAN_BC);
+      }
+
+#pragma unroll 1
+      for (int rb = 0; rb < SCAN_BC / 32; ++rb) {
+        const int jb = rb * 32;
+        f32x16 acc[NCB];
+        f32x16 init = f32x16{};
+        if constexpr (T2) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) init[r] = lds_nc[cur][jb + (r >> 2) * 8 + h * 4 + (r & 3)];
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = init;
+        const CE* ap = lds_c[cur] + (rb * 32 + p) * STR + h * (DP / 2);
+        const int R = rb * 32 + p;
+        const char* rowp = reinterpret_cast<const char*>(lds_c[cur]) + R * CH * 16;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          acc0 = M::mma(M::load_lds(a0p + s * M::KPER), xb[s], acc0);
-          acc1 = M::mma(M::load_lds(a1p + s * M::KPER), xb[s], acc1);
-        }
+          const typename M::frag a = [&] {
+            if constexpr (DMA) {
+              const int off = (h * (DP / 2) + s * M::KPER) * (int)sizeof(CE);
+              return M::load_lds(reinterpret_cast<const CE*>(rowp + (((off >> 4) ^ (R & (CH - 1))) << 4) + (off & 15)));
+            } else {
+              return M::load_lds(ap + s * M::KPER);
+            }
+          }();
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const f32x16& acc = half ? acc1 : acc0;
-          const int jb = (rb + half) * 32;
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = M::mma(a, xb[cb][s], acc[cb]);
+        }
+        if constexpr (T2) {
+          // branch-free: per value one compare, one select, med3 and max
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) {
+            float t[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              t[r] = acc[cb][r];
+              if constexpr (HET) {
+                // -(v_num + gamma * mismatches), one rounding
+                const uint32_t* md = lds_mode[cur] + (jb + (r >> 2) * 8 + h * 4 + (r & 3)) * MAX_CAT;
+                int mm = 0;
+#pragma unroll
+                for (int q = 0; q < MAX_CAT; ++q) mm += (q < het.n_cat && (uint32_t)crow[cb][q] != md[q]) ? 1 : 0;
+                t[r] = __builtin_fmaf(-m2s, t[r], -het.gamma_f * (float)mm);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const bool better = t[r] > a1[cb];
+              j1[cb] = better ? (r >> 2) * 8 + (r & 3) : j1[cb];
+              a2[cb] = __builtin_amdgcn_fmed3f(a1[cb], a2[cb], t[r]);
+              a1[cb] = fmaxf(a1[cb], t[r]);
+            }
+            j1[cb] -= 32;  // indices stay relative to the current 32-centroid block
+          }
+        } else {
+        float ncv[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ncv[r] = lds_nc[cur][jb + (r >> 2) * 8 + h * 4 + (r & 3)];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
           float v[16];
           float vmin = INFINITY;
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const int row = (r >> 2) * 8 + h * 4 + (r & 3);
-            v[r] = __builtin_fmaf(m2s, acc[r], lds_nc[jb + row]);
+            v[r] = __builtin_fmaf(m2s, acc[cb][r], ncv[r]);
             if constexpr (HET) {
-              const uint32_t* md = lds_mode + (jb + row) * MAX_CAT;
+              const uint32_t* md = lds_mode[cur] + (jb + (r >> 2) * 8 + h * 4 + (r & 3)) * MAX_CAT;
               int mm = 0;
 #pragma unroll
-              for (int a = 0; a < MAX_CAT; ++a) mm += (a < het.n_cat && (uint32_t)crow[a] != md[a]) ? 1 : 0;
+              for (int a = 0; a < MAX_CAT; ++a) mm += (a < het.n_cat && (uint32_t)crow[cb][a] != md[a]) ? 1 : 0;
               v[r] = v[r] + het.gamma_f * (float)mm;
             }
             vmin = fminf(vmin, v[r]);
           }
-          if (vmin <= thr) {
+          if (vmin <= thr[cb]) {
+            float* lv = lds_lv + (tid * NCB + cb) * TCAND;
+            int* lj = lds_lj + (tid * NCB + cb) * TCAND;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              if (v[r] <= thr) {
+              if (v[r] <= thr[cb]) {
                 const int j = c0 + jb + (r >> 2) * 8 + h * 4 + (r & 3);
-                if (v[r] < b0) {
-                  b0 = v[r];
-                  thr = b0 + twoeps;
+                if (v[r] < b0[cb]) {
+                  b0[cb] = v[r];
+                  thr[cb] = b0[cb] + twoeps[cb];
                 }
-                if (!ovf) {
-                  if (cnt == TCAND) {
-                    int kept = 0;
+                if (cnt[cb] == TCAND) {
+                  int kept = 0;
 #pragma unroll 1
-                    for (int q = 0; q < TCAND; ++q) {
-                      const float ev = lv[q];
-                      const int ej = lj[q];
-                      if (ev <= thr) {
-                        lv[kept] = ev;
-                        lj[kept] = ej;
-                        ++kept;
-                      }
+                  for (int q = 0; q < TCAND; ++q) {
+                    const float ev = lv[q];
+                    const int ej = lj[q];
+                    if (ev <= thr[cb]) {
+                      lv[kept] = ev;
+                      lj[kept] = ej;
+                      ++kept;
                     }
-                    cnt = kept;
-                    ovf = (cnt == TCAND);
                   }
-                  if (!ovf) {
-                    lv[cnt] = v[r];
-                    lj[cnt] = j;
-                    ++cnt;
-                  }
+                  cnt[cb] = kept;
+                }
+                if (cnt[cb] < TCAND) {
+                  lv[cnt[cb]] = v[r];
+                  lj[cnt[cb]] = j;
+                  ++cnt[cb];
+                } else {
+                  lost[cb] = fminf(lost[cb], v[r]);
                 }
               }
             }
           }
         }
+        }
       }
+      if (more) {
+        if constexpr (DMA) {
+          if (tid < SCAN_BC) lds_nc[cur ^ 1][tid] = stg_nc;
+          __builtin_amdgcn_s_waitcnt(0);  // this wave's chunks of the next stage landed
+        } else if (NBUF == 2) {
+          GEEK_STORE_LDS(cur ^ 1);
+        } else {
+          __syncthreads();
+          GEEK_LOAD_REGS(c0 + SCAN_BC);
+          GEEK_STORE_LDS(0);
+        }
+      }
+      __syncthreads();
     }
 
     // ---- merge the two lanes that share a point, write the candidate record
-    const float bo = __shfl_xor(b0, 32);
-    const float bfin = fminf(b0, bo);
-    const float tfin = bfin < INFINITY ? bfin + twoeps : 3.402823466e38f;
-    int kept = 0;
-    for (int q = 0; q < cnt; ++q) {
-      const float ev = lv[q];
-      const int ej = lj[q];
-      if (ev <= tfin) {
-        lv[kept] = ev;
-        lj[kept] = ej;
-        ++kept;
+    if constexpr (T2) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float a1o = __shfl_xor(a1[cb], 32), a2o = __shfl_xor(a2[cb], 32);
+        const int jg = j1[cb] + k_pad + h * 4;
+        const int jo = __shfl_xor(jg, 32);
+        const float best = fmaxf(a1[cb], a1o);
+        const float second = fmaxf(fminf(a1[cb], a1o), fmaxf(a2[cb], a2o));
+        const int jbest = a1[cb] >= a1o ? jg : jo;
+        // back to distance units (exact): v = m2s * acc, or -t for HET
+        const float vs = HET ? -1.0f : m2s;
+        const float v1 = vs * best, v2 = vs * second;
+        // one candidate iff the runner-up lies beyond the 2 eps window
+        const bool unique = best > -3.402823466e38f && isfinite(v1) && v2 > v1 + twoeps[cb];
+        if (valid[cb] && h == 0) {
+          int32_t* rr = rec + posv[cb] * (TCAND + 1);
+          rr[0] = unique ? 1 : -1;
+          if (unique) rr[1] = jbest;
+        }
+      }
+    } else {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      float* lv = lds_lv + (tid * NCB + cb) * TCAND;
+      int* lj = lds_lj + (tid * NCB + cb) * TCAND;
+      const float bo = __shfl_xor(b0[cb], 32);
+      const float bfin = fminf(b0[cb], bo);
+      const float tfin = bfin < INFINITY ? bfin + twoeps[cb] : 3.402823466e38f;
+      int kept = 0;
+      for (int q = 0; q < cnt[cb]; ++q) {
+        const float ev = lv[q];
+        const int ej = lj[q];
+        if (ev <= tfin) {
+          lv[kept] = ev;
+          lj[kept] = ej;
+          ++kept;
+        }
+      }
+      const int kept_o = __shfl_xor(kept, 32);
+      const float lost_all = fminf(lost[cb], __shfl_xor(lost[cb], 32));
+      // complete unless a dropped value could still be a candidate
+      const bool over = lost_all <= tfin || (kept + kept_o > TCAND);
+      if (valid[cb]) {
+        int32_t* rr = rec + posv[cb] * (TCAND + 1);
+        if (over) {
+          if (h == 0) rr[0] = -1;
+        } else {
+          if (h == 0) rr[0] = kept + kept_o;
+          const int off = h ? kept_o : 0;
+          for (int q = 0; q < kept; ++q) rr[1 + off + q] = lj[q];
+        }
       }
     }
-    const int kept_o = __shfl_xor(kept, 32);
-    const int ovf_o = __shfl_xor((int)ovf, 32);
-    const bool over = ovf || ovf_o || (kept + kept_o > TCAND);
-    if (valid) {
-      int32_t* rr = rec + pos * (TCAND + 1);
-      if (over) {
-        if (h == 0) rr[0] = -1;
-      } else {
-        if (h == 0) rr[0] = kept + kept_o;
-        const int off = h ? kept_o : 0;
-        for (int q = 0; q < kept; ++q) rr[1 + off + q] = lj[q];
-      }
     }
   }
 }
 
+#undef GEEK_LOAD_REGS
+#undef GEEK_STORE_LDS
+#undef GEEK_DMA_STAGE
+
 // ---------------------------------------------------------------- float64 checks
 GEEK_D double d64(const float* __restrict__ xr, const double* __restrict__ cr, int d) {
   double acc = 0.0;
-  for (int t = 0; t < d; ++t) {
+  int t = 0;
+  // 16-byte loads when both rows are aligned (whole cache lines per lane
+  // instead of one scalar per iteration); the summation order is unchanged
+  if (((reinterpret_cast<uintptr_t>(xr) | reinterpret_cast<uintptr_t>(cr)) & 15) == 0) {
+    for (; t + 4 <= d; t += 4) {
+      const float4 xv = *reinterpret_cast<const float4*>(xr + t);
+      const double2 c0 = *reinterpret_cast<const double2*>(cr + t);
+      const double2 c1 = *reinterpret_cast<const double2*>(cr + t + 2);
+      double delta = __dadd_rn((double)xv.x, -c0.x);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+      delta = __dadd_rn((double)xv.y, -c0.y);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+      delta = __dadd_rn((double)xv.z, -c1.x);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+      delta = __dadd_rn((double)xv.w, -c1.y);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+    }
+  }
+  for (; t < d; ++t) {
     const double delta = __dadd_rn((double)xr[t], -cr[t]);
     acc = __dadd_rn(acc, __dmul_rn(delta, delta));
   }
@@ -514,7 +732,7 @@ __global__ __launch_bounds__(256) void k_fallback64(
     const float* __restrict__ X, int64_t ldx, int d, const double* __restrict__ C, int k, Het het,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
     int32_t* __restrict__ assign, double* __restrict__ dist, unsigned long long* __restrict__ ctr) {
-  __shared__ float xs[1024];
+  __shared__ __attribute__((aligned(16))) float xs[1024];
   __shared__ double bd[256];
   __shared__ int bjs[256];
   const uint32_t count = *rows_count;
@@ -588,6 +806,14 @@ __global__ void k_sqrt_inplace(double* __restrict__ v, int k, int do_sqrt) {
   if (j < k && do_sqrt) v[j] = sqrt(v[j]);
 }
 
+__global__ void k_pad_modes(const uint32_t* __restrict__ mode, int k, int n_cat, int k_pad,
+                            uint32_t* __restrict__ out) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= (int64_t)k_pad * MAX_CAT) return;
+  const int j = (int)(g / MAX_CAT), a = (int)(g % MAX_CAT);
+  out[g] = (j < k && a < n_cat) ? mode[(int64_t)j * n_cat + a] : 0u;
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -638,6 +864,7 @@ struct AssignWs {
   double* sse_blk;
   void* modes_ws;
   size_t modes_bytes;
+  uint32_t* mode16;
 };
 
 static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
@@ -658,6 +885,7 @@ static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
   out->sse_blk = c.take<double>((J.n + SSE_BLOCK - 1) / SSE_BLOCK + 1);
   out->modes_bytes = J.metric == GEEK_METRIC_HETERO ? modes_ws(J.n_members, J.n_cat, J.k) : 0;
   out->modes_ws = c.take<char>(out->modes_bytes + 16);
+  out->mode16 = c.take<uint32_t>(J.metric == GEEK_METRIC_HETERO ? k_pad * MAX_CAT : 4);
   return c.used + 256;
 }
 
@@ -666,17 +894,41 @@ size_t assign_euclid_ws(const geek_assign_job& J) {
   return carve_assign(J, nullptr, &W);
 }
 
+// Column blocks per wave and LDS buffering per mode: the low-precision modes
+// reuse every LDS fragment for two column blocks and double-buffer; float32
+// (16x fewer flops per cycle) keeps one block and one buffer.
+// Low-precision first passes keep the best two values per row (T2); the
+// float32 pass, which also rescans rows with several candidates, keeps the
+// full candidate window.
+// Heterogeneous rows carry their categorical values in registers: one
+// column block.
+template <class M, bool HET> struct ScanShape {
+  static constexpr int NCB = HET ? 1 : 2, NBUF = 2;
+  static constexpr bool T2 = true;
+};
+template <bool HET> struct ScanShape<ModeF32, HET> {
+  static constexpr int NCB = 1, NBUF = 1;
+  static constexpr bool T2 = false;
+};
+
+template <class M>
+int scan_rows_per_tile(bool het_on) {
+  return 128 * (het_on ? ScanShape<M, true>::NCB : ScanShape<M, false>::NCB);
+}
+
 template <class M, bool HET>
 static void launch_scan(int DP, int grid, hipStream_t s, const geek_assign_job& J, int64_t n_rows,
                         const uint32_t* rows, const uint32_t* rows_count, const void* cl, const AssignWs& W,
                         int k_pad, const Het& het, int32_t* st) {
   using CE = typename M::ce;
+  constexpr int NCB = ScanShape<M, HET>::NCB, NBUF = ScanShape<M, HET>::NBUF;
+  constexpr bool T2 = ScanShape<M, HET>::T2;
   switch (DP) {
-#define GEEK_SCAN_CASE(DPV)                                                                             \
-  case DPV:                                                                                             \
-    hipLaunchKernelGGL((k_scan<M, DPV, HET>), dim3(grid), dim3(SCAN_THREADS), 0, s, J.X, J.ldx, J.d,   \
-                       n_rows, rows, rows_count, static_cast<const CE*>(cl), W.nc, k_pad, W.cmax,       \
-                       W.cmax + 3, het, J.k, W.rec, st);                                                \
+#define GEEK_SCAN_CASE(DPV)                                                                            \
+  case DPV:                                                                                            \
+    hipLaunchKernelGGL((k_scan<M, DPV, HET, NCB, NBUF, T2>), dim3(grid), dim3(SCAN_THREADS), 0, s, J.X,\
+                       J.ldx, J.d, n_rows, rows, rows_count, static_cast<const CE*>(cl), W.nc, k_pad,  \
+                       W.cmax, W.cmax + 3, het, J.k, W.rec, st);                                       \
     break;
     GEEK_SCAN_CASE(32)
     GEEK_SCAN_CASE(64)
@@ -706,8 +958,8 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
   double* dist = J.dist ? J.dist : W.dist;
   const int nb_rows = ceil_div(J.n, 256);
   const bool het_on = J.metric == GEEK_METRIC_HETERO;
-  Het het{nullptr, nullptr, 0, 0.f, 0.0};
-  if (het_on) het = Het{J.cat, J.modes, J.n_cat, (float)J.gamma, J.gamma};
+  Het het{nullptr, nullptr, nullptr, 0, 0.f, 0.0};
+  if (het_on) het = Het{J.cat, J.modes, W.mode16, J.n_cat, (float)J.gamma, J.gamma};
 
   prof_begin(GEEK_PROF_ASSIGN, s);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, W.counts, 4, 0u);
@@ -719,6 +971,8 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
     if (int32_t rc = modes_compute(reinterpret_cast<const uint32_t*>(J.cat), J.n_cat, J.n_cat, J.n,
                                    J.seed_offsets, J.seed_members, J.k, J.n_members, J.modes, W.modes_ws, st, s))
       return rc;
+    hipLaunchKernelGGL(k_pad_modes, dim3(ceil_div((int64_t)k_pad * MAX_CAT, 256)), dim3(256), 0, s, J.modes, J.k,
+                       J.n_cat, k_pad, W.mode16);
   }
   hipLaunchKernelGGL(k_cprep<ModeF32>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k, J.d, k_pad,
                      DP, W.cl32, W.nc, W.cmax, W.cmax + 3);
@@ -734,9 +988,9 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
   }
   GEEK_LAUNCH_CHECK();
 
-  const int grid_all = ceil_div(J.n, SCAN_BN);
   unsigned long long* ctr = W.ctr;
   if (J.precision == GEEK_PREC_BF16 || J.precision == GEEK_PREC_FP8) {
+    const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeBF16>(het_on));
     prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
     if (J.precision == GEEK_PREC_BF16)
       scan_any<ModeBF16>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cllow, W, k_pad, het, st);
@@ -750,6 +1004,7 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
     hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, (int64_t)0,
                        W.esc, W.counts + 0, W.rec, J.assign, dist, W.fb, W.counts + 1, ctr, 1);
   } else {
+    const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeF32>(het_on));
     prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
     scan_any<ModeF32>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cl32, W, k_pad, het, st);
     prof_end(GEEK_PROF_ASSIGN_SCAN, s);

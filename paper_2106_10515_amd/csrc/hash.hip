@@ -24,6 +24,32 @@ namespace geek {
 constexpr int H_THREADS = 256;
 constexpr int H_BN = 128;   // points per block
 constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks)
+constexpr int H_FIXCAP = 4096;  // fix-up list entries per round
+
+// Exclusive scan over a 256-thread block; *total = block sum.
+__device__ uint32_t block_exscan256(uint32_t v, uint32_t* total, uint32_t* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = 0;
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t c = sh[k];
+      sh[k] = r;
+      r += c;
+    }
+    sh[16] = r;
+  }
+  __syncthreads();
+  const uint32_t res = x - v + sh[wv];
+  *total = sh[16];
+  return res;
+}
 
 template <int DP>
 __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
@@ -37,6 +63,8 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
   __shared__ float lds_b[H_BC], lds_an[H_BC];
   __shared__ int lds_code[H_BN * H_BC];
   __shared__ uint32_t lds_flag[H_BN * H_BC / 32];  // one bit per (point, row)
+  __shared__ uint16_t lds_fix[H_FIXCAP];            // compacted (point << 6 | row)
+  __shared__ uint32_t lds_scan[17];
   __shared__ unsigned int lds_nfix;
 
   const int P = m * L;
@@ -117,10 +145,15 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
     f32x16 acc0 = {}, acc1 = {};
     const float* a0p = lds_a + p * STR + h * S;
     const float* a1p = a0p + 32 * STR;
+    if (rows_used > 32) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0p[s], xb[s], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1p[s], xb[s], acc1, 0, 0, 0);
+      for (int s = 0; s < S; ++s) {
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0p[s], xb[s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1p[s], xb[s], acc1, 0, 0, 0);
+      }
+    } else {  // the second 32-row block holds no projection of this chunk
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0p[s], xb[s], acc0, 0, 0, 0);
     }
     const int pl = wv * 32 + p;  // point within block
 #pragma unroll
@@ -143,27 +176,51 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
       }
     }
     __syncthreads();
-    // ---- float64 recomputation of the uncertified pairs, reference order
+    // ---- float64 recomputation of the uncertified pairs, reference order:
+    // compact the flags into a list, spread it over the block, read a_p
+    // from the LDS tile and x_i with 16-byte loads
     {
-      uint32_t bits = lds_flag[tid];
-      const unsigned int nf = __popc(bits);
-      while (bits) {
-        const int bb = __ffs(bits) - 1;
-        bits &= bits - 1u;
-        const int pp = tid >> 1, row = (tid & 1) * 32 + bb;
-        const int64_t ii = i0 + pp;
-        const float* xi = X + ii * ldx;
-        const float* ap = A + (int64_t)(p0 + row) * d;
-        double sacc = 0.0;
-        for (int t = 0; t < d; ++t) sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xi[t]));
-        const double v = __dadd_rn(sacc, (double)bvec[p0 + row]);
-        const double qd = v / (double)w;
-        const double fl = floor(qd);
-        const bool fits = fl >= -2147483648.0 && fl <= 2147483647.0;
-        if (!fits) set_status(st, GEEK_ERR_RANGE);
-        lds_code[pp * H_BC + row] = fits ? (int)fl : 0;
+      const uint32_t bits0 = lds_flag[tid];
+      uint32_t tot;
+      const uint32_t at0 = block_exscan256(__popc(bits0), &tot, lds_scan);
+      for (uint32_t base = 0; base < tot; base += H_FIXCAP) {
+        uint32_t bits = bits0, at = at0;
+        while (bits) {
+          const int bb = __ffs(bits) - 1;
+          bits &= bits - 1u;
+          if (at >= base && at < base + H_FIXCAP)
+            lds_fix[at - base] = (uint16_t)(((tid >> 1) << 6) | ((tid & 1) * 32 + bb));
+          ++at;
+        }
+        __syncthreads();
+        const uint32_t cnt = (tot - base) < (uint32_t)H_FIXCAP ? (tot - base) : (uint32_t)H_FIXCAP;
+        for (uint32_t q = tid; q < cnt; q += H_THREADS) {
+          const int e = lds_fix[q];
+          const int pp = e >> 6, row = e & 63;
+          const float* xi = X + (i0 + pp) * ldx;
+          const float* ap = lds_a + row * STR;
+          double sacc = 0.0;
+          int t = 0;
+          if (vec4) {
+            for (; t + 4 <= d; t += 4) {
+              const float4 xv = *reinterpret_cast<const float4*>(xi + t);
+              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xv.x));
+              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t + 1], (double)xv.y));
+              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t + 2], (double)xv.z));
+              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t + 3], (double)xv.w));
+            }
+          }
+          for (; t < d; ++t) sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xi[t]));
+          const double v = __dadd_rn(sacc, (double)lds_b[row]);
+          const double qd = v / (double)w;
+          const double fl = floor(qd);
+          const bool fits = fl >= -2147483648.0 && fl <= 2147483647.0;
+          if (!fits) set_status(st, GEEK_ERR_RANGE);
+          lds_code[pp * H_BC + row] = fits ? (int)fl : 0;
+        }
+        __syncthreads();
       }
-      if (nf) atomicAdd(&lds_nfix, nf);
+      if (tid == 0 && tot) lds_nfix += tot;
     }
     __syncthreads();
     // ---- pack the m codes of every (table, point) into a 128-bit key
