@@ -221,7 +221,7 @@ GEEK_D double gamma_n(double nn, double u) { return nn * u / (1.0 - nn * u); }
 // |x^ - x| <= ex = UX X + A0 sqrt(DP) / s (likewise ec) and, by Cauchy-
 // Schwarz, |x^.c^ - x.c| <= ex cm + X ec + ex ec; the float32 accumulation of
 // the (exact) products adds gamma_{DP+1}(2u) |x^| |c^|.
-template <class M, int DP>
+template <class M, int DP, bool T2>
 GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
   const double u32 = 0x1p-24;
   const double g_acc = gamma_n(DP + 1, 2.0 * u32);
@@ -240,7 +240,8 @@ GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
                + 2.0 * u32 * vmax               // epilogue roundings
                + g64 * s2 + 0x1p-52 * het_max   // float64 reference rounding
                + 4.0 * u32 * s2                 // threshold arithmetic
-               + DP * 0x1p-120;                 // flushed subnormal products
+               + DP * 0x1p-120                  // flushed subnormal products
+               + (T2 ? 0x1p-18 * vmax : 0.0);   // index bits in the low mantissa
   eps *= 1.01;
   return (float)(2.0 * eps * (1.0 + 0x1p-20));
 }
@@ -291,6 +292,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
   // T2 starts every accumulator at -s^2 |c_j|^2 / 2 (exact power-of-two
   // scalings), so acc = s^2 (x.c - |c_j|^2 / 2) and v_j = m2s * acc
   const float nc_mul = T2 ? -0.5f * sc * sc : 1.0f;
+  // padded centroids (|c|^2 = +inf) start T2 accumulators at -FLT_MAX
+  auto nc_stage = [nc_mul](float v) { return T2 ? fmaxf(v * nc_mul, -3.402823466e38f) : v; };
   const bool vec4 = ((d & 3) == 0) && ((ldx & 3) == 0);
   const double het_max = HET ? het.gamma * het.n_cat : 0.0;
 
@@ -307,7 +310,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
       stg[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(cl + (int64_t)((C0) + r) * DP) + \
                                                c * 16);                                                    \
     }                                                                                                      \
-    stg_nc = nc[(C0) + (tid & (SCAN_BC - 1))] * nc_mul;                                                    \
+    stg_nc = nc_stage(nc[(C0) + (tid & (SCAN_BC - 1))]);                                                   \
     if constexpr (HET) {                                                                                   \
       _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                                   \
         const int q = min(tid + u * SCAN_THREADS, SCAN_BC * MAX_CAT - 1);                                  \
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
           reinterpret_cast<const char*>(cl + (int64_t)((C0) + r) * DP) + c * 16,                           \
           reinterpret_cast<char*>(lds_c[B]) + slot0 * 16, 16, 0, 0);                                      \
     }                                                                                                      \
-    stg_nc = nc[(C0) + (tid & (SCAN_BC - 1))] * nc_mul; /* lds_nc[B] stored from the register */        \
+    stg_nc = nc_stage(nc[(C0) + (tid & (SCAN_BC - 1))]); /* lds_nc[B] stored from the register */       \
     if constexpr (HET)                                                                                     \
       __builtin_amdgcn_global_load_lds(                                                                    \
           reinterpret_cast<const char*>(het.mode16 + (int64_t)(C0) * MAX_CAT) + (w * 64 + lane) * 16,     \
@@ -397,7 +400,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
       for (int s = 0; s < S; ++s) xb[cb][s] = M::from_f32(xv + s * M::KPER, sc);
       if (!finite) set_status(st, GEEK_ERR_NONFINITE);
       nrm += __shfl_xor(nrm, 32);
-      twoeps[cb] = two_eps<M, DP>(sqrt(nrm) * (1.0 + 1e-12), cm, 1.0 / sc, het_max);
+      twoeps[cb] = two_eps<M, DP, T2>(sqrt(nrm) * (1.0 + 1e-12), cm, 1.0 / sc, het_max);
       if constexpr (HET) {
 #pragma unroll
         for (int a = 0; a < MAX_CAT; ++a)
@@ -408,13 +411,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
     // Window: thr starts at the largest finite float, so padded centroids
     // (|c|^2 = +inf) and non-finite values never enter it; lost is the
     // smallest value dropped from a full window.
-    // T2: best (a1, index j1) and second best (a2) of the values seen, in
-    // accumulator units where larger is nearer; j1 is kept relative to the
-    // current stage (the stage index is added back at the end).
+    // T2: best (a1) and second best (a2) of the values seen, in accumulator
+    // units where larger is nearer.  Each value carries its position within
+    // the lane's 16 values of a 32-centroid block in its low 4 mantissa bits;
+    // blk is the block where a1 last changed.
     float b0[NCB], thr[NCB], lost[NCB];
     int cnt[NCB];
     float a1[NCB], a2[NCB];
-    int j1[NCB];
+    int blk[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       b0[cb] = INFINITY;
@@ -423,7 +427,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
       cnt[cb] = 0;
       a1[cb] = -3.402823466e38f;
       a2[cb] = -3.402823466e38f;
-      j1[cb] = 0;
+      blk[cb] = 0;
     }
 
     __syncthreads();  // previous tile done with the LDS buffers
@@ -474,7 +478,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = M::mma(a, xb[cb][s], acc[cb]);
         }
         if constexpr (T2) {
-          // branch-free: per value one compare, one select, med3 and max
+          // branch-free: per value one bit insert and two med3
+          const int gblk = it * (SCAN_BC / 32) + rb;
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) {
             float t[16];
@@ -490,14 +495,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
                 t[r] = __builtin_fmaf(-m2s, t[r], -het.gamma_f * (float)mm);
               }
             }
+            const float a1_prev = a1[cb];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              const bool better = t[r] > a1[cb];
-              j1[cb] = better ? (r >> 2) * 8 + (r & 3) : j1[cb];
-              a2[cb] = __builtin_amdgcn_fmed3f(a1[cb], a2[cb], t[r]);
-              a1[cb] = fmaxf(a1[cb], t[r]);
+              const float tb = __uint_as_float((__float_as_uint(t[r]) & ~15u) | (uint32_t)r);
+              a2[cb] = __builtin_amdgcn_fmed3f(a1[cb], a2[cb], tb);            // second best
+              a1[cb] = __builtin_amdgcn_fmed3f(a1[cb], tb, 3.402823466e38f);  // best
             }
-            j1[cb] -= 32;  // indices stay relative to the current 32-centroid block
+            blk[cb] = a1[cb] != a1_prev ? gblk : blk[cb];
           }
         } else {
         float ncv[16];
@@ -577,16 +582,19 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
         const float a1o = __shfl_xor(a1[cb], 32), a2o = __shfl_xor(a2[cb], 32);
-        const int jg = j1[cb] + k_pad + h * 4;
-        const int jo = __shfl_xor(jg, 32);
-        const float best = fmaxf(a1[cb], a1o);
+        const int blko = __shfl_xor(blk[cb], 32);
+        const bool mine = a1[cb] > a1o;  // equal values: a tie, never unique
+        const float best = mine ? a1[cb] : a1o;
         const float second = fmaxf(fminf(a1[cb], a1o), fmaxf(a2[cb], a2o));
-        const int jbest = a1[cb] >= a1o ? jg : jo;
+        const int rbits = (int)(__float_as_uint(best) & 15u);
+        const int jbest = (mine ? blk[cb] : blko) * 32 + (rbits >> 2) * 8 + (mine ? h : 1 - h) * 4 + (rbits & 3);
         // back to distance units (exact): v = m2s * acc, or -t for HET
         const float vs = HET ? -1.0f : m2s;
         const float v1 = vs * best, v2 = vs * second;
-        // one candidate iff the runner-up lies beyond the 2 eps window
-        const bool unique = best > -3.402823466e38f && isfinite(v1) && v2 > v1 + twoeps[cb];
+        // one candidate iff the runner-up lies beyond the 2 eps window; the
+        // best must be a normal float (its index bits intact)
+        const bool unique = best > -1e38f && fabsf(best) >= 0x1p-126f && isfinite(v1) && v2 > v1 + twoeps[cb] &&
+                            jbest < k;
         if (valid[cb] && h == 0) {
           int32_t* rr = rec + posv[cb] * (TCAND + 1);
           rr[0] = unique ? 1 : -1;
