@@ -1,24 +1,30 @@
 // Buckets of every table (paper Algorithms 2 and 3: T[G(x_j)].push(j)) on
 // gfx950: group the objects whose table keys are identical.
 //
-//  1. k_bin_count / k_bin_scan / k_bin_scatter: a one-pass MSD partition of
+//  1. k_bin_count / k_bin_*scan / k_bin_scatter: a one-pass MSD partition of
 //     (key, id) records into 2^nb bins per table, the bin being the top bits
 //     of a 32-bit mix of the exact key (equal keys always share a bin).
-//  2. k_bin_sort: one workgroup per bin sorts its records by (key, id) in
-//     LDS (bitonic), finds runs of equal keys and records, for every run, its
-//     smallest id (the run head: ids ascend within a run), length and start.
-//     Bins too large for LDS are sorted by k_big_sort (workgroup LSD radix
-//     sort in global memory) and scanned by k_big_runs.
-//  3. k_scan_*: a segmented scan over ids of (is-head, run length) gives each
-//     bucket its rank in "smallest member" order and its CSR offset.
-//  4. k_emit: every record is copied to its canonical CSR slot and bucket_of.
+//  2. k_bin_group: one workgroup per bin groups its records with an LDS hash
+//     table on the exact key; objects sharing a key get (head = smallest id,
+//     rank among the bucket's ids, bucket size at the head) in id-indexed
+//     arrays plus a flag bit.  Bins too large for LDS are sorted by
+//     k_big_sort (workgroup LSD radix sort in global memory) and their runs
+//     recorded by k_big_runs.
+//  3. k_bz_reduce / k_scan_chunks / k_bz_apply: a scan over ids in id order
+//     gives every bucket its rank in smallest-member order and its CSR
+//     offset; every head (including objects alone in their bucket) is
+//     written to its slot at once.
+//  4. k_bz_members: the remaining members of buckets of two or more go to
+//     head offset + rank.
 #include "common.hpp"
 
 namespace geek {
 
 constexpr int BZ_THREADS = 256;
 constexpr int BZ_CHUNK = 32768;   // records per block in count / scatter
-constexpr int BZ_CAP = 2048;      // largest bin sorted in LDS
+constexpr int BZ_CAP = 2048;      // largest bin grouped in LDS
+constexpr int BZ_HT = 4096;       // LDS hash slots per bin
+constexpr int BZ_SMALL = 32;      // largest group ranked by walking its member list
 constexpr int BZ_MAXBITS = 14;    // at most 16384 bins per table
 constexpr int SC_CHUNK = 4096;    // elements per block in the scans
 constexpr int BIG_THREADS = 1024;
@@ -157,100 +163,149 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bin_scatter(BzArgs a, int nblk, 
   }
 }
 
-// ---------------------------------------------------------------- per-bin sort
-struct RunOut {
-  uint32_t* st_ids;    // [T][n] sorted ids (written back)
-  uint32_t* rec_head;  // [T][n] per record: first id of its run
-  uint32_t* run_len;   // [T][n] per id: run length if the id heads a run, else 0
-  uint32_t* run_pos;   // [T][n] per head id: start of its run in the staging order
+// ---------------------------------------------------------------- per-bin grouping
+// Id-indexed results of the grouping, per table (only objects that share
+// their key with another object are recorded; every other object is a
+// bucket of its own):
+//   flags  bit i set iff object i is in a bucket of two or more
+//   info   for flagged i: x = head (smallest id of the bucket),
+//          y = bucket size if i is the head, else the rank of i in its bucket
+//          (number of smaller ids)
+struct GroupOut {
+  uint32_t* flags;  // [T][flag_words]
+  uint2* info;      // [T][n]
+  int64_t flag_words;
 };
 
-__global__ __launch_bounds__(BZ_THREADS) void k_bin_sort(int64_t n, int nb, const uint32_t* bintot,
-                                                         const uint32_t* binstart, const uint4* st_keys,
-                                                         RunOut ro, uint32_t* big_list,
-                                                         uint32_t* big_count) {
-  __shared__ uint4 sk[BZ_CAP];
+GEEK_D void group_record(const GroupOut& go, int t, int64_t n, uint32_t id, uint32_t head, uint32_t y) {
+  go.info[(int64_t)t * n + id] = make_uint2(head, y);
+  atomicOr(&go.flags[(int64_t)t * go.flag_words + (id >> 5)], 1u << (id & 31));
+}
+
+// One workgroup per (bin, table): records -> LDS; an LDS hash table keyed by
+// the exact key gives each record its group (slot) and the group sizes.
+// Ranks inside groups of at most BZ_SMALL come from a walk of the group's
+// member list; bins with a larger group sort (slot, id) pairs in LDS
+// (bitonic) and rank by position.  A slot word holds the group size in its
+// high 16 bits and, in its low 16 bits, first the representative record + 1
+// (0: empty), then the member-list head + 1, then the first sorted position
+// + 1.
+__global__ __launch_bounds__(BZ_THREADS) void k_bin_group(int64_t n, int nb, const uint32_t* bintot,
+                                                          const uint32_t* binstart, const uint4* st_keys,
+                                                          const uint32_t* st_ids, GroupOut go,
+                                                          uint32_t* big_list, uint32_t* big_count) {
+  __shared__ uint4 sk[BZ_CAP];  // keys; reused as the (slot, id) sort array
   __shared__ uint32_t sid[BZ_CAP];
-  __shared__ int sst[BZ_CAP];
+  __shared__ uint32_t hw[BZ_HT];
+  __shared__ uint16_t grp[BZ_CAP];
+  __shared__ int16_t nxt[BZ_CAP];
+  __shared__ uint32_t smax;
   const int t = blockIdx.y, bin = blockIdx.x;
   const int nbins = 1 << nb;
   const uint32_t size = bintot[(int64_t)t * nbins + bin];
-  if (size == 0) return;
-  const uint32_t s0 = binstart[(int64_t)t * nbins + bin];
+  if (size <= 1) return;  // empty, or one record: a bucket of its own
   if (size > BZ_CAP) {
     if (threadIdx.x == 0) big_list[atomicAdd(big_count, 1u)] = (uint32_t)(t * nbins + bin);
     return;
   }
-  int P2 = 1;
-  while (P2 < (int)size) P2 <<= 1;
+  const uint32_t s0 = binstart[(int64_t)t * nbins + bin];
   const uint4* gk = st_keys + (int64_t)t * n + s0;
-  const uint32_t* gi = ro.st_ids + (int64_t)t * n + s0;
-  for (int q = threadIdx.x; q < P2; q += BZ_THREADS) {
-    if (q < (int)size) {
-      sk[q] = gk[q];
-      sid[q] = gi[q];
-    } else {
-      sk[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
-      sid[q] = ~0u;
+  const uint32_t* gi = st_ids + (int64_t)t * n + s0;
+  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
+    sk[q] = gk[q];
+    sid[q] = gi[q];
+  }
+  for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] = 0u;
+  if (threadIdx.x == 0) smax = 0;
+  __syncthreads();
+  // insert with linear probing; a claimed slot's key is already in LDS
+  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
+    const uint4 k = sk[q];
+    const uint32_t w[4] = {k.x, k.y, k.z, k.w};
+    int h = (int)(key_hash(w, 4) & (BZ_HT - 1));
+    for (;;) {
+      uint32_t cur = hw[h] & 0xFFFFu;
+      if (cur == 0u) {
+        const uint32_t prev = atomicCAS(&hw[h], 0u, (uint32_t)(q + 1));
+        if (prev == 0u) break;
+        cur = prev & 0xFFFFu;
+      }
+      if (key_eq(sk[cur - 1], k)) break;
+      h = (h + 1) & (BZ_HT - 1);
     }
+    grp[q] = (uint16_t)h;
+    atomicAdd(&hw[h], 0x10000u);
   }
   __syncthreads();
-  // bitonic sort by (key, id)
+  for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] &= 0xFFFF0000u;
+  __syncthreads();
+  // member lists (order arbitrary)
+  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
+    const int g = grp[q];
+    uint32_t old = hw[g];
+    for (;;) {
+      const uint32_t prev = atomicCAS(&hw[g], old, (old & 0xFFFF0000u) | (uint32_t)(q + 1));
+      if (prev == old) break;
+      old = prev;
+    }
+    nxt[q] = (int16_t)((int)(old & 0xFFFFu) - 1);
+    atomicMax(&smax, old >> 16);
+  }
+  __syncthreads();
+  const uint32_t big = smax;
+  if (big <= 1) return;  // all keys distinct
+  if (big <= BZ_SMALL) {
+    for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
+      const uint32_t v = hw[grp[q]];
+      const uint32_t c = v >> 16;
+      if (c == 1) continue;
+      const uint32_t me = sid[q];
+      uint32_t r = 0, head = me;
+      for (int e = (int)(v & 0xFFFFu) - 1; e >= 0; e = nxt[e]) {
+        const uint32_t o = sid[e];
+        r += o < me;
+        head = min(head, o);
+      }
+      group_record(go, t, n, me, head, r == 0 ? c : r);
+    }
+    return;
+  }
+  // a larger group: sort (slot, id) pairs, rank by position
+  unsigned long long* sc = reinterpret_cast<unsigned long long*>(sk);
+  int P2 = 1;
+  while (P2 < (int)size) P2 <<= 1;
+  for (int q = threadIdx.x; q < P2; q += BZ_THREADS)
+    sc[q] = q < (int)size ? ((unsigned long long)grp[q] << 32) | sid[q] : ~0ull;
+  for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] |= 0xFFFFu;
+  __syncthreads();
   for (int kk = 2; kk <= P2; kk <<= 1) {
     for (int jj = kk >> 1; jj > 0; jj >>= 1) {
       for (int q = threadIdx.x; q < P2; q += BZ_THREADS) {
         const int o = q ^ jj;
         if (o > q) {
+          const unsigned long long a = sc[q], b = sc[o];
           const bool up = (q & kk) == 0;
-          const uint4 ka = sk[q], kb = sk[o];
-          const uint32_t ia = sid[q], ib = sid[o];
-          const bool sw = up ? rec_less(kb, ib, ka, ia) : rec_less(ka, ia, kb, ib);
-          if (sw) {
-            sk[q] = kb;
-            sk[o] = ka;
-            sid[q] = ib;
-            sid[o] = ia;
+          if (up ? (b < a) : (a < b)) {
+            sc[q] = b;
+            sc[o] = a;
           }
         }
       }
       __syncthreads();
     }
   }
-  // run starts: inclusive max-scan of (head ? q : -1)
-  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS)
-    sst[q] = (q == 0 || !key_eq(sk[q], sk[q - 1])) ? q : -1;
-  __syncthreads();
-  for (int o = 1; o < (int)size; o <<= 1) {
-    int tmp[BZ_CAP / BZ_THREADS];
-#pragma unroll
-    for (int u = 0; u < BZ_CAP / BZ_THREADS; ++u) {
-      const int q = threadIdx.x + u * BZ_THREADS;
-      tmp[u] = (q < (int)size && q >= o) ? max(sst[q], sst[q - o]) : (q < (int)size ? sst[q] : 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < BZ_CAP / BZ_THREADS; ++u) {
-      const int q = threadIdx.x + u * BZ_THREADS;
-      if (q < (int)size) sst[q] = tmp[u];
-    }
-    __syncthreads();
-  }
-  uint32_t* oi = ro.st_ids + (int64_t)t * n + s0;
-  uint32_t* oh = ro.rec_head + (int64_t)t * n + s0;
-  uint32_t* rl = ro.run_len + (int64_t)t * n;
-  uint32_t* rp = ro.run_pos + (int64_t)t * n;
   for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
-    const int rs = sst[q];
-    const uint32_t f = sid[rs];
-    const uint32_t id = sid[q];
-    oi[q] = id;
-    oh[q] = f;
-    const bool last = (q == (int)size - 1) || (sst[q + 1] == q + 1);
-    if (last) {
-      rl[f] = (uint32_t)(q - rs + 1);
-      rp[f] = s0 + (uint32_t)rs;
-    }
-    if (q != rs) rl[id] = 0u;
+    const int g = (int)(sc[q] >> 32);
+    atomicMin(&hw[g], (hw[g] & 0xFFFF0000u) | (uint32_t)(q + 1));
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
+    const uint32_t v = hw[(int)(sc[q] >> 32)];
+    const uint32_t c = v >> 16;
+    if (c == 1) continue;
+    const int f = (int)(v & 0xFFFFu) - 1;
+    const uint32_t me = (uint32_t)sc[q], head = (uint32_t)sc[f];
+    group_record(go, t, n, me, head, q == f ? c : (uint32_t)(q - f));
   }
 }
 
@@ -350,11 +405,12 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_sort(int64_t n, int nb, int
   }
 }
 
-// Run detection of a sorted oversize bin (one workgroup per bin).
+// Run detection of a sorted oversize bin (one workgroup per bin); records
+// the runs of two or more in the grouping output.
 __global__ __launch_bounds__(BIG_THREADS) void k_big_runs(int64_t n, int nb, const uint32_t* bintot,
                                                           const uint32_t* binstart, const uint4* st_keys,
-                                                          RunOut ro, const uint32_t* big_list,
-                                                          const uint32_t* big_count) {
+                                                          const uint32_t* st_ids, GroupOut go,
+                                                          const uint32_t* big_list, const uint32_t* big_count) {
   __shared__ int ss[BIG_THREADS];
   __shared__ int carry;
   const int nbins = 1 << nb;
@@ -364,10 +420,7 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_runs(int64_t n, int nb, con
     const int t = (int)(tb / nbins);
     const uint32_t size = bintot[tb], s0 = binstart[tb];
     const uint4* k = st_keys + (int64_t)t * n + s0;
-    const uint32_t* ids = ro.st_ids + (int64_t)t * n + s0;
-    uint32_t* oh = ro.rec_head + (int64_t)t * n + s0;
-    uint32_t* rl = ro.run_len + (int64_t)t * n;
-    uint32_t* rp = ro.run_pos + (int64_t)t * n;
+    const uint32_t* ids = st_ids + (int64_t)t * n + s0;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (uint32_t r0 = 0; r0 < size; r0 += BIG_THREADS) {
@@ -385,14 +438,11 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_runs(int64_t n, int nb, con
       const int rs = max(ss[threadIdx.x], carry);
       if (q < size) {
         const uint32_t f = ids[rs];
-        const uint32_t id = ids[q];
-        oh[q] = f;
         const bool last = (q == size - 1) || !key_eq(k[q + 1], k[q]);
-        if (last) {
-          rl[f] = q - (uint32_t)rs + 1u;
-          rp[f] = s0 + (uint32_t)rs;
+        if ((int)q != rs) {
+          group_record(go, t, n, ids[q], f, q - (uint32_t)rs);
+          if (last) group_record(go, t, n, f, f, q - (uint32_t)rs + 1u);
         }
-        if ((int)q != rs) rl[id] = 0u;
       }
       __syncthreads();
       if (threadIdx.x == BIG_THREADS - 1) carry = rs;
@@ -401,19 +451,46 @@ __global__ __launch_bounds__(BIG_THREADS) void k_big_runs(int64_t n, int nb, con
   }
 }
 
-// ---------------------------------------------------------------- scans
-// Segmented (per table) scan over ids of (heads, run lengths).
-__global__ __launch_bounds__(BZ_THREADS) void k_scan_reduce(int64_t n, int nch, const uint32_t* run_len,
-                                                            uint2* ctot) {
+// ---------------------------------------------------------------- scans and emission
+// Each thread owns BZ_PER consecutive ids of a SC_CHUNK-id chunk; their flag
+// bits sit in one flag word.
+constexpr int BZ_PER = SC_CHUNK / BZ_THREADS;
+static_assert(BZ_PER == 16, "16 ids per thread: one half flag word");
+
+// Bucket head / bucket length of id i (0 length for non-head members).
+GEEK_D void id_bucket(const GroupOut& go, int t, int64_t n, int64_t i, bool flagged, uint32_t& is_head,
+                      uint32_t& len, uint2& inf) {
+  if (!flagged) {
+    is_head = 1;
+    len = 1;
+    return;
+  }
+  inf = go.info[(int64_t)t * n + i];
+  is_head = inf.x == (uint32_t)i;
+  len = is_head ? inf.y : 0u;
+}
+
+GEEK_D uint32_t flag_bits16(const GroupOut& go, int t, int64_t i0) {
+  return (go.flags[(int64_t)t * go.flag_words + (i0 >> 5)] >> (i0 & 31)) & 0xFFFFu;
+}
+
+__global__ __launch_bounds__(BZ_THREADS) void k_bz_reduce(int64_t n, int nch, GroupOut go, uint2* ctot) {
   __shared__ uint32_t sh[17];
   const int t = blockIdx.y, c = blockIdx.x;
-  const int64_t s = (int64_t)c * SC_CHUNK;
-  const uint32_t* rl = run_len + (int64_t)t * n;
+  const int64_t i0 = (int64_t)c * SC_CHUNK + (int64_t)threadIdx.x * BZ_PER;
   uint32_t h = 0, l = 0;
-  for (int64_t i = s + threadIdx.x; i < s + SC_CHUNK && i < n; i += BZ_THREADS) {
-    const uint32_t v = rl[i];
-    h += v != 0;
-    l += v;
+  if (i0 < n) {
+    const uint32_t fb = flag_bits16(go, t, i0);
+#pragma unroll
+    for (int u = 0; u < BZ_PER; ++u) {
+      const int64_t i = i0 + u;
+      if (i >= n) break;
+      uint32_t ih, len;
+      uint2 inf;
+      id_bucket(go, t, n, i, (fb >> u) & 1u, ih, len, inf);
+      h += ih;
+      l += len;
+    }
   }
   uint32_t th, tl;
   block_exscan(h, &th, sh);
@@ -449,55 +526,67 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(int nch, uint2* ctot, uint
   if (threadIdx.x == 0) nbuckets[t] = tot;
 }
 
-__global__ __launch_bounds__(BZ_THREADS) void k_scan_apply(int64_t n, int nch, const uint2* ctot,
-                                                           uint32_t* run_len /* -> rank */,
-                                                           uint32_t* hoff, uint32_t* offsets,
-                                                           const uint32_t* nbuckets) {
+// Bucket ranks and CSR offsets in smallest-member order; heads (and every
+// object alone in its bucket) are written to their slot; heads of larger
+// buckets leave (start, rank) for their members.
+__global__ __launch_bounds__(BZ_THREADS) void k_bz_apply(int64_t n, int nch, GroupOut go, const uint2* ctot,
+                                                         uint2* hs, uint32_t* members, uint32_t* offsets,
+                                                         uint32_t* bucket_of, const uint32_t* nbuckets) {
   __shared__ uint32_t sh[17];
   const int t = blockIdx.y, c = blockIdx.x;
-  const int64_t s = (int64_t)c * SC_CHUNK;
-  constexpr int PER = SC_CHUNK / BZ_THREADS;
-  uint32_t* rl = run_len + (int64_t)t * n;
-  uint32_t* ho = hoff + (int64_t)t * n;
-  uint32_t* off = offsets + (int64_t)t * (n + 1);
-  uint32_t v[PER];
-  uint32_t lh = 0, ll = 0;
+  const int64_t i0 = (int64_t)c * SC_CHUNK + (int64_t)threadIdx.x * BZ_PER;
+  const int64_t tn = (int64_t)t * n;
+  uint32_t fb = 0, lh = 0, ll = 0;
+  uint32_t ihv[BZ_PER], lenv[BZ_PER];
+  if (i0 < n) fb = flag_bits16(go, t, i0);
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int64_t i = s + threadIdx.x * PER + u;
-    v[u] = i < n ? rl[i] : 0u;
-    lh += v[u] != 0;
-    ll += v[u];
+  for (int u = 0; u < BZ_PER; ++u) {
+    const int64_t i = i0 + u;
+    ihv[u] = 0;
+    lenv[u] = 0;
+    if (i < n) {
+      uint2 inf;
+      id_bucket(go, t, n, i, (fb >> u) & 1u, ihv[u], lenv[u], inf);
+    }
+    lh += ihv[u];
+    ll += lenv[u];
   }
   uint32_t bh = block_exscan(lh, nullptr, sh) + ctot[(int64_t)t * nch + c].x;
   uint32_t bl = block_exscan(ll, nullptr, sh) + ctot[(int64_t)t * nch + c].y;
+  uint32_t* off = offsets + (int64_t)t * (n + 1);
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int64_t i = s + threadIdx.x * PER + u;
-    if (i < n && v[u]) {
-      rl[i] = bh;   // bucket rank of head i
-      ho[i] = bl;   // CSR offset of that bucket
-      off[bh] = bl;
-      ++bh;
-      bl += v[u];
-    }
+  for (int u = 0; u < BZ_PER; ++u) {
+    if (!ihv[u]) continue;
+    const uint32_t i = (uint32_t)(i0 + u);
+    off[bh] = bl;
+    members[tn + bl] = i;
+    if (bucket_of) bucket_of[tn + i] = bh;
+    if ((fb >> u) & 1u) hs[tn + i] = make_uint2(bl, bh);
+    ++bh;
+    bl += lenv[u];
   }
   if (c == 0 && threadIdx.x == 0) off[nbuckets[t]] = (uint32_t)n;
 }
 
-__global__ void k_emit(int64_t n, int T, const uint32_t* st_ids, const uint32_t* rec_head,
-                       const uint32_t* rank, const uint32_t* hoff, const uint32_t* run_pos,
-                       uint32_t* members, uint32_t* bucket_of) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= (int64_t)T * n) return;
-  const int t = (int)(g / n);
-  const int64_t s = g - (int64_t)t * n;
-  const int64_t tb = (int64_t)t * n;
-  const uint32_t id = st_ids[g];
-  const uint32_t f = rec_head[g];
-  const uint32_t pos0 = run_pos[tb + f];
-  members[tb + hoff[tb + f] + (uint32_t)(s - pos0)] = id;
-  if (bucket_of) bucket_of[tb + id] = rank[tb + f];
+// Members of buckets of two or more, other than the head.
+__global__ __launch_bounds__(BZ_THREADS) void k_bz_members(int64_t n, GroupOut go, const uint2* hs,
+                                                           uint32_t* members, uint32_t* bucket_of) {
+  const int t = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * SC_CHUNK + (int64_t)threadIdx.x * BZ_PER;
+  if (i0 >= n) return;
+  const uint32_t fb = flag_bits16(go, t, i0);
+  if (!fb) return;
+  const int64_t tn = (int64_t)t * n;
+#pragma unroll
+  for (int u = 0; u < BZ_PER; ++u) {
+    const int64_t i = i0 + u;
+    if (i >= n || !((fb >> u) & 1u)) continue;
+    const uint2 inf = go.info[tn + i];
+    if (inf.x == (uint32_t)i) continue;  // head: already written
+    const uint2 h = hs[tn + inf.x];
+    members[tn + h.x + inf.y] = (uint32_t)i;
+    if (bucket_of) bucket_of[tn + i] = h.y;
+  }
 }
 
 // ---------------------------------------------------------------- host side
@@ -508,9 +597,9 @@ static int bin_bits(int64_t n) {
 }
 
 struct BzWs {
-  uint32_t *counts, *bintot, *binstart, *st_ids, *rec_head, *run_len, *run_pos, *hoff, *alt_ids;
+  uint32_t *counts, *bintot, *binstart, *st_ids, *alt_ids, *flags;
   uint4 *st_keys, *alt_keys;
-  uint2* ctot;
+  uint2 *info, *hs, *ctot;
   uint32_t *big_list, *big_count;
 };
 
@@ -521,17 +610,17 @@ static size_t carve_bz(const geek_bucketize_job& J, void* ws, BzWs& W) {
   const int nblk = ceil_div(J.n, BZ_CHUNK);
   const int nch = ceil_div(J.n, SC_CHUNK);
   const size_t Tn = (size_t)J.T * J.n;
+  const int64_t fw = ceil_div(J.n, 32);
   W.counts = c.take<uint32_t>((size_t)J.T * nblk * nbins);
   W.bintot = c.take<uint32_t>((size_t)J.T * nbins);
   W.binstart = c.take<uint32_t>((size_t)J.T * nbins);
   W.st_keys = c.take<uint4>(Tn);
   W.alt_keys = c.take<uint4>(Tn);
+  W.hs = reinterpret_cast<uint2*>(W.alt_keys);  // used after the oversize-bin sorts
   W.st_ids = c.take<uint32_t>(Tn);
   W.alt_ids = c.take<uint32_t>(Tn);
-  W.rec_head = c.take<uint32_t>(Tn);
-  W.run_len = c.take<uint32_t>(Tn);
-  W.run_pos = c.take<uint32_t>(Tn);
-  W.hoff = c.take<uint32_t>(Tn);
+  W.flags = c.take<uint32_t>((size_t)J.T * fw);
+  W.info = c.take<uint2>(Tn);
   W.ctot = c.take<uint2>((size_t)J.T * nch);
   W.big_list = c.take<uint32_t>((size_t)J.T * nbins);
   W.big_count = c.take<uint32_t>(4);
@@ -543,8 +632,8 @@ size_t bucketize_ws(const geek_bucketize_job& J) {
   return carve_bz(J, nullptr, W);
 }
 
-__global__ void k_zero_u32(uint32_t* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
 }
 
@@ -557,31 +646,34 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   const int nbins = 1 << nb;
   const int nblk = ceil_div(J.n, BZ_CHUNK);
   const int nch = ceil_div(J.n, SC_CHUNK);
+  const int64_t fw = ceil_div(J.n, 32);
   BzArgs a{J.keys, J.n, J.T, J.key_words, J.table_stride, J.row_stride, nb};
+  GroupOut go{W.flags, W.info, fw};
   const size_t hbytes = (size_t)nbins * 4;
   prof_begin(GEEK_PROF_BUCKETIZE, s);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, W.big_count, 4);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, W.big_count, (int64_t)4);
+  hipLaunchKernelGGL(k_zero_u32, dim3(ceil_div((int64_t)J.T * fw, 256)), dim3(256), 0, s, W.flags,
+                     (int64_t)J.T * fw);
   hipLaunchKernelGGL(k_bin_count, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, W.counts);
   hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div((int64_t)J.T * nbins, 256)), dim3(256), 0, s, J.T,
                      nblk, nbins, W.counts, W.bintot);
   hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
   hipLaunchKernelGGL(k_bin_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, W.counts,
                      W.binstart, W.st_keys, W.st_ids);
-  RunOut ro{W.st_ids, W.rec_head, W.run_len, W.run_pos};
   prof_begin(GEEK_PROF_BZ_SORT, s);
-  hipLaunchKernelGGL(k_bin_sort, dim3(nbins, J.T), dim3(BZ_THREADS), 0, s, J.n, nb, W.bintot,
-                     W.binstart, W.st_keys, ro, W.big_list, W.big_count);
+  hipLaunchKernelGGL(k_bin_group, dim3(nbins, J.T), dim3(BZ_THREADS), 0, s, J.n, nb, W.bintot, W.binstart,
+                     W.st_keys, W.st_ids, go, W.big_list, W.big_count);
   prof_end(GEEK_PROF_BZ_SORT, s);
   hipLaunchKernelGGL(k_big_sort, dim3(256), dim3(BIG_THREADS), 0, s, J.n, nb, J.key_words, W.bintot,
                      W.binstart, W.st_keys, W.st_ids, W.alt_keys, W.alt_ids, W.big_list, W.big_count);
   hipLaunchKernelGGL(k_big_runs, dim3(256), dim3(BIG_THREADS), 0, s, J.n, nb, W.bintot, W.binstart,
-                     W.st_keys, ro, W.big_list, W.big_count);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, W.run_len, W.ctot);
+                     W.st_keys, W.st_ids, go, W.big_list, W.big_count);
+  hipLaunchKernelGGL(k_bz_reduce, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, go, W.ctot);
   hipLaunchKernelGGL(k_scan_chunks, dim3(J.T), dim3(1024), 0, s, nch, W.ctot, J.nbuckets);
-  hipLaunchKernelGGL(k_scan_apply, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, W.ctot, W.run_len,
-                     W.hoff, J.offsets, J.nbuckets);
-  hipLaunchKernelGGL(k_emit, dim3(ceil_div((int64_t)J.T * J.n, 256)), dim3(256), 0, s, J.n, J.T,
-                     W.st_ids, W.rec_head, W.run_len, W.hoff, W.run_pos, J.members, J.bucket_of);
+  hipLaunchKernelGGL(k_bz_apply, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, go, W.ctot, W.hs,
+                     J.members, J.offsets, J.bucket_of, J.nbuckets);
+  hipLaunchKernelGGL(k_bz_members, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, go, W.hs, J.members,
+                     J.bucket_of);
   prof_end(GEEK_PROF_BUCKETIZE, s);
   GEEK_LAUNCH_CHECK();
   return GEEK_OK;

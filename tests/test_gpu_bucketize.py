@@ -51,6 +51,9 @@ def test_bucketize_dense_keys_from_hash():
     (50000, 2, 4, 40, 1),    # many small buckets
     (1, 2, 1, 5, 2),
     (4097, 1, 3, 1000, 3),
+    (30000, 2, 1, 3000, 5),  # groups of about 10: member-list ranks
+    (30000, 2, 1, 300, 6),   # groups of about 100: in-LDS (slot, id) sort
+    (300000, 1, 2, 600, 7),  # mostly buckets of one, some pairs; 256 bins
 ])
 def test_bucketize_synthetic(n, T, kw, alpha, seed):
     api = gpu_api()
