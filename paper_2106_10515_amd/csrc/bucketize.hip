@@ -182,23 +182,24 @@ GEEK_D void group_record(const GroupOut& go, int t, int64_t n, uint32_t id, uint
   atomicOr(&go.flags[(int64_t)t * go.flag_words + (id >> 5)], 1u << (id & 31));
 }
 
-// One workgroup per (bin, table): records -> LDS; an LDS hash table keyed by
-// the exact key gives each record its group (slot) and the group sizes.
+// One workgroup per (bin, table).  Each thread keeps its records (key, id,
+// slot) in registers; an LDS hash table keyed by the exact key gives each
+// record its group (slot) and the group sizes; keys of slot owners are
+// re-read from the bin's staging copy (cache-resident) for comparisons.
 // Ranks inside groups of at most BZ_SMALL come from a walk of the group's
 // member list; bins with a larger group sort (slot, id) pairs in LDS
 // (bitonic) and rank by position.  A slot word holds the group size in its
-// high 16 bits and, in its low 16 bits, first the representative record + 1
+// high 16 bits and, in its low 16 bits, first the owning record + 1
 // (0: empty), then the member-list head + 1, then the first sorted position
-// + 1.
+// + 1.  LDS stays small enough for four workgroups per CU.
+constexpr int BZ_RPT = BZ_CAP / BZ_THREADS;  // records per thread
 __global__ __launch_bounds__(BZ_THREADS) void k_bin_group(int64_t n, int nb, const uint32_t* bintot,
                                                           const uint32_t* binstart, const uint4* st_keys,
                                                           const uint32_t* st_ids, GroupOut go,
                                                           uint32_t* big_list, uint32_t* big_count) {
-  __shared__ uint4 sk[BZ_CAP];  // keys; reused as the (slot, id) sort array
-  __shared__ uint32_t sid[BZ_CAP];
   __shared__ uint32_t hw[BZ_HT];
-  __shared__ uint16_t grp[BZ_CAP];
   __shared__ int16_t nxt[BZ_CAP];
+  __shared__ unsigned long long sc[BZ_CAP];  // (slot, id) sort array
   __shared__ uint32_t smax;
   const int t = blockIdx.y, bin = blockIdx.x;
   const int nbins = 1 << nb;
@@ -211,16 +212,27 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bin_group(int64_t n, int nb, con
   const uint32_t s0 = binstart[(int64_t)t * nbins + bin];
   const uint4* gk = st_keys + (int64_t)t * n + s0;
   const uint32_t* gi = st_ids + (int64_t)t * n + s0;
-  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
-    sk[q] = gk[q];
-    sid[q] = gi[q];
+  uint4 kr[BZ_RPT];
+  uint32_t idr[BZ_RPT];
+  int slot[BZ_RPT];
+#pragma unroll
+  for (int u = 0; u < BZ_RPT; ++u) {
+    const int q = threadIdx.x + u * BZ_THREADS;
+    if (q < (int)size) {
+      kr[u] = gk[q];
+      idr[u] = gi[q];
+    }
   }
   for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] = 0u;
   if (threadIdx.x == 0) smax = 0;
   __syncthreads();
-  // insert with linear probing; a claimed slot's key is already in LDS
-  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
-    const uint4 k = sk[q];
+  // insert with linear probing; an owned slot's key is already in memory
+#pragma unroll
+  for (int u = 0; u < BZ_RPT; ++u) {
+    const int q = threadIdx.x + u * BZ_THREADS;
+    slot[u] = 0;
+    if (q >= (int)size) continue;
+    const uint4 k = kr[u];
     const uint32_t w[4] = {k.x, k.y, k.z, k.w};
     int h = (int)(key_hash(w, 4) & (BZ_HT - 1));
     for (;;) {
@@ -230,18 +242,21 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bin_group(int64_t n, int nb, con
         if (prev == 0u) break;
         cur = prev & 0xFFFFu;
       }
-      if (key_eq(sk[cur - 1], k)) break;
+      if (key_eq(gk[cur - 1], k)) break;
       h = (h + 1) & (BZ_HT - 1);
     }
-    grp[q] = (uint16_t)h;
+    slot[u] = h;
     atomicAdd(&hw[h], 0x10000u);
   }
   __syncthreads();
   for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] &= 0xFFFF0000u;
   __syncthreads();
   // member lists (order arbitrary)
-  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
-    const int g = grp[q];
+#pragma unroll
+  for (int u = 0; u < BZ_RPT; ++u) {
+    const int q = threadIdx.x + u * BZ_THREADS;
+    if (q >= (int)size) continue;
+    const int g = slot[u];
     uint32_t old = hw[g];
     for (;;) {
       const uint32_t prev = atomicCAS(&hw[g], old, (old & 0xFFFF0000u) | (uint32_t)(q + 1));
@@ -249,20 +264,23 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bin_group(int64_t n, int nb, con
       old = prev;
     }
     nxt[q] = (int16_t)((int)(old & 0xFFFFu) - 1);
-    atomicMax(&smax, old >> 16);
+    if ((old >> 16) > 1u) atomicMax(&smax, old >> 16);
   }
   __syncthreads();
   const uint32_t big = smax;
   if (big <= 1) return;  // all keys distinct
   if (big <= BZ_SMALL) {
-    for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
-      const uint32_t v = hw[grp[q]];
+#pragma unroll
+    for (int u = 0; u < BZ_RPT; ++u) {
+      const int q = threadIdx.x + u * BZ_THREADS;
+      if (q >= (int)size) continue;
+      const uint32_t v = hw[slot[u]];
       const uint32_t c = v >> 16;
       if (c == 1) continue;
-      const uint32_t me = sid[q];
+      const uint32_t me = idr[u];
       uint32_t r = 0, head = me;
       for (int e = (int)(v & 0xFFFFu) - 1; e >= 0; e = nxt[e]) {
-        const uint32_t o = sid[e];
+        const uint32_t o = gi[e];
         r += o < me;
         head = min(head, o);
       }
@@ -271,11 +289,13 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bin_group(int64_t n, int nb, con
     return;
   }
   // a larger group: sort (slot, id) pairs, rank by position
-  unsigned long long* sc = reinterpret_cast<unsigned long long*>(sk);
   int P2 = 1;
   while (P2 < (int)size) P2 <<= 1;
-  for (int q = threadIdx.x; q < P2; q += BZ_THREADS)
-    sc[q] = q < (int)size ? ((unsigned long long)grp[q] << 32) | sid[q] : ~0ull;
+#pragma unroll
+  for (int u = 0; u < BZ_RPT; ++u) {
+    const int q = threadIdx.x + u * BZ_THREADS;
+    if (q < P2) sc[q] = q < (int)size ? ((unsigned long long)slot[u] << 32) | idr[u] : ~0ull;
+  }
   for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] |= 0xFFFFu;
   __syncthreads();
   for (int kk = 2; kk <= P2; kk <<= 1) {

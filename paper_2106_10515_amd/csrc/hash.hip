@@ -25,6 +25,7 @@ constexpr int H_THREADS = 256;
 constexpr int H_BN = 128;   // points per block
 constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks)
 constexpr int H_FIXCAP = 4096;  // fix-up list entries per round
+constexpr int H_CS = H_BC + 1;  // LDS stride of a point's codes (odd: conflict-free stores)
 
 // Exclusive scan over a 256-thread block; *total = block sum.
 __device__ uint32_t block_exscan256(uint32_t v, uint32_t* total, uint32_t* sh) {
@@ -60,8 +61,14 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
   constexpr int S = DP / 2;
   constexpr int STR = DP + 4;
   __shared__ __attribute__((aligned(16))) float lds_a[H_BC * STR];
-  __shared__ float lds_b[H_BC], lds_an[H_BC];
-  __shared__ int lds_code[H_BN * H_BC];
+  // per row of the chunk: b, and the two factors of the certification
+  // radius tau = t1 * |x| + t0
+  __shared__ __attribute__((aligned(16))) float lds_b[H_BC];
+  __shared__ __attribute__((aligned(16))) float lds_t1[H_BC];
+  __shared__ __attribute__((aligned(16))) float lds_t0[H_BC];
+  // codes of a point are H_CS ints apart: the epilogue's stores (one row,
+  // 32 points per instruction) then fall into distinct banks
+  __shared__ int lds_code[H_BN * H_CS];
   __shared__ uint32_t lds_flag[H_BN * H_BC / 32];  // one bit per (point, row)
   __shared__ uint16_t lds_fix[H_FIXCAP];            // compacted (point << 6 | row)
   __shared__ uint32_t lds_scan[17];
@@ -78,6 +85,8 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
   const bool vec4 = ((d & 3) == 0) && ((ldx & 3) == 0);
   const float inv_w = 1.0f / w;
   const int B = 128 / m < 32 ? 128 / m : 32;
+  const uint32_t code_off = B == 32 ? 0x80000000u : (1u << (B - 1));
+  const uint32_t code_mask = B == 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
 
   // ---- x fragments (K index of step s for half h: h*DP/2 + s), exact |x|^2
   float xb[S];
@@ -117,27 +126,39 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
                          (DP + 3) * 0x1p-53) * 1.01;
   const float coef = (float)coef_d;
 
+  const float tscale = coef * inv_w;
+  const bool a_vec = ((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+
   if (tid == 0) lds_nfix = 0;
   for (int tb = 0; tb < L; tb += tpc) {
     const int ntab = (L - tb) < tpc ? (L - tb) : tpc;
-    const int p0 = tb * m;
     const int rows_used = ntab * m;
+    const int p0 = tb * m;
+    // A tile of the chunk (rows p0.., zero-padded to H_BC x DP) and the
+    // per-row b and certification factors
     __syncthreads();
     for (int q = tid; q < H_BC * (DP / 4); q += H_THREADS) {
       const int r = q / (DP / 4), c4 = (q % (DP / 4)) * 4;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (r < rows_used) {
         const float* ar = A + (int64_t)(p0 + r) * d;
-        v.x = c4 < d ? ar[c4] : 0.f;
-        v.y = c4 + 1 < d ? ar[c4 + 1] : 0.f;
-        v.z = c4 + 2 < d ? ar[c4 + 2] : 0.f;
-        v.w = c4 + 3 < d ? ar[c4 + 3] : 0.f;
+        if (a_vec && c4 + 3 < d) {
+          v = *reinterpret_cast<const float4*>(ar + c4);
+        } else {
+          v.x = c4 < d ? ar[c4] : 0.f;
+          v.y = c4 + 1 < d ? ar[c4 + 1] : 0.f;
+          v.z = c4 + 2 < d ? ar[c4 + 2] : 0.f;
+          v.w = c4 + 3 < d ? ar[c4 + 3] : 0.f;
+        }
       }
       *reinterpret_cast<float4*>(lds_a + r * STR + c4) = v;
     }
     if (tid < H_BC) {
-      lds_b[tid] = tid < rows_used ? bvec[p0 + tid] : 0.f;
-      lds_an[tid] = tid < rows_used ? anorm[p0 + tid] : 0.f;
+      const bool live = tid < rows_used;
+      const float bv = live ? bvec[p0 + tid] : 0.f;
+      lds_b[tid] = bv;
+      lds_t1[tid] = live ? tscale * anorm[p0 + tid] : 0.f;
+      lds_t0[tid] = live ? __builtin_fmaf(tscale, fabsf(bv), 0x1p-22f) : 0.f;
     }
     lds_flag[tid] = 0u;  // H_THREADS == H_BN * H_BC / 32 words
     __syncthreads();
@@ -145,35 +166,73 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
     f32x16 acc0 = {}, acc1 = {};
     const float* a0p = lds_a + p * STR + h * S;
     const float* a1p = a0p + 32 * STR;
+    // A fragments: four K steps per 16-byte LDS read (rows STR = DP + 4
+    // floats apart, so eight consecutive lanes cover all banks)
     if (rows_used > 32) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0p[s], xb[s], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1p[s], xb[s], acc1, 0, 0, 0);
+      for (int s = 0; s < S; s += 4) {
+        const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
+        const float4 a1 = *reinterpret_cast<const float4*>(a1p + s);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, xb[s], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, xb[s + 1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, xb[s + 2], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, xb[s + 3], acc1, 0, 0, 0);
       }
     } else {  // the second 32-row block holds no projection of this chunk
 #pragma unroll
-      for (int s = 0; s < S; ++s) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0p[s], xb[s], acc0, 0, 0, 0);
+      for (int s = 0; s < S; s += 4) {
+        const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], acc0, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], acc0, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], acc0, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], acc0, 0, 0, 0);
+      }
     }
     const int pl = wv * 32 + p;  // point within block
+    // Register r of half hf holds row hf*32 + (r/4)*8 + h*4 + r%4; rows past
+    // rows_used (zero A rows) are stored but never flagged or read.
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
+      if (half == 1 && rows_used <= 32) break;
       const f32x16& acc = half ? acc1 : acc0;
+      uint32_t bad = 0u, live = 0xFFFFFFFFu;
+      if (half * 32 + 32 > rows_used) {  // the chunk's last rows are padding
+        live = 0u;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = half * 32 + (r >> 2) * 8 + h * 4 + (r & 3);
-        if (row < rows_used) {
-          const float v = acc[r] + lds_b[row];
+        for (int g4 = 0; g4 < 4; ++g4)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            live |= (half * 32 + g4 * 8 + h * 4 + e < rows_used ? 1u : 0u) << (g4 * 8 + h * 4 + e);
+      }
+#pragma unroll
+      for (int g4 = 0; g4 < 4; ++g4) {
+        const int rbase = half * 32 + g4 * 8 + h * 4;
+        const float4 bb = *reinterpret_cast<const float4*>(lds_b + rbase);
+        const float4 t1 = *reinterpret_cast<const float4*>(lds_t1 + rbase);
+        const float4 t0 = *reinterpret_cast<const float4*>(lds_t0 + rbase);
+        const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+        const float t1v[4] = {t1.x, t1.y, t1.z, t1.w};
+        const float t0v[4] = {t0.x, t0.y, t0.z, t0.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = g4 * 4 + e;
+          const float v = acc[r] + bv[e];
           const float q = v * inv_w;
           const float fq = floorf(q);
           const float frac = q - fq;
-          const float tau = coef * __builtin_fmaf(lds_an[row], xn, fabsf(lds_b[row])) * inv_w +
-                            0x1p-22f;
+          const float tau = __builtin_fmaf(t1v[e], xn, t0v[e]);
           const bool ok = frac > tau && frac < 1.0f - tau && fabsf(q) < 0x1p22f;
-          lds_code[pl * H_BC + row] = (int)fq;
-          if (!ok && valid) atomicOr(&lds_flag[pl * 2 + (row >> 5)], 1u << (row & 31));
+          lds_code[pl * H_CS + rbase + e] = (int)fq;
+          const int bitpos = g4 * 8 + h * 4 + e;
+          bad |= (ok ? 0u : 1u) << bitpos;
         }
       }
+      bad &= live;
+      if (bad && valid) atomicOr(&lds_flag[pl * 2 + half], bad);
     }
     __syncthreads();
     // ---- float64 recomputation of the uncertified pairs, reference order:
@@ -216,7 +275,7 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
           const double fl = floor(qd);
           const bool fits = fl >= -2147483648.0 && fl <= 2147483647.0;
           if (!fits) set_status(st, GEEK_ERR_RANGE);
-          lds_code[pp * H_BC + row] = fits ? (int)fl : 0;
+          lds_code[pp * H_CS + row] = fits ? (int)fl : 0;
         }
         __syncthreads();
       }
@@ -228,18 +287,23 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
     for (int q = tid; keys && q < ntab * H_BN; q += H_THREADS) {
       const int t = q / H_BN, pp = q % H_BN;
       if (pp >= np) continue;
-      uint32_t kw[4] = {0u, 0u, 0u, 0u};
+      // code + 2^(B-1) in B bits, code j at bit j*B of a 128-bit key
+      uint64_t lo = 0, hi = 0;
       bool inr = true;
+      const int* cp = lds_code + pp * H_CS + t * m;
       for (int j = 0; j < m; ++j) {
-        const int c = lds_code[pp * H_BC + t * m + j];
-        const int64_t off = (int64_t)c + (B == 32 ? 0x80000000ll : (1ll << (B - 1)));
-        inr = inr && off >= 0 && off < (B == 32 ? 0x100000000ll : (1ll << B));
-        const uint64_t f = (uint64_t)off & (B == 32 ? 0xFFFFFFFFull : ((1ull << B) - 1));
+        const uint32_t u = (uint32_t)cp[j] + code_off;
+        inr = inr && (B == 32 || u < (1u << B));
+        const uint64_t f = (uint64_t)(u & code_mask);
         const int bit = j * B;
-        const int wi = bit >> 5, sh = bit & 31;
-        kw[wi] |= (uint32_t)(f << sh);
-        if (sh + B > 32 && wi < 3) kw[wi + 1] |= (uint32_t)(f >> (32 - sh));
+        if (bit < 64) {
+          lo |= f << bit;
+          if (bit + B > 64) hi |= f >> (64 - bit);
+        } else {
+          hi |= f << (bit - 64);
+        }
       }
+      const uint32_t kw[4] = {(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
       if (!inr) set_status(st, GEEK_ERR_RANGE);
       const int64_t ii = i0 + pp;
       *reinterpret_cast<uint4*>(keys + ((int64_t)(tb + t) * n + ii) * 4) =
@@ -248,7 +312,7 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
     if (codes_out) {
       for (int q = tid; q < H_BN * rows_used; q += H_THREADS) {
         const int pp = q / rows_used, row = q % rows_used;
-        if (pp < np) codes_out[(i0 + pp) * P + p0 + row] = lds_code[pp * H_BC + row];
+        if (pp < np) codes_out[(i0 + pp) * P + p0 + row] = lds_code[pp * H_CS + row];
       }
     }
   }
