@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--clusters", type=int, default=10_000)
-    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--cpu-rows", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
     ap.add_argument("--copy-calibration", action="store_true",
