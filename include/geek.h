@@ -250,6 +250,11 @@ typedef struct geek_assign_job {
   int64_t n_members;        /* host: seed_offsets[k], the total number of seed
                                members (required by SIG and HETERO, which
                                size their mode computation by it) */
+  unsigned long long* t_done; /* optional out [1]: device wall-clock ticks
+                               (geek_wallclock_hz per second) from the start
+                               of the call to the moment this job's outputs
+                               were complete (batched calls), or the absolute
+                               tick count at that moment (njobs = 1) */
 } geek_assign_job;
 
 /* ---- entry points -------------------------------------------------------- */
@@ -267,6 +272,15 @@ int32_t geek_bucketize(const geek_bucketize_job* jobs, int32_t njobs, void* ws,
                        size_t ws_bytes, int32_t* d_status, void* stream);
 int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                         int32_t* d_status, void* stream);
+/* geek_assign with njobs > 1 and every job GEEK_METRIC_EUCLID in one
+ * precision (the many-job workload of the benchmark spec, Section 4's batched
+ * clustering runs): the jobs' centroids are prepared one job after another,
+ * then one persistent matrix-core launch per padded dimension (32, 64, 128,
+ * 256) scans the tiles of all jobs of that dimension in call order, then the
+ * float64 checks run per job.  Each job's outputs are bit-identical to a
+ * call with that job alone.  The workspace is the sum of the jobs' own
+ * workspaces (geek_workspace_size reports it).  Any other mix of jobs runs
+ * one job after another in a shared workspace. */
 int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                     int32_t* d_status, void* stream);
 
@@ -290,6 +304,9 @@ int32_t geek_profile_read(int32_t id, double* total_ms, int64_t* launches);
 
 /* Static description of a status code. */
 const char* geek_status_string(int32_t status);
+/* Ticks per second of the device wall clock used by t_done (device 0 of
+ * the calling thread's current device); 0 if unknown. */
+int64_t geek_wallclock_hz(void);
 /* Library version string, e.g. "geek 0.1.0 gfx950". */
 const char* geek_version(void);
 /* The last HIP error message seen by this thread (empty if none). */

@@ -81,13 +81,13 @@ class AssignJob(C.Structure):
         ("sig", P), ("F", C.c_int32), ("n_cat", C.c_int32), ("cat", P), ("gamma", C.c_double),
         ("seed_offsets", P), ("seed_members", P), ("assign", P), ("centroids", P),
         ("modes", P), ("dist", P), ("sse", P), ("radius", P), ("counters", P),
-        ("n_members", C.c_int64),
+        ("n_members", C.c_int64), ("t_done", P),
     ]
 
 
 EXPORTS = ("geek_workspace_size", "geek_hash", "geek_bucketize", "geek_silk_seeds",
            "geek_assign", "geek_status_string", "geek_version", "geek_last_hip_error",
-           "geek_profile", "geek_profile_read")
+           "geek_profile", "geek_profile_read", "geek_wallclock_hz")
 
 GEEK_PROF_E2LSH, GEEK_PROF_BUCKETIZE, GEEK_PROF_ASSIGN_SCAN, GEEK_PROF_ASSIGN = 0, 1, 2, 3
 GEEK_PROF_MINHASH, GEEK_PROF_SILK, GEEK_PROF_BZ_SORT = 4, 5, 6
@@ -117,6 +117,7 @@ def _load():
     lib.geek_profile.restype = C.c_int32
     lib.geek_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.geek_profile_read.restype = C.c_int32
+    lib.geek_wallclock_hz.restype = C.c_int64
     _LIB = lib
     return lib
 
@@ -142,6 +143,11 @@ def geek_profile_read(kernel_id: int):
     if rc != GEEK_OK:
         raise GeekError(rc, "geek_profile_read")
     return float(ms.value), int(cnt.value)
+
+
+def geek_wallclock_hz() -> int:
+    """Ticks per second of the device wall clock (t_done units)."""
+    return int(_load().geek_wallclock_hz())
 
 
 def workspace_size(op: int, jobs) -> int:

@@ -192,6 +192,45 @@ def assign_euclid(X, seed_offsets, seed_members, k, precision=L.GEEK_PREC_FP32,
     return out
 
 
+def assign_euclid_batch(problems, precision=L.GEEK_PREC_BF16, want_dist=True, want_radius=True,
+                        status=None, check=True):
+    """One geek_assign call over many Euclidean jobs.  ``problems`` is a list
+    of ``(X, seed_offsets, seed_members, k)``.  Returns ``(outs, t_done)``:
+    one output dict per job (as ``assign_euclid``) and an int64 tensor of the
+    jobs' completion times in device wall-clock ticks since the call began
+    (``wallclock_hz()`` ticks per second)."""
+    dev = _dev(problems[0][0])
+    outs, jobs = [], []
+    t_done = torch.zeros((len(problems),), dtype=torch.int64, device=dev)
+    for idx, (X, so, sm, k) in enumerate(problems):
+        n, d = X.shape
+        out = dict(
+            assign=torch.empty((n,), dtype=torch.int32, device=dev),
+            centroids=torch.empty((k, d), dtype=torch.float64, device=dev),
+            dist=torch.empty((n,), dtype=torch.float64, device=dev) if want_dist else None,
+            sse=torch.empty((1,), dtype=torch.float64, device=dev),
+            radius=torch.empty((k,), dtype=torch.float64, device=dev) if want_radius else None,
+            counters=torch.zeros((4,), dtype=torch.int64, device=dev),
+        )
+        outs.append(out)
+        jobs.append(L.AssignJob(metric=L.GEEK_METRIC_EUCLID, precision=precision, n=n, d=d, k=k, X=_p(X),
+                                ldx=X.stride(0), n_members=sm.numel(), seed_offsets=_p(so),
+                                seed_members=_p(sm), assign=_p(out["assign"]),
+                                centroids=_p(out["centroids"]), dist=_p(out["dist"]), sse=_p(out["sse"]),
+                                radius=_p(out["radius"]), counters=_p(out["counters"]),
+                                t_done=t_done.data_ptr() + 8 * idx))
+    status = new_status(dev) if status is None else status
+    _run(L.GEEK_OP_ASSIGN, L.geek_assign, jobs, dev, status)
+    if check:
+        check_status(status, "geek_assign (batch)")
+    return outs, t_done
+
+
+def wallclock_hz() -> int:
+    """Ticks per second of the device clock behind ``t_done``."""
+    return L.geek_wallclock_hz()
+
+
 def assign_sig(sig, seed_offsets, seed_members, k, want_dist=True, status=None, check=True):
     """Modes of the seeds and assignment of signature rows by match count."""
     dev = _dev(sig)

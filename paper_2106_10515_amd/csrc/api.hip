@@ -22,6 +22,10 @@ size_t assign_euclid_ws(const geek_assign_job& J);
 int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st,
                       hipStream_t s);
 size_t assign_sig_ws(const geek_assign_job& J);
+bool assign_batchable(const geek_assign_job* jobs, int njobs);
+size_t assign_batch_ws(const geek_assign_job* jobs, int njobs);
+int32_t assign_euclid_batch(const geek_assign_job* jobs, int njobs, void* ws, size_t ws_bytes, int32_t* st,
+                            hipStream_t s);
 int32_t assign_sig(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
 
 static thread_local std::string g_last_err;
@@ -145,6 +149,13 @@ const char* geek_status_string(int32_t s) {
 
 const char* geek_version(void) { return "geek 0.1.0 gfx950"; }
 
+int64_t geek_wallclock_hz(void) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+  return (int64_t)khz * 1000;
+}
+
 int32_t geek_profile(int32_t enable) {
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (enable) {
@@ -214,6 +225,8 @@ int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t*
     }
     tot = b > tot ? b : tot;  // jobs run one after another and share the workspace
   }
+  if (op == GEEK_OP_ASSIGN && assign_batchable(static_cast<const geek_assign_job*>(jobs), njobs))
+    tot = assign_batch_ws(static_cast<const geek_assign_job*>(jobs), njobs);  // one slice per job
   *bytes = tot;
   return GEEK_OK;
 }
@@ -261,12 +274,17 @@ int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size
 int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                     int32_t* d_status, void* stream) {
   if (!jobs || njobs < 1) return GEEK_ERR_ARG;
-  for (int j = 0; j < njobs; ++j) {
+  for (int j = 0; j < njobs; ++j)
     if (int32_t rc = check_assign(jobs[j])) return rc;
+  if (!ws) return GEEK_ERR_ARG;
+  if (assign_batchable(jobs, njobs)) {
+    if (ws_bytes < assign_batch_ws(jobs, njobs)) return GEEK_ERR_WORKSPACE;
+    return assign_euclid_batch(jobs, njobs, ws, ws_bytes, d_status, (hipStream_t)stream);
+  }
+  for (int j = 0; j < njobs; ++j) {
     const size_t need = jobs[j].metric == GEEK_METRIC_SIG ? assign_sig_ws(jobs[j])
                                                           : assign_euclid_ws(jobs[j]);
     if (ws_bytes < need) return GEEK_ERR_WORKSPACE;
-    if (!ws) return GEEK_ERR_ARG;
   }
   for (int j = 0; j < njobs; ++j) {
     const geek_assign_job& J = jobs[j];

@@ -25,6 +25,9 @@
 // central vector is the per-attribute mode (assign_sig.hip computes modes).
 #include <math.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "common.hpp"
 
 namespace geek {
@@ -257,12 +260,12 @@ GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
 // in flight while the current one is consumed (LDS DMA where rows are at
 // least 64 bytes, else through registers).
 template <class M, int DP, bool HET, int NCB, int NBUF, bool T2>
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan(
+__device__ __forceinline__ void scan_tiles(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n_rows,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
     const typename M::ce* __restrict__ cl, const float* __restrict__ nc, int k_pad,
     const float* __restrict__ cmax_p, const float* __restrict__ scale_p, Het het, int k,
-    int32_t* __restrict__ rec, int32_t* st) {
+    int32_t* __restrict__ rec, int32_t* st, int64_t tile0, int64_t tile_end, int64_t tstep) {
   using CE = typename M::ce;
   constexpr int S = DP / 2 / M::KPER;             // MFMA steps over K
   constexpr int CH = DP * (int)sizeof(CE) / 16;   // 16-byte chunks per centroid row
@@ -355,7 +358,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
           reinterpret_cast<char*>(lds_mode[B]) + w * 64 * 16, 16, 0, 0);                                  \
   } while (0)
 
-  for (int64_t tile = blockIdx.x; tile * BN < count; tile += gridDim.x) {
+  for (int64_t tile = tile0; tile < tile_end && tile * BN < count; tile += tstep) {
     typename M::frag xb[NCB][S];
     float twoeps[NCB];
     int32_t crow[NCB][HET ? MAX_CAT : 1];
@@ -641,6 +644,69 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
 #undef GEEK_LOAD_REGS
 #undef GEEK_STORE_LDS
 #undef GEEK_DMA_STAGE
+
+template <class M, int DP, bool HET, int NCB, int NBUF, bool T2>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan(
+    const float* __restrict__ X, int64_t ldx, int d, int64_t n_rows,
+    const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
+    const typename M::ce* __restrict__ cl, const float* __restrict__ nc, int k_pad,
+    const float* __restrict__ cmax_p, const float* __restrict__ scale_p, Het het, int k,
+    int32_t* __restrict__ rec, int32_t* st) {
+  scan_tiles<M, DP, HET, NCB, NBUF, T2>(X, ldx, d, n_rows, rows, rows_count, cl, nc, k_pad, cmax_p, scale_p, het,
+                                        k, rec, st, blockIdx.x, INT64_MAX, gridDim.x);
+}
+
+// One job of a batched first pass (Euclidean rows, one precision, one DP).
+struct ScanJob {
+  const float* X;
+  int64_t ldx;
+  int64_t n;
+  const void* cl;
+  const float* nc;
+  const float* cmax;
+  const float* scale;
+  int32_t* rec;
+  int64_t tile_begin;  // first global tile of this job
+  int d, k, k_pad, pad0;
+};
+constexpr int SCANJOB_CHUNK = 32;  // table entries written per launch
+struct ScanJobChunk {
+  int count;
+  ScanJob jobs[SCANJOB_CHUNK];
+};
+__global__ void k_put_jobs(ScanJobChunk c, ScanJob* dst) {
+  const int i = threadIdx.x;
+  if (i < c.count) dst[i] = c.jobs[i];
+}
+
+// Persistent first pass over the tiles of many jobs: global tile gt belongs
+// to the last job whose tile_begin <= gt; every tile runs exactly the
+// single-job code, so each job's records equal those of its own launch.
+template <class M, int DP, int NCB, int NBUF, bool T2>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_batch(const ScanJob* __restrict__ jobs, int njobs,
+                                                             int64_t total_tiles, int32_t* st) {
+  const Het none{nullptr, nullptr, nullptr, 0, 0.f, 0.0};
+  for (int64_t gt = blockIdx.x; gt < total_tiles; gt += gridDim.x) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].tile_begin <= gt) lo = mid;
+      else hi = mid - 1;
+    }
+    const ScanJob J = jobs[lo];
+    const int64_t tile = gt - J.tile_begin;
+    scan_tiles<M, DP, false, NCB, NBUF, T2>(J.X, J.ldx, J.d, J.n, nullptr, nullptr,
+                                            static_cast<const typename M::ce*>(J.cl), J.nc, J.k_pad, J.cmax,
+                                            J.scale, none, J.k, J.rec, st, tile, tile + 1, 1);
+  }
+}
+
+__global__ void k_clock_since(const unsigned long long* t0, unsigned long long* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = wall_clock64() - *t0;
+}
+__global__ void k_clock_now(unsigned long long* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = wall_clock64();
+}
 
 // ---------------------------------------------------------------- float64 checks
 GEEK_D double d64(const float* __restrict__ xr, const double* __restrict__ cr, int d) {
@@ -956,26 +1022,32 @@ static void scan_any(bool het_on, int DP, int grid, hipStream_t s, const geek_as
     launch_scan<M, false>(DP, grid, s, J, n_rows, rows, rows_count, cl, W, k_pad, het, st);
 }
 
-int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st,
-                      hipStream_t s) {
+// Per-job state between the three phases of an assignment.
+struct AssignCtx {
   AssignWs W;
-  const size_t need = carve_assign(J, ws, &W);
-  if (ws_bytes < need) return GEEK_ERR_WORKSPACE;
-  const int DP = pick_dp(J.d);
-  const int k_pad = (J.k + SCAN_BC - 1) / SCAN_BC * SCAN_BC;
-  double* dist = J.dist ? J.dist : W.dist;
-  const int nb_rows = ceil_div(J.n, 256);
-  const bool het_on = J.metric == GEEK_METRIC_HETERO;
+  int DP = 0;
+  int k_pad = 0;
+  double* dist = nullptr;
+  bool het_on = false;
   Het het{nullptr, nullptr, nullptr, 0, 0.f, 0.0};
-  if (het_on) het = Het{J.cat, J.modes, W.mode16, J.n_cat, (float)J.gamma, J.gamma};
+};
 
-  prof_begin(GEEK_PROF_ASSIGN, s);
+// Centroids (and modes), matrix-core copies, |c|^2, bounds and scale.
+static int32_t assign_prep(const geek_assign_job& J, void* ws, AssignCtx& C, int32_t* st, hipStream_t s) {
+  carve_assign(J, ws, &C.W);
+  AssignWs& W = C.W;
+  C.DP = pick_dp(J.d);
+  C.k_pad = (J.k + SCAN_BC - 1) / SCAN_BC * SCAN_BC;
+  C.dist = J.dist ? J.dist : W.dist;
+  C.het_on = J.metric == GEEK_METRIC_HETERO;
+  if (C.het_on) C.het = Het{J.cat, J.modes, W.mode16, J.n_cat, (float)J.gamma, J.gamma};
+  const int DP = C.DP, k_pad = C.k_pad;
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, W.counts, 4, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(W.ctr), 8, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(W.cmax), 4, 0u);
   hipLaunchKernelGGL(k_centroids, dim3(ceil_div((int64_t)J.k * J.d, 256)), dim3(256), 0, s, J.X,
                      J.ldx, J.n, J.d, J.seed_offsets, J.seed_members, J.k, J.centroids, st);
-  if (het_on) {
+  if (C.het_on) {
     if (int32_t rc = modes_compute(reinterpret_cast<const uint32_t*>(J.cat), J.n_cat, J.n_cat, J.n,
                                    J.seed_offsets, J.seed_members, J.k, J.n_members, J.modes, W.modes_ws, st, s))
       return rc;
@@ -995,34 +1067,174 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
                        k_pad, DP, static_cast<uint8_t*>(W.cllow), nullptr, nullptr, W.cmax + 3);
   }
   GEEK_LAUNCH_CHECK();
+  return GEEK_OK;
+}
 
-  unsigned long long* ctr = W.ctr;
-  if (J.precision == GEEK_PREC_BF16 || J.precision == GEEK_PREC_FP8) {
-    const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeBF16>(het_on));
-    prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
+static bool low_precision(const geek_assign_job& J) {
+  return J.precision == GEEK_PREC_BF16 || J.precision == GEEK_PREC_FP8;
+}
+
+// The first pass of one job: every row gets a candidate record.
+static void assign_first_pass(const geek_assign_job& J, AssignCtx& C, int32_t* st, hipStream_t s) {
+  if (low_precision(J)) {
+    const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeBF16>(C.het_on));
     if (J.precision == GEEK_PREC_BF16)
-      scan_any<ModeBF16>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cllow, W, k_pad, het, st);
+      scan_any<ModeBF16>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cllow, C.W, C.k_pad, C.het, st);
     else
-      scan_any<ModeFP8>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cllow, W, k_pad, het, st);
-    prof_end(GEEK_PROF_ASSIGN_SCAN, s);
-    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, J.n,
-                       nullptr, nullptr, W.rec, J.assign, dist, W.esc, W.counts + 0, ctr, 0);
-    // rows whose low-precision window overflowed: float32 rescan of those rows
-    scan_any<ModeF32>(het_on, DP, 1024, s, J, 0, W.esc, W.counts + 0, W.cl32, W, k_pad, het, st);
-    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, (int64_t)0,
-                       W.esc, W.counts + 0, W.rec, J.assign, dist, W.fb, W.counts + 1, ctr, 1);
+      scan_any<ModeFP8>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cllow, C.W, C.k_pad, C.het, st);
   } else {
-    const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeF32>(het_on));
-    prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
-    scan_any<ModeF32>(het_on, DP, grid_all, s, J, J.n, nullptr, nullptr, W.cl32, W, k_pad, het, st);
-    prof_end(GEEK_PROF_ASSIGN_SCAN, s);
-    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, J.n,
-                       nullptr, nullptr, W.rec, J.assign, dist, W.fb, W.counts + 1, ctr, 0);
+    const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeF32>(C.het_on));
+    scan_any<ModeF32>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cl32, C.W, C.k_pad, C.het, st);
   }
-  hipLaunchKernelGGL(k_fallback64, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, het, W.fb,
-                     W.counts + 1, J.assign, dist, ctr);
-  sse_and_radius(dist, J.assign, J.n, J.k, J.sse, J.radius, het_on ? 0 : 1, W.sse_blk, s);
+}
+
+// Float64 checks, rescans and fallbacks, SSE, radius, counters.
+static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, hipStream_t s,
+                          const unsigned long long* t0) {
+  AssignWs& W = C.W;
+  unsigned long long* ctr = W.ctr;
+  const int nb_rows = ceil_div(J.n, 256);
+  if (low_precision(J)) {
+    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
+                       nullptr, nullptr, W.rec, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
+    // rows with several low-precision candidates: float32 rescan of those rows
+    scan_any<ModeF32>(C.het_on, C.DP, 1024, s, J, 0, W.esc, W.counts + 0, W.cl32, W, C.k_pad, C.het, st);
+    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het,
+                       (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 1);
+  } else {
+    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
+                       nullptr, nullptr, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 0);
+  }
+  hipLaunchKernelGGL(k_fallback64, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, W.fb,
+                     W.counts + 1, J.assign, C.dist, ctr);
+  sse_and_radius(C.dist, J.assign, J.n, J.k, J.sse, J.radius, C.het_on ? 0 : 1, W.sse_blk, s);
   if (J.counters) hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, ctr, J.counters, 4);
+  if (J.t_done) {
+    if (t0) hipLaunchKernelGGL(k_clock_since, dim3(1), dim3(64), 0, s, t0, J.t_done);
+    else hipLaunchKernelGGL(k_clock_now, dim3(1), dim3(64), 0, s, J.t_done);
+  }
+}
+
+int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st,
+                      hipStream_t s) {
+  AssignCtx C;
+  if (ws_bytes < carve_assign(J, ws, &C.W)) return GEEK_ERR_WORKSPACE;
+  prof_begin(GEEK_PROF_ASSIGN, s);
+  if (int32_t rc = assign_prep(J, ws, C, st, s)) return rc;
+  prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
+  assign_first_pass(J, C, st, s);
+  prof_end(GEEK_PROF_ASSIGN_SCAN, s);
+  assign_finish(J, C, st, s, nullptr);
+  prof_end(GEEK_PROF_ASSIGN, s);
+  GEEK_LAUNCH_CHECK();
+  return GEEK_OK;
+}
+
+// ---------------------------------------------------------------- batches
+// Jobs of one call that can share persistent first-pass launches: Euclidean,
+// all in the same precision.  Each job gets its own workspace slice.
+bool assign_batchable(const geek_assign_job* jobs, int njobs) {
+  if (njobs < 2) return false;
+  for (int j = 0; j < njobs; ++j)
+    if (jobs[j].metric != GEEK_METRIC_EUCLID || jobs[j].precision != jobs[0].precision) return false;
+  return true;
+}
+
+static size_t slice_bytes(const geek_assign_job& J) {
+  AssignWs W;
+  return (carve_assign(J, nullptr, &W) + 255) / 256 * 256;
+}
+
+size_t assign_batch_ws(const geek_assign_job* jobs, int njobs) {
+  size_t b = 0;
+  for (int j = 0; j < njobs; ++j) b += slice_bytes(jobs[j]);
+  return b + (size_t)njobs * sizeof(ScanJob) + 512;
+}
+
+template <class M>
+static void launch_scan_batch(int DP, const ScanJob* table, int nj, int64_t total, int grid, int32_t* st,
+                              hipStream_t s) {
+  constexpr int NCB = ScanShape<M, false>::NCB, NBUF = ScanShape<M, false>::NBUF;
+  constexpr bool T2 = ScanShape<M, false>::T2;
+  switch (DP) {
+#define GEEK_BATCH_CASE(DPV)                                                                        \
+  case DPV:                                                                                         \
+    hipLaunchKernelGGL((k_scan_batch<M, DPV, NCB, NBUF, T2>), dim3(grid), dim3(SCAN_THREADS), 0, s, table, nj, \
+                       total, st);                                                                  \
+    break;
+    GEEK_BATCH_CASE(32)
+    GEEK_BATCH_CASE(64)
+    GEEK_BATCH_CASE(128)
+    GEEK_BATCH_CASE(256)
+#undef GEEK_BATCH_CASE
+  }
+}
+
+int32_t assign_euclid_batch(const geek_assign_job* jobs, int njobs, void* ws, size_t ws_bytes, int32_t* st,
+                            hipStream_t s) {
+  if (ws_bytes < assign_batch_ws(jobs, njobs)) return GEEK_ERR_WORKSPACE;
+  std::vector<AssignCtx> C(njobs);
+  std::vector<char*> slice(njobs);
+  char* base = static_cast<char*>(ws);
+  size_t off = 0;
+  for (int j = 0; j < njobs; ++j) {
+    slice[j] = base + off;
+    off += slice_bytes(jobs[j]);
+  }
+  ScanJob* table = reinterpret_cast<ScanJob*>(base + (off + 255) / 256 * 256);
+  unsigned long long* t0 = reinterpret_cast<unsigned long long*>(table + njobs);
+  const geek_assign_job& J0 = jobs[0];
+  prof_begin(GEEK_PROF_ASSIGN, s);
+  hipLaunchKernelGGL(k_clock_now, dim3(1), dim3(64), 0, s, t0);
+  for (int j = 0; j < njobs; ++j)
+    if (int32_t rc = assign_prep(jobs[j], slice[j], C[j], st, s)) return rc;
+  // one persistent launch per matrix-core K width, jobs in call order
+  const bool low = low_precision(J0);
+  const int rows_per_tile = low ? scan_rows_per_tile<ModeBF16>(false) : scan_rows_per_tile<ModeF32>(false);
+  prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
+  int tslot = 0;
+  for (const int DP : {32, 64, 128, 256}) {
+    std::vector<ScanJob> tab;
+    int64_t total = 0;
+    for (int j = 0; j < njobs; ++j) {
+      if (C[j].DP != DP) continue;
+      const geek_assign_job& J = jobs[j];
+      const AssignWs& W = C[j].W;
+      ScanJob e{};
+      e.X = J.X;
+      e.ldx = J.ldx;
+      e.n = J.n;
+      e.cl = low ? W.cllow : static_cast<const void*>(W.cl32);
+      e.nc = W.nc;
+      e.cmax = W.cmax;
+      e.scale = W.cmax + 3;
+      e.rec = W.rec;
+      e.tile_begin = total;
+      e.d = J.d;
+      e.k = J.k;
+      e.k_pad = C[j].k_pad;
+      tab.push_back(e);
+      total += ceil_div(J.n, rows_per_tile);
+    }
+    if (tab.empty()) continue;
+    ScanJob* dst = table + tslot;
+    for (size_t c0 = 0; c0 < tab.size(); c0 += SCANJOB_CHUNK) {
+      ScanJobChunk ch{};
+      ch.count = (int)std::min<size_t>(SCANJOB_CHUNK, tab.size() - c0);
+      for (int i = 0; i < ch.count; ++i) ch.jobs[i] = tab[c0 + i];
+      hipLaunchKernelGGL(k_put_jobs, dim3(1), dim3(SCANJOB_CHUNK), 0, s, ch, dst + c0);
+    }
+    const int grid = (int)std::min<int64_t>(total, 2048);
+    if (J0.precision == GEEK_PREC_BF16)
+      launch_scan_batch<ModeBF16>(DP, dst, (int)tab.size(), total, grid, st, s);
+    else if (J0.precision == GEEK_PREC_FP8)
+      launch_scan_batch<ModeFP8>(DP, dst, (int)tab.size(), total, grid, st, s);
+    else
+      launch_scan_batch<ModeF32>(DP, dst, (int)tab.size(), total, grid, st, s);
+    tslot += (int)tab.size();
+  }
+  prof_end(GEEK_PROF_ASSIGN_SCAN, s);
+  for (int j = 0; j < njobs; ++j) assign_finish(jobs[j], C[j], st, s, t0);
   prof_end(GEEK_PROF_ASSIGN, s);
   GEEK_LAUNCH_CHECK();
   return GEEK_OK;

@@ -31,5 +31,6 @@ int main(void) {
   F(geek_assign_job, seed_members); F(geek_assign_job, assign); F(geek_assign_job, centroids);
   F(geek_assign_job, modes); F(geek_assign_job, dist); F(geek_assign_job, sse);
   F(geek_assign_job, radius); F(geek_assign_job, counters); F(geek_assign_job, n_members);
+  F(geek_assign_job, t_done);
   return 0;
 }
