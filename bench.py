@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero"],
+                    help="dense_large: the headline metric; batched: 256 mixed dense jobs in one "
+                         "captured HIP graph; hetero: heterogeneous rows (FP8 numeric part)")
+    ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
+    ap.add_argument("--hetero-fp8", action="store_true", help="hetero: FP8 first pass instead of BF16")
     return ap.parse_args()
 
 
@@ -86,6 +91,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "hetero":
+        return bench_hetero(args)
     import numpy as np
     import torch
 
@@ -255,6 +264,160 @@ def cpu_baseline(X, A, b, w, m, Lt, so, sm, a_gpu, rows, n, log):
             "sample": f"first {rows} of {n} points, all {len(so) - 1} centroids; centroid time "
                       f"prorated by rows/n; numpy float64, single thread",
             "seconds": t, "sample_assign_matches_gpu": agree}
+
+
+def _timed_graph(step, steps, warmup):
+    """Capture ``step`` in a HIP graph (after one eager warm-up call) and time
+    ``steps`` replays; returns (ms per replay, graph outputs)."""
+    import torch
+
+    step(True)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = step(False)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, out
+
+
+def bench_batched(args):
+    """Many independent dense jobs (n log-uniform in [1e3, 1e6], d over
+    {16, 32, 64, 128, 256}, 10..5000 planted clusters): one geek_hash, one
+    geek_bucketize and one batched geek_assign call over all jobs, captured
+    in one HIP graph and replayed."""
+    import numpy as np
+    import torch
+
+    from paper_2106_10515_amd import _lib as L
+    from paper_2106_10515_amd import api
+    from workloads import CONFIGS, batched_jobs, dense_mixture, e2lsh_params, planted_seeds
+
+    dev = torch.device("cuda:0")
+    hc = CONFIGS["dense_small"]  # the small dense configuration's hash parameters
+    m, Lt, w = hc["m"], hc["L"], hc["w"]
+    specs = batched_jobs(args.jobs, seed=0)
+    t0 = time.time()
+    probs, hp, total_n = [], {}, 0
+    for sp in specs:
+        X, lab, _ = dense_mixture(sp["n"], sp["d"], sp["clusters"], sp["lo"], sp["hi"], sp["sigma"],
+                                  sp["sizes"], sp["seed"], device=dev)
+        so, sm = planted_seeds(lab, sp["clusters"], 32)
+        if sp["d"] not in hp:
+            A, b = e2lsh_params(m * Lt, sp["d"], w, 0)
+            hp[sp["d"]] = (torch.from_numpy(A).to(dev), torch.from_numpy(b).to(dev))
+        probs.append((X, torch.from_numpy(so.view(np.int32)).to(dev),
+                      torch.from_numpy(sm.view(np.int32)).to(dev), len(so) - 1))
+        total_n += sp["n"]
+    torch.cuda.synchronize()
+    log(f"batched workload ready: {len(specs)} jobs, sum n = {total_n} in {time.time() - t0:.1f}s")
+    status = api.new_status(dev)
+
+    def step(check):
+        keys = api.hash_dense_batch([(X, *hp[X.shape[1]], m, Lt, w) for X, _, _, _ in probs],
+                                    status=status, check=check)
+        bz = api.bucketize_batch([(kk, X.shape[0], Lt, 4, X.shape[0] * 4, 4) for kk, (X, _, _, _)
+                                  in zip(keys, probs)], status=status, check=check)
+        outs, t_done = api.assign_euclid_batch(probs, L.GEEK_PREC_BF16, status=status, check=check)
+        return keys, bz, outs, t_done
+
+    ms, (keys, bz, outs, t_done) = _timed_graph(step, args.steps, args.warmup)
+    api.check_status(status, "graph replays")
+    hz = api.wallclock_hz()
+    lat_ms = t_done.cpu().numpy().astype(np.float64) / hz * 1e3
+    # the same jobs one call per job (eager), for comparison
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    singles = [api.assign_euclid(X, so, sm, k, L.GEEK_PREC_BF16, status=status, check=False)
+               for X, so, sm, k in probs]
+    e1.record()
+    torch.cuda.synchronize()
+    single_ms = e0.elapsed_time(e1)
+    same = all(np.array_equal(a["assign"].cpu().numpy(), b["assign"].cpu().numpy())
+               for a, b in zip(outs, singles))
+    flops = float(sum(2.0 * X.shape[0] * X.shape[1] * k for X, _, _, k in probs))
+    line = {
+        "metric": "points/s (hash+bucketize+assign), 256 mixed dense jobs in one HIP graph",
+        "value": total_n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"batched: {len(specs)} jobs, n log-uniform in [1e3, 1e6] (sum {total_n}), "
+                               "d in {16,32,64,128,256}, 10..5000 planted clusters, E2LSH m=8 L=16 w=4",
+                   "jobs": len(specs), "sum_n": total_n},
+        "assign_job_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                                  "p90": float(np.percentile(lat_ms, 90)),
+                                  "max": float(lat_ms.max())},
+        "assign_flops": flops,
+        "assign_one_call_per_job_ms": single_ms,
+        "batched_equals_single_calls": bool(same),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_hetero(args):
+    """Heterogeneous rows (2e6 rows, 20 numeric + 10 categorical attributes,
+    1000 clusters): MinHash of the combined tokens, bucketize of the bands,
+    heterogeneous assignment with the BF16 (or FP8) numeric part."""
+    import numpy as np
+    import torch
+
+    from paper_2106_10515_amd import _lib as L
+    from paper_2106_10515_amd import api
+    from workloads import CONFIGS, e2lsh_params, hetero_rows, key_words, planted_seeds
+    from workloads.gen import STREAM_MINHASH
+
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS["hetero"]
+    n = cfg["n"]
+    t0 = time.time()
+    X, cat, lab, _ = hetero_rows(n, cfg["d_num"], cfg["n_cat"], cfg["clusters"], seed=0)
+    A, b = e2lsh_params(cfg["P_h"], cfg["d_num"], cfg["w"], 0)
+    K, Lb = cfg["K"], cfg["L"]
+    mh = key_words(K * Lb, 0, STREAM_MINHASH)
+    so, sm = planted_seeds(lab, cfg["clusters"], 32)
+    Xg, catg = torch.from_numpy(X).to(dev), torch.from_numpy(cat).to(dev)
+    Ag, bg = torch.from_numpy(A).to(dev), torch.from_numpy(b).to(dev)
+    mhg = torch.from_numpy(mh.view(np.int32)).to(dev)
+    sog, smg = torch.from_numpy(so.view(np.int32)).to(dev), torch.from_numpy(sm.view(np.int32)).to(dev)
+    k = len(so) - 1
+    torch.cuda.synchronize()
+    log(f"hetero workload ready n={n} k={k} in {time.time() - t0:.1f}s")
+    status = api.new_status(dev)
+    prec = L.GEEK_PREC_FP8 if args.hetero_fp8 else L.GEEK_PREC_BF16
+
+    def step(check):
+        sig = api.hash_hetero(Xg, catg, Ag, bg, cfg["P_h"], 1, cfg["w"], mhg, status=status, check=check)
+        bz = api.bucketize(sig, n, Lb, K, K, K * Lb, status=status, check=check)
+        out = api.assign_hetero(Xg, catg, sog, smg, k, 1.0, prec, status=status, check=check)
+        return sig, bz, out
+
+    ms, (sig, bz, out) = _timed_graph(step, args.steps, args.warmup)
+    api.check_status(status, "graph replays")
+    line = {
+        "metric": "points/s (hash+bucketize+assign), heterogeneous rows",
+        "value": n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp8" if args.hetero_fp8 else "bf16", "data": "synthetic",
+        "config": {"workload": f"hetero: n={n}, 20 numeric + 10 categorical attributes, "
+                               f"{cfg['clusters']} clusters, MinHash K={K} x L={Lb}, k={k} planted seeds",
+                   "n": n, "k": k},
+        "assign_counters": out["counters"].cpu().numpy().tolist(),
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

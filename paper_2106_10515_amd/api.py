@@ -86,6 +86,25 @@ def hash_dense(X, A, b, m, L_tables, w, want_codes=False, status=None, check=Tru
     return keys, codes
 
 
+def hash_dense_batch(problems, status=None, check=True):
+    """One geek_hash call over many dense jobs, ``problems`` a list of
+    ``(X, A, b, m, L_tables, w)``.  Returns the list of key tensors."""
+    dev = _dev(problems[0][0])
+    jobs, keys_out = [], []
+    for X, A, b, m, L_tables, w in problems:
+        n, d = X.shape
+        keys = torch.empty((L_tables, n, 4), dtype=torch.int32, device=dev)
+        keys_out.append((keys, A.contiguous(), b.contiguous()))
+        jobs.append(L.HashJob(kind=L.GEEK_HASH_DENSE, d=d, n=n, X=_p(X), ldx=X.stride(0),
+                              A=_p(keys_out[-1][1]), b=_p(keys_out[-1][2]), m=m, L=L_tables, w=float(w),
+                              F=0, keys=_p(keys)))
+    status = new_status(dev) if status is None else status
+    _run(L.GEEK_OP_HASH, L.geek_hash, jobs, dev, status)
+    if check:
+        check_status(status, "geek_hash (batch)")
+    return [k[0] for k in keys_out]
+
+
 def hash_sets(offsets, tokens, mh_keys, status=None, check=True):
     """MinHash signatures of sets.  Returns ``sig int32 [n, F]``."""
     dev = _dev(tokens)
@@ -137,6 +156,27 @@ def bucketize(keys, n, T, key_words, table_stride, row_stride, want_bucket_of=Tr
     if check:
         check_status(status, "geek_bucketize")
     return members, offsets, nbuckets, bucket_of
+
+
+def bucketize_batch(problems, want_bucket_of=True, status=None, check=True):
+    """One geek_bucketize call over many jobs, ``problems`` a list of
+    ``(keys, n, T, key_words, table_stride, row_stride)``."""
+    dev = _dev(problems[0][0])
+    jobs, outs = [], []
+    for keys, n, T, kw, ts, rs in problems:
+        o = (torch.empty((T, n), dtype=torch.int32, device=dev),
+             torch.empty((T, n + 1), dtype=torch.int32, device=dev),
+             torch.empty((T,), dtype=torch.int32, device=dev),
+             torch.empty((T, n), dtype=torch.int32, device=dev) if want_bucket_of else None)
+        outs.append(o)
+        jobs.append(L.BucketizeJob(n=n, T=T, key_words=kw, keys=_p(keys), table_stride=ts, row_stride=rs,
+                                   members=_p(o[0]), offsets=_p(o[1]), nbuckets=_p(o[2]),
+                                   bucket_of=_p(o[3])))
+    status = new_status(dev) if status is None else status
+    _run(L.GEEK_OP_BUCKETIZE, L.geek_bucketize, jobs, dev, status)
+    if check:
+        check_status(status, "geek_bucketize (batch)")
+    return outs
 
 
 # ---------------------------------------------------------------- geek_silk_seeds

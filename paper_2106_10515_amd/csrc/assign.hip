@@ -26,6 +26,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -295,8 +296,11 @@ __device__ __forceinline__ void scan_tiles(
   // T2 starts every accumulator at -s^2 |c_j|^2 / 2 (exact power-of-two
   // scalings), so acc = s^2 (x.c - |c_j|^2 / 2) and v_j = m2s * acc
   const float nc_mul = T2 ? -0.5f * sc * sc : 1.0f;
-  // padded centroids (|c|^2 = +inf) start T2 accumulators at -FLT_MAX
-  auto nc_stage = [nc_mul](float v) { return T2 ? fmaxf(v * nc_mul, -3.402823466e38f) : v; };
+  // padded centroids (|c|^2 = +inf) start T2 accumulators at -FLT_MAX / 4:
+  // far below any real value, and finite even after the heterogeneous
+  // epilogue doubles it (an infinity would turn into a NaN once the index
+  // bits are inserted)
+  auto nc_stage = [nc_mul](float v) { return T2 ? fmaxf(v * nc_mul, -0x1p126f) : v; };
   const bool vec4 = ((d & 3) == 0) && ((ldx & 3) == 0);
   const double het_max = HET ? het.gamma * het.n_cat : 0.0;
 
@@ -596,8 +600,8 @@ __device__ __forceinline__ void scan_tiles(
         const float v1 = vs * best, v2 = vs * second;
         // one candidate iff the runner-up lies beyond the 2 eps window; the
         // best must be a normal float (its index bits intact)
-        const bool unique = best > -1e38f && fabsf(best) >= 0x1p-126f && isfinite(v1) && v2 > v1 + twoeps[cb] &&
-                            jbest < k;
+        const bool unique = best > -1e37f && best < 1e37f && fabsf(best) >= 0x1p-126f && isfinite(v1) &&
+                            v2 > v1 + twoeps[cb] && jbest < k;
         if (valid[cb] && h == 0) {
           int32_t* rr = rec + posv[cb] * (TCAND + 1);
           rr[0] = unique ? 1 : -1;
@@ -848,14 +852,21 @@ __global__ __launch_bounds__(256) void k_fallback64(
 }
 
 // ---------------------------------------------------------------- SSE, radius
-__global__ void k_sse_blocks(const double* __restrict__ dist, int64_t n, double* __restrict__ blk) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// One wavefront per 4096-row block: a coalesced copy into LDS, then one lane
+// adds the block's values in row order (the reference summation order).
+__global__ __launch_bounds__(64) void k_sse_blocks(const double* __restrict__ dist, int64_t n,
+                                                   double* __restrict__ blk) {
+  __shared__ double v[SSE_BLOCK];
+  const int64_t b = blockIdx.x;
   const int64_t s = b * SSE_BLOCK;
-  if (s >= n) return;
-  const int64_t e = s + SSE_BLOCK < n ? s + SSE_BLOCK : n;
-  double acc = 0.0;
-  for (int64_t i = s; i < e; ++i) acc = __dadd_rn(acc, dist[i]);
-  blk[b] = acc;
+  const int cnt = (int)(n - s < SSE_BLOCK ? n - s : SSE_BLOCK);
+  for (int i = threadIdx.x; i < cnt; i += 64) v[i] = dist[s + i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < cnt; ++i) acc = __dadd_rn(acc, v[i]);
+    blk[b] = acc;
+  }
 }
 
 __global__ void k_sse_total(const double* __restrict__ blk, int64_t nb, double* __restrict__ out) {
@@ -873,6 +884,24 @@ __global__ void k_radius(const int32_t* __restrict__ assign, const double* __res
   double* slot = rad + assign[i];
   if (v > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
     atomic_max_nonneg(slot, v);
+}
+
+// Few clusters: per-workgroup maxima in LDS (bit patterns of non-negative
+// doubles order like the values), then one global atomic per touched slot.
+constexpr int RAD_LDS = 4096;
+__global__ __launch_bounds__(256) void k_radius_lds(const int32_t* __restrict__ assign,
+                                                    const double* __restrict__ dist, int64_t n, int k,
+                                                    double* __restrict__ rad) {
+  __shared__ unsigned long long m[RAD_LDS];
+  for (int j = threadIdx.x; j < k; j += 256) m[j] = 0ull;
+  __syncthreads();
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int a = assign[i];
+    if ((unsigned)a < (unsigned)k) atomicMax(&m[a], (unsigned long long)__double_as_longlong(dist[i]));
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += 256)
+    if (m[j]) atomic_max_nonneg(rad + j, __longlong_as_double((long long)m[j]));
 }
 
 __global__ void k_sqrt_inplace(double* __restrict__ v, int k, int do_sqrt) {
@@ -907,11 +936,15 @@ __global__ void k_copy_u64(const unsigned long long* a, unsigned long long* b, i
 void sse_and_radius(const double* dist, const int32_t* assign, int64_t n, int k, double* sse, double* radius,
                     int take_sqrt, double* sse_blk, hipStream_t s) {
   const int64_t nblk = (n + SSE_BLOCK - 1) / SSE_BLOCK;
-  hipLaunchKernelGGL(k_sse_blocks, dim3(ceil_div(nblk, 64)), dim3(64), 0, s, dist, n, sse_blk);
+  hipLaunchKernelGGL(k_sse_blocks, dim3(nblk), dim3(64), 0, s, dist, n, sse_blk);
   hipLaunchKernelGGL(k_sse_total, dim3(1), dim3(1), 0, s, sse_blk, nblk, sse);
   if (radius) {
     hipLaunchKernelGGL(k_fill_f64, dim3(ceil_div(k, 256)), dim3(256), 0, s, radius, k, 0.0);
-    hipLaunchKernelGGL(k_radius, dim3(ceil_div(n, 256)), dim3(256), 0, s, assign, dist, n, k, radius);
+    if (k <= RAD_LDS)
+      hipLaunchKernelGGL(k_radius_lds, dim3((int)std::min<int64_t>(ceil_div(n, 4096), 512)), dim3(256), 0, s,
+                         assign, dist, n, k, radius);
+    else
+      hipLaunchKernelGGL(k_radius, dim3(ceil_div(n, 256)), dim3(256), 0, s, assign, dist, n, k, radius);
     hipLaunchKernelGGL(k_sqrt_inplace, dim3(ceil_div(k, 256)), dim3(256), 0, s, radius, k, take_sqrt);
   }
 }
@@ -971,14 +1004,16 @@ size_t assign_euclid_ws(const geek_assign_job& J) {
 // Column blocks per wave and LDS buffering per mode: the low-precision modes
 // reuse every LDS fragment for two column blocks and double-buffer; float32
 // (16x fewer flops per cycle) keeps one block and one buffer.
-// Low-precision first passes keep the best two values per row (T2); the
-// float32 pass, which also rescans rows with several candidates, keeps the
+// The BF16 first pass keeps the best two values per row (T2); FP8 and the
+// float32 pass, which also rescans rows with several candidates, keep the
 // full candidate window.
 // Heterogeneous rows carry their categorical values in registers: one
 // column block.
 template <class M, bool HET> struct ScanShape {
   static constexpr int NCB = HET ? 1 : 2, NBUF = 2;
-  static constexpr bool T2 = true;
+  // e4m3's coarse rounding leaves most rows with a few candidates: FP8 keeps
+  // the full candidate window (float64 recheck of up to TCAND) instead
+  static constexpr bool T2 = std::is_same<M, ModeBF16>::value;
 };
 template <bool HET> struct ScanShape<ModeF32, HET> {
   static constexpr int NCB = 1, NBUF = 1;
@@ -1070,6 +1105,11 @@ static int32_t assign_prep(const geek_assign_job& J, void* ws, AssignCtx& C, int
   return GEEK_OK;
 }
 
+// Workgroups of a persistent pass over a device-counted subset of n rows.
+static int esc_grid(int64_t n, int rows_per_group) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, rows_per_group)));
+}
+
 static bool low_precision(const geek_assign_job& J) {
   return J.precision == GEEK_PREC_BF16 || J.precision == GEEK_PREC_FP8;
 }
@@ -1098,15 +1138,18 @@ static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, h
     hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
                        nullptr, nullptr, W.rec, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
     // rows with several low-precision candidates: float32 rescan of those rows
-    scan_any<ModeF32>(C.het_on, C.DP, 1024, s, J, 0, W.esc, W.counts + 0, W.cl32, W, C.k_pad, C.het, st);
-    hipLaunchKernelGGL(k_finalize, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het,
-                       (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 1);
+    // (persistent grids, at most one row tile / row block per workgroup)
+    scan_any<ModeF32>(C.het_on, C.DP, esc_grid(J.n, 128), s, J, 0, W.esc, W.counts + 0, W.cl32, W, C.k_pad,
+                      C.het, st);
+    hipLaunchKernelGGL(k_finalize, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
+                       C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr,
+                       1);
   } else {
     hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
                        nullptr, nullptr, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 0);
   }
-  hipLaunchKernelGGL(k_fallback64, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, W.fb,
-                     W.counts + 1, J.assign, C.dist, ctr);
+  hipLaunchKernelGGL(k_fallback64, dim3(esc_grid(J.n, 1)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
+                     C.het, W.fb, W.counts + 1, J.assign, C.dist, ctr);
   sse_and_radius(C.dist, J.assign, J.n, J.k, J.sse, J.radius, C.het_on ? 0 : 1, W.sse_blk, s);
   if (J.counters) hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, ctr, J.counters, 4);
   if (J.t_done) {

@@ -50,3 +50,24 @@ def test_fp8_euclid_matches_oracle(n, d, clusters, per, seed):
     assert np.array_equal(out["assign"].cpu().numpy(), a)
     assert np.array_equal(out["dist"].cpu().numpy(), dist)
     assert out["sse"].item() == oracle.sse(dist)
+
+
+@pytest.mark.parametrize("metric", ["euclid", "hetero"])
+def test_bf16_first_pass_settles_well_separated_rows(metric):
+    # planted clusters far apart relative to the BF16 error bound: the first
+    # pass must settle (almost) every row by itself, with padded centroid
+    # slots present (k = 100 is padded to 128) and for both epilogues
+    api = gpu_api()
+    X, cat, lab, _ = hetero_rows(6000, 20, 10, 100, seed=7)
+    so, sm = planted_seeds(lab, 100, 16)
+    k = len(so) - 1
+    announce(f"bf16 first pass settles {metric} n=6000 k={k}")
+    if metric == "euclid":
+        out = api.assign_euclid(cuda(X), cuda(so), cuda(sm), k, 1)
+        a, _ = oracle.assign_euclid(X, oracle.centroids(X, so, sm))
+    else:
+        out = api.assign_hetero(cuda(X), cuda(cat), cuda(so), cuda(sm), k, 1.0, 1)
+        a, _ = oracle.assign_hetero(X, cat, oracle.centroids(X, so, sm), oracle.modes(cat, so, sm), 1.0)
+    assert np.array_equal(out["assign"].cpu().numpy(), a)
+    ctr = out["counters"].cpu().numpy()
+    assert ctr[0] >= 0.99 * len(X), ctr
