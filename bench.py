@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero"],
+    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets"],
                     help="dense_large: the headline metric; batched: 256 mixed dense jobs in one "
-                         "captured HIP graph; hetero: heterogeneous rows (FP8 numeric part)")
+                         "captured HIP graph; hetero: heterogeneous rows; sets: sparse sets "
+                         "(MinHash, band buckets, signature assignment)")
     ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
     ap.add_argument("--hetero-fp8", action="store_true", help="hetero: FP8 first pass instead of BF16")
     return ap.parse_args()
@@ -95,6 +96,8 @@ def main():
         return bench_batched(args)
     if args.workload == "hetero":
         return bench_hetero(args)
+    if args.workload == "sets":
+        return bench_sets(args)
     import numpy as np
     import torch
 
@@ -415,6 +418,67 @@ def bench_hetero(args):
         "config": {"workload": f"hetero: n={n}, 20 numeric + 10 categorical attributes, "
                                f"{cfg['clusters']} clusters, MinHash K={K} x L={Lb}, k={k} planted seeds",
                    "n": n, "k": k},
+        "assign_counters": out["counters"].cpu().numpy().tolist(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sets(args):
+    """Sparse sets (5e6 sets over a 1e6-token vocabulary, 2000 planted
+    clusters): MinHash signatures (K=4 x L=64 = 256 functions), buckets of
+    the 64 bands, and assignment of the signatures to the modes of the
+    planted seeds."""
+    import numpy as np
+    import torch
+
+    from paper_2106_10515_amd import api
+    from workloads import CONFIGS, key_words, planted_seeds, sparse_sets
+    from workloads.gen import STREAM_MINHASH
+
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS["sets"]
+    n = cfg["n"] if args.n == 10_000_000 else args.n
+    K, Lb = cfg["K"], cfg["L"]
+    t0 = time.time()
+    off, tok, lab = sparse_sets(n, cfg["vocab"], cfg["clusters"], seed=0, device=dev)
+    mh = torch.from_numpy(key_words(K * Lb, 0, STREAM_MINHASH).view(np.int32)).to(dev)
+    so, sm = planted_seeds(lab, cfg["clusters"], 32)
+    sog, smg = torch.from_numpy(so.view(np.int32)).to(dev), torch.from_numpy(sm.view(np.int32)).to(dev)
+    k = len(so) - 1
+    nnz = int(off[-1].item())
+    torch.cuda.synchronize()
+    log(f"sets workload ready n={n} nnz={nnz} k={k} in {time.time() - t0:.1f}s")
+    status = api.new_status(dev)
+
+    def step(check):
+        sig = api.hash_sets(off, tok, mh, status=status, check=check)
+        bz = api.bucketize(sig, n, Lb, K, K, K * Lb, status=status, check=check)
+        out = api.assign_sig(sig, sog, smg, k, status=status, check=check)
+        return sig, bz, out
+
+    ms, (sig, bz, out) = _timed_graph(step, args.steps, args.warmup)
+    api.check_status(status, "graph replays")
+    # stage times (eager, events)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    sig2 = api.hash_sets(off, tok, mh, status=status, check=False)
+    ev[1].record()
+    api.bucketize(sig2, n, Lb, K, K, K * Lb, status=status, check=False)
+    ev[2].record()
+    api.assign_sig(sig2, sog, smg, k, status=status, check=False)
+    ev[3].record()
+    torch.cuda.synchronize()
+    stages = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    line = {
+        "metric": "sets/s (MinHash+bucketize+assign), sparse sets",
+        "value": n / (ms * 1e-3), "unit": "sets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"sets: n={n} sets, {nnz} tokens over a {cfg['vocab']}-token vocabulary, "
+                               f"{cfg['clusters']} planted clusters, MinHash K={K} x L={Lb}, k={k} planted seeds",
+                   "n": n, "nnz": nnz, "k": k},
+        "stages_ms": {"minhash": stages[0], "bucketize": stages[1], "assign": stages[2]},
+        "minhash_evals_per_s": nnz * K * Lb / (stages[0] * 1e-3),
         "assign_counters": out["counters"].cpu().numpy().tolist(),
     }
     print(json.dumps(line), flush=True)

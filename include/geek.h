@@ -223,7 +223,6 @@ typedef struct geek_silk_job {
 #define GEEK_PREC_FP32 0
 #define GEEK_PREC_BF16 1
 #define GEEK_PREC_FP8 2
-#define GEEK_PREC_BF16X3 3   /* BF16 hi/lo split, three products */
 
 typedef struct geek_assign_job {
   int32_t metric;           /* GEEK_METRIC_* */

@@ -26,7 +26,7 @@ GEEK_ERR_EMPTY_SET = 5
 
 GEEK_HASH_DENSE, GEEK_HASH_SETS, GEEK_HASH_HETERO = 0, 1, 2
 GEEK_METRIC_EUCLID, GEEK_METRIC_SIG, GEEK_METRIC_HETERO = 0, 1, 2
-GEEK_PREC_FP32, GEEK_PREC_BF16, GEEK_PREC_FP8, GEEK_PREC_BF16X3 = 0, 1, 2, 3
+GEEK_PREC_FP32, GEEK_PREC_BF16, GEEK_PREC_FP8 = 0, 1, 2
 GEEK_OP_HASH, GEEK_OP_BUCKETIZE, GEEK_OP_SILK, GEEK_OP_ASSIGN = 0, 1, 2, 3
 
 P = C.c_void_p

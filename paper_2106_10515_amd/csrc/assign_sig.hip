@@ -14,6 +14,8 @@
 //               run (lowest j on ties); a row whose matches overflow the LDS
 //               list is compared against every mode instead.  Rows with no
 //               match at all take seed 0 (every count is 0).
+#include <algorithm>
+
 #include "common.hpp"
 #include "radix.hpp"
 
@@ -24,6 +26,8 @@ void sse_and_radius(const double* dist, const int32_t* assign, int64_t n, int k,
 size_t sse_blk_words(int64_t n);
 
 constexpr int SG_CAP = 2048;  // matched seeds held in LDS per row
+// k * F up to which every row is compared against every mode directly
+constexpr int64_t SIG_DENSE_MAX = 1 << 20;
 
 __device__ __forceinline__ int seed_of(const uint32_t* __restrict__ so, int k, uint32_t pos) {
   int lo = 0, hi = k;  // so[lo] <= pos < so[hi]
@@ -223,47 +227,90 @@ __global__ __launch_bounds__(64) void k_sig_assign(const uint32_t* __restrict__ 
   }
 }
 
-// Rows whose matches overflowed: count against every mode, lowest j on ties.
+// Rows whose match lists overflowed: count against every mode, lowest j on
+// ties.  One lane per row, 256 rows per workgroup; blocks of 32 seeds x 256
+// signature positions are staged in LDS and read by every lane at the same
+// address (broadcast); each lane keeps 16 of its row's words and 32 match
+// counters in registers (a compare and an add-with-carry per comparison).
+constexpr int SD_SEEDS = 32;   // seeds per register block
+constexpr int SD_F = 16;       // signature words per register chunk
+constexpr int SD_SEG = 256;    // signature positions per LDS segment
 __global__ __launch_bounds__(256) void k_sig_dense(const uint32_t* __restrict__ S, int64_t lds, int F,
                                                    const uint32_t* __restrict__ modes, int k,
                                                    const uint32_t* __restrict__ rows,
-                                                   const uint32_t* __restrict__ count, int32_t* __restrict__ assign,
-                                                   double* __restrict__ dist, unsigned long long* __restrict__ ctr) {
-  __shared__ uint32_t row[1024];
-  __shared__ uint32_t bc[256], bj[256];
-  const uint32_t nr = *count;
-  for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
-    const int64_t i = rows[r];
-    __syncthreads();
-    for (int f = threadIdx.x; f < F; f += blockDim.x) row[f] = S[i * lds + f];
-    __syncthreads();
-    uint32_t best = 0, bjj = 0x7fffffff;
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
-      const uint32_t* mj = modes + (int64_t)j * F;
-      uint32_t m = 0;
-      for (int f = 0; f < F; ++f) m += (mj[f] == row[f]) ? 1u : 0u;
-      if (m > best || bjj == 0x7fffffff) {
-        best = m;
-        bjj = (uint32_t)j;
-      }
-    }
-    bc[threadIdx.x] = best;
-    bj[threadIdx.x] = bjj;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) {
-        const uint32_t oc = bc[threadIdx.x + o], oj = bj[threadIdx.x + o];
-        if (oc > bc[threadIdx.x] || (oc == bc[threadIdx.x] && oj < bj[threadIdx.x])) {
-          bc[threadIdx.x] = oc;
-          bj[threadIdx.x] = oj;
+                                                   const uint32_t* __restrict__ count, int64_t n_rows,
+                                                   int32_t* __restrict__ assign, double* __restrict__ dist,
+                                                   unsigned long long* __restrict__ ctr) {
+  __shared__ __attribute__((aligned(16))) uint32_t lm[SD_SEEDS * SD_SEG];
+  const int64_t nr = rows ? (int64_t)*count : n_rows;  // rows == nullptr: every row
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < nr; base += (int64_t)gridDim.x * 256) {
+    const int64_t pos = base + threadIdx.x;
+    const bool live = pos < nr;
+    const int64_t i = !live ? 0 : rows ? (int64_t)rows[pos] : pos;
+    const uint32_t* srow = S + i * lds;
+    const bool row_vec = (lds & 3) == 0;
+    uint32_t best = 0, bj = 0x7fffffffu;
+    for (int jb = 0; jb < k; jb += SD_SEEDS) {
+      uint32_t cnt[SD_SEEDS];
+#pragma unroll
+      for (int q = 0; q < SD_SEEDS; ++q) cnt[q] = 0u;
+      for (int fs = 0; fs < F; fs += SD_SEG) {
+        const int seg = F - fs < SD_SEG ? F - fs : SD_SEG;
+        __syncthreads();  // previous segment consumed
+        for (int t = threadIdx.x; t < SD_SEEDS * SD_SEG; t += 256) {
+          const int q = t / SD_SEG, f = t % SD_SEG;
+          lm[t] = (jb + q < k && f < seg) ? modes[(int64_t)(jb + q) * F + fs + f] : 0u;
+        }
+        __syncthreads();
+        for (int f0 = 0; f0 < seg; f0 += SD_F) {
+          if (row_vec && f0 + SD_F <= seg) {
+            uint32_t x[SD_F];
+#pragma unroll
+            for (int e = 0; e < SD_F; e += 4) {
+              const uint4 v = *reinterpret_cast<const uint4*>(srow + fs + f0 + e);
+              x[e] = v.x;
+              x[e + 1] = v.y;
+              x[e + 2] = v.z;
+              x[e + 3] = v.w;
+            }
+#pragma unroll
+            for (int q = 0; q < SD_SEEDS; ++q) {
+#pragma unroll
+              for (int e = 0; e < SD_F; e += 4) {
+                const uint4 m = *reinterpret_cast<const uint4*>(lm + q * SD_SEG + f0 + e);
+                cnt[q] += (x[e] == m.x) ? 1u : 0u;
+                cnt[q] += (x[e + 1] == m.y) ? 1u : 0u;
+                cnt[q] += (x[e + 2] == m.z) ? 1u : 0u;
+                cnt[q] += (x[e + 3] == m.w) ? 1u : 0u;
+              }
+            }
+          } else {
+            for (int f = f0; f < seg && f < f0 + SD_F; ++f) {
+              const uint32_t xv = srow[fs + f];
+#pragma unroll
+              for (int q = 0; q < SD_SEEDS; ++q) cnt[q] += (xv == lm[q * SD_SEG + f]) ? 1u : 0u;
+            }
+          }
         }
       }
-      __syncthreads();
+      // strict > with ascending j keeps the lowest index on ties
+#pragma unroll
+      for (int q = 0; q < SD_SEEDS; ++q) {
+        const int j = jb + q;
+        if (j < k && (cnt[q] > best || bj == 0x7fffffffu)) {
+          best = cnt[q];
+          bj = (uint32_t)j;
+        }
+      }
     }
-    if (threadIdx.x == 0) {
-      assign[i] = (int32_t)bj[0];
-      dist[i] = 1.0 - (double)bc[0] / (double)F;
-      if (ctr) atomicAdd(ctr + 2, 1ull);
+    if (live) {
+      assign[i] = (int32_t)bj;
+      dist[i] = 1.0 - (double)best / (double)F;
+    }
+    if (ctr) {
+      const unsigned long long nlive = __popcll(__ballot(live));
+      if (lane == 0 && nlive) atomicAdd(ctr + 2, nlive);
     }
   }
 }
@@ -419,12 +466,20 @@ int32_t assign_sig(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t*
   hipLaunchKernelGGL(k_index_insert, dim3(ceil_div(KI, 256)), dim3(256), 0, s, sv, sf, KI, W.hkey, W.hval,
                      W.hmask);
   prof_begin(GEEK_PROF_ASSIGN_SCAN, s);
-  const int grid = J.n < 65536 ? (int)J.n : 65536;
-  hipLaunchKernelGGL(k_sig_assign, dim3(grid), dim3(64), 0, s, J.sig, (int64_t)F, F, J.n, W.hkey, W.hval, W.hmask,
-                     sj, J.assign, dist, W.dense, W.small, W.ctr);
+  const int dgrid = (int)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(J.n, 256)));
+  if ((int64_t)k * F <= SIG_DENSE_MAX) {
+    // few seeds: comparing against every mode costs less than building and
+    // sorting per-row match lists
+    hipLaunchKernelGGL(k_sig_dense, dim3(dgrid), dim3(256), 0, s, J.sig, (int64_t)F, F, J.modes, k, nullptr,
+                       nullptr, J.n, J.assign, dist, W.ctr);
+  } else {
+    const int grid = J.n < 65536 ? (int)J.n : 65536;
+    hipLaunchKernelGGL(k_sig_assign, dim3(grid), dim3(64), 0, s, J.sig, (int64_t)F, F, J.n, W.hkey, W.hval,
+                       W.hmask, sj, J.assign, dist, W.dense, W.small, W.ctr);
+    hipLaunchKernelGGL(k_sig_dense, dim3(dgrid), dim3(256), 0, s, J.sig, (int64_t)F, F, J.modes, k, W.dense,
+                       W.small, (int64_t)0, J.assign, dist, W.ctr);
+  }
   prof_end(GEEK_PROF_ASSIGN_SCAN, s);
-  hipLaunchKernelGGL(k_sig_dense, dim3(1024), dim3(256), 0, s, J.sig, (int64_t)F, F, J.modes, k, W.dense, W.small,
-                     J.assign, dist, W.ctr);
   sse_and_radius(dist, J.assign, J.n, k, J.sse, J.radius, 0, W.sse_blk, s);
   if (J.counters) hipLaunchKernelGGL(k_copy_ctr, dim3(1), dim3(64), 0, s, W.ctr, J.counters);
   prof_end(GEEK_PROF_ASSIGN, s);

@@ -63,3 +63,23 @@ def test_sig_assign_ties_and_dense_fallback():
     sm = np.sort(g.choice(n, size=3 * k, replace=True).reshape(k, 3), axis=1).reshape(-1).astype(np.uint32)
     ctr = _check(api, sig, so, sm, "ties")
     assert ctr[2] > 0
+
+
+@pytest.mark.parametrize("alphabet", [100_000, 4])
+def test_sig_assign_many_seeds_index_path(alphabet):
+    # k * F above the direct-comparison limit: rows go through the inverted
+    # index on (position, mode value); with a 4-letter alphabet most rows'
+    # match lists overflow and fall back to comparing against every mode
+    api = gpu_api()
+    g = np.random.default_rng(11 + alphabet)
+    n, F, k = 600, 256, 4500
+    sig = g.integers(0, alphabet, size=(n, F)).astype(np.uint32)
+    sizes = g.integers(1, 4, size=k)
+    so = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
+    sm = np.concatenate([np.sort(g.choice(n, size=s, replace=False)) for s in sizes]).astype(np.uint32)
+    ctr = _check(api, sig, so, sm, f"index alphabet={alphabet}")
+    assert ctr[0] + ctr[2] == n
+    if alphabet > 4:
+        assert ctr[0] > 0  # resolved by the index
+    else:
+        assert ctr[2] > 0  # dense fallback

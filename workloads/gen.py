@@ -141,28 +141,101 @@ def _zipf_sampler(vocab, s):
     return cdf
 
 
-def _distinct_prefix_rows(cand, want):
-    """Row-wise: keep the first ``want[i]`` distinct values of ``cand[i]`` in
-    order of first appearance; returns a list of sorted uint32 arrays."""
-    n, w = cand.shape
-    out = []
-    for i in range(n):
-        _, first = np.unique(cand[i], return_index=True)
-        keep = cand[i][np.sort(first)][: want[i]]
-        out.append(np.sort(keep).astype(np.uint32))
-    return out
+def _first_distinct(rows, toks, quota, nrows):
+    """Flat candidates ``(rows, toks)`` in row-major order of appearance:
+    per row keep the first ``quota[row]`` distinct tokens in order of first
+    appearance; returns the kept flat indices in the same order."""
+    key = (rows.astype(np.int64) << 32) | toks.astype(np.int64)
+    order = np.argsort(key, kind="stable")          # ties keep appearance order
+    ks = key[order]
+    first = np.ones(len(ks), dtype=bool)
+    first[1:] = ks[1:] != ks[:-1]
+    keep = np.sort(order[first])                     # back to appearance order
+    kr = rows[keep]
+    start = np.searchsorted(kr, np.arange(nrows))    # rows are sorted in ``keep``
+    rank = np.arange(len(keep)) - start[kr]
+    return keep[rank < quota[kr]]
+
+
+def _first_distinct_t(rows, toks, quota, nrows):
+    """``_first_distinct`` on torch tensors (same rule)."""
+    import torch
+
+    key = (rows.to(torch.int64) << 32) | toks.to(torch.int64)
+    order = torch.argsort(key, stable=True)
+    ks = key[order]
+    first = torch.ones(len(ks), dtype=torch.bool, device=ks.device)
+    first[1:] = ks[1:] != ks[:-1]
+    keep = torch.sort(order[first]).values
+    kr = rows[keep]
+    start = torch.searchsorted(kr, torch.arange(nrows, device=kr.device))
+    rank = torch.arange(len(keep), device=kr.device) - start[kr]
+    return keep[rank < quota[kr]]
+
+
+def _sparse_sets_device(n, labels, s_all, p_toks, p_off, cdf, share, chunk, device, seed):
+    """The per-set draws of ``sparse_sets`` on a torch device (torch's
+    generator supplies the uniforms; the recipe is the same)."""
+    import torch
+
+    tg = torch.Generator(device=device)
+    tg.manual_seed(int(seed))
+    cdf_t = torch.from_numpy(cdf).to(device)
+    p_toks_t = torch.from_numpy(p_toks.astype(np.int64)).to(device)
+    p_off_t = torch.from_numpy(p_off).to(device)
+    labels_t = torch.from_numpy(labels).to(device)
+    s_t = torch.from_numpy(s_all).to(device)
+    vocab = len(cdf)
+
+    def zipf(size):
+        u = torch.rand(size, generator=tg, device=device, dtype=torch.float64)
+        return torch.clamp(torch.searchsorted(cdf_t, u), max=vocab - 1)
+
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    toks = []
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        m = c1 - c0
+        lab = labels_t[c0:c1]
+        s = s_t[c0:c1]
+        plen = p_off_t[lab + 1] - p_off_t[lab]
+        r = torch.minimum(torch.round(share * s.to(torch.float64)).to(torch.int64), plen)
+        npick = torch.where(r > 0, 2 * r + 8, torch.zeros_like(r))
+        ar = torch.arange(m, device=device)
+        prow = torch.repeat_interleave(ar, npick)
+        u = (torch.rand(len(prow), generator=tg, device=device, dtype=torch.float64) * plen[prow]).to(torch.int64)
+        ptok = p_toks_t[p_off_t[lab[prow]] + u]
+        pk = _first_distinct_t(prow, ptok, r, m)
+        prow, ptok = prow[pk], ptok[pk]
+        zrow = torch.repeat_interleave(ar, 3 * (s - r) + 16)
+        ztok = zipf(len(zrow))
+        allrow = torch.cat([prow, zrow])
+        alltok = torch.cat([ptok, ztok])
+        o = torch.argsort(allrow, stable=True)
+        allrow, alltok = allrow[o], alltok[o]
+        keep = _first_distinct_t(allrow, alltok, s, m)
+        krow, ktok = allrow[keep], alltok[keep]
+        o = torch.argsort((krow << 32) | ktok)
+        toks.append(ktok[o].to(torch.int32))
+        cnt = torch.bincount(krow, minlength=m)
+        offsets[c0 + 1:c1 + 1] = offsets[c0] + torch.cumsum(cnt, 0)
+    return offsets, torch.cat(toks)
 
 
 def sparse_sets(n, vocab=1_000_000, clusters=2_000, seed=0, mu=4.5, sig=0.6,
-                lo=5, hi=2000, zipf_s=1.1, share=0.6):
+                lo=5, hi=2000, zipf_s=1.1, share=0.6, chunk=50_000, device=None):
     """Sparse sets over ``[0, vocab)``: sizes lognormal(mu, sig) rounded and
     clipped to [lo, hi]; tokens Zipf(zipf_s) (token id = rank - 1); each set
     belongs to a uniformly drawn planted cluster and takes
-    ``min(round(share*s), |prototype|)`` tokens uniformly from the cluster's
-    prototype plus fresh Zipf tokens, deduplicated until the size is reached.
+    ``r = min(round(share*s), |prototype|)`` distinct tokens uniformly from
+    the cluster's prototype (draws with replacement, repeats skipped), then
+    fresh Zipf tokens, repeats skipped, until the size is reached.  Sets are
+    drawn ``chunk`` at a time with vectorized de-duplication.
 
     Returns ``(offsets int64 [n+1], tokens uint32 [nnz], labels)`` with every
-    set sorted ascending and free of repeats.
+    set sorted ascending and free of repeats; with ``device`` the per-set
+    draws run there and offsets / tokens (int32 bit patterns) are torch
+    tensors on it.
     """
     g = rng(seed, STREAM_DATA, 3)
     cdf = _zipf_sampler(vocab, zipf_s)
@@ -174,24 +247,54 @@ def sparse_sets(n, vocab=1_000_000, clusters=2_000, seed=0, mu=4.5, sig=0.6,
         s = np.rint(np.exp(g.normal(mu, sig, size=k))).astype(np.int64)
         return np.clip(s, lo, hi)
 
+    # prototypes: the first distinct Zipf draws
     proto_sizes = sizes(clusters)
-    protos = []
+    p_toks, p_off = [], [0]
     for c in range(clusters):
         want = int(proto_sizes[c])
         cand = zipf(want * 3 + 32)
-        protos.append(_distinct_prefix_rows(cand[None, :], [want])[0])
+        keep = _first_distinct(np.zeros(len(cand), np.int64), cand, np.array([want]), 1)
+        row = np.sort(cand[keep])
+        p_toks.append(row)
+        p_off.append(p_off[-1] + len(row))
+    p_toks = np.concatenate(p_toks).astype(np.uint32)
+    p_off = np.asarray(p_off, dtype=np.int64)
     labels = g.integers(0, clusters, size=n)
-    s = sizes(n)
+    s_all = sizes(n)
+    if device is not None:
+        off_t, tok_t = _sparse_sets_device(n, labels, s_all, p_toks, p_off, cdf, share, chunk, device,
+                                           g.integers(0, 2**62))
+        return off_t, tok_t, labels
     offsets = np.zeros(n + 1, dtype=np.int64)
     toks = []
-    for i in range(n):
-        P = protos[labels[i]]
-        r = min(int(round(share * s[i])), len(P))
-        pick = P[g.choice(len(P), size=r, replace=False)] if r > 0 else np.zeros(0, np.uint32)
-        cand = np.concatenate([pick, zipf(int(s[i] - r) * 3 + 16)])
-        row = _distinct_prefix_rows(cand[None, :], [int(s[i])])[0]
-        toks.append(row)
-        offsets[i + 1] = offsets[i] + len(row)
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        m = c1 - c0
+        lab = labels[c0:c1]
+        s = s_all[c0:c1]
+        plen = p_off[lab + 1] - p_off[lab]
+        r = np.minimum(np.rint(share * s).astype(np.int64), plen)
+        # prototype part: 2r + 8 uniform draws (with replacement), first r distinct
+        npick = np.where(r > 0, 2 * r + 8, 0)
+        prow = np.repeat(np.arange(m), npick)
+        u = (g.random(len(prow)) * plen[prow]).astype(np.int64)
+        ptok = p_toks[p_off[lab[prow]] + u]
+        pk = _first_distinct(prow, ptok, r, m)
+        prow, ptok = prow[pk], ptok[pk]
+        # fresh Zipf part: 3(s - r) + 16 draws; the whole row keeps its first s distinct
+        nz = 3 * (s - r) + 16
+        zrow = np.repeat(np.arange(m), nz)
+        ztok = zipf(len(zrow))
+        allrow = np.concatenate([prow, zrow])
+        alltok = np.concatenate([ptok, ztok])
+        o = np.argsort(allrow, kind="stable")        # row-major, prototype draws first
+        allrow, alltok = allrow[o], alltok[o]
+        keep = _first_distinct(allrow, alltok, s, m)
+        krow, ktok = allrow[keep], alltok[keep]
+        o = np.lexsort((ktok, krow))                   # sorted within each set
+        toks.append(ktok[o].astype(np.uint32))
+        cnt = np.bincount(krow, minlength=m)
+        offsets[c0 + 1:c1 + 1] = offsets[c0] + np.cumsum(cnt)
     return offsets, np.concatenate(toks).astype(np.uint32), labels
 
 
