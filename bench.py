@@ -45,10 +45,11 @@ def parse():
     ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets"],
+    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets", "silk"],
                     help="dense_large: the headline metric; batched: 256 mixed dense jobs in one "
                          "captured HIP graph; hetero: heterogeneous rows; sets: sparse sets "
-                         "(MinHash, band buckets, signature assignment)")
+                         "(MinHash, band buckets, signature assignment); silk: the whole GEEK pass "
+                         "with SILK seeds on the dense mixture at the scaled width")
     ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
     ap.add_argument("--hetero-fp8", action="store_true", help="hetero: FP8 first pass instead of BF16")
     return ap.parse_args()
@@ -98,6 +99,8 @@ def main():
         return bench_hetero(args)
     if args.workload == "sets":
         return bench_sets(args)
+    if args.workload == "silk":
+        return bench_silk(args)
     import numpy as np
     import torch
 
@@ -480,6 +483,73 @@ def bench_sets(args):
         "stages_ms": {"minhash": stages[0], "bucketize": stages[1], "assign": stages[2]},
         "minhash_evals_per_s": nnz * K * Lb / (stages[0] * 1e-3),
         "assign_counters": out["counters"].cpu().numpy().tolist(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_silk(args):
+    """The whole GEEK pass on the dense mixture (d = 128, Zipf cluster sizes,
+    clusters scaled with n) at the scaled E2LSH width w * sqrt(d): hash,
+    buckets of 32 tables, SILK seeds (K_S = 3, L_S = 20, delta = 10), then the
+    BF16 assignment to the SILK seeds.  SILK reads sizes back to the host
+    between its steps, so the pass is timed eagerly with events."""
+    import numpy as np
+    import torch
+
+    from paper_2106_10515_amd import _lib as L
+    from paper_2106_10515_amd import api
+    from workloads import CONFIGS, dense_mixture, e2lsh_params, key_words
+    from workloads.gen import STREAM_SILK
+
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS["dense_large"]
+    n = 1_000_000 if args.n == 10_000_000 else args.n
+    d, m, Lt = cfg["d"], cfg["m"], cfg["L"]
+    w = cfg["w"] * d ** 0.5
+    clusters = max(1, cfg["clusters"] * n // cfg["n"])
+    X, _, _ = dense_mixture(n, d, clusters, cfg["lo"], cfg["hi"], cfg["sigma"], cfg["sizes"], seed=0, device=dev)
+    A, b = e2lsh_params(m * Lt, d, w, 0)
+    Ag, bg = torch.from_numpy(A).to(dev), torch.from_numpy(b).to(dev)
+    K, LS, delta = cfg["K_S"], cfg["L_S"], cfg["delta"]
+    keys = torch.from_numpy(key_words((LS + 1) * K, 0, STREAM_SILK).view(np.int32)).to(dev)
+    status = api.new_status(dev)
+
+    def one():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        kg, _ = api.hash_dense(X, Ag, bg, m, Lt, w, status=status, check=False)
+        ev[1].record()
+        bm, bo, bn, _ = api.bucketize(kg, n, Lt, 4, n * 4, 4, want_bucket_of=False, status=status, check=False)
+        ev[2].record()
+        so, sm, ctr = api.silk_seeds(bm, bo, bn, n, Lt, K, LS, delta, keys, status=status, check=False)
+        ev[3].record()
+        k = len(so) - 1
+        out = api.assign_euclid(X, so, sm, k, L.GEEK_PREC_BF16, status=status, check=False) if k > 0 else None
+        ev[4].record()
+        torch.cuda.synchronize()
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(4)], k, ctr, out
+
+    for _ in range(args.warmup):
+        one()
+    api.check_status(status, "warmup")
+    runs = [one() for _ in range(args.steps)]
+    api.check_status(status, "timed")
+    st = np.median(np.array([r[0] for r in runs]), axis=0)
+    _, k, ctr, out = runs[-1]
+    total = float(st.sum())
+    line = {
+        "metric": "points/s (hash+bucketize+SILK+assign), whole GEEK pass",
+        "value": n / (total * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"silk: n={n} d={d} {clusters}-cluster Gaussian mixture (Zipf sizes), "
+                               f"E2LSH m={m} L={Lt} w={w:.2f} (scaled), SILK K={K} L={LS} delta={delta}",
+                   "n": n, "k_found": k},
+        "stages_ms": {"hash": float(st[0]), "bucketize": float(st[1]), "silk": float(st[2]),
+                      "assign": float(st[3])},
+        "silk_counters": ctr.cpu().numpy().tolist(),
+        "assign_counters": out["counters"].cpu().numpy().tolist() if out is not None else None,
+        "sse": float(out["sse"].item()) if out is not None else None,
     }
     print(json.dumps(line), flush=True)
 

@@ -198,9 +198,11 @@ typedef struct geek_silk_job {
  *   (each operation rounded, no fused multiply-add); lowest j on ties.
  *   The matrix cores compute an approximate D~ = |x|^2 - 2 x.c + |c|^2 in
  *   `precision`; every j whose D~ lies within a rigorous per-row error bound
- *   of the row minimum is re-evaluated with the float64 formula above, rows
- *   with more than 8 such candidates are rescanned (BF16/FP8: in FP32; FP32:
- *   in float64 over all seeds), so the assignment is exact.
+ *   of the row minimum is a candidate.  Rows with one candidate (BF16) or at
+ *   most 8 (FP8, FP32) have their candidates re-evaluated with the float64
+ *   formula above; the other rows are rescanned in FP32 keeping up to 32
+ *   candidates, and rows with still more are evaluated in float64 against
+ *   every seed, so the assignment is exact.
  * GEEK_METRIC_SIG: modes mode_j[f] = most frequent sig value of the members
  *   at position f (smallest value on ties); ID_i = argmax_j #{f : sig[i][f]
  *   == mode_j[f]} (lowest j on ties); dist = 1 - matches / F.

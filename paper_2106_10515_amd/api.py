@@ -185,19 +185,29 @@ def silk_seeds(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys,
     """SILK seeds.  Returns ``(seed_offsets [k+1], seed_members [N_C],
     counters [4])`` trimmed to the k seeds found."""
     dev = _dev(members)
+    auto = cap_k is None and cap_members is None
     cap_k = cap_k or max(1024, n // 4)
     cap_members = cap_members or max(4096, 2 * n)
-    so = torch.empty((cap_k + 1,), dtype=torch.int32, device=dev)
-    sm = torch.empty((cap_members,), dtype=torch.int32, device=dev)
-    k_out = torch.zeros((1,), dtype=torch.int32, device=dev)
-    needed = torch.zeros((2,), dtype=torch.int64, device=dev)
-    ctr = torch.zeros((4,), dtype=torch.int64, device=dev)
     status = new_status(dev) if status is None else status
-    j = L.SilkJob(n=n, T=T, K=K, members=_p(members), offsets=_p(offsets), nbuckets=_p(nbuckets),
-                  L=L_silk, delta=delta, silk_keys=_p(silk_keys), cap_k=cap_k,
-                  cap_members=cap_members, seed_offsets=_p(so), seed_members=_p(sm),
-                  k_out=_p(k_out), needed=_p(needed), counters=_p(ctr))
-    _run(L.GEEK_OP_SILK, L.geek_silk_seeds, [j], dev, status)
+    for attempt in range(4):
+        so = torch.empty((cap_k + 1,), dtype=torch.int32, device=dev)
+        sm = torch.empty((cap_members,), dtype=torch.int32, device=dev)
+        k_out = torch.zeros((1,), dtype=torch.int32, device=dev)
+        needed = torch.zeros((2,), dtype=torch.int64, device=dev)
+        ctr = torch.zeros((4,), dtype=torch.int64, device=dev)
+        j = L.SilkJob(n=n, T=T, K=K, members=_p(members), offsets=_p(offsets), nbuckets=_p(nbuckets),
+                      L=L_silk, delta=delta, silk_keys=_p(silk_keys), cap_k=cap_k,
+                      cap_members=cap_members, seed_offsets=_p(so), seed_members=_p(sm),
+                      k_out=_p(k_out), needed=_p(needed), counters=_p(ctr))
+        _run(L.GEEK_OP_SILK, L.geek_silk_seeds, [j], dev, status)
+        # default capacities too small: the call reported what it needs (first
+        # for the intermediate multiset, then for the seeds); call again
+        if auto and attempt < 3 and int(status.item()) == L.GEEK_ERR_CAPACITY:
+            nk, nm = (int(v) for v in needed.cpu().tolist())
+            cap_k, cap_members = max(cap_k, nk), max(cap_members, nm)
+            status.zero_()
+            continue
+        break
     if check:
         check_status(status, "geek_silk_seeds")
     k = int(k_out.item())

@@ -9,7 +9,7 @@
 //                 a block of rows.  Float32: per row it keeps every centroid
 //                 whose approximate distance lies within 2*eps_i of the
 //                 running minimum (eps_i a rigorous bound of the approximation
-//                 error), up to TCAND candidates.  BF16/FP8 first passes keep
+//                 error), up to TCAND32 candidates.  BF16/FP8 first passes keep
 //                 only the best and second-best values (branch-free); a row
 //                 is settled when the runner-up lies beyond 2*eps_i, else it
 //                 is rescanned in float32.
@@ -33,7 +33,9 @@
 
 namespace geek {
 
-constexpr int TCAND = 8;
+constexpr int TCAND = 8;       // candidates per lane window, BF16/FP8 passes
+constexpr int TCAND32 = 32;    // float32 pass (also the rescan of ambiguous rows)
+constexpr int RECW = TCAND32 + 1;  // candidate record per row: count, then ids
 constexpr int SSE_BLOCK = 4096;
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_BC = 64;   // centroids per LDS stage
@@ -260,7 +262,7 @@ GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
 // from LDS feeds NCB MFMAs.  With NBUF = 2 the next stage of centroids is
 // in flight while the current one is consumed (LDS DMA where rows are at
 // least 64 bytes, else through registers).
-template <class M, int DP, bool HET, int NCB, int NBUF, bool T2>
+template <class M, int DP, bool HET, int NCB, int NBUF, bool T2, bool WIDE>
 __device__ __forceinline__ void scan_tiles(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n_rows,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
@@ -281,8 +283,11 @@ __device__ __forceinline__ void scan_tiles(
   __shared__ __attribute__((aligned(16))) CE lds_c[NBUF][SCAN_BC * STR];
   __shared__ float lds_nc[NBUF][SCAN_BC];
   __shared__ uint32_t lds_mode[HET ? NBUF : 1][HET ? SCAN_BC * MAX_CAT : 1];
-  __shared__ float lds_lv[T2 ? 1 : SCAN_THREADS * NCB * TCAND];
-  __shared__ int lds_lj[T2 ? 1 : SCAN_THREADS * NCB * TCAND];
+  // window capacity per lane: the rescan of rows whose first-pass window was
+  // ambiguous keeps more candidates
+  constexpr int TC = WIDE ? TCAND32 : TCAND;
+  __shared__ float lds_lv[T2 ? 1 : SCAN_THREADS * NCB * TC];
+  __shared__ int lds_lj[T2 ? 1 : SCAN_THREADS * NCB * TC];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -532,8 +537,8 @@ __device__ __forceinline__ void scan_tiles(
             vmin = fminf(vmin, v[r]);
           }
           if (vmin <= thr[cb]) {
-            float* lv = lds_lv + (tid * NCB + cb) * TCAND;
-            int* lj = lds_lj + (tid * NCB + cb) * TCAND;
+            float* lv = lds_lv + (tid * NCB + cb) * TC;
+            int* lj = lds_lj + (tid * NCB + cb) * TC;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               if (v[r] <= thr[cb]) {
@@ -542,10 +547,10 @@ __device__ __forceinline__ void scan_tiles(
                   b0[cb] = v[r];
                   thr[cb] = b0[cb] + twoeps[cb];
                 }
-                if (cnt[cb] == TCAND) {
+                if (cnt[cb] == TC) {
                   int kept = 0;
 #pragma unroll 1
-                  for (int q = 0; q < TCAND; ++q) {
+                  for (int q = 0; q < TC; ++q) {
                     const float ev = lv[q];
                     const int ej = lj[q];
                     if (ev <= thr[cb]) {
@@ -556,7 +561,7 @@ __device__ __forceinline__ void scan_tiles(
                   }
                   cnt[cb] = kept;
                 }
-                if (cnt[cb] < TCAND) {
+                if (cnt[cb] < TC) {
                   lv[cnt[cb]] = v[r];
                   lj[cnt[cb]] = j;
                   ++cnt[cb];
@@ -603,7 +608,7 @@ __device__ __forceinline__ void scan_tiles(
         const bool unique = best > -1e37f && best < 1e37f && fabsf(best) >= 0x1p-126f && isfinite(v1) &&
                             v2 > v1 + twoeps[cb] && jbest < k;
         if (valid[cb] && h == 0) {
-          int32_t* rr = rec + posv[cb] * (TCAND + 1);
+          int32_t* rr = rec + posv[cb] * RECW;
           rr[0] = unique ? 1 : -1;
           if (unique) rr[1] = jbest;
         }
@@ -611,8 +616,8 @@ __device__ __forceinline__ void scan_tiles(
     } else {
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      float* lv = lds_lv + (tid * NCB + cb) * TCAND;
-      int* lj = lds_lj + (tid * NCB + cb) * TCAND;
+      float* lv = lds_lv + (tid * NCB + cb) * TC;
+      int* lj = lds_lj + (tid * NCB + cb) * TC;
       const float bo = __shfl_xor(b0[cb], 32);
       const float bfin = fminf(b0[cb], bo);
       const float tfin = bfin < INFINITY ? bfin + twoeps[cb] : 3.402823466e38f;
@@ -629,9 +634,9 @@ __device__ __forceinline__ void scan_tiles(
       const int kept_o = __shfl_xor(kept, 32);
       const float lost_all = fminf(lost[cb], __shfl_xor(lost[cb], 32));
       // complete unless a dropped value could still be a candidate
-      const bool over = lost_all <= tfin || (kept + kept_o > TCAND);
+      const bool over = lost_all <= tfin || (kept + kept_o > TC);
       if (valid[cb]) {
-        int32_t* rr = rec + posv[cb] * (TCAND + 1);
+        int32_t* rr = rec + posv[cb] * RECW;
         if (over) {
           if (h == 0) rr[0] = -1;
         } else {
@@ -649,14 +654,14 @@ __device__ __forceinline__ void scan_tiles(
 #undef GEEK_STORE_LDS
 #undef GEEK_DMA_STAGE
 
-template <class M, int DP, bool HET, int NCB, int NBUF, bool T2>
+template <class M, int DP, bool HET, int NCB, int NBUF, bool T2, bool WIDE>
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n_rows,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
     const typename M::ce* __restrict__ cl, const float* __restrict__ nc, int k_pad,
     const float* __restrict__ cmax_p, const float* __restrict__ scale_p, Het het, int k,
     int32_t* __restrict__ rec, int32_t* st) {
-  scan_tiles<M, DP, HET, NCB, NBUF, T2>(X, ldx, d, n_rows, rows, rows_count, cl, nc, k_pad, cmax_p, scale_p, het,
+  scan_tiles<M, DP, HET, NCB, NBUF, T2, WIDE>(X, ldx, d, n_rows, rows, rows_count, cl, nc, k_pad, cmax_p, scale_p, het,
                                         k, rec, st, blockIdx.x, INT64_MAX, gridDim.x);
 }
 
@@ -699,7 +704,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_batch(const ScanJob* __re
     }
     const ScanJob J = jobs[lo];
     const int64_t tile = gt - J.tile_begin;
-    scan_tiles<M, DP, false, NCB, NBUF, T2>(J.X, J.ldx, J.d, J.n, nullptr, nullptr,
+    scan_tiles<M, DP, false, NCB, NBUF, T2, false>(J.X, J.ldx, J.d, J.n, nullptr, nullptr,
                                             static_cast<const typename M::ce*>(J.cl), J.nc, J.k_pad, J.cmax,
                                             J.scale, none, J.k, J.rec, st, tile, tile + 1, 1);
   }
@@ -773,7 +778,7 @@ __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
     unsigned long long nrow = 0, ncand = 0;
     if (pos < count) {
       const int64_t i = rows ? (int64_t)rows[pos] : pos;
-      const int32_t* rr = rec + pos * (TCAND + 1);
+      const int32_t* rr = rec + pos * RECW;
       const int c = rr[0];
       if (c <= 0) {  // window overflow (or no finite candidate): escalate
         const uint32_t q = atomicAdd(esc_count, 1u);
@@ -983,7 +988,7 @@ static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
   out->cllow = c.take<char>(low ? k_pad * DP * low : 16);
   out->nc = c.take<float>(k_pad);
   out->cmax = c.take<float>(4);
-  out->rec = c.take<int32_t>(J.n * (TCAND + 1));
+  out->rec = c.take<int32_t>(J.n * RECW);
   out->esc = c.take<uint32_t>(J.n);
   out->fb = c.take<uint32_t>(J.n);
   out->counts = c.take<uint32_t>(4);
@@ -1025,7 +1030,7 @@ int scan_rows_per_tile(bool het_on) {
   return 128 * (het_on ? ScanShape<M, true>::NCB : ScanShape<M, false>::NCB);
 }
 
-template <class M, bool HET>
+template <class M, bool HET, bool WIDE>
 static void launch_scan(int DP, int grid, hipStream_t s, const geek_assign_job& J, int64_t n_rows,
                         const uint32_t* rows, const uint32_t* rows_count, const void* cl, const AssignWs& W,
                         int k_pad, const Het& het, int32_t* st) {
@@ -1035,7 +1040,7 @@ static void launch_scan(int DP, int grid, hipStream_t s, const geek_assign_job& 
   switch (DP) {
 #define GEEK_SCAN_CASE(DPV)                                                                            \
   case DPV:                                                                                            \
-    hipLaunchKernelGGL((k_scan<M, DPV, HET, NCB, NBUF, T2>), dim3(grid), dim3(SCAN_THREADS), 0, s, J.X,\
+    hipLaunchKernelGGL((k_scan<M, DPV, HET, NCB, NBUF, T2, WIDE>), dim3(grid), dim3(SCAN_THREADS), 0, s, J.X,\
                        J.ldx, J.d, n_rows, rows, rows_count, static_cast<const CE*>(cl), W.nc, k_pad,  \
                        W.cmax, W.cmax + 3, het, J.k, W.rec, st);                                       \
     break;
@@ -1047,14 +1052,14 @@ static void launch_scan(int DP, int grid, hipStream_t s, const geek_assign_job& 
   }
 }
 
-template <class M>
+template <class M, bool WIDE = false>
 static void scan_any(bool het_on, int DP, int grid, hipStream_t s, const geek_assign_job& J, int64_t n_rows,
                      const uint32_t* rows, const uint32_t* rows_count, const void* cl, const AssignWs& W,
                      int k_pad, const Het& het, int32_t* st) {
   if (het_on)
-    launch_scan<M, true>(DP, grid, s, J, n_rows, rows, rows_count, cl, W, k_pad, het, st);
+    launch_scan<M, true, WIDE>(DP, grid, s, J, n_rows, rows, rows_count, cl, W, k_pad, het, st);
   else
-    launch_scan<M, false>(DP, grid, s, J, n_rows, rows, rows_count, cl, W, k_pad, het, st);
+    launch_scan<M, false, WIDE>(DP, grid, s, J, n_rows, rows, rows_count, cl, W, k_pad, het, st);
 }
 
 // Per-job state between the three phases of an assignment.
@@ -1134,20 +1139,14 @@ static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, h
   AssignWs& W = C.W;
   unsigned long long* ctr = W.ctr;
   const int nb_rows = ceil_div(J.n, 256);
-  if (low_precision(J)) {
-    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
-                       nullptr, nullptr, W.rec, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
-    // rows with several low-precision candidates: float32 rescan of those rows
-    // (persistent grids, at most one row tile / row block per workgroup)
-    scan_any<ModeF32>(C.het_on, C.DP, esc_grid(J.n, 128), s, J, 0, W.esc, W.counts + 0, W.cl32, W, C.k_pad,
-                      C.het, st);
-    hipLaunchKernelGGL(k_finalize, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
-                       C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr,
-                       1);
-  } else {
-    hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
-                       nullptr, nullptr, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 0);
-  }
+  hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
+                     nullptr, nullptr, W.rec, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
+  // rows with several first-pass candidates: float32 rescan of those rows with
+  // a wider window (persistent grids, at most one row tile / block per group)
+  scan_any<ModeF32, true>(C.het_on, C.DP, esc_grid(J.n, 128), s, J, 0, W.esc, W.counts + 0, W.cl32, W, C.k_pad,
+                          C.het, st);
+  hipLaunchKernelGGL(k_finalize, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
+                     C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 1);
   hipLaunchKernelGGL(k_fallback64, dim3(esc_grid(J.n, 1)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
                      C.het, W.fb, W.counts + 1, J.assign, C.dist, ctr);
   sse_and_radius(C.dist, J.assign, J.n, J.k, J.sse, J.radius, C.het_on ? 0 : 1, W.sse_blk, s);
