@@ -745,15 +745,20 @@ GEEK_D double d64(const float* __restrict__ xr, const double* __restrict__ cr, i
   return acc;
 }
 
+// Categorical attributes of row i that differ from seed j's modes.
+GEEK_D int mismatches(const Het& het, int64_t i, int j) {
+  int mm = 0;
+  for (int a = 0; a < het.n_cat; ++a)
+    mm += ((uint32_t)het.cat[i * het.n_cat + a] != het.mode[(int64_t)j * het.n_cat + a]) ? 1 : 0;
+  return mm;
+}
+
 // D_num + gamma * mismatches, in that float64 order (reference formula).
 GEEK_D double d64h(const float* __restrict__ xr, const double* __restrict__ cr, int d, const Het& het,
                    int64_t i, int j) {
   const double dn = d64(xr, cr, d);
   if (!het.cat) return dn;
-  int mm = 0;
-  for (int a = 0; a < het.n_cat; ++a)
-    mm += ((uint32_t)het.cat[i * het.n_cat + a] != het.mode[(int64_t)j * het.n_cat + a]) ? 1 : 0;
-  return __dadd_rn(dn, __dmul_rn(het.gamma, (double)mm));
+  return __dadd_rn(dn, __dmul_rn(het.gamma, (double)mismatches(het, i, j)));
 }
 
 __device__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
@@ -810,49 +815,213 @@ __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
   }
 }
 
-// One block per row: float64 distance to every centroid, lowest index on ties.
+// Rows left after the rescans: float64 distance to every seed, lowest index on
+// ties.  A workgroup takes FB_R rows and a range of FB_C-seed tiles; each
+// thread holds a 4 x 4 block of (row, seed) sums with both operands staged in
+// LDS, so one read of a seed row from L2 serves FB_R rows.  Every sum runs
+// over t = 0..d-1 in order with the operations of d64 (the zero padding of
+// t >= d adds +0.0, which leaves a sum of squares unchanged), so the values
+// are those of the reference formula.  With fewer row groups than workgroups
+// the seed tiles of a group are split over up to FB_SPLIT workgroups, whose
+// per-row (D, j) minima k_fb_merge combines.
+constexpr int FB_R = 64, FB_C = 64, FB_TK = 16, FB_GRID = 1024, FB_SPLIT = 16;
+constexpr int FB_XS = FB_R + 4;  // LDS row stride (floats) of the staged rows
+constexpr int FB_CS = FB_C + 2;  // LDS row stride (doubles) of a seed chunk
+
+// Row groups and seed-tile splits for `count` rows against k seeds.
+GEEK_HD void fb_shape(uint32_t count, int k, int64_t* R, int* S) {
+  *R = ((int64_t)count + FB_R - 1) / FB_R;
+  const int T = (k + FB_C - 1) / FB_C;
+  int sp = 1;
+  if (*R > 0 && *R < FB_GRID) {
+    const int want = (int)((FB_GRID + *R - 1) / *R);
+    sp = want < T ? want : T;
+    if (sp > FB_SPLIT) sp = FB_SPLIT;
+    if (sp < 1) sp = 1;
+  }
+  *S = sp;
+}
+
+// Capacity (entries) of the partial minima buffer for n rows.
+inline int64_t fb_part_cap(int64_t n) {
+  return std::max<int64_t>(1, std::min<int64_t>(n * FB_SPLIT, (int64_t)2 * FB_GRID * FB_R));
+}
+
+template <int DP>
 __global__ __launch_bounds__(256) void k_fallback64(
     const float* __restrict__ X, int64_t ldx, int d, const double* __restrict__ C, int k, Het het,
-    const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
-    int32_t* __restrict__ assign, double* __restrict__ dist, unsigned long long* __restrict__ ctr) {
-  __shared__ __attribute__((aligned(16))) float xs[1024];
-  __shared__ double bd[256];
-  __shared__ int bjs[256];
+    const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count, int32_t* __restrict__ assign,
+    double* __restrict__ dist, double* __restrict__ part_d, int32_t* __restrict__ part_j,
+    unsigned long long* __restrict__ ctr) {
+  constexpr int XS_WORDS = DP * FB_XS > FB_R * 16 * 3 ? DP * FB_XS : FB_R * 16 * 3;
+  __shared__ __attribute__((aligned(16))) float xs[XS_WORDS];  // [t][row]; later the reduction
+  __shared__ __attribute__((aligned(16))) double cs[FB_TK * FB_CS];  // [t][seed]
+  __shared__ int64_t rid[FB_R];
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;  // rows 4tr..4tr+3, seeds 4tc..4tc+3 of a tile
   const uint32_t count = *rows_count;
-  for (uint32_t pos = blockIdx.x; pos < count; pos += gridDim.x) {
-    const int64_t i = rows[pos];
-    __syncthreads();
-    for (int t = threadIdx.x; t < d; t += blockDim.x) xs[t] = X[i * ldx + t];
-    __syncthreads();
-    double best = INFINITY;
-    int bj = 0x7fffffff;
-    for (int j = threadIdx.x; j < k; j += blockDim.x) {
-      const double D = d64h(xs, C + (int64_t)j * d, d, het, i, j);
-      if (D < best) {  // j increases along this thread: strict keeps the lowest
-        best = D;
-        bj = j;
-      }
+  int64_t R;
+  int S;
+  fb_shape(count, k, &R, &S);
+  const int T = (k + FB_C - 1) / FB_C;
+  const int dp16 = (d + FB_TK - 1) / FB_TK * FB_TK;
+  const int nch = dp16 / FB_TK;
+  for (int64_t q = blockIdx.x; q < R * S; q += gridDim.x) {
+    const int64_t g = q / S;
+    const int sp = (int)(q % S);
+    const int tile0 = (int)((int64_t)sp * T / S), tile1 = (int)((int64_t)(sp + 1) * T / S);
+    __syncthreads();  // the previous item's reduction has read xs and rid
+    if (tid < FB_R) {
+      const int64_t pos = g * FB_R + tid;
+      rid[tid] = pos < count ? (int64_t)rows[pos] : -1;
     }
-    bd[threadIdx.x] = best;
-    bjs[threadIdx.x] = bj;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) {
-        const double od = bd[threadIdx.x + o];
-        const int oj = bjs[threadIdx.x + o];
-        if (od < bd[threadIdx.x] || (od == bd[threadIdx.x] && oj < bjs[threadIdx.x])) {
-          bd[threadIdx.x] = od;
-          bjs[threadIdx.x] = oj;
+    for (int idx = tid; idx < FB_R * dp16; idx += 256) {
+      const int r = idx / dp16, t = idx - r * dp16;
+      const int64_t i = rid[r];
+      xs[t * FB_XS + r] = (i >= 0 && t < d) ? X[i * ldx + t] : 0.f;
+    }
+    double best[4];
+    int bj[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      best[a] = INFINITY;
+      bj[a] = 0x7fffffff;
+    }
+    // register prefetch of the next (tile, chunk) of seeds
+    double pre[4];
+    auto fetch = [&](int tile, int ch) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = tid + u * 256;
+        const int jj = idx >> 4, tt = idx & 15;
+        const int j = tile * FB_C + jj, t = ch * FB_TK + tt;
+        pre[u] = (j < k && t < d) ? C[(int64_t)j * d + t] : 0.0;
+      }
+    };
+    if (tile0 < tile1) fetch(tile0, 0);
+    for (int tile = tile0; tile < tile1; ++tile) {
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      for (int ch = 0; ch < nch; ++ch) {
+        __syncthreads();  // readers of the previous chunk are done (and xs is staged)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int idx = tid + u * 256;
+          cs[(idx & 15) * FB_CS + (idx >> 4)] = pre[u];
+        }
+        __syncthreads();
+        if (ch + 1 < nch) fetch(tile, ch + 1);
+        else if (tile + 1 < tile1) fetch(tile + 1, 0);
+        const float* xp = xs + ch * FB_TK * FB_XS + tr * 4;
+        const double* cp = cs + tc * 4;
+#pragma unroll 4
+        for (int tt = 0; tt < FB_TK; ++tt) {
+          const float4 xv = *reinterpret_cast<const float4*>(xp + tt * FB_XS);
+          const double2 c01 = *reinterpret_cast<const double2*>(cp + tt * FB_CS);
+          const double2 c23 = *reinterpret_cast<const double2*>(cp + tt * FB_CS + 2);
+          const double xd[4] = {(double)xv.x, (double)xv.y, (double)xv.z, (double)xv.w};
+          const double cd[4] = {c01.x, c01.y, c23.x, c23.y};
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const double delta = __dadd_rn(xd[a], -cd[b]);
+              acc[a][b] = __dadd_rn(acc[a][b], __dmul_rn(delta, delta));
+            }
         }
       }
-      __syncthreads();
+      // j increases along this thread's sequence: strict < keeps the lowest
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int64_t i = rid[tr * 4 + a];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = tile * FB_C + tc * 4 + b;
+          if (j >= k) continue;
+          double D = acc[a][b];
+          if (het.cat && i >= 0) D = __dadd_rn(D, __dmul_rn(het.gamma, (double)mismatches(het, i, j)));
+          if (D < best[a]) {
+            best[a] = D;
+            bj[a] = j;
+          }
+        }
+      }
     }
-    if (threadIdx.x == 0) {
-      // no finite distance (non-finite input, already flagged): centroid 0
-      assign[i] = bjs[0] == 0x7fffffff ? 0 : bjs[0];
-      dist[i] = bd[0];
-      if (ctr) atomicAdd(ctr + 2, 1ull);
+    // combine the 16 column threads of each row, in seed order
+    __syncthreads();
+    double* red_d = reinterpret_cast<double*>(xs);
+    int* red_j = reinterpret_cast<int*>(xs + FB_R * 16 * 2);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      red_d[(tr * 4 + a) * 16 + tc] = best[a];
+      red_j[(tr * 4 + a) * 16 + tc] = bj[a];
     }
+    __syncthreads();
+    unsigned long long done = 0;
+    if (tid < FB_R && rid[tid] >= 0) {
+      double bd = INFINITY;
+      int bb = 0x7fffffff;
+      for (int c = 0; c < 16; ++c) {
+        const double od = red_d[tid * 16 + c];
+        const int oj = red_j[tid * 16 + c];
+        if (od < bd || (od == bd && oj < bb)) {
+          bd = od;
+          bb = oj;
+        }
+      }
+      const int64_t i = rid[tid];
+      if (S == 1) {
+        // no finite distance (non-finite input, already flagged): seed 0
+        assign[i] = bb == 0x7fffffff ? 0 : bb;
+        dist[i] = bd;
+        done = 1;
+      } else {
+        const int64_t e = (g * FB_R + tid) * S + sp;
+        part_d[e] = bd;
+        part_j[e] = bb;
+      }
+    }
+    if (ctr && tid < 64) block_add_u64(ctr + 2, done);
+  }
+}
+
+// Per-row minimum over the seed-tile splits of k_fallback64 (split order is
+// seed order, so (D, j) comparison keeps the lowest index on ties).
+__global__ void k_fb_merge(const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count, int k,
+                           const double* __restrict__ part_d, const int32_t* __restrict__ part_j,
+                           int32_t* __restrict__ assign, double* __restrict__ dist,
+                           unsigned long long* __restrict__ ctr) {
+  const uint32_t count = *rows_count;
+  int64_t R;
+  int S;
+  fb_shape(count, k, &R, &S);
+  if (S == 1) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t iters = ((int64_t)count + stride - 1) / stride;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t pos = it * stride + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    unsigned long long done = 0;
+    if (pos < count) {
+      double bd = INFINITY;
+      int bb = 0x7fffffff;
+      for (int sp = 0; sp < S; ++sp) {
+        const double od = part_d[pos * S + sp];
+        const int oj = part_j[pos * S + sp];
+        if (od < bd || (od == bd && oj < bb)) {
+          bd = od;
+          bb = oj;
+        }
+      }
+      const int64_t i = rows[pos];
+      assign[i] = bb == 0x7fffffff ? 0 : bb;
+      dist[i] = bd;
+      done = 1;
+    }
+    if (ctr) block_add_u64(ctr + 2, done);
   }
 }
 
@@ -971,6 +1140,8 @@ struct AssignWs {
   uint32_t* esc;
   uint32_t* fb;
   uint32_t* counts;  // [0] esc count, [1] fb count
+  double* part_d;    // per-split minima of the float64 full scans
+  int32_t* part_j;
   unsigned long long* ctr;
   double* dist;
   double* sse_blk;
@@ -992,6 +1163,8 @@ static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
   out->esc = c.take<uint32_t>(J.n);
   out->fb = c.take<uint32_t>(J.n);
   out->counts = c.take<uint32_t>(4);
+  out->part_d = c.take<double>(fb_part_cap(J.n));
+  out->part_j = c.take<int32_t>(fb_part_cap(J.n));
   out->ctr = c.take<unsigned long long>(4);
   out->dist = c.take<double>(J.dist ? 1 : J.n);
   out->sse_blk = c.take<double>((J.n + SSE_BLOCK - 1) / SSE_BLOCK + 1);
@@ -1147,8 +1320,21 @@ static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, h
                           C.het, st);
   hipLaunchKernelGGL(k_finalize, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
                      C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 1);
-  hipLaunchKernelGGL(k_fallback64, dim3(esc_grid(J.n, 1)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
-                     C.het, W.fb, W.counts + 1, J.assign, C.dist, ctr);
+  const int fb_grid = (int)std::min<int64_t>(FB_GRID, ceil_div(J.n, FB_R) * FB_SPLIT);
+  switch (C.DP) {
+#define GEEK_FB_CASE(DPV)                                                                                  \
+  case DPV:                                                                                                \
+    hipLaunchKernelGGL(k_fallback64<DPV>, dim3(fb_grid), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, \
+                       C.het, W.fb, W.counts + 1, J.assign, C.dist, W.part_d, W.part_j, ctr);               \
+    break;
+    GEEK_FB_CASE(32)
+    GEEK_FB_CASE(64)
+    GEEK_FB_CASE(128)
+    GEEK_FB_CASE(256)
+#undef GEEK_FB_CASE
+  }
+  hipLaunchKernelGGL(k_fb_merge, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, W.fb, W.counts + 1, J.k, W.part_d,
+                     W.part_j, J.assign, C.dist, ctr);
   sse_and_radius(C.dist, J.assign, J.n, J.k, J.sse, J.radius, C.het_on ? 0 : 1, W.sse_blk, s);
   if (J.counters) hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(64), 0, s, ctr, J.counters, 4);
   if (J.t_done) {

@@ -85,6 +85,29 @@ def test_assign_ties_and_degenerate(prec):
     _check(api, X[:1], np.array([0, 1], np.uint32), np.array([0], np.uint32), prec, "n=1")
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,d,clusters,copies,seed", [
+    (3000, 32, 10, 36, 8),     # 47 row groups: seed tiles split over workgroups
+    (2000, 100, 40, 36, 9),    # k = 1440 (23 tiles) in 16 uneven splits, d padded
+    (70000, 16, 10, 34, 10),   # 1094 row groups: no split, direct writes
+])
+def test_assign_full_scan_rows(prec, n, d, clusters, copies, seed):
+    # every planted seed repeated `copies` (> 32) times: each row keeps more
+    # exact ties than any candidate window, so every row takes the float64
+    # scan over all seeds and must land on the first copy
+    api = gpu_api()
+    X, lab, _ = dense_mixture(n, d, clusters, -10, 10, 1.0, "equal", seed)
+    so1, sm1 = planted_seeds(lab, clusters, 6)
+    offs, mem = [0], []
+    for c in range(len(so1) - 1):
+        for _ in range(copies):
+            mem.append(sm1[so1[c]:so1[c + 1]])
+            offs.append(offs[-1] + len(mem[-1]))
+    so, sm = np.asarray(offs, np.uint32), np.concatenate(mem).astype(np.uint32)
+    ctr = _check(api, X, so, sm, prec, f"full-scan copies={copies}")
+    assert ctr[2] == n
+
+
 def test_assign_nonfinite_input_is_reported():
     api = gpu_api()
     from paper_2106_10515_amd import GeekError
