@@ -6,8 +6,10 @@
 // differs from the float64 reference quotient (sum over t in order, + b, / w)
 // by at most tau = c * (|a_p| |x_i| + |b_p|) / w, so when [q - tau, q + tau]
 // holds no integer the float32 floor equals the reference floor.  Otherwise
-// the pair is recomputed in float64 in exactly the reference order.  The m
-// codes of each table are then packed into a 128-bit exact key.
+// the pair gets a float64 dot product (16 lanes, FMA), certified the same way
+// with a radius of a few float64 ulps, and only the pairs that this leaves
+// open are summed in exactly the reference order.  The m codes of each table
+// are then packed into a 128-bit exact key.
 //
 // MinHash of sets / heterogeneous rows: one wavefront per object; lane f
 // handles functions f, f+64, ...; the tokens of the object are loaded once
@@ -26,6 +28,7 @@ constexpr int H_BN = 128;   // points per block
 constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks)
 constexpr int H_FIXCAP = 4096;  // fix-up list entries per round
 constexpr int H_CS = H_BC + 1;  // LDS stride of a point's codes (odd: conflict-free stores)
+constexpr int H_KB = 16;        // products per accumulation block of the GEMM
 
 // Exclusive scan over a 256-thread block; *total = block sum.
 __device__ uint32_t block_exscan256(uint32_t v, uint32_t* total, uint32_t* sh) {
@@ -53,7 +56,7 @@ __device__ uint32_t block_exscan256(uint32_t v, uint32_t* total, uint32_t* sh) {
 }
 
 template <int DP>
-__global__ __launch_bounds__(H_THREADS) void k_e2lsh(
+__global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n, const float* __restrict__ A,
     const float* __restrict__ bvec, const float* __restrict__ anorm, int m, int L, float w,
     int tpc, uint32_t* __restrict__ keys, int32_t* __restrict__ codes_out,
@@ -66,6 +69,8 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
   __shared__ __attribute__((aligned(16))) float lds_b[H_BC];
   __shared__ __attribute__((aligned(16))) float lds_t1[H_BC];
   __shared__ __attribute__((aligned(16))) float lds_t0[H_BC];
+  __shared__ float lds_an[H_BC];   // |a_p| (rounded up) per row of the chunk
+  __shared__ float lds_xn[H_BN];   // |x_i| (rounded up) per point of the block
   // codes of a point are H_CS ints apart: the epilogue's stores (one row,
   // 32 points per instruction) then fall into distinct banks
   __shared__ int lds_code[H_BN * H_CS];
@@ -119,12 +124,19 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
   if (!finite) set_status(st, GEEK_ERR_NONFINITE);
   nrm += __shfl_xor(nrm, 32);
   const float xn = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
-  // |q32 - q64| <= coef * (|a||x| + |b|) / w: float32 GEMM (2u per step,
-  // d+1 steps), + b, * (1/w) with 1/w rounded, float64 reference rounding.
+  if (h == 0) lds_xn[wv * 32 + p] = xn;
+  // |q32 - q64| <= coef * (|a||x| + |b|) / w.  The GEMM sums blocks of
+  // H_KB products in fresh accumulators and then adds the block sums, so a
+  // product passes through at most H_KB + DP/H_KB + 1 roundings (2u each,
+  // b included); then * (1/w) with 1/w rounded, and the float64 reference's
+  // own rounding.
   const double u32 = 0x1p-24;
-  const double coef_d = ((DP + 1) * 2.0 * u32 / (1.0 - (DP + 1) * 2.0 * u32) + 6.0 * u32 +
-                         (DP + 3) * 0x1p-53) * 1.01;
+  constexpr int NR = H_KB + DP / H_KB + 1;
+  const double coef_d = (NR * 2.0 * u32 / (1.0 - NR * 2.0 * u32) + 6.0 * u32 + (DP + 3) * 0x1p-53) * 1.01;
   const float coef = (float)coef_d;
+  // second stage (float64 dot of 16 partial sums, FMA): |q_fast - q64| <=
+  // coef64 * (|a||x| + |b|) / w, covering both float64 evaluations
+  const double coef64 = ((DP / 16 + 6) + (DP + 3)) * 0x1p-53 * 1.02;
 
   const float tscale = coef * inv_w;
   const bool a_vec = ((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
@@ -158,6 +170,7 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
       const float bv = live ? bvec[p0 + tid] : 0.f;
       lds_b[tid] = bv;
       lds_t1[tid] = live ? tscale * anorm[p0 + tid] : 0.f;
+      lds_an[tid] = live ? anorm[p0 + tid] : 0.f;
       lds_t0[tid] = live ? __builtin_fmaf(tscale, fabsf(bv), 0x1p-22f) : 0.f;
     }
     lds_flag[tid] = 0u;  // H_THREADS == H_BN * H_BC / 32 words
@@ -168,28 +181,45 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
     const float* a1p = a0p + 32 * STR;
     // A fragments: four K steps per 16-byte LDS read (rows STR = DP + 4
     // floats apart, so eight consecutive lanes cover all banks)
+    // blocks of H_KB / 2 steps (H_KB products per output) accumulate from
+    // zero and are then added to the running sums
     if (rows_used > 32) {
 #pragma unroll
-      for (int s = 0; s < S; s += 4) {
-        const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
-        const float4 a1 = *reinterpret_cast<const float4*>(a1p + s);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, xb[s], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, xb[s + 1], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, xb[s + 2], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, xb[s + 3], acc1, 0, 0, 0);
+      for (int s0 = 0; s0 < S; s0 += H_KB / 2) {
+        f32x16 b0 = {}, b1 = {};
+#pragma unroll
+        for (int s = s0; s < s0 + H_KB / 2; s += 4) {
+          const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
+          const float4 a1 = *reinterpret_cast<const float4*>(a1p + s);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], b0, 0, 0, 0);
+          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, xb[s], b1, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], b0, 0, 0, 0);
+          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, xb[s + 1], b1, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], b0, 0, 0, 0);
+          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, xb[s + 2], b1, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], b0, 0, 0, 0);
+          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, xb[s + 3], b1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          acc0[r] += b0[r];
+          acc1[r] += b1[r];
+        }
       }
     } else {  // the second 32-row block holds no projection of this chunk
 #pragma unroll
-      for (int s = 0; s < S; s += 4) {
-        const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], acc0, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], acc0, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], acc0, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], acc0, 0, 0, 0);
+      for (int s0 = 0; s0 < S; s0 += H_KB / 2) {
+        f32x16 b0 = {};
+#pragma unroll
+        for (int s = s0; s < s0 + H_KB / 2; s += 4) {
+          const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], b0, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], b0, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], b0, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], b0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc0[r] += b0[r];
       }
     }
     const int pl = wv * 32 + p;  // point within block
@@ -235,9 +265,8 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
       if (bad && valid) atomicOr(&lds_flag[pl * 2 + half], bad);
     }
     __syncthreads();
-    // ---- float64 recomputation of the uncertified pairs, reference order:
-    // compact the flags into a list, spread it over the block, read a_p
-    // from the LDS tile and x_i with 16-byte loads
+    // ---- float64 check of the uncertified pairs: compact the flags into a
+    // list and spread it over the block (a_p from the LDS tile)
     {
       const uint32_t bits0 = lds_flag[tid];
       uint32_t tot;
@@ -253,29 +282,39 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh(
         }
         __syncthreads();
         const uint32_t cnt = (tot - base) < (uint32_t)H_FIXCAP ? (tot - base) : (uint32_t)H_FIXCAP;
-        for (uint32_t q = tid; q < cnt; q += H_THREADS) {
-          const int e = lds_fix[q];
+        // 16 lanes per pair: FMA partial sums over t = lane, lane + 16, ...
+        // reduced by shuffles give q_fast; when no integer lies within
+        // coef64 * (|a||x| + |b|) / w of it, its floor is the reference
+        // floor, else one lane evaluates the reference sum itself
+        const int grp = tid >> 4, gl = tid & 15;
+        for (uint32_t q0 = 0; q0 < cnt; q0 += H_THREADS / 16) {
+          const uint32_t q = q0 + grp;
+          const bool act = q < cnt;
+          const int e = act ? lds_fix[q] : 0;
           const int pp = e >> 6, row = e & 63;
           const float* xi = X + (i0 + pp) * ldx;
           const float* ap = lds_a + row * STR;
-          double sacc = 0.0;
-          int t = 0;
-          if (vec4) {
-            for (; t + 4 <= d; t += 4) {
-              const float4 xv = *reinterpret_cast<const float4*>(xi + t);
-              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xv.x));
-              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t + 1], (double)xv.y));
-              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t + 2], (double)xv.z));
-              sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t + 3], (double)xv.w));
+          double part = 0.0;
+          if (act)
+            for (int t = gl; t < d; t += 16) part = __fma_rn((double)ap[t], (double)xi[t], part);
+          part += __shfl_xor(part, 8);
+          part += __shfl_xor(part, 4);
+          part += __shfl_xor(part, 2);
+          part += __shfl_xor(part, 1);
+          if (act && gl == 0) {
+            const double bv = (double)lds_b[row];
+            const double qf = (part + bv) / (double)w;
+            const double rad = coef64 * ((double)lds_an[row] * (double)lds_xn[pp] + fabs(bv)) / (double)w;
+            double fl = floor(qf);
+            if (!(qf - fl > rad && fl + 1.0 - qf > rad)) {
+              double sacc = 0.0;
+              for (int t = 0; t < d; ++t) sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xi[t]));
+              fl = floor(__dadd_rn(sacc, bv) / (double)w);
             }
+            const bool fits = fl >= -2147483648.0 && fl <= 2147483647.0;
+            if (!fits) set_status(st, GEEK_ERR_RANGE);
+            lds_code[pp * H_CS + row] = fits ? (int)fl : 0;
           }
-          for (; t < d; ++t) sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xi[t]));
-          const double v = __dadd_rn(sacc, (double)lds_b[row]);
-          const double qd = v / (double)w;
-          const double fl = floor(qd);
-          const bool fits = fl >= -2147483648.0 && fl <= 2147483647.0;
-          if (!fits) set_status(st, GEEK_ERR_RANGE);
-          lds_code[pp * H_CS + row] = fits ? (int)fl : 0;
         }
         __syncthreads();
       }
