@@ -51,6 +51,7 @@ def parse():
                          "(MinHash, band buckets, signature assignment); silk: the whole GEEK pass "
                          "with SILK seeds on the dense mixture at the scaled width")
     ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
+    ap.add_argument("--no-tune", action="store_true", help="batched: keep the installed tile shapes")
     ap.add_argument("--hetero-fp8", action="store_true", help="hetero: FP8 first pass instead of BF16")
     return ap.parse_args()
 
@@ -331,6 +332,16 @@ def bench_batched(args):
     torch.cuda.synchronize()
     log(f"batched workload ready: {len(specs)} jobs, sum n = {total_n} in {time.time() - t0:.1f}s")
     status = api.new_status(dev)
+    # tile shapes of the batched first pass: measured on these jobs (untimed)
+    tiles = None
+    if not args.no_tune:
+        from paper_2106_10515_amd import autotune
+
+        t0 = time.time()
+        tuned = autotune.tune_batch_tiles(probs, L.GEEK_PREC_BF16, reps=2, status=status)
+        tiles = {str(dp): {"shape": list(r["best"]), "first_pass_ms": round(r["ms"][r["best"]], 4),
+                           "shapes_timed": len(r["ms"])} for dp, r in tuned.items()}
+        log(f"autotuned tile shapes in {time.time() - t0:.1f}s: {tiles}")
 
     def step(check):
         keys = api.hash_dense_batch([(X, *hp[X.shape[1]], m, Lt, w) for X, _, _, _ in probs],
@@ -365,8 +376,9 @@ def bench_batched(args):
                                "d in {16,32,64,128,256}, 10..5000 planted clusters, E2LSH m=8 L=16 w=4",
                    "jobs": len(specs), "sum_n": total_n},
         "assign_job_latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
-                                  "p90": float(np.percentile(lat_ms, 90)),
+                                  "p99": float(np.percentile(lat_ms, 99)),
                                   "max": float(lat_ms.max())},
+        "tiles": tiles,
         "assign_flops": flops,
         "assign_one_call_per_job_ms": single_ms,
         "batched_equals_single_calls": bool(same),

@@ -303,6 +303,23 @@ int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t
 int32_t geek_profile(int32_t enable);
 int32_t geek_profile_read(int32_t id, double* total_ms, int64_t* launches);
 
+/* Tile shape of the batched Euclidean first pass (geek_assign with several
+ * jobs) for one precision (GEEK_PREC_*) and padded depth dp (32, 64, 128 or
+ * 256, the next of these at or above d): ncb column blocks of 32 rows per
+ * wavefront (tiles of 128 * ncb rows; 1 or 2), nbuf LDS stages of seeds
+ * (1 or 2), and blocks_per_cu persistent workgroups per compute unit
+ * (1..64).  All shapes give identical results; the package's autotuner times
+ * them and installs the fastest.  ncb = nbuf = blocks_per_cu = 0 restores the
+ * built-in default (ncb 2, nbuf 2 for BF16/FP8; 1, 1 for FP32; 8 workgroups
+ * per CU).  The table is process-wide host state: set it before the calls it
+ * should affect (a call reads it when it is enqueued).  Returns GEEK_ERR_ARG
+ * for an unknown precision or depth or blocks_per_cu out of range, and
+ * GEEK_ERR_UNSUPPORTED for a shape that is not compiled (FP32 allows ncb 2
+ * only with nbuf 1 and dp <= 64).  Host only: makes no HIP call. */
+int32_t geek_set_scan_tiles(int32_t precision, int32_t dp, int32_t ncb, int32_t nbuf, int32_t blocks_per_cu);
+/* The shape geek_set_scan_tiles last installed (or the default). */
+int32_t geek_get_scan_tiles(int32_t precision, int32_t dp, int32_t* ncb, int32_t* nbuf, int32_t* blocks_per_cu);
+
 /* Static description of a status code. */
 const char* geek_status_string(int32_t status);
 /* Ticks per second of the device wall clock used by t_done (device 0 of

@@ -87,7 +87,8 @@ class AssignJob(C.Structure):
 
 EXPORTS = ("geek_workspace_size", "geek_hash", "geek_bucketize", "geek_silk_seeds",
            "geek_assign", "geek_status_string", "geek_version", "geek_last_hip_error",
-           "geek_profile", "geek_profile_read", "geek_wallclock_hz")
+           "geek_profile", "geek_profile_read", "geek_wallclock_hz", "geek_set_scan_tiles",
+           "geek_get_scan_tiles")
 
 GEEK_PROF_E2LSH, GEEK_PROF_BUCKETIZE, GEEK_PROF_ASSIGN_SCAN, GEEK_PROF_ASSIGN = 0, 1, 2, 3
 GEEK_PROF_MINHASH, GEEK_PROF_SILK, GEEK_PROF_BZ_SORT = 4, 5, 6
@@ -118,7 +119,14 @@ def _load():
     lib.geek_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.geek_profile_read.restype = C.c_int32
     lib.geek_wallclock_hz.restype = C.c_int64
+    lib.geek_set_scan_tiles.argtypes = [C.c_int32] * 5
+    lib.geek_set_scan_tiles.restype = C.c_int32
+    lib.geek_get_scan_tiles.argtypes = [C.c_int32, C.c_int32] + [C.POINTER(C.c_int32)] * 3
+    lib.geek_get_scan_tiles.restype = C.c_int32
     _LIB = lib
+    # tile shapes measured by the autotuner, if a table was saved
+    from . import autotune
+    autotune.install_table(autotune.TABLE_PATH, missing_ok=True)
     return lib
 
 
@@ -148,6 +156,20 @@ def geek_profile_read(kernel_id: int):
 def geek_wallclock_hz() -> int:
     """Ticks per second of the device wall clock (t_done units)."""
     return int(_load().geek_wallclock_hz())
+
+
+def geek_set_scan_tiles(precision: int, dp: int, ncb: int, nbuf: int, blocks_per_cu: int) -> int:
+    """Install a tile shape of the batched first pass; returns the status."""
+    return int(_load().geek_set_scan_tiles(precision, dp, ncb, nbuf, blocks_per_cu))
+
+
+def geek_get_scan_tiles(precision: int, dp: int):
+    """(ncb, nbuf, blocks_per_cu) currently used for (precision, dp)."""
+    v = [C.c_int32(0) for _ in range(3)]
+    rc = _load().geek_get_scan_tiles(precision, dp, *[C.byref(x) for x in v])
+    if rc != GEEK_OK:
+        raise GeekError(rc, "geek_get_scan_tiles")
+    return tuple(int(x.value) for x in v)
 
 
 def workspace_size(op: int, jobs) -> int:

@@ -24,6 +24,11 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
 size_t assign_sig_ws(const geek_assign_job& J);
 bool assign_batchable(const geek_assign_job* jobs, int njobs);
 size_t assign_batch_ws(const geek_assign_job* jobs, int njobs);
+struct ScanTiles {
+  int ncb, nbuf, blocks_per_cu;
+};
+ScanTiles scan_tiles_get(int precision, int dp);
+int32_t scan_tiles_set(int precision, int dp, ScanTiles t);
 int32_t assign_euclid_batch(const geek_assign_job* jobs, int njobs, void* ws, size_t ws_bytes, int32_t* st,
                             hipStream_t s);
 int32_t assign_sig(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
@@ -148,6 +153,20 @@ const char* geek_status_string(int32_t s) {
 }
 
 const char* geek_version(void) { return "geek 0.1.0 gfx950"; }
+
+int32_t geek_set_scan_tiles(int32_t precision, int32_t dp, int32_t ncb, int32_t nbuf, int32_t blocks_per_cu) {
+  return geek::scan_tiles_set(precision, dp, geek::ScanTiles{ncb, nbuf, blocks_per_cu});
+}
+
+int32_t geek_get_scan_tiles(int32_t precision, int32_t dp, int32_t* ncb, int32_t* nbuf, int32_t* blocks_per_cu) {
+  if (!ncb || !nbuf || !blocks_per_cu) return GEEK_ERR_ARG;
+  if (!(precision >= 0 && precision <= 2) || !(dp == 32 || dp == 64 || dp == 128 || dp == 256)) return GEEK_ERR_ARG;
+  const geek::ScanTiles t = geek::scan_tiles_get(precision, dp);
+  *ncb = t.ncb;
+  *nbuf = t.nbuf;
+  *blocks_per_cu = t.blocks_per_cu;
+  return GEEK_OK;
+}
 
 int64_t geek_wallclock_hz(void) {
   int dev = 0, khz = 0;

@@ -69,3 +69,35 @@ def test_argument_errors_need_no_gpu():
     assert nb.value > 3 * 1000 * 20
     # a too-small workspace is refused before any launch
     assert lib.geek_bucketize(C.byref(ok), 1, C.c_void_p(256), 16, None, None) == L.GEEK_ERR_WORKSPACE
+
+
+def test_scan_tile_table_host_only(tmp_path):
+    # the tile table of the batched first pass is host state: validated and
+    # installed without touching a GPU; saved tables round-trip
+    from paper_2106_10515_amd import autotune
+
+    saved = {(p, dp): L.geek_get_scan_tiles(p, dp) for p in (0, 1, 2) for dp in (32, 64, 128, 256)}
+    try:
+        for p in (0, 1, 2):
+            assert L.geek_set_scan_tiles(p, 128, 0, 0, 0) == L.GEEK_OK
+        assert L.geek_get_scan_tiles(L.GEEK_PREC_BF16, 128) == (2, 2, 8)
+        assert L.geek_get_scan_tiles(L.GEEK_PREC_FP32, 128) == (1, 1, 8)
+        assert L.geek_set_scan_tiles(L.GEEK_PREC_BF16, 128, 1, 2, 4) == L.GEEK_OK
+        assert L.geek_get_scan_tiles(L.GEEK_PREC_BF16, 128) == (1, 2, 4)
+        assert L.geek_set_scan_tiles(L.GEEK_PREC_BF16, 48, 1, 1, 4) == L.GEEK_ERR_ARG
+        assert L.geek_set_scan_tiles(L.GEEK_PREC_BF16, 128, 1, 1, 65) == L.GEEK_ERR_ARG
+        assert L.geek_set_scan_tiles(7, 128, 1, 1, 4) == L.GEEK_ERR_ARG
+        assert L.geek_set_scan_tiles(L.GEEK_PREC_BF16, 128, 3, 1, 4) == L.GEEK_ERR_UNSUPPORTED
+        assert L.geek_set_scan_tiles(L.GEEK_PREC_FP32, 128, 2, 1, 4) == L.GEEK_ERR_UNSUPPORTED
+        assert L.geek_set_scan_tiles(L.GEEK_PREC_FP32, 64, 2, 1, 4) == L.GEEK_OK
+        assert len(autotune.candidates(L.GEEK_PREC_BF16, 256)) == 16
+        assert len(autotune.candidates(L.GEEK_PREC_FP32, 256)) == 8
+        assert [autotune.padded_depth(d) for d in (1, 32, 33, 100, 256)] == [32, 32, 64, 128, 256]
+        res = {L.GEEK_PREC_FP8: {64: {"best": (1, 2, 16), "ms": {(1, 2, 16): 0.5, (2, 2, 8): 0.7}}}}
+        path = str(tmp_path / "tiles.json")
+        autotune.save_table(res, path)
+        assert autotune.install_table(path) == 1
+        assert L.geek_get_scan_tiles(L.GEEK_PREC_FP8, 64) == (1, 2, 16)
+    finally:
+        for (p, dp), shape in saved.items():
+            L.geek_set_scan_tiles(p, dp, *shape)

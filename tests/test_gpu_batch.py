@@ -86,3 +86,55 @@ def test_batch_graph_replays():
         api.check_status(status, f"replay {rep}")
         for j in range(len(probs)):
             _same(outs[j], ref[j], (rep, j))
+
+
+@pytest.fixture
+def default_tiles():
+    from paper_2106_10515_amd import _lib as L
+
+    saved = {(p, dp): L.geek_get_scan_tiles(p, dp) for p in (0, 1, 2) for dp in (32, 64, 128, 256)}
+    yield L
+    for (p, dp), shape in saved.items():
+        L.geek_set_scan_tiles(p, dp, *shape)
+
+
+@pytest.mark.parametrize("prec,seed", [("bf16", 4), ("fp8", 5), ("fp32", 6)])
+def test_batch_every_tile_shape_same_records(prec, seed, default_tiles):
+    # every compiled tile shape of the batched first pass gives the same
+    # outputs as the single-job calls
+    from paper_2106_10515_amd import autotune
+
+    L = default_tiles
+    api = gpu_api()
+    probs, _ = _problems(10, seed)
+    singles = [api.assign_euclid(X, so, sm, k, PRECS[prec]) for X, so, sm, k in probs]
+    dps = sorted({autotune.padded_depth(p[0].shape[1]) for p in probs})
+    shapes = set()
+    for dp in dps:
+        shapes.update(autotune.candidates(PRECS[prec], dp, blocks=(1, 3)))
+    for shape in sorted(shapes):
+        for dp in dps:
+            if L.geek_set_scan_tiles(PRECS[prec], dp, *shape) != L.GEEK_OK:
+                L.geek_set_scan_tiles(PRECS[prec], dp, 0, 0, 0)
+        announce(f"batch {prec} tile shape {shape}")
+        outs, _ = api.assign_euclid_batch(probs, PRECS[prec])
+        for j, single in enumerate(singles):
+            _same(outs[j], single, (shape, j))
+
+
+def test_autotune_installs_fastest(default_tiles):
+    from paper_2106_10515_amd import autotune
+
+    L = default_tiles
+    api = gpu_api()
+    probs, _ = _problems(8, 7)
+    announce("autotune bf16 on 8 small jobs")
+    res = autotune.tune_batch_tiles(probs, PRECS["bf16"], reps=1, blocks=(2, 8))
+    assert res
+    for dp, r in res.items():
+        assert r["best"] == min(r["ms"], key=r["ms"].get)
+        assert L.geek_get_scan_tiles(PRECS["bf16"], dp) == r["best"]
+        assert len(r["ms"]) == len(autotune.candidates(PRECS["bf16"], dp, blocks=(2, 8)))
+    outs, _ = api.assign_euclid_batch(probs, PRECS["bf16"])
+    for j, (X, so, sm, k) in enumerate(probs):
+        _same(outs[j], api.assign_euclid(X, so, sm, k, PRECS["bf16"]), j)
