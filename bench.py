@@ -59,7 +59,7 @@ def parse():
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_scan_bf16_dense_large_pmc.txt")
 
 
-def measured_traffic(kernel_prefix="k_scan<ModeBF16, 128"):
+def measured_traffic(kernel_prefix="k_scan<ModeBF16, 128, false, 2, 2, true, false>"):
     """HBM bytes per launch of the scan kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a plain
     copy), or None when there is no summary for the current kernel."""
@@ -78,11 +78,15 @@ def measured_traffic(kernel_prefix="k_scan<ModeBF16, 128"):
 
 
 def kernel_source_hash():
+    """Hash of the sources the assignment scan kernel is built from (its
+    tile loop and epilogues, and the shared helpers)."""
     import hashlib
 
-    p = os.path.join(ROOT, "paper_2106_10515_amd", "csrc", "assign.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("scan.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2106_10515_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):

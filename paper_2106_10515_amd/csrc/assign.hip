@@ -628,7 +628,9 @@ size_t assign_euclid_ws(const geek_assign_job& J) {
 // Heterogeneous rows carry their categorical values in registers: one
 // column block.
 template <class M, bool HET> struct ScanShape {
-  static constexpr int NCB = HET ? 1 : 2, NBUF = 2;
+  // FP8's candidate window with two column blocks per wave runs 2-3x slower
+  // than with one (measured across depths); BF16 keeps two off HET
+  static constexpr int NCB = (HET || std::is_same<M, ModeFP8>::value) ? 1 : 2, NBUF = 2;
   // e4m3's coarse rounding leaves most rows with a few candidates: FP8 keeps
   // the full candidate window (float64 recheck of up to TCAND) instead
   static constexpr bool T2 = std::is_same<M, ModeBF16>::value;
@@ -734,12 +736,12 @@ static bool low_precision(const geek_assign_job& J) {
 
 // The first pass of one job: every row gets a candidate record.
 static void assign_first_pass(const geek_assign_job& J, AssignCtx& C, int32_t* st, hipStream_t s) {
-  if (low_precision(J)) {
+  if (J.precision == GEEK_PREC_BF16) {
     const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeBF16>(C.het_on));
-    if (J.precision == GEEK_PREC_BF16)
-      scan_any<ModeBF16>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cllow, C.W, C.k_pad, C.het, st);
-    else
-      scan_any<ModeFP8>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cllow, C.W, C.k_pad, C.het, st);
+    scan_any<ModeBF16>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cllow, C.W, C.k_pad, C.het, st);
+  } else if (J.precision == GEEK_PREC_FP8) {
+    const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeFP8>(C.het_on));
+    scan_any<ModeFP8>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cllow, C.W, C.k_pad, C.het, st);
   } else {
     const int grid_all = ceil_div(J.n, scan_rows_per_tile<ModeF32>(C.het_on));
     scan_any<ModeF32>(C.het_on, C.DP, grid_all, s, J, J.n, nullptr, nullptr, C.W.cl32, C.W, C.k_pad, C.het, st);

@@ -11,6 +11,9 @@
 
 namespace geek {
 
+template <int V>
+using IC = std::integral_constant<int, V>;
+
 constexpr int TCAND = 8;       // candidates per lane window, BF16/FP8 passes
 constexpr int TCAND32 = 32;    // float32 pass (also the rescan of ambiguous rows)
 constexpr int RECW = TCAND32 + 1;  // candidate record per row: count, then ids
@@ -165,9 +168,22 @@ __device__ __forceinline__ void scan_tiles(
   constexpr int STR = DMA ? DP : DP + 16 / (int)sizeof(CE);  // LDS row (elements)
   constexpr int BN = 128 * NCB;                   // rows per tile
   constexpr int CPT = DMA ? 1 : (SCAN_BC * CH + SCAN_THREADS - 1) / SCAN_THREADS;
-  __shared__ __attribute__((aligned(16))) CE lds_c[NBUF][SCAN_BC * STR];
+  // one LDS object per stage buffer: with the buffer known at compile time
+  // the compiler can tell that reads of the current stage do not alias the
+  // LDS DMA filling the next one, and does not wait for that DMA
+  __shared__ __attribute__((aligned(16))) CE lds_c0[SCAN_BC * STR];
+  __shared__ __attribute__((aligned(16))) CE lds_c1[NBUF == 2 ? SCAN_BC * STR : 1];
   __shared__ float lds_nc[NBUF][SCAN_BC];
-  __shared__ uint32_t lds_mode[HET ? NBUF : 1][HET ? SCAN_BC * MAX_CAT : 1];
+  __shared__ __attribute__((aligned(16))) uint32_t lds_mode0[HET ? SCAN_BC * MAX_CAT : 1];
+  __shared__ __attribute__((aligned(16))) uint32_t lds_mode1[HET && NBUF == 2 ? SCAN_BC * MAX_CAT : 1];
+  auto cbuf = [&](auto bc) -> CE* {
+    if constexpr (decltype(bc)::value == 0) return lds_c0;
+    else return lds_c1;
+  };
+  auto mbuf = [&](auto bc) -> uint32_t* {
+    if constexpr (decltype(bc)::value == 0) return lds_mode0;
+    else return lds_mode1;
+  };
   // window capacity per lane: the rescan of rows whose first-pass window was
   // ambiguous keeps more candidates
   constexpr int TC = WIDE ? TCAND32 : TCAND;
@@ -207,7 +223,7 @@ __device__ __forceinline__ void scan_tiles(
       stg[u] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(cl + (int64_t)((C0) + r) * DP) + \
                                                c * 16);                                                    \
     }                                                                                                      \
-    stg_nc = nc_stage(nc[(C0) + (tid & (SCAN_BC - 1))]);                                                   \
+    stg_nc = nc[(C0) + (tid & (SCAN_BC - 1))];                                                             \
     if constexpr (HET) {                                                                                   \
       _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                                   \
         const int q = min(tid + u * SCAN_THREADS, SCAN_BC * MAX_CAT - 1);                                  \
@@ -224,14 +240,14 @@ __device__ __forceinline__ void scan_tiles(
       const int q = tid + u * SCAN_THREADS;                                                                \
       if (q < SCAN_BC * CH) {                                                                              \
         const int r = q / CH, c = q % CH;                                                                  \
-        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds_c[B] + r * STR) + c * 16) = stg[u];          \
+        *reinterpret_cast<uint4*>(reinterpret_cast<char*>(cbuf(IC<(B)>{}) + r * STR) + c * 16) = stg[u];   \
       }                                                                                                    \
     }                                                                                                      \
-    if (tid < SCAN_BC) lds_nc[B][tid] = stg_nc;                                                            \
+    if (tid < SCAN_BC) lds_nc[B][tid] = nc_stage(stg_nc);                                                  \
     if constexpr (HET) {                                                                                   \
       _Pragma("unroll") for (int u = 0; u < MPT; ++u) {                                                   \
         const int q = tid + u * SCAN_THREADS;                                                              \
-        if (q < SCAN_BC * MAX_CAT) lds_mode[B][q] = stg_mode[u];                                           \
+        if (q < SCAN_BC * MAX_CAT) mbuf(IC<(B)>{})[q] = stg_mode[u];                                       \
       }                                                                                                    \
     }                                                                                                      \
   } while (0)
@@ -243,13 +259,15 @@ __device__ __forceinline__ void scan_tiles(
       const int r = slot / CH, c = (slot % CH) ^ (r & (CH - 1));                                           \
       __builtin_amdgcn_global_load_lds(                                                                    \
           reinterpret_cast<const char*>(cl + (int64_t)((C0) + r) * DP) + c * 16,                           \
-          reinterpret_cast<char*>(lds_c[B]) + slot0 * 16, 16, 0, 0);                                      \
+          reinterpret_cast<char*>(cbuf(IC<(B)>{})) + slot0 * 16, 16, 0, 0);                               \
     }                                                                                                      \
-    stg_nc = nc_stage(nc[(C0) + (tid & (SCAN_BC - 1))]); /* lds_nc[B] stored from the register */       \
+    /* raw |c|^2 in a register, converted when lds_nc[B] is stored: a use here \
+       would make the wave wait for the whole stage at once */                 \
+    stg_nc = nc[(C0) + (tid & (SCAN_BC - 1))];                                                             \
     if constexpr (HET)                                                                                     \
       __builtin_amdgcn_global_load_lds(                                                                    \
           reinterpret_cast<const char*>(het.mode16 + (int64_t)(C0) * MAX_CAT) + (w * 64 + lane) * 16,     \
-          reinterpret_cast<char*>(lds_mode[B]) + w * 64 * 16, 16, 0, 0);                                  \
+          reinterpret_cast<char*>(mbuf(IC<(B)>{})) + w * 64 * 16, 16, 0, 0);                              \
   } while (0)
 
   for (int64_t tile = tile0; tile < tile_end && tile * BN < count; tile += tstep) {
@@ -330,19 +348,33 @@ __device__ __forceinline__ void scan_tiles(
     __syncthreads();  // previous tile done with the LDS buffers
     if constexpr (DMA) {
       GEEK_DMA_STAGE(0, 0);
-      if (tid < SCAN_BC) lds_nc[0][tid] = stg_nc;
+      if (tid < SCAN_BC) lds_nc[0][tid] = nc_stage(stg_nc);
       __builtin_amdgcn_s_waitcnt(0);
     } else {
       GEEK_LOAD_REGS(0);
       GEEK_STORE_LDS(0);
     }
     __syncthreads();
-    int it = 0;
-    for (int c0 = 0; c0 < k_pad; c0 += SCAN_BC, ++it) {
-      const int cur = NBUF == 2 ? (it & 1) : 0;
+    // T2: values of 32 centroids enter the running best two with one bit
+    // insert and two med3 each; blk records the block where a1 changed
+    auto t2_update = [&](int cb, const f32x16& t, int gb) {
+      const float a1_prev = a1[cb];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float tb = __uint_as_float((__float_as_uint(t[r]) & ~15u) | (uint32_t)r);
+        a2[cb] = __builtin_amdgcn_fmed3f(a1[cb], a2[cb], tb);            // second best
+        a1[cb] = __builtin_amdgcn_fmed3f(a1[cb], tb, 3.402823466e38f);  // best
+      }
+      blk[cb] = a1[cb] != a1_prev ? gb : blk[cb];
+    };
+    // one stage of SCAN_BC centroids from buffer `cur` (a compile-time
+    // constant), with the next stage loading into the other buffer
+    auto stage = [&](auto curc, const int c0, const int it) {
+      constexpr int cur = NBUF == 2 ? decltype(curc)::value : 0;
+      constexpr int nxt = NBUF == 2 ? 1 - cur : 0;
       const bool more = c0 + SCAN_BC < k_pad;
       if constexpr (DMA) {
-        if (more) GEEK_DMA_STAGE(c0 + SCAN_BC, cur ^ 1);
+        if (more) GEEK_DMA_STAGE(c0 + SCAN_BC, nxt);
       } else {
         if (NBUF == 2 && more) GEEK_LOAD_REGS(c0 + SCAN_BC);
       }
@@ -358,19 +390,20 @@ __device__ __forceinline__ void scan_tiles(
         }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[cb] = init;
-        const CE* ap = lds_c[cur] + (rb * 32 + p) * STR + h * (DP / 2);
+        const CE* ap = cbuf(IC<cur>{}) + (rb * 32 + p) * STR + h * (DP / 2);
         const int R = rb * 32 + p;
-        const char* rowp = reinterpret_cast<const char*>(lds_c[cur]) + R * CH * 16;
+        const char* rowp = reinterpret_cast<const char*>(cbuf(IC<cur>{})) + R * CH * 16;
+        auto afrag = [&](int s) {
+          if constexpr (DMA) {
+            const int off = (h * (DP / 2) + s * M::KPER) * (int)sizeof(CE);
+            return M::load_lds(reinterpret_cast<const CE*>(rowp + (((off >> 4) ^ (R & (CH - 1))) << 4) + (off & 15)));
+          } else {
+            return M::load_lds(ap + s * M::KPER);
+          }
+        };
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          const typename M::frag a = [&] {
-            if constexpr (DMA) {
-              const int off = (h * (DP / 2) + s * M::KPER) * (int)sizeof(CE);
-              return M::load_lds(reinterpret_cast<const CE*>(rowp + (((off >> 4) ^ (R & (CH - 1))) << 4) + (off & 15)));
-            } else {
-              return M::load_lds(ap + s * M::KPER);
-            }
-          }();
+          const typename M::frag a = afrag(s);
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = M::mma(a, xb[cb][s], acc[cb]);
         }
@@ -385,21 +418,17 @@ __device__ __forceinline__ void scan_tiles(
               t[r] = acc[cb][r];
               if constexpr (HET) {
                 // -(v_num + gamma * mismatches), one rounding
-                const uint32_t* md = lds_mode[cur] + (jb + (r >> 2) * 8 + h * 4 + (r & 3)) * MAX_CAT;
+                const uint32_t* md = mbuf(IC<cur>{}) + (jb + (r >> 2) * 8 + h * 4 + (r & 3)) * MAX_CAT;
                 int mm = 0;
 #pragma unroll
                 for (int q = 0; q < MAX_CAT; ++q) mm += (q < het.n_cat && (uint32_t)crow[cb][q] != md[q]) ? 1 : 0;
                 t[r] = __builtin_fmaf(-m2s, t[r], -het.gamma_f * (float)mm);
               }
             }
-            const float a1_prev = a1[cb];
+            f32x16 tv;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const float tb = __uint_as_float((__float_as_uint(t[r]) & ~15u) | (uint32_t)r);
-              a2[cb] = __builtin_amdgcn_fmed3f(a1[cb], a2[cb], tb);            // second best
-              a1[cb] = __builtin_amdgcn_fmed3f(a1[cb], tb, 3.402823466e38f);  // best
-            }
-            blk[cb] = a1[cb] != a1_prev ? gblk : blk[cb];
+            for (int r = 0; r < 16; ++r) tv[r] = t[r];
+            t2_update(cb, tv, gblk);
           }
         } else {
         float ncv[16];
@@ -413,7 +442,7 @@ __device__ __forceinline__ void scan_tiles(
           for (int r = 0; r < 16; ++r) {
             v[r] = __builtin_fmaf(m2s, acc[cb][r], ncv[r]);
             if constexpr (HET) {
-              const uint32_t* md = lds_mode[cur] + (jb + (r >> 2) * 8 + h * 4 + (r & 3)) * MAX_CAT;
+              const uint32_t* md = mbuf(IC<cur>{}) + (jb + (r >> 2) * 8 + h * 4 + (r & 3)) * MAX_CAT;
               int mm = 0;
 #pragma unroll
               for (int a = 0; a < MAX_CAT; ++a) mm += (a < het.n_cat && (uint32_t)crow[cb][a] != md[a]) ? 1 : 0;
@@ -461,10 +490,10 @@ __device__ __forceinline__ void scan_tiles(
       }
       if (more) {
         if constexpr (DMA) {
-          if (tid < SCAN_BC) lds_nc[cur ^ 1][tid] = stg_nc;
+          if (tid < SCAN_BC) lds_nc[nxt][tid] = nc_stage(stg_nc);
           __builtin_amdgcn_s_waitcnt(0);  // this wave's chunks of the next stage landed
         } else if (NBUF == 2) {
-          GEEK_STORE_LDS(cur ^ 1);
+          GEEK_STORE_LDS(nxt);
         } else {
           __syncthreads();
           GEEK_LOAD_REGS(c0 + SCAN_BC);
@@ -472,6 +501,18 @@ __device__ __forceinline__ void scan_tiles(
         }
       }
       __syncthreads();
+    };
+    for (int c0 = 0, it = 0; c0 < k_pad;) {
+      stage(IC<0>{}, c0, it);
+      c0 += SCAN_BC;
+      ++it;
+      if constexpr (NBUF == 2) {
+        if (c0 < k_pad) {
+          stage(IC<1>{}, c0, it);
+          c0 += SCAN_BC;
+          ++it;
+        }
+      }
     }
 
     // ---- merge the two lanes that share a point, write the candidate record
