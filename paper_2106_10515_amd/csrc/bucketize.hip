@@ -1,9 +1,13 @@
 // Buckets of every table (paper Algorithms 2 and 3: T[G(x_j)].push(j)) on
 // gfx950: group the objects whose table keys are identical.
 //
-//  1. k_bin_count / k_bin_*scan / k_bin_scatter: a one-pass MSD partition of
-//     (key, id) records into 2^nb bins per table, the bin being the top bits
-//     of a 32-bit mix of the exact key (equal keys always share a bin).
+//  1. A partition of (key, id) records into 2^nb bins per table, the bin
+//     being the top bits of a 32-bit mix of the exact key (equal keys always
+//     share a bin).  Up to 2^PT_B1 bins it is one pass (k_bin_count, the
+//     scans, k_p1_scatter); beyond, a second pass splits every first-pass bin
+//     by the next bits (k_p2_*).  Each scatter sorts rounds of PT_ROUND
+//     records by bin in LDS before writing, so the stores are runs of
+//     consecutive records instead of single scattered records.
 //  2. k_bin_group: one workgroup per bin groups its records with an LDS hash
 //     table on the exact key; objects sharing a key get (head = smallest id,
 //     rank among the bucket's ids, bucket size at the head) in id-indexed
@@ -21,7 +25,6 @@
 namespace geek {
 
 constexpr int BZ_THREADS = 256;
-constexpr int BZ_CHUNK = 32768;   // records per block in count / scatter
 constexpr int BZ_CAP = 2048;      // largest bin grouped in LDS
 constexpr int BZ_HT = 4096;       // LDS hash slots per bin
 constexpr int BZ_SMALL = 32;      // largest group ranked by walking its member list
@@ -63,14 +66,14 @@ GEEK_D bool rec_less(const uint4& a, uint32_t ia, const uint4& b, uint32_t ib) {
 }
 
 // ---------------------------------------------------------------- partition
-__global__ __launch_bounds__(BZ_THREADS) void k_bin_count(BzArgs a, int nblk, uint32_t* counts) {
+__global__ __launch_bounds__(BZ_THREADS) void k_bin_count(BzArgs a, int nblk, int chunk, uint32_t* counts) {
   extern __shared__ uint32_t hist[];
   const int t = blockIdx.y, blk = blockIdx.x;
   const int nbins = 1 << a.nb;
   for (int b = threadIdx.x; b < nbins; b += BZ_THREADS) hist[b] = 0;
   __syncthreads();
-  const int64_t s = (int64_t)blk * BZ_CHUNK;
-  const int64_t e = s + BZ_CHUNK < a.n ? s + BZ_CHUNK : a.n;
+  const int64_t s = (int64_t)blk * chunk;
+  const int64_t e = s + chunk < a.n ? s + chunk : a.n;
   for (int64_t i = s + threadIdx.x; i < e; i += BZ_THREADS)
     atomicAdd(&hist[bin_of(load_key(a, t, i), a.nb)], 1u);
   __syncthreads();
@@ -84,10 +87,21 @@ __global__ void k_bin_colscan(int T, int nblk, int nbins, uint32_t* counts, uint
   if (g >= (int64_t)T * nbins) return;
   const int t = (int)(g / nbins), b = (int)(g % nbins);
   uint32_t run = 0;
-  for (int k = 0; k < nblk; ++k) {
-    uint32_t* c = counts + ((int64_t)t * nblk + k) * nbins + b;
-    const uint32_t v = *c;
-    *c = run;
+  uint32_t* c = counts + (int64_t)t * nblk * nbins + b;
+  int k = 0;
+  for (; k + 8 <= nblk; k += 8) {  // eight loads in flight
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = c[(int64_t)(k + u) * nbins];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[(int64_t)(k + u) * nbins] = run;
+      run += v[u];
+    }
+  }
+  for (; k < nblk; ++k) {
+    const uint32_t v = c[(int64_t)k * nbins];
+    c[(int64_t)k * nbins] = run;
     run += v;
   }
   bintot[g] = run;
@@ -141,25 +155,187 @@ __global__ __launch_bounds__(1024) void k_bin_rowscan(int nbins, const uint32_t*
   }
 }
 
-__global__ __launch_bounds__(BZ_THREADS) void k_bin_scatter(BzArgs a, int nblk, const uint32_t* counts,
-                                                            const uint32_t* binstart, uint4* st_keys,
-                                                            uint32_t* st_ids) {
-  extern __shared__ uint32_t cur[];
+constexpr int PT_B1 = 6;          // bits of the first partition pass (64 bins)
+constexpr int PT_ROUND = 2048;    // records sorted by bin in LDS per round
+constexpr int PT_SUPER = 16384;   // records per workgroup of a partition pass
+constexpr int PT_RPT = PT_ROUND / BZ_THREADS;
+
+// One round of a partition scatter: the block's `cnt` records (key, id,
+// bin) are counted per bin, placed in LDS in bin order, and written out so
+// that consecutive threads store consecutive records of a bin.  cur[b] is
+// the global position of bin b's next record and advances by the round's
+// count.  Records of a bin keep no particular order (the grouping that
+// follows does not depend on it).
+struct PartLds {
+  uint4 key[PT_ROUND];
+  uint32_t id[PT_ROUND];
+  uint16_t bin[PT_ROUND];
+  uint32_t hist[256], lst[256], cur[256], sh[17];
+};
+
+template <class Load>
+__device__ void part_round(PartLds& L, int nbins, int cnt, const Load& load, uint4* out_keys,
+                           uint32_t* out_ids) {
+  const int tid = threadIdx.x;
+  for (int b = tid; b < nbins; b += BZ_THREADS) L.hist[b] = 0u;
+  __syncthreads();
+  uint4 k[PT_RPT];
+  uint32_t id[PT_RPT], rk[PT_RPT];
+  int bn[PT_RPT];
+#pragma unroll
+  for (int u = 0; u < PT_RPT; ++u) {
+    const int q = tid + u * BZ_THREADS;
+    if (q < cnt) {
+      load(q, k[u], id[u], bn[u]);
+      rk[u] = atomicAdd(&L.hist[bn[u]], 1u);
+    }
+  }
+  __syncthreads();
+  // exclusive scan of the round's bin counts (nbins <= 256 = one per thread)
+  const uint32_t hv = tid < nbins ? L.hist[tid] : 0u;
+  const uint32_t ex = block_exscan(hv, nullptr, L.sh);
+  if (tid < nbins) L.lst[tid] = ex;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PT_RPT; ++u) {
+    const int q = tid + u * BZ_THREADS;
+    if (q < cnt) {
+      const uint32_t p = L.lst[bn[u]] + rk[u];
+      L.key[p] = k[u];
+      L.id[p] = id[u];
+      L.bin[p] = (uint16_t)bn[u];
+    }
+  }
+  __syncthreads();
+  for (int p = tid; p < cnt; p += BZ_THREADS) {
+    const int b = L.bin[p];
+    const uint32_t gp = L.cur[b] + (uint32_t)p - L.lst[b];
+    out_keys[gp] = L.key[p];
+    out_ids[gp] = L.id[p];
+  }
+  __syncthreads();
+  for (int b = tid; b < nbins; b += BZ_THREADS) L.cur[b] += L.hist[b];
+}
+
+// First pass: block (chunk of PT_SUPER ids, table) -> 2^a.nb bins (a.nb <= PT_B1).
+__global__ __launch_bounds__(BZ_THREADS) void k_p1_scatter(BzArgs a, int nblk, const uint32_t* counts,
+                                                           const uint32_t* binstart, uint4* out_keys,
+                                                           uint32_t* out_ids) {
+  __shared__ PartLds L;
   const int t = blockIdx.y, blk = blockIdx.x;
   const int nbins = 1 << a.nb;
-  const uint32_t* c = counts + ((int64_t)t * nblk + blk) * nbins;
-  const uint32_t* bs = binstart + (int64_t)t * nbins;
-  for (int b = threadIdx.x; b < nbins; b += BZ_THREADS) cur[b] = bs[b] + c[b];
+  for (int b = threadIdx.x; b < nbins; b += BZ_THREADS)
+    L.cur[b] = binstart[(int64_t)t * nbins + b] + counts[((int64_t)t * nblk + blk) * nbins + b];
+  const int64_t s = (int64_t)blk * PT_SUPER;
+  const int64_t e = s + PT_SUPER < a.n ? s + PT_SUPER : a.n;
+  for (int64_t r0 = s; r0 < e; r0 += PT_ROUND) {
+    const int cnt = (int)(e - r0 < PT_ROUND ? e - r0 : PT_ROUND);
+    part_round(L, nbins, cnt,
+               [&](int q, uint4& k, uint32_t& id, int& bn) {
+                 k = load_key(a, t, r0 + q);
+                 id = (uint32_t)(r0 + q);
+                 bn = (int)bin_of(k, a.nb);
+               },
+               out_keys + (int64_t)t * a.n, out_ids + (int64_t)t * a.n);
+  }
+}
+
+// Second pass.  The records of first-pass bin (t, B) are cut into chunks of
+// PT_SUPER; cbase[t * 2^PT_B1 + B] is the first global chunk of that bin.
+__global__ __launch_bounds__(1024) void k_p2_chunks(int nb1bins, const uint32_t* bintot1, uint32_t* cbase) {
+  __shared__ uint32_t sh[17];
+  const int per = (nb1bins + 1023) / 1024;
+  uint32_t loc = 0;
+  for (int q = 0; q < per; ++q) {
+    const int i = threadIdx.x * per + q;
+    loc += i < nb1bins ? (bintot1[i] + PT_SUPER - 1) / PT_SUPER : 0u;
+  }
+  uint32_t total;
+  uint32_t base = block_exscan(loc, &total, sh);
+  for (int q = 0; q < per; ++q) {
+    const int i = threadIdx.x * per + q;
+    if (i < nb1bins) {
+      cbase[i] = base;
+      base += (bintot1[i] + PT_SUPER - 1) / PT_SUPER;
+    }
+  }
+  if (threadIdx.x == 0) cbase[nb1bins] = total;
+}
+
+// The first-pass bin of global chunk g (the last i with cbase[i] <= g).
+GEEK_D int p2_bin_of_chunk(const uint32_t* cbase, int nb1bins, uint32_t g) {
+  int lo = 0, hi = nb1bins - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cbase[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Per chunk: counts of the second-pass bins (the next nb - PT_B1 bits).
+__global__ __launch_bounds__(BZ_THREADS) void k_p2_count(int64_t n, int nb, const uint32_t* cbase, int nb1bins,
+                                                         const uint32_t* bintot1, const uint32_t* binstart1,
+                                                         const uint4* keys1, uint32_t* counts2) {
+  __shared__ uint32_t hist[256];
+  const uint32_t g = blockIdx.x;
+  if (g >= cbase[nb1bins]) return;
+  const int F = 1 << (nb - PT_B1);
+  const int tb = p2_bin_of_chunk(cbase, nb1bins, g);
+  const int t = tb >> PT_B1;
+  const uint32_t off = (g - cbase[tb]) * (uint32_t)PT_SUPER;
+  const uint32_t cnt = min((uint32_t)PT_SUPER, bintot1[tb] - off);
+  const uint4* src = keys1 + (int64_t)t * n + binstart1[tb] + off;
+  for (int b = threadIdx.x; b < F; b += BZ_THREADS) hist[b] = 0u;
   __syncthreads();
-  const int64_t s = (int64_t)blk * BZ_CHUNK;
-  const int64_t e = s + BZ_CHUNK < a.n ? s + BZ_CHUNK : a.n;
-  uint4* sk = st_keys + (int64_t)t * a.n;
-  uint32_t* si = st_ids + (int64_t)t * a.n;
-  for (int64_t i = s + threadIdx.x; i < e; i += BZ_THREADS) {
-    const uint4 k = load_key(a, t, i);
-    const uint32_t pos = atomicAdd(&cur[bin_of(k, a.nb)], 1u);
-    sk[pos] = k;
-    si[pos] = (uint32_t)i;
+  for (uint32_t q = threadIdx.x; q < cnt; q += BZ_THREADS) {
+    const uint4 k = src[q];
+    atomicAdd(&hist[bin_of(k, nb) & (uint32_t)(F - 1)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < F; b += BZ_THREADS) counts2[(int64_t)g * F + b] = hist[b];
+}
+
+// Per (first-pass bin, second-pass bin): exclusive scan over the bin's
+// chunks; totals in bintot [t][B * F + f] (the final 2^nb bins per table).
+__global__ void k_p2_colscan(int nb1bins, int F, const uint32_t* cbase, uint32_t* counts2, uint32_t* bintot) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nb1bins * F) return;
+  const int tb = (int)(i / F), f = (int)(i % F);
+  uint32_t run = 0;
+  for (uint32_t g = cbase[tb]; g < cbase[tb + 1]; ++g) {
+    const uint32_t v = counts2[(int64_t)g * F + f];
+    counts2[(int64_t)g * F + f] = run;
+    run += v;
+  }
+  bintot[(int64_t)tb * F + f] = run;
+}
+
+__global__ __launch_bounds__(BZ_THREADS) void k_p2_scatter(int64_t n, int nb, const uint32_t* cbase, int nb1bins,
+                                                           const uint32_t* bintot1, const uint32_t* binstart1,
+                                                           const uint4* keys1, const uint32_t* ids1,
+                                                           const uint32_t* counts2, const uint32_t* binstart,
+                                                           uint4* out_keys, uint32_t* out_ids) {
+  __shared__ PartLds L;
+  const uint32_t g = blockIdx.x;
+  if (g >= cbase[nb1bins]) return;
+  const int F = 1 << (nb - PT_B1);
+  const int tb = p2_bin_of_chunk(cbase, nb1bins, g);
+  const int t = tb >> PT_B1;
+  const uint32_t off = (g - cbase[tb]) * (uint32_t)PT_SUPER;
+  const uint32_t cnt_all = min((uint32_t)PT_SUPER, bintot1[tb] - off);
+  const int64_t s = (int64_t)t * n + binstart1[tb] + off;
+  for (int b = threadIdx.x; b < F; b += BZ_THREADS)
+    L.cur[b] = binstart[(int64_t)tb * F + b] + counts2[(int64_t)g * F + b];
+  for (uint32_t r0 = 0; r0 < cnt_all; r0 += PT_ROUND) {
+    const int cnt = (int)min((uint32_t)PT_ROUND, cnt_all - r0);
+    part_round(L, F, cnt,
+               [&](int q, uint4& k, uint32_t& id, int& bn) {
+                 k = keys1[s + r0 + q];
+                 id = ids1[s + r0 + q];
+                 bn = (int)(bin_of(k, nb) & (uint32_t)(F - 1));
+               },
+               out_keys + (int64_t)t * n, out_ids + (int64_t)t * n);
   }
 }
 
@@ -610,6 +786,12 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bz_members(int64_t n, GroupOut g
 }
 
 // ---------------------------------------------------------------- host side
+// Chunks of the second partition pass: at most one partial chunk per
+// first-pass bin beyond the full ones.
+static size_t p2_max_chunks(int64_t n, int T) {
+  return (size_t)T * ((size_t)1 << PT_B1) + (size_t)ceil_div((int64_t)T * n, PT_SUPER);
+}
+
 static int bin_bits(int64_t n) {
   int nb = 0;
   while (nb < BZ_MAXBITS && (n >> nb) > 1536) ++nb;
@@ -618,6 +800,7 @@ static int bin_bits(int64_t n) {
 
 struct BzWs {
   uint32_t *counts, *bintot, *binstart, *st_ids, *alt_ids, *flags;
+  uint32_t *counts2, *bintot1, *binstart1, *cbase;  // second partition pass
   uint4 *st_keys, *alt_keys;
   uint2 *info, *hs, *ctot;
   uint32_t *big_list, *big_count;
@@ -627,11 +810,18 @@ static size_t carve_bz(const geek_bucketize_job& J, void* ws, BzWs& W) {
   Carver c(ws);
   const int nb = bin_bits(J.n);
   const int nbins = 1 << nb;
-  const int nblk = ceil_div(J.n, BZ_CHUNK);
+  const int nblk = ceil_div(J.n, PT_SUPER);
   const int nch = ceil_div(J.n, SC_CHUNK);
   const size_t Tn = (size_t)J.T * J.n;
   const int64_t fw = ceil_div(J.n, 32);
-  W.counts = c.take<uint32_t>((size_t)J.T * nblk * nbins);
+  const bool two = nb > PT_B1;
+  const int nb1bins = 1 << (two ? PT_B1 : nb);
+  W.counts = c.take<uint32_t>((size_t)J.T * nblk * nb1bins);
+  const size_t maxchunks = two ? p2_max_chunks(J.n, J.T) : 0;
+  W.counts2 = c.take<uint32_t>(two ? maxchunks * ((size_t)1 << (nb - PT_B1)) : 4);
+  W.bintot1 = c.take<uint32_t>((size_t)J.T * nb1bins);
+  W.binstart1 = c.take<uint32_t>((size_t)J.T * nb1bins);
+  W.cbase = c.take<uint32_t>((size_t)J.T * nb1bins + 1);
   W.bintot = c.take<uint32_t>((size_t)J.T * nbins);
   W.binstart = c.take<uint32_t>((size_t)J.T * nbins);
   W.st_keys = c.take<uint4>(Tn);
@@ -664,7 +854,7 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   if (ws_bytes < carve_bz(J, ws, W)) return GEEK_ERR_WORKSPACE;
   const int nb = bin_bits(J.n);
   const int nbins = 1 << nb;
-  const int nblk = ceil_div(J.n, BZ_CHUNK);
+  const int nblk = ceil_div(J.n, PT_SUPER);
   const int nch = ceil_div(J.n, SC_CHUNK);
   const int64_t fw = ceil_div(J.n, 32);
   BzArgs a{J.keys, J.n, J.T, J.key_words, J.table_stride, J.row_stride, nb};
@@ -674,12 +864,37 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, W.big_count, (int64_t)4);
   hipLaunchKernelGGL(k_zero_u32, dim3(ceil_div((int64_t)J.T * fw, 256)), dim3(256), 0, s, W.flags,
                      (int64_t)J.T * fw);
-  hipLaunchKernelGGL(k_bin_count, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, W.counts);
-  hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div((int64_t)J.T * nbins, 256)), dim3(256), 0, s, J.T,
-                     nblk, nbins, W.counts, W.bintot);
-  hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, W.counts,
-                     W.binstart, W.st_keys, W.st_ids);
+  if (nb <= PT_B1) {
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, PT_SUPER, W.counts);
+    hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div((int64_t)J.T * nbins, 256)), dim3(256), 0, s, J.T,
+                       nblk, nbins, W.counts, W.bintot);
+    hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
+    hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a, nblk, W.counts, W.binstart,
+                       W.st_keys, W.st_ids);
+  } else {
+    // first pass into the alternate buffers by the top PT_B1 bits, second
+    // pass by the next nb - PT_B1 bits into the staging buffers
+    BzArgs a1 = a;
+    a1.nb = PT_B1;
+    const int nb1bins = J.T << PT_B1;
+    const int F = 1 << (nb - PT_B1);
+    const int maxchunks = (int)p2_max_chunks(J.n, J.T);
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)4 << PT_B1, s, a1, nblk, PT_SUPER,
+                       W.counts);
+    hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div(nb1bins, 256)), dim3(256), 0, s, J.T, nblk, 1 << PT_B1,
+                       W.counts, W.bintot1);
+    hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, 1 << PT_B1, W.bintot1, W.binstart1);
+    hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a1, nblk, W.counts, W.binstart1,
+                       W.alt_keys, W.alt_ids);
+    hipLaunchKernelGGL(k_p2_chunks, dim3(1), dim3(1024), 0, s, nb1bins, W.bintot1, W.cbase);
+    hipLaunchKernelGGL(k_p2_count, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, nb1bins, W.bintot1,
+                       W.binstart1, W.alt_keys, W.counts2);
+    hipLaunchKernelGGL(k_p2_colscan, dim3(ceil_div((int64_t)nb1bins * F, 256)), dim3(256), 0, s, nb1bins, F,
+                       W.cbase, W.counts2, W.bintot);
+    hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
+    hipLaunchKernelGGL(k_p2_scatter, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, nb1bins,
+                       W.bintot1, W.binstart1, W.alt_keys, W.alt_ids, W.counts2, W.binstart, W.st_keys, W.st_ids);
+  }
   prof_begin(GEEK_PROF_BZ_SORT, s);
   hipLaunchKernelGGL(k_bin_group, dim3(nbins, J.T), dim3(BZ_THREADS), 0, s, J.n, nb, W.bintot, W.binstart,
                      W.st_keys, W.st_ids, go, W.big_list, W.big_count);

@@ -54,6 +54,9 @@ def test_bucketize_dense_keys_from_hash():
     (30000, 2, 1, 3000, 5),  # groups of about 10: member-list ranks
     (30000, 2, 1, 300, 6),   # groups of about 100: in-LDS (slot, id) sort
     (300000, 1, 2, 600, 7),  # mostly buckets of one, some pairs; 256 bins
+    (2000000, 2, 4, 1 << 20, 8),  # two partition passes, 2048 bins, 2 chunks per first-pass bin
+    (600000, 2, 2, 700, 9),       # two passes, pairs and triples among singletons
+    (400000, 1, 4, 3, 10),        # two passes, 81 distinct keys: every bin oversized
 ])
 def test_bucketize_synthetic(n, T, kw, alpha, seed):
     api = gpu_api()
