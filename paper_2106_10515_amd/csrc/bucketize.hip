@@ -724,13 +724,20 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(int nch, uint2* ctot, uint
 
 // Bucket ranks and CSR offsets in smallest-member order; heads (and every
 // object alone in its bucket) are written to their slot; heads of larger
-// buckets leave (start, rank) for their members.
+// buckets leave (start, rank) for their members.  Each thread scans 16
+// consecutive ids; the chunk's heads (consecutive ranks) are staged in LDS
+// and written by consecutive threads, so the offsets and the member slots of
+// buckets of one are stored as contiguous runs.
 __global__ __launch_bounds__(BZ_THREADS) void k_bz_apply(int64_t n, int nch, GroupOut go, const uint2* ctot,
                                                          uint2* hs, uint32_t* members, uint32_t* offsets,
                                                          uint32_t* bucket_of, const uint32_t* nbuckets) {
   __shared__ uint32_t sh[17];
+  __shared__ uint32_t s_slot[SC_CHUNK];  // member slot of the chunk's q-th head
+  __shared__ uint32_t s_id[SC_CHUNK];    // its id
+  __shared__ uint32_t s_bof[SC_CHUNK];   // bucket rank of each head id of the chunk, else ~0
   const int t = blockIdx.y, c = blockIdx.x;
-  const int64_t i0 = (int64_t)c * SC_CHUNK + (int64_t)threadIdx.x * BZ_PER;
+  const int64_t c0 = (int64_t)c * SC_CHUNK;
+  const int64_t i0 = c0 + (int64_t)threadIdx.x * BZ_PER;
   const int64_t tn = (int64_t)t * n;
   uint32_t fb = 0, lh = 0, ll = 0;
   uint32_t ihv[BZ_PER], lenv[BZ_PER];
@@ -747,19 +754,34 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bz_apply(int64_t n, int nch, Gro
     lh += ihv[u];
     ll += lenv[u];
   }
-  uint32_t bh = block_exscan(lh, nullptr, sh) + ctot[(int64_t)t * nch + c].x;
-  uint32_t bl = block_exscan(ll, nullptr, sh) + ctot[(int64_t)t * nch + c].y;
-  uint32_t* off = offsets + (int64_t)t * (n + 1);
+  const uint2 base = ctot[(int64_t)t * nch + c];
+  uint32_t nh;
+  const uint32_t q0 = block_exscan(lh, &nh, sh);
+  uint32_t bl = block_exscan(ll, nullptr, sh) + base.y;
+  uint32_t q = q0;
 #pragma unroll
   for (int u = 0; u < BZ_PER; ++u) {
+    const int l = threadIdx.x * BZ_PER + u;
+    if (bucket_of) s_bof[l] = ihv[u] ? base.x + q : 0xFFFFFFFFu;
     if (!ihv[u]) continue;
     const uint32_t i = (uint32_t)(i0 + u);
-    off[bh] = bl;
-    members[tn + bl] = i;
-    if (bucket_of) bucket_of[tn + i] = bh;
-    if ((fb >> u) & 1u) hs[tn + i] = make_uint2(bl, bh);
-    ++bh;
+    s_slot[q] = bl;
+    s_id[q] = i;
+    if ((fb >> u) & 1u) hs[tn + i] = make_uint2(bl, base.x + q);
+    ++q;
     bl += lenv[u];
+  }
+  __syncthreads();
+  uint32_t* off = offsets + (int64_t)t * (n + 1);
+  for (uint32_t k = threadIdx.x; k < nh; k += BZ_THREADS) {
+    const uint32_t sl = s_slot[k];
+    off[base.x + k] = sl;
+    members[tn + sl] = s_id[k];
+  }
+  if (bucket_of) {
+    const int64_t cl = n - c0 < SC_CHUNK ? n - c0 : SC_CHUNK;
+    for (int l = threadIdx.x; l < cl; l += BZ_THREADS)
+      if (s_bof[l] != 0xFFFFFFFFu) bucket_of[tn + c0 + l] = s_bof[l];
   }
   if (c == 0 && threadIdx.x == 0) off[nbuckets[t]] = (uint32_t)n;
 }
