@@ -26,34 +26,8 @@ namespace geek {
 constexpr int H_THREADS = 256;
 constexpr int H_BN = 128;   // points per block
 constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks)
-constexpr int H_FIXCAP = 4096;  // fix-up list entries per round
 constexpr int H_CS = H_BC + 1;  // LDS stride of a point's codes (odd: conflict-free stores)
 constexpr int H_KB = 16;        // products per accumulation block of the GEMM
-
-// Exclusive scan over a 256-thread block; *total = block sum.
-__device__ uint32_t block_exscan256(uint32_t v, uint32_t* total, uint32_t* sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wv] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t r = 0;
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t c = sh[k];
-      sh[k] = r;
-      r += c;
-    }
-    sh[16] = r;
-  }
-  __syncthreads();
-  const uint32_t res = x - v + sh[wv];
-  *total = sh[16];
-  return res;
-}
 
 template <int DP>
 __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
@@ -70,14 +44,9 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   __shared__ __attribute__((aligned(16))) float lds_t1[H_BC];
   __shared__ __attribute__((aligned(16))) float lds_t0[H_BC];
   __shared__ float lds_an[H_BC];   // |a_p| (rounded up) per row of the chunk
-  __shared__ float lds_xn[H_BN];   // |x_i| (rounded up) per point of the block
   // codes of a point are H_CS ints apart: the epilogue's stores (one row,
   // 32 points per instruction) then fall into distinct banks
   __shared__ int lds_code[H_BN * H_CS];
-  __shared__ uint32_t lds_flag[H_BN * H_BC / 32];  // one bit per (point, row)
-  __shared__ uint16_t lds_fix[H_FIXCAP];            // compacted (point << 6 | row)
-  __shared__ uint32_t lds_scan[17];
-  __shared__ unsigned int lds_nfix;
 
   const int P = m * L;
   const int tid = threadIdx.x;
@@ -124,7 +93,6 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   if (!finite) set_status(st, GEEK_ERR_NONFINITE);
   nrm += __shfl_xor(nrm, 32);
   const float xn = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
-  if (h == 0) lds_xn[wv * 32 + p] = xn;
   // |q32 - q64| <= coef * (|a||x| + |b|) / w.  The GEMM sums blocks of
   // H_KB products in fresh accumulators and then adds the block sums, so a
   // product passes through at most H_KB + DP/H_KB + 1 roundings (2u each,
@@ -134,14 +102,16 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   constexpr int NR = H_KB + DP / H_KB + 1;
   const double coef_d = (NR * 2.0 * u32 / (1.0 - NR * 2.0 * u32) + 6.0 * u32 + (DP + 3) * 0x1p-53) * 1.01;
   const float coef = (float)coef_d;
-  // second stage (float64 dot of 16 partial sums, FMA): |q_fast - q64| <=
-  // coef64 * (|a||x| + |b|) / w, covering both float64 evaluations
-  const double coef64 = ((DP / 16 + 6) + (DP + 3)) * 0x1p-53 * 1.02;
+  // second stage (float64 dot: four FMA chains per K half, summed pairwise,
+  // then across the halves; + b; * (1/w) with 1/w rounded): |q_fast - q64|
+  // <= coef64 * (|a||x| + |b|) / w, covering both float64 evaluations
+  const double coef64 = ((DP / 8 + 8) + (DP + 3)) * 0x1p-53 * 1.02;
+  const double inv_wd = 1.0 / (double)w;
 
   const float tscale = coef * inv_w;
   const bool a_vec = ((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
 
-  if (tid == 0) lds_nfix = 0;
+  unsigned long long nfix = 0;  // uncertified pairs owned by this lane
   for (int tb = 0; tb < L; tb += tpc) {
     const int ntab = (L - tb) < tpc ? (L - tb) : tpc;
     const int rows_used = ntab * m;
@@ -173,7 +143,6 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       lds_an[tid] = live ? anorm[p0 + tid] : 0.f;
       lds_t0[tid] = live ? __builtin_fmaf(tscale, fabsf(bv), 0x1p-22f) : 0.f;
     }
-    lds_flag[tid] = 0u;  // H_THREADS == H_BN * H_BC / 32 words
     __syncthreads();
 
     f32x16 acc0 = {}, acc1 = {};
@@ -225,6 +194,7 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     const int pl = wv * 32 + p;  // point within block
     // Register r of half hf holds row hf*32 + (r/4)*8 + h*4 + r%4; rows past
     // rows_used (zero A rows) are stored but never flagged or read.
+    uint32_t badv[2] = {0u, 0u};
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       if (half == 1 && rows_used <= 32) break;
@@ -262,63 +232,59 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
         }
       }
       bad &= live;
-      if (bad && valid) atomicOr(&lds_flag[pl * 2 + half], bad);
+      badv[half] = valid ? bad : 0u;
     }
-    __syncthreads();
-    // ---- float64 check of the uncertified pairs: compact the flags into a
-    // list and spread it over the block (a_p from the LDS tile)
-    {
-      const uint32_t bits0 = lds_flag[tid];
-      uint32_t tot;
-      const uint32_t at0 = block_exscan256(__popc(bits0), &tot, lds_scan);
-      for (uint32_t base = 0; base < tot; base += H_FIXCAP) {
-        uint32_t bits = bits0, at = at0;
-        while (bits) {
-          const int bb = __ffs(bits) - 1;
-          bits &= bits - 1u;
-          if (at >= base && at < base + H_FIXCAP)
-            lds_fix[at - base] = (uint16_t)(((tid >> 1) << 6) | ((tid & 1) * 32 + bb));
-          ++at;
-        }
-        __syncthreads();
-        const uint32_t cnt = (tot - base) < (uint32_t)H_FIXCAP ? (tot - base) : (uint32_t)H_FIXCAP;
-        // 16 lanes per pair: FMA partial sums over t = lane, lane + 16, ...
-        // reduced by shuffles give q_fast; when no integer lies within
-        // coef64 * (|a||x| + |b|) / w of it, its floor is the reference
-        // floor, else one lane evaluates the reference sum itself
-        const int grp = tid >> 4, gl = tid & 15;
-        for (uint32_t q0 = 0; q0 < cnt; q0 += H_THREADS / 16) {
-          const uint32_t q = q0 + grp;
-          const bool act = q < cnt;
-          const int e = act ? lds_fix[q] : 0;
-          const int pp = e >> 6, row = e & 63;
-          const float* xi = X + (i0 + pp) * ldx;
-          const float* ap = lds_a + row * STR;
-          double part = 0.0;
-          if (act)
-            for (int t = gl; t < d; t += 16) part = __fma_rn((double)ap[t], (double)xi[t], part);
-          part += __shfl_xor(part, 8);
-          part += __shfl_xor(part, 4);
-          part += __shfl_xor(part, 2);
-          part += __shfl_xor(part, 1);
-          if (act && gl == 0) {
-            const double bv = (double)lds_b[row];
-            const double qf = (part + bv) / (double)w;
-            const double rad = coef64 * ((double)lds_an[row] * (double)lds_xn[pp] + fabs(bv)) / (double)w;
-            double fl = floor(qf);
-            if (!(qf - fl > rad && fl + 1.0 - qf > rad)) {
-              double sacc = 0.0;
-              for (int t = 0; t < d; ++t) sacc = __dadd_rn(sacc, __dmul_rn((double)ap[t], (double)xi[t]));
-              fl = floor(__dadd_rn(sacc, bv) / (double)w);
-            }
-            const bool fits = fl >= -2147483648.0 && fl <= 2147483647.0;
-            if (!fits) set_status(st, GEEK_ERR_RANGE);
-            lds_code[pp * H_CS + row] = fits ? (int)fl : 0;
+    // ---- float64 check of the uncertified pairs, by the two lanes that hold
+    // the point's x (each its half of the K range, in registers).  Both lanes
+    // walk the union of their flagged rows in the same order: FMA partial
+    // sums over their halves, added across the pair, give q_fast; when no
+    // integer lies within coef64 * (|a||x| + |b|) / w of it, its floor is the
+    // reference floor, else the lane that owns the row evaluates the
+    // reference sum itself.  The owner writes the code it stored before.
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      nfix += __popc(badv[half]);
+      uint32_t fl = badv[half] | __shfl_xor(badv[half], 32);
+      while (__any(fl != 0u)) {
+        const int bit = fl ? __ffs(fl) - 1 : 0;
+        const int row = half * 32 + bit;
+        double part = 0.0;
+        if (fl) {
+          // four independent FMA chains (k mod 4), then summed pairwise
+          const float* ap = lds_a + row * STR + h * S;
+          double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < S; k += 4) {
+            const float4 av = *reinterpret_cast<const float4*>(ap + k);
+            float xk[4] = {xb[k], xb[k + 1], xb[k + 2], xb[k + 3]};
+            // opaque copies: converting all of x to float64 once, outside
+            // the loop over flagged rows, would need 2*S more registers
+            asm volatile("" : "+v"(xk[0]), "+v"(xk[1]), "+v"(xk[2]), "+v"(xk[3]));
+            p4[0] = __fma_rn((double)av.x, (double)xk[0], p4[0]);
+            p4[1] = __fma_rn((double)av.y, (double)xk[1], p4[1]);
+            p4[2] = __fma_rn((double)av.z, (double)xk[2], p4[2]);
+            p4[3] = __fma_rn((double)av.w, (double)xk[3], p4[3]);
           }
+          part = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         }
-        __syncthreads();
+        part += __shfl_xor(part, 32);
+        if (fl && ((bit >> 2) & 1) == h) {
+          const double bv = (double)lds_b[row];
+          const double qf = (part + bv) * inv_wd;
+          const double rad = coef64 * ((double)lds_an[row] * (double)xn + fabs(bv)) / (double)w;
+          double flo = floor(qf);
+          if (!(qf - flo > rad && flo + 1.0 - qf > rad)) {
+            const float* ar = lds_a + row * STR;
+            double sacc = 0.0;
+            for (int t = 0; t < d; ++t) sacc = __dadd_rn(sacc, __dmul_rn((double)ar[t], (double)xr[t]));
+            flo = floor(__dadd_rn(sacc, bv) / (double)w);
+          }
+          const bool fits = flo >= -2147483648.0 && flo <= 2147483647.0;
+          if (!fits) set_status(st, GEEK_ERR_RANGE);
+          lds_code[pl * H_CS + row] = fits ? (int)flo : 0;
+        }
+        fl &= fl - 1u;
       }
-      if (tid == 0 && tot) lds_nfix += tot;
     }
     __syncthreads();
     // ---- pack the m codes of every (table, point) into a 128-bit key
@@ -355,8 +321,10 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       }
     }
   }
-  __syncthreads();
-  if (n_fixup && tid == 0 && lds_nfix) atomicAdd(n_fixup, (unsigned long long)lds_nfix);
+  if (n_fixup) {
+    for (int o = 32; o > 0; o >>= 1) nfix += __shfl_xor(nfix, o);
+    if (lane == 0 && nfix) atomicAdd(n_fixup, nfix);
+  }
 }
 
 // |a_p| rounded up (float64 sum of squares), per projection.
