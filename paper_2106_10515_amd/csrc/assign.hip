@@ -207,10 +207,12 @@ __device__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
 }
 
+// Candidate records: rstride int32 per row (count, then seed indices); the
+// BF16 first pass writes 2 per row, the windows RECW.
 __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
                            const double* __restrict__ C, int k, Het het, int64_t n_rows,
                            const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
-                           const int32_t* __restrict__ rec, int32_t* __restrict__ assign,
+                           const int32_t* __restrict__ rec, int rstride, int32_t* __restrict__ assign,
                            double* __restrict__ dist, uint32_t* __restrict__ esc,
                            uint32_t* __restrict__ esc_count, unsigned long long* __restrict__ ctr,
                            int ctr_rows) {
@@ -218,40 +220,39 @@ __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t start = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t iters = (count + stride - 1) / stride;
+  unsigned long long nrow = 0, ncand = 0;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t pos = start + it * stride;
-    unsigned long long nrow = 0, ncand = 0;
-    if (pos < count) {
-      const int64_t i = rows ? (int64_t)rows[pos] : pos;
-      const int32_t* rr = rec + pos * RECW;
-      const int c = rr[0];
-      if (c <= 0) {  // window overflow (or no finite candidate): escalate
-        const uint32_t q = atomicAdd(esc_count, 1u);
-        esc[q] = (uint32_t)i;
-      } else {
-        double best = INFINITY;
-        int bj = 0x7fffffff;
-        const float* xr = X + i * ldx;
-        for (int q = 0; q < c; ++q) {
-          const int j = rr[1 + q];
-          if ((unsigned)j >= (unsigned)k) continue;
-          const double D = d64h(xr, C + (int64_t)j * d, d, het, i, j);
-          if (D < best || (D == best && j < bj)) {
-            best = D;
-            bj = j;
-          }
-        }
-        if (bj == 0x7fffffff) bj = 0;
-        assign[i] = bj;
-        dist[i] = best;
-        nrow = 1;
-        ncand = (unsigned long long)c;
+    if (pos >= count) continue;
+    const int64_t i = rows ? (int64_t)rows[pos] : pos;
+    const int32_t* rr = rec + pos * rstride;
+    const int c = rr[0];
+    if (c <= 0) {  // window overflow (or no finite candidate): escalate
+      const uint32_t q = atomicAdd(esc_count, 1u);
+      esc[q] = (uint32_t)i;
+      continue;
+    }
+    double best = INFINITY;
+    int bj = 0x7fffffff;
+    const float* xr = X + i * ldx;
+    for (int q = 0; q < c; ++q) {
+      const int j = rr[1 + q];
+      if ((unsigned)j >= (unsigned)k) continue;
+      const double D = d64h(xr, C + (int64_t)j * d, d, het, i, j);
+      if (D < best || (D == best && j < bj)) {
+        best = D;
+        bj = j;
       }
     }
-    if (ctr) {
-      block_add_u64(ctr + ctr_rows, nrow);
-      block_add_u64(ctr + 3, ncand);
-    }
+    if (bj == 0x7fffffff) bj = 0;
+    assign[i] = bj;
+    dist[i] = best;
+    nrow += 1;
+    ncand += (unsigned long long)c;
+  }
+  if (ctr) {
+    block_add_u64(ctr + ctr_rows, nrow);
+    block_add_u64(ctr + 3, ncand);
   }
 }
 
@@ -754,14 +755,16 @@ static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, h
   AssignWs& W = C.W;
   unsigned long long* ctr = W.ctr;
   const int nb_rows = ceil_div(J.n, 256);
+  const int rstride = J.precision == GEEK_PREC_BF16 ? RECW_T2 : RECW;
   hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
-                     nullptr, nullptr, W.rec, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
+                     nullptr, nullptr, W.rec, rstride, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
   // rows with several first-pass candidates: float32 rescan of those rows with
   // a wider window (persistent grids, at most one row tile / block per group)
   scan_any<ModeF32, true>(C.het_on, C.DP, esc_grid(J.n, 128), s, J, 0, W.esc, W.counts + 0, W.cl32, W, C.k_pad,
                           C.het, st);
   hipLaunchKernelGGL(k_finalize, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
-                     C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, J.assign, C.dist, W.fb, W.counts + 1, ctr, 1);
+                     C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, RECW, J.assign, C.dist, W.fb, W.counts + 1, ctr,
+                     1);
   const int fb_grid = (int)std::min<int64_t>(FB_GRID, ceil_div(J.n, FB_R) * FB_SPLIT);
   switch (C.DP) {
 #define GEEK_FB_CASE(DPV)                                                                                  \

@@ -17,6 +17,7 @@ using IC = std::integral_constant<int, V>;
 constexpr int TCAND = 8;       // candidates per lane window, BF16/FP8 passes
 constexpr int TCAND32 = 32;    // float32 pass (also the rescan of ambiguous rows)
 constexpr int RECW = TCAND32 + 1;  // candidate record per row: count, then ids
+constexpr int RECW_T2 = 2;         // the BF16 pass's record: 1 and the index, or -1
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_BC = 64;   // centroids per LDS stage
 
@@ -534,7 +535,7 @@ __device__ __forceinline__ void scan_tiles(
         const bool unique = best > -1e37f && best < 1e37f && fabsf(best) >= 0x1p-126f && isfinite(v1) &&
                             v2 > v1 + twoeps[cb] && jbest < k;
         if (valid[cb] && h == 0) {
-          int32_t* rr = rec + posv[cb] * RECW;
+          int32_t* rr = rec + posv[cb] * RECW_T2;
           rr[0] = unique ? 1 : -1;
           if (unique) rr[1] = jbest;
         }
