@@ -501,13 +501,15 @@ __global__ void k_radius(const int32_t* __restrict__ assign, const double* __res
     atomic_max_nonneg(slot, v);
 }
 
-// Few clusters: per-workgroup maxima in LDS (bit patterns of non-negative
-// doubles order like the values), then one global atomic per touched slot.
-constexpr int RAD_LDS = 4096;
+// Up to CAP clusters: per-workgroup maxima in LDS (bit patterns of
+// non-negative doubles order like the values), then one global atomic per
+// touched slot.
+constexpr int RAD_LDS = 4096, RAD_LDS_BIG = 16384;
+template <int CAP>
 __global__ __launch_bounds__(256) void k_radius_lds(const int32_t* __restrict__ assign,
                                                     const double* __restrict__ dist, int64_t n, int k,
                                                     double* __restrict__ rad) {
-  __shared__ unsigned long long m[RAD_LDS];
+  __shared__ unsigned long long m[CAP];
   for (int j = threadIdx.x; j < k; j += 256) m[j] = 0ull;
   __syncthreads();
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -556,8 +558,11 @@ void sse_and_radius(const double* dist, const int32_t* assign, int64_t n, int k,
   if (radius) {
     hipLaunchKernelGGL(k_fill_f64, dim3(ceil_div(k, 256)), dim3(256), 0, s, radius, k, 0.0);
     if (k <= RAD_LDS)
-      hipLaunchKernelGGL(k_radius_lds, dim3((int)std::min<int64_t>(ceil_div(n, 4096), 512)), dim3(256), 0, s,
-                         assign, dist, n, k, radius);
+      hipLaunchKernelGGL(k_radius_lds<RAD_LDS>, dim3((int)std::min<int64_t>(ceil_div(n, 4096), 512)), dim3(256), 0,
+                         s, assign, dist, n, k, radius);
+    else if (k <= RAD_LDS_BIG)  // 128 KB of LDS: one workgroup per CU, fewer of them
+      hipLaunchKernelGGL(k_radius_lds<RAD_LDS_BIG>, dim3((int)std::min<int64_t>(ceil_div(n, 16384), 128)), dim3(256),
+                         0, s, assign, dist, n, k, radius);
     else
       hipLaunchKernelGGL(k_radius, dim3(ceil_div(n, 256)), dim3(256), 0, s, assign, dist, n, k, radius);
     hipLaunchKernelGGL(k_sqrt_inplace, dim3(ceil_div(k, 256)), dim3(256), 0, s, radius, k, take_sqrt);

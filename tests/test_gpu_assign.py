@@ -108,6 +108,17 @@ def test_assign_full_scan_rows(prec, n, d, clusters, copies, seed):
     assert ctr[2] == n
 
 
+@pytest.mark.parametrize("n,d,clusters", [
+    (12000, 8, 6000),    # k = 6000: per-workgroup radius maxima in a 128 KB LDS table
+    (30000, 4, 30000),   # k = 30000: radius by global atomics
+])
+def test_assign_many_seeds_radius_paths(n, d, clusters):
+    api = gpu_api()
+    X, lab, _ = dense_mixture(n, d, clusters, -10, 10, 1.0, "equal", 11)
+    so, sm = planted_seeds(lab, clusters, 2)
+    _check(api, X, so, sm, "bf16", f"radius k={len(so) - 1}")
+
+
 def test_assign_nonfinite_input_is_reported():
     api = gpu_api()
     from paper_2106_10515_amd import GeekError
