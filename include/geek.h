@@ -41,6 +41,13 @@
  *   kernels of the same call become no-ops once it is non-zero).  The caller
  *   zeroes ``*d_status`` before a call chain and reads it after synchronizing
  *   the stream.
+ * - A call with several jobs may run independent jobs on up to four
+ *   internal streams of the device (default priority, created by the first
+ *   such call and kept until the process ends): an event recorded on
+ *   ``stream`` starts them and ``stream`` waits for all of them before the
+ *   call's later work, so the call stays ordered on ``stream`` and can be
+ *   captured in a HIP graph (as parallel branches).  The first multi-job
+ *   call on a device should not itself be under capture.
  * - Ids are 0-based uint32.  Matrices are row-major.
  */
 #ifndef GEEK_H
@@ -57,7 +64,7 @@ extern "C" {
 #define GEEK_OK 0
 #define GEEK_ERR_ARG (-1)         /* null/misaligned pointer, inconsistent sizes */
 #define GEEK_ERR_WORKSPACE (-2)   /* ws_bytes below geek_workspace_size */
-#define GEEK_ERR_UNSUPPORTED (-3) /* a size this build does not handle */
+#define GEEK_ERR_UNSUPPORTED (-3) /* a size the library does not handle */
 #define GEEK_ERR_HIP (-4)         /* HIP launch failure; see geek_last_hip_error */
 /* data-dependent, written to *d_status */
 #define GEEK_ERR_NONFINITE 1      /* NaN or Inf in a float input */
@@ -254,8 +261,9 @@ typedef struct geek_assign_job {
   unsigned long long* t_done; /* optional out [1]: device wall-clock ticks
                                (geek_wallclock_hz per second) from the start
                                of the call to the moment this job's outputs
-                               were complete (batched calls), or the absolute
-                               tick count at that moment (njobs = 1) */
+                               were complete (batched calls; jobs finish in
+                               any order), or the absolute tick count at that
+                               moment (njobs = 1) */
 } geek_assign_job;
 
 /* ---- entry points -------------------------------------------------------- */
@@ -264,7 +272,10 @@ typedef struct geek_assign_job {
 #define GEEK_OP_SILK 2
 #define GEEK_OP_ASSIGN 3
 
-/* Bytes of device workspace the call `op` needs for these jobs (host). */
+/* Bytes of device workspace the call `op` needs for these jobs (host).  For
+ * geek_hash and geek_bucketize with several jobs it is min(njobs, 4) slices
+ * of the largest job's workspace (one per stream the jobs run on); a smaller
+ * workspace of at least one slice runs fewer jobs at once. */
 int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t* bytes);
 
 int32_t geek_hash(const geek_hash_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
@@ -274,14 +285,15 @@ int32_t geek_bucketize(const geek_bucketize_job* jobs, int32_t njobs, void* ws,
 int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                         int32_t* d_status, void* stream);
 /* geek_assign with njobs > 1 and every job GEEK_METRIC_EUCLID in one
- * precision (the many-job workload of the benchmark spec, Section 4's batched
- * clustering runs): the jobs' centroids are prepared one job after another,
- * then one persistent matrix-core launch per padded dimension (32, 64, 128,
- * 256) scans the tiles of all jobs of that dimension in call order, then the
- * float64 checks run per job.  Each job's outputs are bit-identical to a
- * call with that job alone.  The workspace is the sum of the jobs' own
- * workspaces (geek_workspace_size reports it).  Any other mix of jobs runs
- * one job after another in a shared workspace. */
+ * precision (many independent clustering problems at once): the jobs'
+ * centroids are prepared on the internal streams, then one persistent
+ * matrix-core launch per padded dimension (32, 64, 128, 256) scans the tiles
+ * of all jobs of that dimension in call order, with the tile shape set by
+ * geek_set_scan_tiles, then the float64 checks of each job run on the
+ * internal streams.  Each job's outputs are bit-identical to a call with
+ * that job alone.  The workspace is the sum of the jobs' own workspaces
+ * (geek_workspace_size reports it).  Any other mix of jobs runs one job
+ * after another in a shared workspace. */
 int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                     int32_t* d_status, void* stream);
 

@@ -3,6 +3,7 @@
 // and assign.hip.
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -62,6 +63,54 @@ void prof_end(int id, hipStream_t s) {
   hipEventRecord(g_prof[k].b, s);
   g_open[id] = -1;
 }
+
+namespace {
+constexpr int FAN_DEVS = 64;
+std::mutex g_fan_mu;
+struct FanDev {
+  bool tried = false, ok = false;
+  hipStream_t side[FAN_LANES] = {};
+  hipEvent_t fork = nullptr, join[FAN_LANES] = {};
+};
+FanDev g_fan[FAN_DEVS];
+}  // namespace
+
+Fan::Fan(hipStream_t main, int jobs) : main_(main) {
+  if (jobs < 2 || hipGetDevice(&dev_) != hipSuccess || dev_ < 0 || dev_ >= FAN_DEVS) return;
+  g_fan_mu.lock();
+  FanDev& F = g_fan[dev_];
+  if (!F.tried) {
+    F.tried = true;
+    bool ok = hipEventCreateWithFlags(&F.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < FAN_LANES; ++i)
+      ok = hipStreamCreateWithFlags(&F.side[i], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&F.join[i], hipEventDisableTiming) == hipSuccess;
+    F.ok = ok;
+    if (!ok) (void)hipGetLastError();
+  }
+  if (!F.ok) {
+    g_fan_mu.unlock();
+    return;
+  }
+  n_ = jobs < FAN_LANES ? jobs : FAN_LANES;
+  hipEventRecord(F.fork, main_);
+  for (int i = 0; i < n_; ++i) {
+    side_[i] = F.side[i];
+    hipStreamWaitEvent(side_[i], F.fork, 0);
+  }
+}
+
+Fan::~Fan() {
+  if (n_ <= 1) return;
+  FanDev& F = g_fan[dev_];
+  for (int i = 0; i < n_; ++i) {
+    hipEventRecord(F.join[i], side_[i]);
+    hipStreamWaitEvent(main_, F.join[i], 0);
+  }
+  g_fan_mu.unlock();
+}
+
+size_t ws_slice(size_t bytes) { return (bytes + 255) / 256 * 256; }
 
 int32_t hip_fail(hipError_t e) {
   g_last_err = hipGetErrorString(e);
@@ -242,8 +291,12 @@ int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t*
       default:
         return GEEK_ERR_ARG;
     }
-    tot = b > tot ? b : tot;  // jobs run one after another and share the workspace
+    tot = b > tot ? b : tot;
   }
+  // hash and bucketize jobs run on up to FAN_LANES streams at once, each lane
+  // reusing its own slice of the workspace for its jobs in turn
+  if (op == GEEK_OP_HASH || op == GEEK_OP_BUCKETIZE)
+    tot = ws_slice(tot) * (size_t)(njobs < FAN_LANES ? njobs : FAN_LANES);
   if (op == GEEK_OP_ASSIGN && assign_batchable(static_cast<const geek_assign_job*>(jobs), njobs))
     tot = assign_batch_ws(static_cast<const geek_assign_job*>(jobs), njobs);  // one slice per job
   *bytes = tot;
@@ -253,13 +306,17 @@ int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t*
 int32_t geek_hash(const geek_hash_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                   int32_t* d_status, void* stream) {
   if (!jobs || njobs < 1) return GEEK_ERR_ARG;
-  for (int j = 0; j < njobs; ++j)
+  size_t slice = 0;
+  for (int j = 0; j < njobs; ++j) {
     if (int32_t rc = check_hash(jobs[j])) return rc;
-  for (int j = 0; j < njobs; ++j) {
-    if (ws_bytes < hash_ws(jobs[j])) return GEEK_ERR_WORKSPACE;
+    slice = std::max(slice, ws_slice(hash_ws(jobs[j])));
   }
+  if (ws_bytes < slice) return GEEK_ERR_WORKSPACE;
+  // as many lanes as the workspace holds slices for
+  Fan fan((hipStream_t)stream, (int)std::min<size_t>((size_t)njobs, ws_bytes / slice));
   for (int j = 0; j < njobs; ++j) {
-    int32_t rc = hash_run(jobs[j], ws, ws_bytes, d_status, (hipStream_t)stream);
+    const int l = fan.lanes() > 1 ? j % fan.lanes() : 0;
+    int32_t rc = hash_run(jobs[j], static_cast<char*>(ws) + (size_t)l * slice, slice, d_status, fan.lane(j));
     if (rc) return rc;
   }
   return GEEK_OK;
@@ -268,13 +325,17 @@ int32_t geek_hash(const geek_hash_job* jobs, int32_t njobs, void* ws, size_t ws_
 int32_t geek_bucketize(const geek_bucketize_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                        int32_t* d_status, void* stream) {
   if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  size_t slice = 0;
   for (int j = 0; j < njobs; ++j) {
     if (int32_t rc = check_bz(jobs[j])) return rc;
-    if (ws_bytes < bucketize_ws(jobs[j])) return GEEK_ERR_WORKSPACE;
-    if (!ws) return GEEK_ERR_ARG;
+    slice = std::max(slice, ws_slice(bucketize_ws(jobs[j])));
   }
+  if (!ws) return GEEK_ERR_ARG;
+  if (ws_bytes < slice) return GEEK_ERR_WORKSPACE;
+  Fan fan((hipStream_t)stream, (int)std::min<size_t>((size_t)njobs, ws_bytes / slice));
   for (int j = 0; j < njobs; ++j) {
-    int32_t rc = bucketize_run(jobs[j], ws, ws_bytes, d_status, (hipStream_t)stream);
+    const int l = fan.lanes() > 1 ? j % fan.lanes() : 0;
+    int32_t rc = bucketize_run(jobs[j], static_cast<char*>(ws) + (size_t)l * slice, slice, d_status, fan.lane(j));
     if (rc) return rc;
   }
   return GEEK_OK;

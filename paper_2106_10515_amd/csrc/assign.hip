@@ -845,8 +845,11 @@ int32_t assign_euclid_batch(const geek_assign_job* jobs, int njobs, void* ws, si
   const geek_assign_job& J0 = jobs[0];
   prof_begin(GEEK_PROF_ASSIGN, s);
   hipLaunchKernelGGL(k_clock_now, dim3(1), dim3(64), 0, s, t0);
-  for (int j = 0; j < njobs; ++j)
-    if (int32_t rc = assign_prep(jobs[j], slice[j], C[j], st, s)) return rc;
+  {  // jobs prepared concurrently on the fan-out lanes (independent slices)
+    Fan fan(s, njobs);
+    for (int j = 0; j < njobs; ++j)
+      if (int32_t rc = assign_prep(jobs[j], slice[j], C[j], st, fan.lane(j))) return rc;
+  }
   // one persistent launch per padded depth, jobs in call order, with the
   // tile shape set for that (precision, depth)
   const bool low = low_precision(J0);
@@ -888,7 +891,10 @@ int32_t assign_euclid_batch(const geek_assign_job* jobs, int njobs, void* ws, si
     tslot += (int)tab.size();
   }
   prof_end(GEEK_PROF_ASSIGN_SCAN, s);
-  for (int j = 0; j < njobs; ++j) assign_finish(jobs[j], C[j], st, s, t0);
+  {
+    Fan fan(s, njobs);
+    for (int j = 0; j < njobs; ++j) assign_finish(jobs[j], C[j], st, fan.lane(j), t0);
+  }
   prof_end(GEEK_PROF_ASSIGN, s);
   GEEK_LAUNCH_CHECK();
   return GEEK_OK;

@@ -78,6 +78,32 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 void prof_begin(int id, hipStream_t s);
 void prof_end(int id, hipStream_t s);
 
+// Independent per-job work of a multi-job call fanned out over up to
+// FAN_LANES streams and joined back into the caller's stream: an event
+// recorded on the caller's stream is waited on by every lane, and the caller's
+// stream waits on an event recorded on every lane at the end (HIP graph
+// capture records this as parallel branches).  The lane streams (default
+// priority, one set per device) and events are created on the first call that
+// fans out and kept until the process ends; a mutex keeps the enqueue of one
+// fanned-out call from interleaving with another's.  With one lane, or if the
+// streams cannot be created, everything stays on the caller's stream.
+constexpr int FAN_LANES = 4;
+class Fan {
+ public:
+  Fan(hipStream_t main, int jobs);
+  ~Fan();
+  int lanes() const { return n_; }
+  hipStream_t lane(int j) const { return n_ > 1 ? side_[j % n_] : main_; }
+
+ private:
+  hipStream_t main_;
+  int n_ = 1, dev_ = 0;
+  hipStream_t side_[FAN_LANES] = {};
+};
+
+// Workspace bytes rounded up to a 256-byte slice.
+size_t ws_slice(size_t bytes);
+
 // Records the HIP error string for geek_last_hip_error and maps to a status.
 int32_t hip_fail(hipError_t e);
 #define GEEK_LAUNCH_CHECK()                                   \

@@ -55,7 +55,8 @@ def test_batch_equals_single_calls(prec, njobs, seed):
         assert np.array_equal(outs[j]["dist"].cpu().numpy(), dist), j
         assert outs[j]["sse"].item() == oracle.sse(dist), j
     t = t_done.cpu().numpy()
-    assert (t > 0).all() and (np.diff(t) >= 0).all(), t
+    # jobs finish on several streams at once: any order, all after the start
+    assert (t > 0).all(), t
     assert api.wallclock_hz() > 0
 
 
