@@ -241,9 +241,30 @@ __global__ void k_seg_emit(const uint32_t* __restrict__ sstart, int64_t S, const
                            uint32_t* __restrict__ cmem, uint32_t* __restrict__ coff) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= S || esize[s] == 0u) return;
-  const uint32_t o = m0 + eoff[s];
-  coff[s0 + eidx[s]] = o;
-  for (uint32_t q = 0; q < esize[s]; ++q) cmem[o + q] = klo[sstart[s] + q];
+  coff[s0 + eidx[s]] = m0 + eoff[s];  // the members are copied by k_seg_copy
+}
+
+// The last index r in [0, cnt) with off[r] <= e (off non-decreasing): the
+// non-empty entry whose output range holds position e.
+GEEK_D int64_t range_of(const uint32_t* __restrict__ off, int64_t cnt, uint32_t e) {
+  int64_t lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One thread per emitted member: C's members of this table, segment by
+// segment (a segment can hold a large share of the table, so the copy is
+// spread over threads rather than done by one thread per segment).
+__global__ void k_seg_copy(const uint32_t* __restrict__ sstart, int64_t S, const uint32_t* __restrict__ eoff,
+                           const uint32_t* __restrict__ klo, uint32_t m0, uint32_t em, uint32_t* __restrict__ cmem) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= em) return;
+  const int64_t s = range_of(eoff, S, (uint32_t)e);
+  cmem[m0 + e] = klo[sstart[s] + ((uint32_t)e - eoff[s])];
 }
 
 __global__ void k_put(uint32_t* p, int64_t i, uint32_t v) {
@@ -311,17 +332,23 @@ __global__ void k_emit_seeds(const uint32_t* __restrict__ ord, int64_t nbins, co
                              uint32_t* __restrict__ seed_off, uint32_t* __restrict__ seed_mem) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r >= nbins || osz[r] == 0u) return;
+  seed_off[oidx[r]] = ooff[r];  // the members are copied by k_seed_copy
+}
+
+// One thread per seed member: from the set that passes through (C) or from
+// the voted ids of the bin.
+__global__ void k_seed_copy(const uint32_t* __restrict__ ord, int64_t nbins, const uint32_t* __restrict__ ooff,
+                            const uint32_t* __restrict__ src_kind, const uint32_t* __restrict__ binoff,
+                            const uint32_t* __restrict__ binmem, const uint32_t* __restrict__ cmem,
+                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ segof,
+                            const uint32_t* __restrict__ sstart, const uint32_t* __restrict__ klo, uint32_t tot,
+                            uint32_t* __restrict__ seed_mem) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= tot) return;
+  const int64_t r = range_of(ooff, nbins, (uint32_t)e);
   const uint32_t b = ord[r];
-  const uint32_t o = ooff[r];
-  seed_off[oidx[r]] = o;
-  if (src_kind[b]) {
-    const uint32_t set = binmem[binoff[b]];
-    const uint32_t* src = cmem + coff[set];
-    for (uint32_t q = 0; q < osz[r]; ++q) seed_mem[o + q] = src[q];
-  } else {
-    const uint32_t* src = klo + sstart[segof[b]];
-    for (uint32_t q = 0; q < osz[r]; ++q) seed_mem[o + q] = src[q];
-  }
+  const uint32_t q = (uint32_t)e - ooff[r];
+  seed_mem[e] = src_kind[b] ? cmem[coff[binmem[binoff[b]]] + q] : klo[sstart[segof[b]] + q];
 }
 
 __global__ void k_silk_capacity(unsigned long long ns, unsigned long long nm, uint32_t* k_out,
@@ -579,6 +606,9 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
     }
     hipLaunchKernelGGL(k_seg_emit, dim3(nblk(o.S)), dim3(256), 0, s, W.sstart, (int64_t)o.S, W.esize, W.eoff,
                        W.eidx, W.klo, cm, cs, W.cmem, W.coff);
+    if (em)
+      hipLaunchKernelGGL(k_seg_copy, dim3(nblk(em)), dim3(256), 0, s, W.sstart, (int64_t)o.S, W.eoff, W.klo, cm, em,
+                         W.cmem);
     cm += em;
     cs += es;
   }
@@ -634,10 +664,14 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
   exscan_u32(W.esize, W.eoff, nb2, W.scan_tmp, W.eoff + nb2, s);
   exscan_u32(W.eone, W.eidx, nb2, W.scan_tmp, W.eidx + nb2, s);
   const uint32_t tot_m = H.read(W.eoff + nb2), k = H.read(W.eidx + nb2);
-  if ((int64_t)k <= J.cap_k && (int64_t)tot_m <= J.cap_members)
+  if ((int64_t)k <= J.cap_k && (int64_t)tot_m <= J.cap_members) {
     hipLaunchKernelGGL(k_emit_seeds, dim3(nblk(nb2)), dim3(256), 0, s, ord, nb2, W.esize, W.eoff, W.eidx,
                        W.src_kind, W.binoff, W.binmem, W.cmem, W.coff, W.segof, W.sstart, W.klo, J.seed_offsets,
                        J.seed_members);
+    if (tot_m)
+      hipLaunchKernelGGL(k_seed_copy, dim3(nblk(tot_m)), dim3(256), 0, s, ord, nb2, W.eoff, W.src_kind, W.binoff,
+                         W.binmem, W.cmem, W.coff, W.segof, W.sstart, W.klo, tot_m, J.seed_members);
+  }
   hipLaunchKernelGGL(k_silk_finish, dim3(1), dim3(1), 0, s, k, tot_m, (unsigned long long)J.cap_k,
                      (unsigned long long)J.cap_members, J.seed_offsets, J.k_out, J.needed, J.counters, hash_evals,
                      pairs, (unsigned long long)cs, multi, st);
