@@ -139,3 +139,57 @@ def test_autotune_installs_fastest(default_tiles):
     outs, _ = api.assign_euclid_batch(probs, PRECS["bf16"])
     for j, (X, so, sm, k) in enumerate(probs):
         _same(outs[j], api.assign_euclid(X, so, sm, k, PRECS["bf16"]), j)
+
+
+def test_hash_and_bucketize_batches_equal_single_calls():
+    # multi-job geek_hash / geek_bucketize run their jobs on several streams,
+    # each with its own workspace slice: every job's keys and buckets equal
+    # those of a call with that job alone (also when replayed from a graph)
+    import torch
+
+    from workloads import e2lsh_params
+
+    api = gpu_api()
+    probs, _ = _problems(9, 9)
+    m, Lt, w = 8, 16, 4.0 * 4
+    hp = {}
+    for X, _, _, _ in probs:
+        d = X.shape[1]
+        if d not in hp:
+            A, b = e2lsh_params(m * Lt, d, w, 3)
+            hp[d] = (cuda(A), cuda(b))
+    hjobs = [(X, *hp[X.shape[1]], m, Lt, w) for X, _, _, _ in probs]
+    announce(f"hash/bucketize batch of {len(hjobs)} jobs")
+    keys_b = api.hash_dense_batch(hjobs)
+    singles = [api.hash_dense(*job)[0] for job in hjobs]
+    for j, (kb, ks) in enumerate(zip(keys_b, singles)):
+        assert torch.equal(kb, ks), j
+    bjobs = [(k, X.shape[0], Lt, 4, X.shape[0] * 4, 4) for k, (X, _, _, _) in zip(keys_b, probs)]
+
+    def same_buckets(outs):
+        for j, (ob, job) in enumerate(zip(outs, bjobs)):
+            os_ = api.bucketize(*job)
+            nb = ob[2].cpu().numpy()
+            assert np.array_equal(nb, os_[2].cpu().numpy()), j
+            assert torch.equal(ob[0], os_[0]) and torch.equal(ob[3], os_[3]), j
+            for t in range(Lt):
+                assert torch.equal(ob[1][t, :nb[t] + 1], os_[1][t, :nb[t] + 1]), (j, t)
+
+    same_buckets(api.bucketize_batch(bjobs))
+    status = api.new_status(torch.device("cuda"))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm the workspace cache outside capture
+        api.bucketize_batch(bjobs, status=status, check=False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        outs = api.bucketize_batch(bjobs, status=status, check=False)
+    for rep in range(2):
+        for o in outs:
+            o[0].fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        api.check_status(status, f"replay {rep}")
+        same_buckets(outs)
