@@ -24,6 +24,7 @@ constexpr int SCAN_BC = 64;   // centroids per LDS stage
 // ---------------------------------------------------------------- modes
 struct ModeF32 {
   static constexpr int KPER = 1;  // K elements per lane per instruction
+  static constexpr int KB = 16;   // products per fresh-accumulator block (0 = one chain)
   static constexpr bool SCALED = false;
   using ce = float;
   using frag = float;
@@ -41,6 +42,7 @@ struct ModeF32 {
 
 struct ModeBF16 {
   static constexpr int KPER = 8;
+  static constexpr int KB = 0;  // input rounding (2^-8) dominates the accumulation
   static constexpr bool SCALED = false;
   using ce = __bf16;
   using frag = bf16x8;
@@ -73,6 +75,7 @@ struct ModeBF16 {
 // either e4m3 variant).
 struct ModeFP8 {
   static constexpr int KPER = 8;
+  static constexpr int KB = 0;
   static constexpr bool SCALED = true;
   using ce = uint8_t;
   using frag = long;
@@ -115,11 +118,14 @@ GEEK_D double gamma_n(double nn, double u) { return nn * u / (1.0 - nn * u); }
 // rounded with relative error UX/UC and absolute error A0/s per element, so
 // |x^ - x| <= ex = UX X + A0 sqrt(DP) / s (likewise ec) and, by Cauchy-
 // Schwarz, |x^.c^ - x.c| <= ex cm + X ec + ex ec; the float32 accumulation of
-// the (exact) products adds gamma_{DP+1}(2u) |x^| |c^|.
-template <class M, int DP, bool T2>
+// the (exact) products adds gamma_n(2u) |x^| |c^| with n = DP + 1 roundings
+// per product for one accumulator chain, or n = KB + DP/KB + 1 when blocks of
+// KB products start from zero and their sums are added to the running value.
+template <class M, int DP, bool T2, bool BLK>
 GEEK_D float two_eps(double xn, double cm, double inv_scale, double het_max) {
   const double u32 = 0x1p-24;
-  const double g_acc = gamma_n(DP + 1, 2.0 * u32);
+  constexpr int NACC = BLK ? M::KB + DP / M::KB + 1 : DP + 1;
+  const double g_acc = gamma_n(NACC, 2.0 * u32);
   const double g64 = gamma_n(DP + 2, 0x1p-53);
   const double ab = M::A0 * inv_scale * sqrt((double)DP);
   const double ex = M::UX * xn + ab, ec = M::UC * cm + ab;
@@ -188,6 +194,11 @@ __device__ __forceinline__ void scan_tiles(
   // window capacity per lane: the rescan of rows whose first-pass window was
   // ambiguous keeps more candidates
   constexpr int TC = WIDE ? TCAND32 : TCAND;
+  // blocked accumulation: float32 rescans of ambiguous rows, where the
+  // tighter bound keeps candidate windows from overflowing (the categorical
+  // epilogue leaves no registers for the block sums; a first pass, whose rows
+  // are mostly clear-cut, keeps the single chain)
+  constexpr bool BLK = M::KB > 0 && !HET && WIDE;
   __shared__ float lds_lv[T2 ? 1 : SCAN_THREADS * NCB * TC];
   __shared__ int lds_lj[T2 ? 1 : SCAN_THREADS * NCB * TC];
 
@@ -316,7 +327,7 @@ __device__ __forceinline__ void scan_tiles(
       for (int s = 0; s < S; ++s) xb[cb][s] = M::from_f32(xv + s * M::KPER, sc);
       if (!finite) set_status(st, GEEK_ERR_NONFINITE);
       nrm += __shfl_xor(nrm, 32);
-      twoeps[cb] = two_eps<M, DP, T2>(sqrt(nrm) * (1.0 + 1e-12), cm, 1.0 / sc, het_max);
+      twoeps[cb] = two_eps<M, DP, T2, BLK>(sqrt(nrm) * (1.0 + 1e-12), cm, 1.0 / sc, het_max);
       if constexpr (HET) {
 #pragma unroll
         for (int a = 0; a < MAX_CAT; ++a)
@@ -402,11 +413,33 @@ __device__ __forceinline__ void scan_tiles(
             return M::load_lds(ap + s * M::KPER);
           }
         };
+        if constexpr (BLK) {
+          // blocks of KB products (KB / (2 KPER) steps) in fresh accumulators,
+          // then added to the running sums (see two_eps)
+          constexpr int SB = M::KB / (2 * M::KPER);
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const typename M::frag a = afrag(s);
+          for (int s0 = 0; s0 < S; s0 += SB) {
+            f32x16 blk[NCB];
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) acc[cb] = M::mma(a, xb[cb][s], acc[cb]);
+            for (int cb = 0; cb < NCB; ++cb) blk[cb] = f32x16{};
+#pragma unroll
+            for (int s = s0; s < s0 + SB; ++s) {
+              const typename M::frag a = afrag(s);
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) blk[cb] = M::mma(a, xb[cb][s], blk[cb]);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+              for (int r = 0; r < 16; ++r) acc[cb][r] += blk[cb][r];
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const typename M::frag a = afrag(s);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = M::mma(a, xb[cb][s], acc[cb]);
+          }
         }
         if constexpr (T2) {
           // branch-free: per value one bit insert and two med3
