@@ -253,17 +253,25 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
           // four independent FMA chains (k mod 4), then summed pairwise
           const float* ap = lds_a + row * STR + h * S;
           double p4[4] = {0.0, 0.0, 0.0, 0.0};
+          // the row is read sixteen attributes at a time: four LDS reads in
+          // flight per wait
 #pragma unroll
-          for (int k = 0; k < S; k += 4) {
-            const float4 av = *reinterpret_cast<const float4*>(ap + k);
-            float xk[4] = {xb[k], xb[k + 1], xb[k + 2], xb[k + 3]};
-            // opaque copies: converting all of x to float64 once, outside
-            // the loop over flagged rows, would need 2*S more registers
-            asm volatile("" : "+v"(xk[0]), "+v"(xk[1]), "+v"(xk[2]), "+v"(xk[3]));
-            p4[0] = __fma_rn((double)av.x, (double)xk[0], p4[0]);
-            p4[1] = __fma_rn((double)av.y, (double)xk[1], p4[1]);
-            p4[2] = __fma_rn((double)av.z, (double)xk[2], p4[2]);
-            p4[3] = __fma_rn((double)av.w, (double)xk[3], p4[3]);
+          for (int k0 = 0; k0 < S; k0 += 16) {
+            float4 av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = *reinterpret_cast<const float4*>(ap + k0 + 4 * u);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int k = k0 + 4 * u;
+              float xk[4] = {xb[k], xb[k + 1], xb[k + 2], xb[k + 3]};
+              // opaque copies: converting all of x to float64 once, outside
+              // the loop over flagged rows, would need 2*S more registers
+              asm volatile("" : "+v"(xk[0]), "+v"(xk[1]), "+v"(xk[2]), "+v"(xk[3]));
+              p4[0] = __fma_rn((double)av[u].x, (double)xk[0], p4[0]);
+              p4[1] = __fma_rn((double)av[u].y, (double)xk[1], p4[1]);
+              p4[2] = __fma_rn((double)av[u].z, (double)xk[2], p4[2]);
+              p4[3] = __fma_rn((double)av[u].w, (double)xk[3], p4[3]);
+            }
           }
           part = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         }
