@@ -13,10 +13,14 @@ bucketing, centroids, nearest-centre assignment, SSE) the oracle computes that
 definition directly in a stated floating-point order.  SILK is a heuristic, so
 the oracle follows Algorithm 4's steps in the paper's order.
 
+A further assignment pass (Section 4.3) regroups the objects by their
+assigned centre and assigns them again to the recomputed centroids.
+
 Pins (see ``tests/test_oracle_*.py``): exact rational arithmetic, closed forms
 (E2LSH collision probability, MinHash collision probability = Jaccard),
-published MurmurHash3 finalizer vectors, brute force on tiny inputs, and the
-SILK worked example (Example 2).
+published MurmurHash3 finalizer vectors, brute force on tiny inputs, the
+SILK worked example (Example 2), and for further passes the invariants that
+determine the regrouping plus Lloyd's monotone SSE and a hand-worked case.
 
 Parity unpinned: SILK's end-to-end seed sets on hashed inputs.  The paper's
 figures carry no coordinates, so only the worked example (explicit bins) and
@@ -45,3 +49,4 @@ from .assign import (  # noqa: F401
     radius,
     sse,
 )
+from .refine import assignment_pass, regroup  # noqa: F401
