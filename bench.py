@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets", "silk"],
+    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets", "silk", "refine"],
                     help="dense_large: the headline metric; batched: 256 mixed dense jobs in one "
                          "captured HIP graph; hetero: heterogeneous rows; sets: sparse sets "
                          "(MinHash, band buckets, signature assignment); silk: the whole GEEK pass "
@@ -106,6 +106,8 @@ def main():
         return bench_sets(args)
     if args.workload == "silk":
         return bench_silk(args)
+    if args.workload == "refine":
+        return bench_refine(args)
     import numpy as np
     import torch
 
@@ -566,6 +568,79 @@ def bench_silk(args):
         "silk_counters": ctr.cpu().numpy().tolist(),
         "assign_counters": out["counters"].cpu().numpy().tolist() if out is not None else None,
         "sse": float(out["sse"].item()) if out is not None else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_refine(args):
+    """A further assignment pass (Section 4.3) on the dense large workload:
+    the clusters of the BF16 assignment to the 10,000 planted seeds become the
+    seeds (geek_regroup), their centroids are recomputed and all 10^7 points
+    are assigned again on the BF16 matrix cores (geek_assign).  One step =
+    one such pass from the same first assignment; the cluster count is read
+    back to the host between the two calls, so steps are timed eagerly with
+    events."""
+    import numpy as np
+    import torch
+
+    from paper_2106_10515_amd import _lib as L
+    from paper_2106_10515_amd import api
+    from workloads import CONFIGS, dense_mixture, planted_seeds
+
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS["dense_large"]
+    n, d = args.n, cfg["d"]
+    clusters = min(args.clusters, n)
+    X, labels, _ = dense_mixture(n, d, clusters, cfg["lo"], cfg["hi"], cfg["sigma"], cfg["sizes"],
+                                 seed=0, device=dev)
+    so, sm = planted_seeds(labels, clusters, 32)
+    k = len(so) - 1
+    sog = torch.from_numpy(so.view(np.int32)).to(dev)
+    smg = torch.from_numpy(sm.view(np.int32)).to(dev)
+    status = api.new_status(dev)
+    first = api.assign_euclid(X, sog, smg, k, L.GEEK_PREC_BF16, status=status)
+    a0 = first["assign"]
+
+    def one():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        so2, sm2, k_out, lab = api.regroup(a0, k, status=status, check=False)
+        ev[1].record()
+        k2 = int(k_out.item())
+        out = api.assign_euclid(X, so2[:k2 + 1], sm2, k2, L.GEEK_PREC_BF16, status=status, check=False)
+        ev[2].record()
+        torch.cuda.synchronize()
+        return [ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])], k2, out
+
+    for _ in range(args.warmup):
+        one()
+    api.check_status(status, "warmup")
+    L.geek_profile(True)
+    runs = [one() for _ in range(args.steps)]
+    scan_ms, scan_n = L.geek_profile_read(L.GEEK_PROF_ASSIGN_SCAN)
+    L.geek_profile(False)
+    api.check_status(status, "timed")
+    st = np.median(np.array([r[0] for r in runs]), axis=0)
+    _, k2, out = runs[-1]
+    total = float(st.sum())
+    scan_avg = scan_ms / max(scan_n, 1)
+    flops = 2.0 * n * d * k2
+    ach = flops / (scan_avg * 1e-3) / 1e12
+    line = {
+        "metric": "points/s of one further assignment pass (regroup + centroids + BF16 assignment)",
+        "value": n / (total * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": total, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"refine: dense_large n={n} d={d} {clusters}-cluster Gaussian mixture "
+                               f"(Zipf sizes); pass from the assignment to k={k} planted seeds",
+                   "n": n, "k_in": k, "k_out": k2},
+        "stages_ms": {"regroup": float(st[0]), "assign": float(st[1])},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_BF16, "traffic": None, "kernel": "k_scan<ModeBF16,128>",
+                     "avg_launch_ms": scan_avg, "flop_per_launch": flops},
+        "assign_counters": out["counters"].cpu().numpy().tolist(),
+        "sse_first": float(first["sse"].item()),
+        "sse_after_pass": float(out["sse"].item()),
     }
     print(json.dumps(line), flush=True)
 

@@ -7,7 +7,7 @@
  * transformation that turns objects into buckets with LSH (Section 3.1),
  * SILK seeding from similar buckets (Section 3.2, Algorithm 4), and a
  * one-pass assignment of every object to its closest central vector
- * (Section 3.3, Eq. (1)).  This library exposes four calls:
+ * (Section 3.3, Eq. (1)).  This library exposes five calls:
  *
  *   geek_hash        LSH values of every object (E2LSH codes packed into an
  *                    exact per-table key; MinHash signatures of sets or of
@@ -16,6 +16,8 @@
  *   geek_silk_seeds  SILK: bins of similar buckets, majority voting, the
  *                    seeding threshold and near-duplicate removal
  *   geek_assign      central vectors of the seeds and the one-pass assignment
+ *   geek_regroup     the clusters of an assignment as the seeds of a further
+ *                    assignment pass
  *
  * Conventions shared by every call
  * --------------------------------
@@ -31,7 +33,7 @@
  * - Calls are stream-ordered and return without waiting for the GPU, except
  *   ``geek_silk_seeds``, which synchronizes ``stream`` internally because the
  *   sizes of its intermediate collections are only known on the device.
- *   ``geek_hash``, ``geek_bucketize`` and ``geek_assign`` perform no host
+ *   ``geek_hash``, ``geek_bucketize``, ``geek_assign`` and ``geek_regroup`` perform no host
  *   synchronization and no device allocation.
  * - Host-detectable errors (bad arguments, workspace too small, unsupported
  *   sizes, launch failure) return a negative status at once and enqueue no
@@ -266,11 +268,36 @@ typedef struct geek_assign_job {
                                moment (njobs = 1) */
 } geek_assign_job;
 
+/* ---- geek_regroup ---------------------------------------------------------
+ * The clusters of an assignment as seeds for a further assignment pass
+ * (Section 4.3, Clustering Performance: several passes of the data
+ * assignment give more compact clusters).  Cluster j = {i : assign[i] == j}
+ * with its members in ascending i; clusters with no member are dropped and
+ * the others keep the order of j, so the r-th output cluster is the r-th
+ * non-empty label.  Passing the result to geek_assign (seed_offsets,
+ * seed_members, k = *k_out) recomputes the central vectors from the clusters
+ * and assigns every object again: one step of Lloyd's iteration.
+ * Outputs: seed_offsets [k + 1] (entries 0 .. *k_out written, the last = n),
+ *   seed_members [n], *k_out, label_of [k] (optional; entries 0 .. *k_out - 1:
+ *   the label j of each output cluster).  A label outside [0, k) sets
+ *   GEEK_ERR_RANGE in *d_status (the outputs are then unspecified).
+ */
+typedef struct geek_regroup_job {
+  int64_t n;                 /* objects (0 <= n < 2^31) */
+  int32_t k;                 /* host: labels lie in [0, k), k >= 1 */
+  const int32_t* assign;     /* [n] */
+  uint32_t* seed_offsets;    /* out [k + 1] */
+  uint32_t* seed_members;    /* out [n] */
+  uint32_t* k_out;           /* out [1] */
+  int32_t* label_of;         /* optional out [k] */
+} geek_regroup_job;
+
 /* ---- entry points -------------------------------------------------------- */
 #define GEEK_OP_HASH 0
 #define GEEK_OP_BUCKETIZE 1
 #define GEEK_OP_SILK 2
 #define GEEK_OP_ASSIGN 3
+#define GEEK_OP_REGROUP 4
 
 /* Bytes of device workspace the call `op` needs for these jobs (host).  For
  * geek_hash and geek_bucketize with several jobs it is min(njobs, 4) slices
@@ -296,6 +323,10 @@ int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size
  * after another in a shared workspace. */
 int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                     int32_t* d_status, void* stream);
+/* geek_regroup: jobs run one after another in a shared workspace; no host
+ * synchronization, no device allocation. */
+int32_t geek_regroup(const geek_regroup_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                     int32_t* d_status, void* stream);
 
 /* ---- profiling (opt-in) -------------------------------------------------
  * With profiling enabled the library brackets its main kernels with HIP

@@ -27,7 +27,7 @@ GEEK_ERR_EMPTY_SET = 5
 GEEK_HASH_DENSE, GEEK_HASH_SETS, GEEK_HASH_HETERO = 0, 1, 2
 GEEK_METRIC_EUCLID, GEEK_METRIC_SIG, GEEK_METRIC_HETERO = 0, 1, 2
 GEEK_PREC_FP32, GEEK_PREC_BF16, GEEK_PREC_FP8 = 0, 1, 2
-GEEK_OP_HASH, GEEK_OP_BUCKETIZE, GEEK_OP_SILK, GEEK_OP_ASSIGN = 0, 1, 2, 3
+GEEK_OP_HASH, GEEK_OP_BUCKETIZE, GEEK_OP_SILK, GEEK_OP_ASSIGN, GEEK_OP_REGROUP = 0, 1, 2, 3, 4
 
 P = C.c_void_p
 
@@ -85,8 +85,15 @@ class AssignJob(C.Structure):
     ]
 
 
+class RegroupJob(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("k", C.c_int32), ("pad0", C.c_int32), ("assign", P),
+        ("seed_offsets", P), ("seed_members", P), ("k_out", P), ("label_of", P),
+    ]
+
+
 EXPORTS = ("geek_workspace_size", "geek_hash", "geek_bucketize", "geek_silk_seeds",
-           "geek_assign", "geek_status_string", "geek_version", "geek_last_hip_error",
+           "geek_assign", "geek_regroup", "geek_status_string", "geek_version", "geek_last_hip_error",
            "geek_profile", "geek_profile_read", "geek_wallclock_hz", "geek_set_scan_tiles",
            "geek_get_scan_tiles")
 
@@ -106,7 +113,8 @@ def _load():
     lib.geek_workspace_size.argtypes = [C.c_int32, P, C.c_int32, C.POINTER(C.c_size_t)]
     lib.geek_workspace_size.restype = C.c_int32
     for name, jt in (("geek_hash", HashJob), ("geek_bucketize", BucketizeJob),
-                     ("geek_silk_seeds", SilkJob), ("geek_assign", AssignJob)):
+                     ("geek_silk_seeds", SilkJob), ("geek_assign", AssignJob),
+                     ("geek_regroup", RegroupJob)):
         f = getattr(lib, name)
         f.argtypes = [C.POINTER(jt), C.c_int32, P, C.c_size_t, P, P]
         f.restype = C.c_int32
@@ -203,3 +211,7 @@ def geek_silk_seeds(jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr):
 
 def geek_assign(jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr):
     return _call("geek_assign", jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr)
+
+
+def geek_regroup(jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr):
+    return _call("geek_regroup", jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr)

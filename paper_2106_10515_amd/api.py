@@ -242,6 +242,42 @@ def assign_euclid(X, seed_offsets, seed_members, k, precision=L.GEEK_PREC_FP32,
     return out
 
 
+def regroup(assign, k, want_label_of=True, status=None, check=True):
+    """The clusters of an assignment as a seeds CSR for a further pass
+    (geek_regroup).  Returns ``(seed_offsets, seed_members, k_out, label_of)``
+    as device tensors: offsets int32 [k + 1] (the first k_out + 1 entries are
+    written), members int32 [n], k_out int32 [1] and label_of int32 [k]."""
+    dev = _dev(assign)
+    n = assign.numel()
+    so = torch.empty((k + 1,), dtype=torch.int32, device=dev)
+    sm = torch.empty((max(n, 1),), dtype=torch.int32, device=dev)
+    k_out = torch.zeros((1,), dtype=torch.int32, device=dev)
+    lab = torch.empty((k,), dtype=torch.int32, device=dev) if want_label_of else None
+    status = new_status(dev) if status is None else status
+    j = L.RegroupJob(n=n, k=k, assign=_p(assign), seed_offsets=_p(so), seed_members=_p(sm),
+                     k_out=_p(k_out), label_of=_p(lab))
+    _run(L.GEEK_OP_REGROUP, L.geek_regroup, [j], dev, status)
+    if check:
+        check_status(status, "geek_regroup")
+    return so, sm[:n], k_out, lab
+
+
+def assignment_pass(X, assign, k, precision=L.GEEK_PREC_BF16, want_dist=True, want_radius=True,
+                    status=None, check=True):
+    """A further assignment pass: the clusters of ``assign`` become the seeds
+    (geek_regroup), their centroids are recomputed and every row is assigned
+    again (geek_assign).  Reads the cluster count back to the host.  Returns
+    the ``assign_euclid`` dict plus ``label_of`` (the previous index of each
+    new cluster) and ``k``."""
+    so, sm, k_out, lab = regroup(assign, k, status=status, check=check)
+    k2 = int(k_out.item())
+    out = assign_euclid(X, so[:k2 + 1], sm, k2, precision, want_dist=want_dist, want_radius=want_radius,
+                        status=status, check=check)
+    out["label_of"] = lab[:k2] if lab is not None else None
+    out["k"] = k2
+    return out
+
+
 def assign_euclid_batch(problems, precision=L.GEEK_PREC_BF16, want_dist=True, want_radius=True,
                         status=None, check=True):
     """One geek_assign call over many Euclidean jobs.  ``problems`` is a list

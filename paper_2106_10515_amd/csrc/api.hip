@@ -1,6 +1,6 @@
 // extern "C" entry points of libgeek.so: argument validation, workspace
-// sizing and dispatch to the kernels of hash.hip, bucketize.hip, silk.hip
-// and assign.hip.
+// sizing and dispatch to the kernels of hash.hip, bucketize.hip, silk.hip,
+// assign.hip and regroup.hip.
 #include <string.h>
 
 #include <algorithm>
@@ -33,6 +33,8 @@ int32_t scan_tiles_set(int precision, int dp, ScanTiles t);
 int32_t assign_euclid_batch(const geek_assign_job* jobs, int njobs, void* ws, size_t ws_bytes, int32_t* st,
                             hipStream_t s);
 int32_t assign_sig(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
+size_t regroup_ws(const geek_regroup_job& J);
+int32_t regroup_run(const geek_regroup_job& J, void* ws, int32_t* st, hipStream_t s);
 
 static thread_local std::string g_last_err;
 
@@ -179,6 +181,13 @@ static int32_t check_assign(const geek_assign_job& J) {
   return GEEK_OK;
 }
 
+static int32_t check_regroup(const geek_regroup_job& J) {
+  if (J.n < 0 || J.n >= (1ll << 31) || J.k < 1) return GEEK_ERR_ARG;
+  if (!J.seed_offsets || !J.k_out) return GEEK_ERR_ARG;
+  if (J.n > 0 && (!J.assign || !J.seed_members)) return GEEK_ERR_ARG;
+  return GEEK_OK;
+}
+
 }  // namespace geek
 
 using namespace geek;
@@ -288,6 +297,12 @@ int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t*
         b = J.metric == GEEK_METRIC_SIG ? assign_sig_ws(J) : assign_euclid_ws(J);
         break;
       }
+      case GEEK_OP_REGROUP: {
+        const geek_regroup_job& J = static_cast<const geek_regroup_job*>(jobs)[j];
+        if (int32_t rc = check_regroup(J)) return rc;
+        b = regroup_ws(J);
+        break;
+      }
       default:
         return GEEK_ERR_ARG;
     }
@@ -373,6 +388,19 @@ int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t
                      : assign_euclid(J, ws, ws_bytes, d_status, (hipStream_t)stream);
     if (rc) return rc;
   }
+  return GEEK_OK;
+}
+
+int32_t geek_regroup(const geek_regroup_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                     int32_t* d_status, void* stream) {
+  if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    if (int32_t rc = check_regroup(jobs[j])) return rc;
+    if (ws_bytes < regroup_ws(jobs[j])) return GEEK_ERR_WORKSPACE;
+  }
+  if (!ws) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j)
+    if (int32_t rc = regroup_run(jobs[j], ws, d_status, (hipStream_t)stream)) return rc;
   return GEEK_OK;
 }
 

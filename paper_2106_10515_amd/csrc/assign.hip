@@ -2,7 +2,8 @@
 //
 // Pipeline for Euclidean data (all stream-ordered, no host synchronization):
 //   k_centroids   float64 centroids, one thread per (seed, dim), members summed
-//                 in ascending order one rounding at a time (exact parity).
+//                 in ascending order one rounding at a time (exact parity),
+//                 their values loaded 32 at a time.
 //   k_cprep       centroid copies in the matrix-core input type (fp32 / bf16),
 //                 |c|^2 and max |c| for the error bound.
 //   k_scan<M,DP>  matrix-core tile |x|^2 - 2 x.c + |c|^2 over all centroids for
@@ -38,6 +39,11 @@ namespace geek {
 constexpr int SSE_BLOCK = 4096;
 
 // ---------------------------------------------------------------- centroids
+// The sum over a seed's members is one chain of float64 additions (the
+// reference order), so a seed with many members is bound by memory latency:
+// members are taken CB at a time, their values loaded together (the next
+// batch's ids already in flight), then added in order.
+constexpr int CB = 32;
 __global__ void k_centroids(const float* __restrict__ X, int64_t ldx, int64_t n, int d,
                             const uint32_t* __restrict__ offs, const uint32_t* __restrict__ mem,
                             int k, double* __restrict__ C, int32_t* st) {
@@ -51,14 +57,29 @@ __global__ void k_centroids(const float* __restrict__ X, int64_t ldx, int64_t n,
     return;
   }
   double acc = 0.0;
-  for (uint32_t q = s; q < e; ++q) {
-    uint32_t i = mem[q];
-    if ((int64_t)i >= n) {
-      set_status(st, GEEK_ERR_ARG);
-      break;
+  bool bad = false;
+  // ids of member q (clamped into the seed's range: reads past the end are
+  // repeated ids whose values are not added)
+  auto id_at = [&](uint32_t q) { return mem[q < e ? q : e - 1]; };
+  uint32_t ids[CB];
+#pragma unroll
+  for (int u = 0; u < CB; ++u) ids[u] = id_at(s + u);
+  for (uint32_t q = s; q < e; q += CB) {
+    float v[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const bool ok = (int64_t)ids[u] < n;
+      bad |= !ok;
+      v[u] = X[(int64_t)(ok ? ids[u] : 0u) * ldx + t];
     }
-    acc = __dadd_rn(acc, (double)X[(int64_t)i * ldx + t]);
+#pragma unroll
+    for (int u = 0; u < CB; ++u) ids[u] = id_at(q + CB + u);
+    const uint32_t cnt = e - q < (uint32_t)CB ? e - q : (uint32_t)CB;
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if ((uint32_t)u < cnt) acc = __dadd_rn(acc, (double)v[u]);
   }
+  if (bad) set_status(st, GEEK_ERR_ARG);
   C[gid] = acc / (double)(e - s);
 }
 

@@ -37,7 +37,8 @@ def test_struct_layouts_match_header(tmp_path):
                     os.path.join(ROOT, "tests", "abi_layout.c"), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     structs = {"geek_hash_job": L.HashJob, "geek_bucketize_job": L.BucketizeJob,
-               "geek_silk_job": L.SilkJob, "geek_assign_job": L.AssignJob}
+               "geek_silk_job": L.SilkJob, "geek_assign_job": L.AssignJob,
+               "geek_regroup_job": L.RegroupJob}
     n = 0
     for line in out.splitlines():
         sname, field, val = line.split()
@@ -69,6 +70,14 @@ def test_argument_errors_need_no_gpu():
     assert nb.value > 3 * 1000 * 20
     # a too-small workspace is refused before any launch
     assert lib.geek_bucketize(C.byref(ok), 1, C.c_void_p(256), 16, None, None) == L.GEEK_ERR_WORKSPACE
+    bad = L.RegroupJob(n=10, k=0, assign=16, seed_offsets=16, seed_members=16, k_out=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_REGROUP, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_ARG
+    bad = L.RegroupJob(n=10, k=3, assign=None, seed_offsets=16, seed_members=16, k_out=16)
+    assert lib.geek_regroup(C.byref(bad), 1, C.c_void_p(256), 1 << 20, None, None) == L.GEEK_ERR_ARG
+    ok = L.RegroupJob(n=1000, k=3, assign=16, seed_offsets=16, seed_members=16, k_out=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_REGROUP, C.byref(ok), 1, C.byref(nb)) == 0
+    assert nb.value >= 5 * 1000 * 4
+    assert lib.geek_regroup(C.byref(ok), 1, C.c_void_p(256), 16, None, None) == L.GEEK_ERR_WORKSPACE
 
 
 def test_scan_tile_table_host_only(tmp_path):

@@ -1,0 +1,84 @@
+"""GPU parity of geek_regroup and of a further assignment pass (paper
+Section 4.3) against the FP64 oracle: clusters bit for bit (offsets, members,
+labels), then centroids, assignments, distances and SSE of the next pass."""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import dense_mixture, planted_seeds
+
+from .gpu_util import announce, cuda, gpu_api, host_u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _regroup_case(api, a, k, name):
+    announce(f"regroup {name} n={len(a)} k={k}")
+    off, mem, lab = oracle.regroup(a, k)
+    so, sm, k_out, lab_g = api.regroup(cuda(np.asarray(a, np.int32)), k)
+    ko = int(k_out.item())
+    assert ko == len(lab)
+    assert np.array_equal(host_u32(so)[:ko + 1], off)
+    assert np.array_equal(host_u32(sm), mem)
+    assert np.array_equal(lab_g.cpu().numpy()[:ko], lab)
+
+
+@pytest.mark.parametrize("n,k,used,seed", [
+    (1, 1, 1, 0),             # one object
+    (1001, 1, 1, 1),          # k = 1: no sort digits at all
+    (5000, 7, 3, 2),          # most labels unused
+    (20000, 300, 300, 3),     # two 8-bit digits, every label used
+    (33333, 70000, 9000, 4),  # three digits, ragged n, most labels unused
+])
+def test_regroup_matches_oracle(n, k, used, seed):
+    api = gpu_api()
+    g = np.random.default_rng(seed)
+    labels = g.choice(k, size=used, replace=False)
+    _regroup_case(api, g.choice(labels, size=n).astype(np.int32), k, "random")
+
+
+def test_regroup_special_cases():
+    api = gpu_api()
+    import torch
+    from paper_2106_10515_amd import GeekError
+
+    _regroup_case(api, np.full(3000, 6, np.int32), 7, "one-label")
+    _regroup_case(api, np.arange(4097, dtype=np.int32)[::-1].copy(), 4097, "all-singletons")
+    so, sm, k_out, _ = api.regroup(torch.zeros(0, dtype=torch.int32, device="cuda"), 5)
+    assert int(k_out.item()) == 0 and int(so[0].item()) == 0
+    with pytest.raises(GeekError) as e:
+        api.regroup(cuda(np.array([0, 1, 5, 2], np.int32)), 5)
+    assert e.value.code == 2
+    with pytest.raises(GeekError) as e:
+        api.regroup(cuda(np.array([0, -1], np.int32)), 5)
+    assert e.value.code == 2
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n,d,clusters,per,seed", [
+    (4000, 32, 40, 4, 0),     # few seed members: the first pass is rough
+    (3001, 128, 150, 2, 1),   # ragged rows, several centroid tiles
+])
+def test_assignment_passes_match_oracle(prec, n, d, clusters, per, seed):
+    api = gpu_api()
+    X, lab, _ = dense_mixture(n, d, clusters, -5, 5, 1.5, "zipf", seed)
+    so, sm = planted_seeds(lab, clusters, per)
+    k = len(so) - 1
+    a, _ = oracle.assign_euclid(X, oracle.centroids(X, so, sm))
+    Xg = cuda(X)
+    cur = api.assign_euclid(Xg, cuda(so), cuda(sm), k, prec)
+    assert np.array_equal(cur["assign"].cpu().numpy(), a)
+    for p in range(3):
+        announce(f"assignment pass {p + 1} n={n} d={d} k={k} prec={prec}")
+        off, mem, lab_of, C, a2, d2 = oracle.assignment_pass(X, a, k)
+        out = api.assignment_pass(Xg, cur["assign"], k, prec)
+        assert out["k"] == len(lab_of)
+        assert np.array_equal(out["label_of"].cpu().numpy(), lab_of)
+        assert np.array_equal(out["centroids"].cpu().numpy(), C)
+        got = out["assign"].cpu().numpy()
+        bad = np.flatnonzero(got != a2)
+        assert bad.size == 0, (bad[:10], got[bad[:10]], a2[bad[:10]])
+        assert np.array_equal(out["dist"].cpu().numpy(), d2)
+        assert out["sse"].item() == oracle.sse(d2)
+        a, k, cur = a2, len(lab_of), out
