@@ -259,7 +259,13 @@ typedef struct geek_assign_job {
   unsigned long long* counters; /* optional out [4] */
   int64_t n_members;        /* host: seed_offsets[k], the total number of seed
                                members (required by SIG and HETERO, which
-                               size their mode computation by it) */
+                               size their mode computation by it; EUCLID also
+                               accepts 0 = not given, or the capacity of
+                               seed_members).  When EUCLID / HETERO seeds
+                               average 64 members or more, centroids are
+                               computed from a dimension-major copy of the
+                               members' values (n_members x d floats of
+                               workspace) */
   unsigned long long* t_done; /* optional out [1]: device wall-clock ticks
                                (geek_wallclock_hz per second) from the start
                                of the call to the moment this job's outputs

@@ -83,6 +83,95 @@ __global__ void k_centroids(const float* __restrict__ X, int64_t ldx, int64_t n,
   C[gid] = acc / (double)(e - s);
 }
 
+// Seeds with many members (a further assignment pass takes whole clusters
+// as seeds): the members' values are first gathered into groups of four
+// member positions, Xt[q / 4][t][q % 4] = X[mem[q]][t] (a 64 x 64 tile
+// transposed through LDS), so that the (seed, dim) chains of one wave read
+// four values each per 16-byte load, the wave's loads one contiguous run:
+// streaming, where loads of whole rows of scattered members (or of
+// dimension-major rows far apart) were bound by address translation.
+constexpr int GT_TILE = 64;
+__global__ __launch_bounds__(256) void k_gather_t(const float* __restrict__ X, int64_t ldx, int64_t n, int d,
+                                                  const uint32_t* __restrict__ offs, int k,
+                                                  const uint32_t* __restrict__ mem, int64_t nm_cap, int64_t nm_pad,
+                                                  float* __restrict__ Xt, int32_t* st) {
+  __shared__ float tile[GT_TILE][GT_TILE + 1];
+  // members actually used (seed_offsets[k]); positions past them are zeros
+  const int64_t nm = offs[k] < nm_cap ? (int64_t)offs[k] : nm_cap;
+  const int64_t q0 = (int64_t)blockIdx.x * GT_TILE;
+  const int t0 = blockIdx.y * GT_TILE;
+  const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int r = r0; r < GT_TILE; r += 4) {
+    const int64_t q = q0 + r;
+    float v = 0.f;
+    if (q < nm && t0 + c < d) {
+      const uint32_t i = mem[q];
+      if ((int64_t)i < n) v = X[(int64_t)i * ldx + t0 + c];
+      else set_status(st, GEEK_ERR_ARG);
+    }
+    tile[r][c] = v;
+  }
+  __syncthreads();
+  // group g of the tile (members q0 + 4g .. + 3) covers the contiguous run
+  // Xt[(q0 / 4 + g) * 4 d + 4 t0 ..] of 4 x 64 values: thread i writes its
+  // element i of the run
+#pragma unroll 4
+  for (int i = threadIdx.x; i < GT_TILE * GT_TILE; i += 256) {
+    const int g = i >> 8, rem = i & 255, tl = rem >> 2, r = rem & 3;
+    const int64_t q = q0 + g * 4 + r;
+    if (q < nm_pad && t0 + tl < d) Xt[(q >> 2) * 4 * (int64_t)d + (int64_t)(t0 + tl) * 4 + r] = tile[g * 4 + r][tl];
+  }
+}
+
+// Centroids from the grouped copy: the same ascending chain of float64
+// additions as k_centroids.
+constexpr int CT_B = 16;  // 16-byte loads in flight per batch (64 members)
+__global__ void k_centroids_t(const float* __restrict__ Xt, int64_t nm, int d,
+                              const uint32_t* __restrict__ offs, int k, double* __restrict__ C, int32_t* st) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)k * d) return;
+  const int j = (int)(gid / d), t = (int)(gid % d);
+  const int64_t s = offs[j], e = offs[j + 1];
+  if (e <= s) {
+    set_status(st, GEEK_ERR_EMPTY_SET);
+    C[gid] = 0.0;
+    return;
+  }
+  if (e > nm) {  // seed_offsets disagree with the member count of the job
+    set_status(st, GEEK_ERR_ARG);
+    C[gid] = 0.0;
+    return;
+  }
+  const int64_t gs = 4 * (int64_t)d;  // floats per group of four members
+  const float* p = Xt + (int64_t)t * 4;
+  auto at = [&](int64_t q) { return p[(q >> 2) * gs + (q & 3)]; };
+  double acc = 0.0;
+  int64_t q = s;
+  for (; q < e && (q & 3); ++q) acc = __dadd_rn(acc, (double)at(q));
+  for (; q + 4 * CT_B <= e; q += 4 * CT_B) {
+    float4 v[CT_B];
+#pragma unroll
+    for (int u = 0; u < CT_B; ++u) v[u] = *reinterpret_cast<const float4*>(p + ((q >> 2) + u) * gs);
+#pragma unroll
+    for (int u = 0; u < CT_B; ++u) {
+      acc = __dadd_rn(acc, (double)v[u].x);
+      acc = __dadd_rn(acc, (double)v[u].y);
+      acc = __dadd_rn(acc, (double)v[u].z);
+      acc = __dadd_rn(acc, (double)v[u].w);
+    }
+  }
+  for (; q < e; ++q) acc = __dadd_rn(acc, (double)at(q));
+  C[gid] = acc / (double)(e - s);
+}
+
+// Whether the centroids go through the dimension-major copy: seeds of 64
+// members or more on average, with the member count known.
+static bool centroids_transposed(const geek_assign_job& J) {
+  return J.n_members > 0 && J.n_members >= 64 * (int64_t)J.k;
+}
+static int64_t members_pad(const geek_assign_job& J) { return (J.n_members + 3) / 4 * 4; }
+
 // Largest |value| of a float32 matrix / float64 centroids (FP8 scaling).
 __global__ void k_absmax_x(const float* __restrict__ X, int64_t ldx, int64_t n, int d, float* __restrict__ out) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -615,6 +704,7 @@ struct AssignWs {
   void* modes_ws;
   size_t modes_bytes;
   uint32_t* mode16;
+  float* xt;  // dimension-major member values (centroids_transposed)
 };
 
 static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
@@ -638,6 +728,7 @@ static size_t carve_assign(const geek_assign_job& J, void* ws, AssignWs* out) {
   out->modes_bytes = J.metric == GEEK_METRIC_HETERO ? modes_ws(J.n_members, J.n_cat, J.k) : 0;
   out->modes_ws = c.take<char>(out->modes_bytes + 16);
   out->mode16 = c.take<uint32_t>(J.metric == GEEK_METRIC_HETERO ? k_pad * MAX_CAT : 4);
+  out->xt = c.take<float>(centroids_transposed(J) ? (size_t)members_pad(J) * J.d : 4);
   return c.used + 256;
 }
 
@@ -727,8 +818,16 @@ static int32_t assign_prep(const geek_assign_job& J, void* ws, AssignCtx& C, int
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, W.counts, 4, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(W.ctr), 8, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(W.cmax), 4, 0u);
-  hipLaunchKernelGGL(k_centroids, dim3(ceil_div((int64_t)J.k * J.d, 256)), dim3(256), 0, s, J.X,
-                     J.ldx, J.n, J.d, J.seed_offsets, J.seed_members, J.k, J.centroids, st);
+  if (centroids_transposed(J)) {
+    const int64_t nmp = members_pad(J);
+    hipLaunchKernelGGL(k_gather_t, dim3(ceil_div(nmp, GT_TILE), ceil_div(J.d, GT_TILE)), dim3(256), 0, s, J.X,
+                       J.ldx, J.n, J.d, J.seed_offsets, J.k, J.seed_members, J.n_members, nmp, W.xt, st);
+    hipLaunchKernelGGL(k_centroids_t, dim3(ceil_div((int64_t)J.k * J.d, 256)), dim3(256), 0, s, W.xt,
+                       J.n_members, J.d, J.seed_offsets, J.k, J.centroids, st);
+  } else {
+    hipLaunchKernelGGL(k_centroids, dim3(ceil_div((int64_t)J.k * J.d, 256)), dim3(256), 0, s, J.X,
+                       J.ldx, J.n, J.d, J.seed_offsets, J.seed_members, J.k, J.centroids, st);
+  }
   if (C.het_on) {
     if (int32_t rc = modes_compute(reinterpret_cast<const uint32_t*>(J.cat), J.n_cat, J.n_cat, J.n,
                                    J.seed_offsets, J.seed_members, J.k, J.n_members, J.modes, W.modes_ws, st, s))

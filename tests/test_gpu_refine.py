@@ -82,3 +82,25 @@ def test_assignment_passes_match_oracle(prec, n, d, clusters, per, seed):
         assert np.array_equal(out["dist"].cpu().numpy(), d2)
         assert out["sse"].item() == oracle.sse(d2)
         a, k, cur = a2, len(lab_of), out
+
+
+@pytest.mark.parametrize("n,d,clusters,per,spare,seed", [
+    (3001, 20, 9, 400, 0, 5),     # narrow rows (one dimension tile, ragged)
+    (2500, 256, 12, 250, 7, 6),   # four dimension tiles; members buffer 7 entries longer than used
+    (5003, 128, 3, 5000, 0, 7),   # three huge seeds, member count not a multiple of 4
+])
+def test_centroids_of_large_seeds(n, d, clusters, per, spare, seed):
+    # seeds averaging 64 members or more take the dimension-major centroid path
+    api = gpu_api()
+    X, lab, _ = dense_mixture(n, d, clusters, -10, 10, 1.0, "zipf", seed)
+    so, sm = planted_seeds(lab, clusters, per)
+    k = len(so) - 1
+    assert len(sm) >= 64 * k
+    announce(f"large seeds n={n} d={d} k={k} members={len(sm)} spare={spare}")
+    C = oracle.centroids(X, so, sm)
+    a, dist = oracle.assign_euclid(X, C)
+    smg = cuda(np.concatenate([sm, np.zeros(spare, np.uint32)]))
+    out = api.assign_euclid(cuda(X), cuda(so), smg, k, 1)
+    assert np.array_equal(out["centroids"].cpu().numpy(), C)
+    assert np.array_equal(out["assign"].cpu().numpy(), a)
+    assert np.array_equal(out["dist"].cpu().numpy(), dist)
