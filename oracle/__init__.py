@@ -15,6 +15,8 @@ the oracle follows Algorithm 4's steps in the paper's order.
 
 A further assignment pass (Section 4.3) regroups the objects by their
 assigned centre and assigns them again to the recomputed centroids.
+Quantile bucketing (Algorithm 1) ranks the objects by each QALSH value and
+splits the ranks evenly into t buckets.
 
 Pins (see ``tests/test_oracle_*.py``): exact rational arithmetic, closed forms
 (E2LSH collision probability, MinHash collision probability = Jaccard),
@@ -50,3 +52,4 @@ from .assign import (  # noqa: F401
     sse,
 )
 from .refine import assignment_pass, regroup  # noqa: F401
+from .quantile import qalsh_values, quantile_buckets  # noqa: F401
