@@ -7,7 +7,7 @@
  * transformation that turns objects into buckets with LSH (Section 3.1),
  * SILK seeding from similar buckets (Section 3.2, Algorithm 4), and a
  * one-pass assignment of every object to its closest central vector
- * (Section 3.3, Eq. (1)).  This library exposes five calls:
+ * (Section 3.3, Eq. (1)).  This library exposes six calls:
  *
  *   geek_hash        LSH values of every object (E2LSH codes packed into an
  *                    exact per-table key; MinHash signatures of sets or of
@@ -18,6 +18,8 @@
  *   geek_assign      central vectors of the seeds and the one-pass assignment
  *   geek_regroup     the clusters of an assignment as the seeds of a further
  *                    assignment pass
+ *   geek_quantile_buckets  Algorithm 1's dense transformation: buckets of
+ *                    equal size along each projection
  *
  * Conventions shared by every call
  * --------------------------------
@@ -33,7 +35,8 @@
  * - Calls are stream-ordered and return without waiting for the GPU, except
  *   ``geek_silk_seeds``, which synchronizes ``stream`` internally because the
  *   sizes of its intermediate collections are only known on the device.
- *   ``geek_hash``, ``geek_bucketize``, ``geek_assign`` and ``geek_regroup`` perform no host
+ *   ``geek_hash``, ``geek_bucketize``, ``geek_assign``, ``geek_regroup`` and
+ *   ``geek_quantile_buckets`` perform no host
  *   synchronization and no device allocation.
  * - Host-detectable errors (bad arguments, workspace too small, unsupported
  *   sizes, launch failure) return a negative status at once and enqueue no
@@ -298,12 +301,41 @@ typedef struct geek_regroup_job {
   int32_t* label_of;         /* optional out [k] */
 } geek_regroup_job;
 
+/* ---- geek_quantile_buckets -------------------------------------------------
+ * Quantile bucketing of dense rows (Algorithm 1, the homogeneous dense data
+ * transformation): for each of m projection vectors a_p, table p ranks the
+ * objects by the QALSH value a_p . x_i and splits the ranks evenly into t
+ * buckets.  The value is evaluated in float64 exactly as: s = 0; for t = 0 ..
+ * d-1: s = s + a_pt * x_it (the product of two float32 values is exact in
+ * float64; one rounding per addition).  Equal values are ordered by id; rank
+ * r goes to bucket floor(r * t / n), so bucket b holds the ranks
+ * ceil(b n / t) .. ceil((b + 1) n / t) - 1 and sizes differ by at most one.
+ * Outputs per table p: members [m][n] (bucket b of table p is members[p][
+ * offsets[p][b] .. offsets[p][b + 1]), ids ascending within a bucket),
+ * offsets [m][t + 1], optional bucket_of [m][n].  A non-finite x or a sets
+ * GEEK_ERR_NONFINITE.  Requires 1 <= t <= n < 2^31, 1 <= d <= 256.
+ */
+typedef struct geek_quantile_job {
+  int64_t n;
+  int32_t d;
+  int32_t m;                 /* projections = tables */
+  int32_t t;                 /* buckets per table */
+  int32_t pad0;
+  const float* X;            /* [n][ldx] */
+  int64_t ldx;
+  const float* A;            /* [m][d] projection vectors */
+  uint32_t* members;         /* out [m][n] */
+  uint32_t* offsets;         /* out [m][t + 1] */
+  uint32_t* bucket_of;       /* optional out [m][n] */
+} geek_quantile_job;
+
 /* ---- entry points -------------------------------------------------------- */
 #define GEEK_OP_HASH 0
 #define GEEK_OP_BUCKETIZE 1
 #define GEEK_OP_SILK 2
 #define GEEK_OP_ASSIGN 3
 #define GEEK_OP_REGROUP 4
+#define GEEK_OP_QUANTILE 5
 
 /* Bytes of device workspace the call `op` needs for these jobs (host).  For
  * geek_hash and geek_bucketize with several jobs it is min(njobs, 4) slices
@@ -333,6 +365,10 @@ int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t
  * synchronization, no device allocation. */
 int32_t geek_regroup(const geek_regroup_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                      int32_t* d_status, void* stream);
+/* geek_quantile_buckets: jobs and tables run one after another in a shared
+ * workspace; no host synchronization, no device allocation. */
+int32_t geek_quantile_buckets(const geek_quantile_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                              int32_t* d_status, void* stream);
 
 /* ---- profiling (opt-in) -------------------------------------------------
  * With profiling enabled the library brackets its main kernels with HIP

@@ -28,6 +28,7 @@ GEEK_HASH_DENSE, GEEK_HASH_SETS, GEEK_HASH_HETERO = 0, 1, 2
 GEEK_METRIC_EUCLID, GEEK_METRIC_SIG, GEEK_METRIC_HETERO = 0, 1, 2
 GEEK_PREC_FP32, GEEK_PREC_BF16, GEEK_PREC_FP8 = 0, 1, 2
 GEEK_OP_HASH, GEEK_OP_BUCKETIZE, GEEK_OP_SILK, GEEK_OP_ASSIGN, GEEK_OP_REGROUP = 0, 1, 2, 3, 4
+GEEK_OP_QUANTILE = 5
 
 P = C.c_void_p
 
@@ -92,8 +93,16 @@ class RegroupJob(C.Structure):
     ]
 
 
+class QuantileJob(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("d", C.c_int32), ("m", C.c_int32), ("t", C.c_int32), ("pad0", C.c_int32),
+        ("X", P), ("ldx", C.c_int64), ("A", P),
+        ("members", P), ("offsets", P), ("bucket_of", P),
+    ]
+
+
 EXPORTS = ("geek_workspace_size", "geek_hash", "geek_bucketize", "geek_silk_seeds",
-           "geek_assign", "geek_regroup", "geek_status_string", "geek_version", "geek_last_hip_error",
+           "geek_assign", "geek_regroup", "geek_quantile_buckets", "geek_status_string", "geek_version", "geek_last_hip_error",
            "geek_profile", "geek_profile_read", "geek_wallclock_hz", "geek_set_scan_tiles",
            "geek_get_scan_tiles")
 
@@ -114,7 +123,7 @@ def _load():
     lib.geek_workspace_size.restype = C.c_int32
     for name, jt in (("geek_hash", HashJob), ("geek_bucketize", BucketizeJob),
                      ("geek_silk_seeds", SilkJob), ("geek_assign", AssignJob),
-                     ("geek_regroup", RegroupJob)):
+                     ("geek_regroup", RegroupJob), ("geek_quantile_buckets", QuantileJob)):
         f = getattr(lib, name)
         f.argtypes = [C.POINTER(jt), C.c_int32, P, C.c_size_t, P, P]
         f.restype = C.c_int32
@@ -215,3 +224,7 @@ def geek_assign(jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr):
 
 def geek_regroup(jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr):
     return _call("geek_regroup", jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr)
+
+
+def geek_quantile_buckets(jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr):
+    return _call("geek_quantile_buckets", jobs, ws_ptr, ws_bytes, status_ptr, stream_ptr)

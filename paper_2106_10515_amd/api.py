@@ -242,6 +242,27 @@ def assign_euclid(X, seed_offsets, seed_members, k, precision=L.GEEK_PREC_FP32,
     return out
 
 
+def quantile_buckets(X, A, t, want_bucket_of=True, status=None, check=True):
+    """Algorithm 1's dense transformation (geek_quantile_buckets): for each
+    row of A [m, d], the n rows of X ranked by a . x (ties by id) and split
+    evenly into t buckets.  Returns ``(members, offsets, bucket_of)`` as
+    int32 device tensors [m, n], [m, t + 1], [m, n] (bucket_of None unless
+    wanted)."""
+    dev = _dev(X)
+    n, d = X.shape
+    m = A.shape[0]
+    mem = torch.empty((m, n), dtype=torch.int32, device=dev)
+    off = torch.empty((m, t + 1), dtype=torch.int32, device=dev)
+    bof = torch.empty((m, n), dtype=torch.int32, device=dev) if want_bucket_of else None
+    status = new_status(dev) if status is None else status
+    j = L.QuantileJob(n=n, d=d, m=m, t=t, X=_p(X), ldx=X.stride(0), A=_p(A.contiguous()),
+                      members=_p(mem), offsets=_p(off), bucket_of=_p(bof))
+    _run(L.GEEK_OP_QUANTILE, L.geek_quantile_buckets, [j], dev, status)
+    if check:
+        check_status(status, "geek_quantile_buckets")
+    return mem, off, bof
+
+
 def regroup(assign, k, want_label_of=True, status=None, check=True):
     """The clusters of an assignment as a seeds CSR for a further pass
     (geek_regroup).  Returns ``(seed_offsets, seed_members, k_out, label_of)``

@@ -1,6 +1,6 @@
 // extern "C" entry points of libgeek.so: argument validation, workspace
 // sizing and dispatch to the kernels of hash.hip, bucketize.hip, silk.hip,
-// assign.hip and regroup.hip.
+// assign.hip, regroup.hip and quantile.hip.
 #include <string.h>
 
 #include <algorithm>
@@ -35,6 +35,8 @@ int32_t assign_euclid_batch(const geek_assign_job* jobs, int njobs, void* ws, si
 int32_t assign_sig(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
 size_t regroup_ws(const geek_regroup_job& J);
 int32_t regroup_run(const geek_regroup_job& J, void* ws, int32_t* st, hipStream_t s);
+size_t quantile_ws(const geek_quantile_job& J);
+int32_t quantile_run(const geek_quantile_job& J, void* ws, int32_t* st, hipStream_t s);
 
 static thread_local std::string g_last_err;
 
@@ -188,6 +190,13 @@ static int32_t check_regroup(const geek_regroup_job& J) {
   return GEEK_OK;
 }
 
+static int32_t check_quantile(const geek_quantile_job& J) {
+  if (J.n < 1 || J.n >= (1ll << 31) || J.m < 1 || J.t < 1 || (int64_t)J.t > J.n || J.d < 1) return GEEK_ERR_ARG;
+  if (!J.X || !J.A || !J.members || !J.offsets || J.ldx < J.d) return GEEK_ERR_ARG;
+  if (J.d > 256) return GEEK_ERR_UNSUPPORTED;
+  return GEEK_OK;
+}
+
 }  // namespace geek
 
 using namespace geek;
@@ -297,6 +306,12 @@ int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t*
         b = J.metric == GEEK_METRIC_SIG ? assign_sig_ws(J) : assign_euclid_ws(J);
         break;
       }
+      case GEEK_OP_QUANTILE: {
+        const geek_quantile_job& J = static_cast<const geek_quantile_job*>(jobs)[j];
+        if (int32_t rc = check_quantile(J)) return rc;
+        b = quantile_ws(J);
+        break;
+      }
       case GEEK_OP_REGROUP: {
         const geek_regroup_job& J = static_cast<const geek_regroup_job*>(jobs)[j];
         if (int32_t rc = check_regroup(J)) return rc;
@@ -401,6 +416,19 @@ int32_t geek_regroup(const geek_regroup_job* jobs, int32_t njobs, void* ws, size
   if (!ws) return GEEK_ERR_ARG;
   for (int j = 0; j < njobs; ++j)
     if (int32_t rc = regroup_run(jobs[j], ws, d_status, (hipStream_t)stream)) return rc;
+  return GEEK_OK;
+}
+
+int32_t geek_quantile_buckets(const geek_quantile_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                              int32_t* d_status, void* stream) {
+  if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    if (int32_t rc = check_quantile(jobs[j])) return rc;
+    if (ws_bytes < quantile_ws(jobs[j])) return GEEK_ERR_WORKSPACE;
+  }
+  if (!ws) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j)
+    if (int32_t rc = quantile_run(jobs[j], ws, d_status, (hipStream_t)stream)) return rc;
   return GEEK_OK;
 }
 

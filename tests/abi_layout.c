@@ -36,5 +36,9 @@ int main(void) {
   F(geek_regroup_job, n); F(geek_regroup_job, k); F(geek_regroup_job, assign);
   F(geek_regroup_job, seed_offsets); F(geek_regroup_job, seed_members); F(geek_regroup_job, k_out);
   F(geek_regroup_job, label_of);
+  printf("geek_quantile_job sizeof %zu\n", sizeof(geek_quantile_job));
+  F(geek_quantile_job, n); F(geek_quantile_job, d); F(geek_quantile_job, m); F(geek_quantile_job, t);
+  F(geek_quantile_job, X); F(geek_quantile_job, ldx); F(geek_quantile_job, A);
+  F(geek_quantile_job, members); F(geek_quantile_job, offsets); F(geek_quantile_job, bucket_of);
   return 0;
 }

@@ -38,7 +38,7 @@ def test_struct_layouts_match_header(tmp_path):
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     structs = {"geek_hash_job": L.HashJob, "geek_bucketize_job": L.BucketizeJob,
                "geek_silk_job": L.SilkJob, "geek_assign_job": L.AssignJob,
-               "geek_regroup_job": L.RegroupJob}
+               "geek_regroup_job": L.RegroupJob, "geek_quantile_job": L.QuantileJob}
     n = 0
     for line in out.splitlines():
         sname, field, val = line.split()
@@ -78,6 +78,12 @@ def test_argument_errors_need_no_gpu():
     assert lib.geek_workspace_size(L.GEEK_OP_REGROUP, C.byref(ok), 1, C.byref(nb)) == 0
     assert nb.value >= 5 * 1000 * 4
     assert lib.geek_regroup(C.byref(ok), 1, C.c_void_p(256), 16, None, None) == L.GEEK_ERR_WORKSPACE
+    bad = L.QuantileJob(n=10, d=4, m=2, t=11, X=16, ldx=4, A=16, members=16, offsets=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_QUANTILE, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_ARG
+    bad = L.QuantileJob(n=10, d=300, m=2, t=3, X=16, ldx=300, A=16, members=16, offsets=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_QUANTILE, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_UNSUPPORTED
+    ok = L.QuantileJob(n=10, d=4, m=2, t=3, X=16, ldx=4, A=16, members=16, offsets=16)
+    assert lib.geek_quantile_buckets(C.byref(ok), 1, C.c_void_p(256), 16, None, None) == L.GEEK_ERR_WORKSPACE
 
 
 def test_scan_tile_table_host_only(tmp_path):
