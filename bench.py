@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets", "silk", "refine"],
+    ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets", "silk", "refine", "quantile"],
                     help="dense_large: the headline metric; batched: 256 mixed dense jobs in one "
                          "captured HIP graph; hetero: heterogeneous rows; sets: sparse sets "
                          "(MinHash, band buckets, signature assignment); silk: the whole GEEK pass "
@@ -108,6 +108,8 @@ def main():
         return bench_silk(args)
     if args.workload == "refine":
         return bench_refine(args)
+    if args.workload == "quantile":
+        return bench_quantile(args)
     import numpy as np
     import torch
 
@@ -641,6 +643,58 @@ def bench_refine(args):
         "assign_counters": out["counters"].cpu().numpy().tolist(),
         "sse_first": float(first["sse"].item()),
         "sse_after_pass": float(out["sse"].item()),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_quantile(args):
+    """Algorithm 1's dense transformation on the dense large mixture: m = 40
+    projections a ~ N(0, I), each table ranked by a . x in float64 and split
+    evenly into t = 10,000 buckets (the paper's parameter study fixes m = 40
+    and varies t from 5,000 to 30,000).  One step = one geek_quantile_buckets
+    call over all 10^7 points."""
+    import numpy as np
+    import torch
+
+    from paper_2106_10515_amd import api
+    from workloads import CONFIGS, dense_mixture, e2lsh_params
+
+    dev = torch.device("cuda:0")
+    cfg = CONFIGS["dense_large"]
+    n, d = args.n, cfg["d"]
+    m, t = 40, 10_000
+    clusters = min(args.clusters, n)
+    X, _, _ = dense_mixture(n, d, clusters, cfg["lo"], cfg["hi"], cfg["sigma"], cfg["sizes"], seed=0, device=dev)
+    A, _ = e2lsh_params(m, d, 1.0, 0)
+    Ag = torch.from_numpy(A).to(dev)
+    status = api.new_status(dev)
+    for _ in range(args.warmup):
+        api.quantile_buckets(X, Ag, t, status=status, check=False)
+    torch.cuda.synchronize()
+    api.check_status(status, "warmup")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        mem, off, bof = api.quantile_buckets(X, Ag, t, status=status, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    api.check_status(status, "timed")
+    ms = e0.elapsed_time(e1) / args.steps
+    algo = 4.0 * n * d + 2 * 4.0 * m * n + 4.0 * m * (t + 1)  # X once; members + bucket_of; offsets
+    gbs = algo / (ms * 1e-3) / 1e9
+    sizes = np.diff(off.cpu().numpy().astype(np.int64), axis=1)
+    line = {
+        "metric": "points/s of Algorithm 1's quantile bucketing (m tables, t buckets each)",
+        "value": n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"quantile: dense_large n={n} d={d} {clusters}-cluster Gaussian mixture "
+                               f"(Zipf sizes), m={m} projections a~N(0,I), t={t}",
+                   "n": n, "d": d, "m": m, "t": t},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM, "unit": "GB/s", "frac": gbs / PEAK_HBM,
+                     "traffic": None, "kernel": "geek_quantile_buckets (whole call)",
+                     "bytes_per_launch": algo},
+        "bucket_sizes": [int(sizes.min()), int(sizes.max())],
     }
     print(json.dumps(line), flush=True)
 

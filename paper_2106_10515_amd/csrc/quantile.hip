@@ -1,8 +1,9 @@
 // Quantile bucketing of dense data (paper Algorithm 1): for each projection
 // a_p, the objects are ranked by the QALSH value a_p . x_i (ties by id) and
 // the ranks split evenly into t buckets, rank r going to bucket
-// floor(r t / n).  Per table: exact float64 values (the attributes summed in
-// order, one rounding per addition, products exact), a stable LSD radix sort
+// floor(r t / n).  Exact float64 values of all tables first (the attributes
+// summed in order, one rounding per addition, products exact; X read once
+// per group of projections); then per table a stable LSD radix sort
 // of the values' order-preserving 64-bit patterns carrying the ids (so equal
 // values keep id order), each object's bucket from its rank, and a second
 // stable sort of the ids by bucket, which lists every bucket's members in
@@ -17,41 +18,68 @@ namespace geek {
 constexpr int QV_ROWS = 64;     // rows of X staged in LDS per block
 constexpr int QV_THREADS = 256;
 constexpr int QV_MAXD = 256;
+constexpr int QV_AFLOATS = 4096;  // projection values staged per launch (pm * d <= this)
+constexpr int QV_ILP = 8;         // float64 chains per thread
 
-// values of one projection for QV_ROWS rows: the rows are staged in LDS
-// (coalesced), then each of the first QV_ROWS threads sums one row's products
-// in attribute order; the value is written as an order-preserving pattern
+// values of projections p0 .. p0 + pm - 1 for QV_ROWS rows: the rows and the
+// projections are staged in LDS (X is read once per launch, not once per
+// table), then each thread sums (row, projection) pairs' products in
+// attribute order; the value is written as an order-preserving pattern
 // (negative values complemented, positive ones with the sign bit set; -0
-// becomes +0 so that equal values compare equal)
+// becomes +0 so that equal values compare equal) into the table's key words
 __global__ __launch_bounds__(QV_THREADS) void k_qv(const float* __restrict__ X, int64_t ldx, int64_t n, int d,
-                                                   const float* __restrict__ a, uint32_t* __restrict__ klo,
-                                                   uint32_t* __restrict__ khi, uint32_t* __restrict__ ids,
+                                                   const float* __restrict__ A, int p0, int pm,
+                                                   uint32_t* __restrict__ klo, uint32_t* __restrict__ khi,
                                                    int32_t* st) {
   __shared__ float xs[QV_ROWS][QV_MAXD + 1];
-  __shared__ float as[QV_MAXD];
+  __shared__ float as[QV_AFLOATS];
   const int64_t i0 = (int64_t)blockIdx.x * QV_ROWS;
   for (int q = threadIdx.x; q < QV_ROWS * d; q += QV_THREADS) {
     const int r = q / d, c = q % d;
     xs[r][c] = i0 + r < n ? X[(i0 + r) * ldx + c] : 0.f;
   }
-  for (int c = threadIdx.x; c < d; c += QV_THREADS) as[c] = a[c];
+  for (int q = threadIdx.x; q < pm * d; q += QV_THREADS) as[q] = A[(int64_t)p0 * d + q];
   __syncthreads();
-  const int r = threadIdx.x;
-  if (r >= QV_ROWS || i0 + r >= n) return;
-  double s = 0.0;
-  bool finite = true;
-  for (int c = 0; c < d; ++c) {
-    const float xv = xs[r][c];
-    finite = finite && isfinite(xv) && isfinite(as[c]);
-    s = __fma_rn((double)as[c], (double)xv, s);
+  // thread = one row and the projections w, w + 4, w + 8, ... (w = its
+  // wave): up to QV_ILP independent float64 chains advance together, each in
+  // attribute order; the projection values are wave-uniform LDS reads
+  const int r = threadIdx.x % QV_ROWS, w = threadIdx.x / QV_ROWS;
+  constexpr int NW = QV_THREADS / QV_ROWS;
+  if (i0 + r >= n) return;
+  for (int pb = w; pb < pm; pb += NW * QV_ILP) {
+    double acc[QV_ILP];
+    bool finite = true;
+#pragma unroll
+    for (int u = 0; u < QV_ILP; ++u) acc[u] = 0.0;
+    for (int c = 0; c < d; ++c) {
+      const float xv = xs[r][c];
+      finite = finite && isfinite(xv);
+#pragma unroll
+      for (int u = 0; u < QV_ILP; ++u) {
+        const int pp = pb + u * NW;
+        const float av = pp < pm ? as[pp * d + c] : 0.f;
+        finite = finite && isfinite(av);
+        acc[u] = __fma_rn((double)av, (double)xv, acc[u]);
+      }
+    }
+    if (!finite) set_status(st, GEEK_ERR_NONFINITE);
+#pragma unroll
+    for (int u = 0; u < QV_ILP; ++u) {
+      const int pp = pb + u * NW;
+      if (pp >= pm) break;
+      const double sv = acc[u] + 0.0;  // -0 -> +0
+      uint64_t uv = (uint64_t)__double_as_longlong(sv);
+      uv = (uv >> 63) ? ~uv : (uv | 0x8000000000000000ull);
+      const int64_t o = (int64_t)(p0 + pp) * n + i0 + r;
+      klo[o] = (uint32_t)uv;
+      khi[o] = (uint32_t)(uv >> 32);
+    }
   }
-  if (!finite) set_status(st, GEEK_ERR_NONFINITE);
-  s = s + 0.0;  // -0 -> +0
-  uint64_t u = (uint64_t)__double_as_longlong(s);
-  u = (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-  klo[i0 + r] = (uint32_t)u;
-  khi[i0 + r] = (uint32_t)(u >> 32);
-  ids[i0 + r] = (uint32_t)(i0 + r);
+}
+
+__global__ void k_q_iota(int64_t n, uint32_t* __restrict__ ids) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q < n) ids[q] = (uint32_t)q;
 }
 
 // bucket of every object from its rank; the id-ordered bucket keys and ids
@@ -80,43 +108,53 @@ __global__ void k_q_offsets(int64_t n, int t, uint32_t* __restrict__ off) {
 }
 
 struct QWs {
-  uint32_t *klo, *khi, *ids, *klo2, *khi2, *ids2, *rtmp;
+  uint32_t *klo, *khi;                  // [m][n] value patterns of every table
+  uint32_t *ids, *klo2, *khi2, *ids2;   // [n] sort buffers of one table
+  uint32_t* rtmp;
 };
 
-static size_t carve_q(int64_t n, void* base, QWs& W) {
+static size_t carve_q(const geek_quantile_job& J, void* base, QWs& W) {
   Carver c(base);
-  W.klo = c.take<uint32_t>(n);
-  W.khi = c.take<uint32_t>(n);
-  W.ids = c.take<uint32_t>(n);
-  W.klo2 = c.take<uint32_t>(n);
-  W.khi2 = c.take<uint32_t>(n);
-  W.ids2 = c.take<uint32_t>(n);
-  W.rtmp = c.take<uint32_t>(radix_tmp_words(n));
+  W.klo = c.take<uint32_t>((size_t)J.m * J.n);
+  W.khi = c.take<uint32_t>((size_t)J.m * J.n);
+  W.ids = c.take<uint32_t>(J.n);
+  W.klo2 = c.take<uint32_t>(J.n);
+  W.khi2 = c.take<uint32_t>(J.n);
+  W.ids2 = c.take<uint32_t>(J.n);
+  W.rtmp = c.take<uint32_t>(radix_tmp_words(J.n));
   return c.used + 256;
 }
 
 size_t quantile_ws(const geek_quantile_job& J) {
   QWs W;
-  return carve_q(J.n, nullptr, W);
+  return carve_q(J, nullptr, W);
 }
 
 int32_t quantile_run(const geek_quantile_job& J, void* ws, int32_t* st, hipStream_t s) {
   QWs W;
-  carve_q(J.n, ws, W);
+  carve_q(J, ws, W);
   const int grid = ceil_div(J.n, 256);
+  // values of all tables, as many projections per pass over X as LDS holds
+  const int per = QV_AFLOATS / J.d;
+  for (int p0 = 0; p0 < J.m; p0 += per) {
+    const int pm = J.m - p0 < per ? J.m - p0 : per;
+    hipLaunchKernelGGL(k_qv, dim3(ceil_div(J.n, QV_ROWS)), dim3(QV_THREADS), 0, s, J.X, J.ldx, J.n, J.d, J.A, p0,
+                       pm, W.klo, W.khi, st);
+  }
   for (int p = 0; p < J.m; ++p) {
     uint32_t* members = J.members + (int64_t)p * J.n;
     uint32_t* bof = J.bucket_of ? J.bucket_of + (int64_t)p * J.n : nullptr;
-    hipLaunchKernelGGL(k_qv, dim3(ceil_div(J.n, QV_ROWS)), dim3(QV_THREADS), 0, s, J.X, J.ldx, J.n, J.d,
-                       J.A + (int64_t)p * J.d, W.klo, W.khi, W.ids, st);
+    uint32_t* klo = W.klo + (int64_t)p * J.n;
+    uint32_t* khi = W.khi + (int64_t)p * J.n;
+    hipLaunchKernelGGL(k_q_iota, dim3(grid), dim3(256), 0, s, J.n, W.ids);
     // 64-bit value patterns, least significant byte first; ties keep id order
     const int words[8] = {0, 0, 0, 0, 1, 1, 1, 1}, shifts[8] = {0, 8, 16, 24, 0, 8, 16, 24};
-    RsView A{{W.klo, W.khi, nullptr, nullptr}, W.ids}, B{{W.klo2, W.khi2, nullptr, nullptr}, W.ids2};
+    RsView A{{klo, khi, nullptr, nullptr}, W.ids}, B{{W.klo2, W.khi2, nullptr, nullptr}, W.ids2};
     const int alt = radix_sort(A, B, 2, J.n, words, shifts, 8, W.rtmp, s);
     const uint32_t* sorted_ids = alt ? W.ids2 : W.ids;
-    // second sort: ids in id order keyed by bucket (klo2 / ids2 free again
-    // when the sorted ids are in ids, and vice versa)
-    uint32_t* bkey = alt ? W.klo : W.klo2;
+    // second sort: ids in id order keyed by bucket, in the buffers the first
+    // sort's result does not occupy (the table's own key words are free now)
+    uint32_t* bkey = alt ? klo : W.klo2;
     uint32_t* bid = alt ? W.ids : W.ids2;
     hipLaunchKernelGGL(k_q_rank, dim3(grid), dim3(256), 0, s, sorted_ids, J.n, J.t, bkey, bid, bof);
     int w2[4], s2[4], np = 0;
@@ -124,7 +162,7 @@ int32_t quantile_run(const geek_quantile_job& J, void* ws, int32_t* st, hipStrea
       w2[np] = 0;
       s2[np++] = sh;
     }
-    uint32_t* bkey2 = alt ? W.khi : W.khi2;
+    uint32_t* bkey2 = alt ? khi : W.khi2;
     uint32_t* bid2 = alt ? W.ids2 : W.ids;
     RsView C{{bkey, nullptr, nullptr, nullptr}, bid}, D{{bkey2, nullptr, nullptr, nullptr}, bid2};
     const int alt2 = radix_sort(C, D, 1, J.n, w2, s2, np, W.rtmp, s);
