@@ -17,49 +17,59 @@ namespace geek {
 
 constexpr int QV_ROWS = 64;     // rows of X staged in LDS per block
 constexpr int QV_THREADS = 256;
-constexpr int QV_MAXD = 256;
 constexpr int QV_AFLOATS = 4096;  // projection values staged per launch (pm * d <= this)
 constexpr int QV_ILP = 8;         // float64 chains per thread
 
 // values of projections p0 .. p0 + pm - 1 for QV_ROWS rows: the rows and the
 // projections are staged in LDS (X is read once per launch, not once per
-// table), then each thread sums (row, projection) pairs' products in
-// attribute order; the value is written as an order-preserving pattern
-// (negative values complemented, positive ones with the sign bit set; -0
-// becomes +0 so that equal values compare equal) into the table's key words
+// table; rows padded to a multiple of four attributes plus four), then each
+// thread takes one row and the projections w, w + 4, w + 8, ... (w = its
+// wave): up to QV_ILP independent float64 chains advance together, each in
+// attribute order, four attributes per 16-byte LDS read (the projection
+// reads are wave-uniform).  The value is written as an order-preserving
+// pattern (negative values complemented, positive ones with the sign bit
+// set; -0 becomes +0 so that equal values compare equal) into the table's
+// key words.
 __global__ __launch_bounds__(QV_THREADS) void k_qv(const float* __restrict__ X, int64_t ldx, int64_t n, int d,
                                                    const float* __restrict__ A, int p0, int pm,
                                                    uint32_t* __restrict__ klo, uint32_t* __restrict__ khi,
                                                    int32_t* st) {
-  __shared__ float xs[QV_ROWS][QV_MAXD + 1];
-  __shared__ float as[QV_AFLOATS];
+  extern __shared__ __attribute__((aligned(16))) float qv_smem[];
+  const int d4 = (d + 3) & ~3, xstr = d4 + 4;
+  float* xs = qv_smem;                   // [QV_ROWS][xstr]
+  float* as = qv_smem + QV_ROWS * xstr;  // [pm][d4]
   const int64_t i0 = (int64_t)blockIdx.x * QV_ROWS;
-  for (int q = threadIdx.x; q < QV_ROWS * d; q += QV_THREADS) {
-    const int r = q / d, c = q % d;
-    xs[r][c] = i0 + r < n ? X[(i0 + r) * ldx + c] : 0.f;
+  for (int q = threadIdx.x; q < QV_ROWS * d4; q += QV_THREADS) {
+    const int r = q / d4, c = q % d4;
+    xs[r * xstr + c] = (i0 + r < n && c < d) ? X[(i0 + r) * ldx + c] : 0.f;
   }
-  for (int q = threadIdx.x; q < pm * d; q += QV_THREADS) as[q] = A[(int64_t)p0 * d + q];
+  for (int q = threadIdx.x; q < pm * d4; q += QV_THREADS) {
+    const int pp = q / d4, c = q % d4;
+    as[q] = c < d ? A[(int64_t)(p0 + pp) * d + c] : 0.f;
+  }
   __syncthreads();
-  // thread = one row and the projections w, w + 4, w + 8, ... (w = its
-  // wave): up to QV_ILP independent float64 chains advance together, each in
-  // attribute order; the projection values are wave-uniform LDS reads
   const int r = threadIdx.x % QV_ROWS, w = threadIdx.x / QV_ROWS;
   constexpr int NW = QV_THREADS / QV_ROWS;
   if (i0 + r >= n) return;
+  const float* xr = xs + r * xstr;
   for (int pb = w; pb < pm; pb += NW * QV_ILP) {
     double acc[QV_ILP];
     bool finite = true;
 #pragma unroll
     for (int u = 0; u < QV_ILP; ++u) acc[u] = 0.0;
-    for (int c = 0; c < d; ++c) {
-      const float xv = xs[r][c];
-      finite = finite && isfinite(xv);
+    for (int c = 0; c < d4; c += 4) {
+      const float4 xv = *reinterpret_cast<const float4*>(xr + c);
+      finite = finite && isfinite(xv.x) && isfinite(xv.y) && isfinite(xv.z) && isfinite(xv.w);
 #pragma unroll
       for (int u = 0; u < QV_ILP; ++u) {
-        const int pp = pb + u * NW;
-        const float av = pp < pm ? as[pp * d + c] : 0.f;
-        finite = finite && isfinite(av);
-        acc[u] = __fma_rn((double)av, (double)xv, acc[u]);
+        const int pp = pb + u * NW < pm ? pb + u * NW : pm - 1;  // repeats are not written
+        const float4 av = *reinterpret_cast<const float4*>(as + pp * d4 + c);
+        finite = finite && isfinite(av.x) && isfinite(av.y) && isfinite(av.z) && isfinite(av.w);
+        // attributes past d are zero on both sides: exact zero products
+        acc[u] = __fma_rn((double)av.x, (double)xv.x, acc[u]);
+        acc[u] = __fma_rn((double)av.y, (double)xv.y, acc[u]);
+        acc[u] = __fma_rn((double)av.z, (double)xv.z, acc[u]);
+        acc[u] = __fma_rn((double)av.w, (double)xv.w, acc[u]);
       }
     }
     if (!finite) set_status(st, GEEK_ERR_NONFINITE);
@@ -134,12 +144,15 @@ int32_t quantile_run(const geek_quantile_job& J, void* ws, int32_t* st, hipStrea
   QWs W;
   carve_q(J, ws, W);
   const int grid = ceil_div(J.n, 256);
-  // values of all tables, as many projections per pass over X as LDS holds
-  const int per = QV_AFLOATS / J.d;
+  // values of all tables, as many projections per pass over X as the
+  // staging area holds
+  const int d4 = (J.d + 3) & ~3;
+  const int per = QV_AFLOATS / d4;
   for (int p0 = 0; p0 < J.m; p0 += per) {
     const int pm = J.m - p0 < per ? J.m - p0 : per;
-    hipLaunchKernelGGL(k_qv, dim3(ceil_div(J.n, QV_ROWS)), dim3(QV_THREADS), 0, s, J.X, J.ldx, J.n, J.d, J.A, p0,
-                       pm, W.klo, W.khi, st);
+    const size_t lds = sizeof(float) * ((size_t)QV_ROWS * (d4 + 4) + (size_t)pm * d4);
+    hipLaunchKernelGGL(k_qv, dim3(ceil_div(J.n, QV_ROWS)), dim3(QV_THREADS), lds, s, J.X, J.ldx, J.n, J.d, J.A,
+                       p0, pm, W.klo, W.khi, st);
   }
   for (int p = 0; p < J.m; ++p) {
     uint32_t* members = J.members + (int64_t)p * J.n;
