@@ -1,0 +1,107 @@
+"""Parity at the full sizes of the sparse-set and heterogeneous workloads, in
+the benchmark's launch configuration: 5e6 sets over a 1e6-token vocabulary
+(MinHash K = 4 x L = 64, 2,000 planted clusters) and 2e6 heterogeneous rows
+(20 numeric + 10 categorical attributes, 1,000 clusters).  Sampled rows are
+checked against the FP64 oracle one by one; bucket CSRs through properties
+that hold at any size; central vectors and modes of the planted seeds in
+full."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads import CONFIGS, e2lsh_params, hetero_rows, key_words, planted_seeds, sparse_sets
+from workloads.gen import STREAM_MINHASH
+
+from .gpu_util import announce, gpu_api, host_u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _rows(n, seed):
+    g = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, n - 1], g.integers(0, n, 509)]))
+
+
+def _band_csr_properties(sig, mem, off, nb, band, K):
+    n = mem.numel()
+    nb = int(nb)
+    o = off[:nb + 1].long()
+    assert int(o[0]) == 0 and int(o[-1]) == n and bool((o[1:] > o[:-1]).all())
+    m64 = mem.long()
+    assert torch.equal(torch.sort(m64).values, torch.arange(n, device="cuda"))
+    start = torch.zeros(n, dtype=torch.bool, device="cuda")
+    start[o[:-1]] = True
+    inner = ~start[1:]
+    assert bool((m64[1:][inner] > m64[:-1][inner]).all())
+    heads = m64[o[:-1]]
+    assert bool((heads[1:] > heads[:-1]).all())
+    key = sig[:, band * K:(band + 1) * K].long()[m64]
+    assert bool((key[1:][inner] == key[:-1][inner]).all())
+    assert torch.unique(key[o[:-1]], dim=0).shape[0] == nb
+
+
+def test_full_sets():
+    api = gpu_api()
+    cfg = CONFIGS["sets"]
+    n, K, L = cfg["n"], cfg["K"], cfg["L"]
+    announce(f"full size sets: generating n={n}")
+    off, tok, lab = sparse_sets(n, cfg["vocab"], cfg["clusters"], seed=0, device="cuda")
+    mh = key_words(K * L, 0, STREAM_MINHASH)
+    sig = api.hash_sets(off, tok, torch.from_numpy(mh.view(np.int32)).cuda())
+    rows = _rows(n, 21)
+    off_h = off.cpu().numpy()
+    parts = [tok[int(off_h[i]):int(off_h[i + 1])].cpu().numpy().view(np.uint32) for i in rows]
+    sub_off = np.concatenate([[0], np.cumsum([len(p) for p in parts])]).astype(np.int64)
+    ref = oracle.minhash_sets(sub_off, np.concatenate(parts), mh)
+    assert np.array_equal(host_u32(sig[torch.from_numpy(rows).cuda()]), ref)
+    announce("full size sets: bucketize")
+    mem, boff, nb, _ = api.bucketize(sig, n, L, K, K, K * L, want_bucket_of=False)
+    for band in (0, L - 1):
+        _band_csr_properties(sig, mem[band], boff[band], nb[band], band, K)
+    announce("full size sets: assign")
+    so, sm = planted_seeds(lab, cfg["clusters"], 32)
+    k = len(so) - 1
+    out = api.assign_sig(sig, torch.from_numpy(so.view(np.int32)).cuda(), torch.from_numpy(sm.view(np.int32)).cuda(), k)
+    S_members = host_u32(sig[torch.from_numpy(sm.astype(np.int64)).cuda()])
+    M = oracle.modes(S_members, so, np.arange(len(sm), dtype=np.uint32))
+    assert np.array_equal(host_u32(out["modes"]), M)
+    a, dist = oracle.assign_sig(host_u32(sig[torch.from_numpy(rows).cuda()]), M)
+    assert np.array_equal(out["assign"].cpu().numpy()[rows], a)
+    assert np.array_equal(out["dist"].cpu().numpy()[rows], dist)
+
+
+def test_full_hetero():
+    api = gpu_api()
+    cfg = CONFIGS["hetero"]
+    n = cfg["n"]
+    announce(f"full size hetero: generating n={n}")
+    X, cat, lab, _ = hetero_rows(n, cfg["d_num"], cfg["n_cat"], cfg["clusters"], seed=0)
+    A, b = e2lsh_params(cfg["P_h"], cfg["d_num"], cfg["w"], 0)
+    K, L = cfg["K"], cfg["L"]
+    mh = key_words(K * L, 0, STREAM_MINHASH)
+    Xg, catg = torch.from_numpy(X).cuda(), torch.from_numpy(cat).cuda()
+    sig = api.hash_hetero(Xg, catg, torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda(), cfg["P_h"], 1,
+                          cfg["w"], torch.from_numpy(mh.view(np.int32)).cuda())
+    rows = _rows(n, 22)
+    codes = oracle.e2lsh_codes(X[rows], A, b, cfg["w"])
+    tk = oracle.hetero_tokens(cat[rows], codes)
+    ref = oracle.minhash_sets(np.arange(0, tk.size + 1, tk.shape[1], dtype=np.int64), tk.reshape(-1), mh)
+    assert np.array_equal(host_u32(sig[torch.from_numpy(rows).cuda()]), ref)
+    announce("full size hetero: bucketize")
+    mem, boff, nb, _ = api.bucketize(sig, n, L, K, K, K * L, want_bucket_of=False)
+    _band_csr_properties(sig, mem[0], boff[0], nb[0], 0, K)
+    announce("full size hetero: assign (BF16 numeric part)")
+    so, sm = planted_seeds(lab, cfg["clusters"], 32)
+    k = len(so) - 1
+    out = api.assign_hetero(Xg, catg, torch.from_numpy(so.view(np.int32)).cuda(),
+                            torch.from_numpy(sm.view(np.int32)).cuda(), k, 1.0, 1)
+    Cn = oracle.centroids(X, so, sm)
+    Mc = oracle.modes(cat, so, sm)
+    assert np.array_equal(out["centroids"].cpu().numpy(), Cn)
+    assert np.array_equal(out["modes"].cpu().numpy(), Mc)
+    a, dist = oracle.assign_hetero(X[rows], cat[rows], Cn, Mc, 1.0)
+    assert np.array_equal(out["assign"].cpu().numpy()[rows], a)
+    assert np.array_equal(out["dist"].cpu().numpy()[rows], dist)
+    assert out["sse"].item() == oracle.sse(out["dist"].cpu().numpy())
