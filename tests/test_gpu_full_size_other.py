@@ -105,3 +105,41 @@ def test_full_hetero():
     assert np.array_equal(out["assign"].cpu().numpy()[rows], a)
     assert np.array_equal(out["dist"].cpu().numpy()[rows], dist)
     assert out["sse"].item() == oracle.sse(out["dist"].cpu().numpy())
+
+
+def test_full_batched_jobs():
+    # the 256-job batched workload: one batched BF16 assignment over all jobs;
+    # eight jobs (the largest, the smallest and six drawn) equal their
+    # single-job calls bit for bit and match the oracle on sampled rows
+    api = gpu_api()
+    from workloads import batched_jobs, dense_mixture
+
+    specs = batched_jobs(CONFIGS["batched"]["jobs"], seed=0)
+    announce(f"full size batched: generating {len(specs)} jobs")
+    probs, host = [], []
+    for sp in specs:
+        X, lab, _ = dense_mixture(sp["n"], sp["d"], sp["clusters"], sp["lo"], sp["hi"], sp["sigma"],
+                                  sp["sizes"], sp["seed"], device="cuda")
+        so, sm = planted_seeds(lab, sp["clusters"], 32)
+        probs.append((X, torch.from_numpy(so.view(np.int32)).cuda(), torch.from_numpy(sm.view(np.int32)).cuda(),
+                      len(so) - 1))
+        host.append((so, sm))
+    outs, t_done = api.assign_euclid_batch(probs, 1)
+    sizes = [sp["n"] for sp in specs]
+    g = np.random.default_rng(23)
+    pick = sorted(set([int(np.argmax(sizes)), int(np.argmin(sizes))] + g.choice(len(specs), 6, replace=False).tolist()))
+    assert bool((t_done > 0).all())
+    for j in pick:
+        X, sog, smg, k = probs[j]
+        announce(f"full size batched: job {j} n={X.shape[0]} d={X.shape[1]} k={k}")
+        one = api.assign_euclid(X, sog, smg, k, 1)
+        for key in ("assign", "centroids", "dist", "sse", "radius"):
+            assert torch.equal(outs[j][key], one[key]), (j, key)
+        so, sm = host[j]
+        Xm = X[torch.from_numpy(sm.astype(np.int64)).cuda()].cpu().numpy()
+        C = oracle.centroids(Xm, so, np.arange(len(sm), dtype=np.uint32))
+        assert np.array_equal(one["centroids"].cpu().numpy(), C)
+        rows = _rows(X.shape[0], 30 + j)
+        a, dist = oracle.assign_euclid(X[torch.from_numpy(rows).cuda()].cpu().numpy(), C)
+        assert np.array_equal(one["assign"].cpu().numpy()[rows], a)
+        assert np.array_equal(one["dist"].cpu().numpy()[rows], dist)
