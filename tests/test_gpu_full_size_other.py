@@ -143,3 +143,37 @@ def test_full_batched_jobs():
         a, dist = oracle.assign_euclid(X[torch.from_numpy(rows).cuda()].cpu().numpy(), C)
         assert np.array_equal(one["assign"].cpu().numpy()[rows], a)
         assert np.array_equal(one["dist"].cpu().numpy()[rows], dist)
+
+
+def test_full_silk_pass_properties():
+    # the SILK pass of the benchmark (10^6 points of the dense mixture, scaled
+    # width, 32 tables, K_S = 3, L_S = 20, delta = 10): the seed CSR is
+    # canonical (members ascending, every seed at least delta members) and a
+    # second run gives the same seeds and counters bit for bit
+    api = gpu_api()
+    from workloads import dense_mixture
+    from workloads.gen import STREAM_SILK
+
+    cfg = CONFIGS["dense_large"]
+    n, d, m, L = 1_000_000, cfg["d"], cfg["m"], cfg["L"]
+    w = cfg["w"] * d ** 0.5
+    K, LS, delta = cfg["K_S"], cfg["L_S"], cfg["delta"]
+    announce(f"full size silk pass: n={n}")
+    X, _, _ = dense_mixture(n, d, cfg["clusters"] * n // cfg["n"], cfg["lo"], cfg["hi"], cfg["sigma"], cfg["sizes"],
+                            seed=0, device="cuda")
+    A, b = e2lsh_params(m * L, d, w, 0)
+    keys = torch.from_numpy(key_words((LS + 1) * K, 0, STREAM_SILK).view(np.int32)).cuda()
+    kg, _ = api.hash_dense(X, torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda(), m, L, w)
+    bm, bo, bn, _ = api.bucketize(kg, n, L, 4, n * 4, 4, want_bucket_of=False)
+    runs = [api.silk_seeds(bm, bo, bn, n, L, K, LS, delta, keys) for _ in range(2)]
+    so, sm, ctr = (host_u32(runs[0][0]), host_u32(runs[0][1]), runs[0][2].cpu().numpy())
+    assert np.array_equal(so, host_u32(runs[1][0])) and np.array_equal(sm, host_u32(runs[1][1]))
+    assert np.array_equal(ctr, runs[1][2].cpu().numpy())
+    k = len(so) - 1
+    assert k > 1000 and so[0] == 0 and so[-1] == len(sm)
+    sizes = np.diff(so.astype(np.int64))
+    assert (sizes >= delta).all()
+    assert int(sm.max()) < n
+    seg = np.repeat(np.arange(k), sizes)
+    inner = seg[1:] == seg[:-1]
+    assert (sm[1:][inner].astype(np.int64) > sm[:-1][inner].astype(np.int64)).all()
