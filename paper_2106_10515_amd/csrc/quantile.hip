@@ -5,9 +5,10 @@
 // summed in order, one rounding per addition, products exact; X read once
 // per group of projections); then per table a stable LSD radix sort
 // of the values' order-preserving 64-bit patterns carrying the ids (so equal
-// values keep id order), each object's bucket from its rank, and a second
-// stable sort of the ids by bucket, which lists every bucket's members in
-// ascending id.  Bucket b starts at rank ceil(b n / t).
+// values keep id order); then every bucket's ids in ascending order: sorted
+// in LDS per bucket when buckets hold at most QS_MAX objects, else by a
+// second stable sort of the ids keyed by bucket (rank-derived).  Bucket b
+// starts at rank ceil(b n / t).
 #include <math.h>
 
 #include "common.hpp"
@@ -110,6 +111,44 @@ __global__ void k_q_copy(const uint32_t* __restrict__ src, int64_t n, uint32_t* 
   if (q < n) dst[q] = src[q];
 }
 
+// Buckets of at most QS_MAX objects: bucket b's ids (ranks ceil(b n / t) ..
+// ceil((b + 1) n / t) - 1 of the value order) are sorted ascending in LDS
+// (bitonic, padded with ~0) and written as its members; bucket_of is
+// scattered from the same LDS copy.  One workgroup per bucket.
+constexpr int QS_MAX = 4096;
+__global__ __launch_bounds__(256) void k_q_segsort(const uint32_t* __restrict__ sorted_ids, int64_t n, int t,
+                                                   uint32_t* __restrict__ members, uint32_t* __restrict__ bucket_of) {
+  __shared__ uint32_t v[QS_MAX];
+  const int b = blockIdx.x;
+  const int64_t s0 = ((uint64_t)b * (uint64_t)n + (uint64_t)t - 1) / (uint64_t)t;
+  const int64_t s1 = ((uint64_t)(b + 1) * (uint64_t)n + (uint64_t)t - 1) / (uint64_t)t;
+  const int len = (int)(s1 - s0);
+  int P = 1;
+  while (P < len) P <<= 1;
+  for (int q = threadIdx.x; q < P; q += blockDim.x) v[q] = q < len ? sorted_ids[s0 + q] : 0xFFFFFFFFu;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = threadIdx.x; q < P; q += blockDim.x) {
+        const int o = q ^ j;
+        if (o > q) {
+          const uint32_t a = v[q], c = v[o];
+          const bool up = (q & k) == 0;
+          if ((a > c) == up) {
+            v[q] = c;
+            v[o] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = threadIdx.x; q < len; q += blockDim.x) {
+    members[s0 + q] = v[q];
+    if (bucket_of) bucket_of[v[q]] = (uint32_t)b;
+  }
+}
+
 // bucket b starts at rank ceil(b n / t)
 __global__ void k_q_offsets(int64_t n, int t, uint32_t* __restrict__ off) {
   const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -165,6 +204,12 @@ int32_t quantile_run(const geek_quantile_job& J, void* ws, int32_t* st, hipStrea
     RsView A{{klo, khi, nullptr, nullptr}, W.ids}, B{{W.klo2, W.khi2, nullptr, nullptr}, W.ids2};
     const int alt = radix_sort(A, B, 2, J.n, words, shifts, 8, W.rtmp, s);
     const uint32_t* sorted_ids = alt ? W.ids2 : W.ids;
+    if ((J.n + J.t - 1) / J.t <= QS_MAX) {  // every bucket fits one workgroup's LDS
+      hipLaunchKernelGGL(k_q_segsort, dim3(J.t), dim3(256), 0, s, sorted_ids, J.n, J.t, members, bof);
+      hipLaunchKernelGGL(k_q_offsets, dim3(ceil_div((int64_t)J.t + 1, 256)), dim3(256), 0, s, J.n, J.t,
+                         J.offsets + (int64_t)p * (J.t + 1));
+      continue;
+    }
     // second sort: ids in id order keyed by bucket, in the buffers the first
     // sort's result does not occupy (the table's own key words are free now)
     uint32_t* bkey = alt ? klo : W.klo2;

@@ -26,7 +26,9 @@ def _case(api, X, A, t, name):
     (3001, 128, 3, 97, 1),     # ragged n, t not dividing n
     (777, 20, 2, 777, 2),      # t = n: one object per bucket
     (1000, 256, 2, 1, 3),      # t = 1: one bucket per table
-    (70001, 16, 2, 300, 4),    # two bucket digits in the second sort
+    (70001, 16, 2, 300, 4),    # buckets of 233-234 sorted in LDS
+    (20000, 8, 2, 3, 5),       # buckets of 6,667: the second radix sort by bucket
+    (12288, 8, 2, 3, 6),       # buckets of exactly 4,096: the largest sorted in LDS
 ])
 def test_quantile_buckets_match_oracle(n, d, m, t, seed):
     api = gpu_api()
