@@ -128,17 +128,30 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restri
 }
 
 // Stable scatter: items of a tile are ranked in index order (rounds of 256
-// in thread order; within a wave by ballot matching of the 8 digit bits).
+// in thread order; within a wave by ballot matching of the 8 digit bits),
+// placed in LDS in digit order, then written out by consecutive threads, so
+// every digit's items of the tile leave as one contiguous run.  The tile's
+// digit counts come from the scanned histogram (the next entry of the
+// flattened [digit][tile] scan, or n for the last).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(RsView in, RsView out, int W, int64_t n,
                                                            int word, int shift,
                                                            const uint32_t* __restrict__ hist, int nblk) {
-  __shared__ uint32_t gbase[256];
+  extern __shared__ uint32_t rs_stage[];  // [W (+1 with a payload)][RS_TILE]
+  __shared__ uint32_t gstart[256], lstart[256], lrun[256];
   __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+  __shared__ uint32_t sh[17];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  gbase[threadIdx.x] = hist[(int64_t)threadIdx.x * nblk + blockIdx.x];
+  const int64_t flat = (int64_t)threadIdx.x * nblk + blockIdx.x;
+  const uint32_t g0 = hist[flat];
+  const uint32_t g1 = flat + 1 < (int64_t)256 * nblk ? hist[flat + 1] : (uint32_t)n;
+  gstart[threadIdx.x] = g0;
+  const uint32_t l0 = blk_exscan(g1 - g0, nullptr, sh);
+  lstart[threadIdx.x] = l0;
+  lrun[threadIdx.x] = l0;
   for (int w2 = 0; w2 < RS_THREADS / 64; ++w2) wcnt[w2][threadIdx.x] = 0;
   __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * RS_TILE;
+  const int len = n - s < RS_TILE ? (int)(n - s) : RS_TILE;
   for (int r = 0; r < RS_ITEMS; ++r) {
     const int64_t i = s + r * RS_THREADS + threadIdx.x;
     const bool has = i < n;
@@ -165,21 +178,30 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(RsView in, RsView out
     if (has) {
       uint32_t before = 0;
       for (int w2 = 0; w2 < wv; ++w2) before += wcnt[w2][dg];
-      const uint32_t pos = gbase[dg] + before + below;
+      const uint32_t lp = lrun[dg] + before + below;
 #pragma unroll
       for (int w = 0; w < 4; ++w)
-        if (w < W) out.k[w][pos] = key[w];
-      if (out.v) out.v[pos] = val;
+        if (w < W) rs_stage[w * RS_TILE + lp] = key[w];
+      if (in.v) rs_stage[W * RS_TILE + lp] = val;
     }
     __syncthreads();
     {
       uint32_t tot = 0;
       for (int w2 = 0; w2 < RS_THREADS / 64; ++w2) tot += wcnt[w2][threadIdx.x];
-      gbase[threadIdx.x] += tot;
+      lrun[threadIdx.x] += tot;
     }
     __syncthreads();
     if (leader) wcnt[wv][dg] = 0u;
     __syncthreads();
+  }
+  // the tile in digit order: position q of digit d goes to gstart[d] + q - lstart[d]
+  for (int q = threadIdx.x; q < len; q += RS_THREADS) {
+    const uint32_t d = (rs_stage[word * RS_TILE + q] >> shift) & 255u;
+    const uint32_t pos = gstart[d] + (uint32_t)q - lstart[d];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      if (w < W) out.k[w][pos] = rs_stage[w * RS_TILE + q];
+    if (out.v) out.v[pos] = in.v ? rs_stage[W * RS_TILE + q] : 0u;
   }
 }
 
@@ -201,7 +223,8 @@ int radix_sort(RsView buf, RsView alt, int W, int64_t n, const int* words, const
     hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, s, a.k[words[p]], n, shifts[p], hist,
                        nblk);
     exscan_u32(hist, hist, (int64_t)256 * nblk, stmp, nullptr, s);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), 0, s, a, b, W, n, words[p], shifts[p],
+    const size_t stage = sizeof(uint32_t) * RS_TILE * (size_t)(W + (a.v ? 1 : 0));
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), stage, s, a, b, W, n, words[p], shifts[p],
                        hist, nblk);
     RsView t = a;
     a = b;
