@@ -24,8 +24,10 @@ def _dev(t: torch.Tensor) -> torch.device:
 
 
 def workspace(nbytes: int, device) -> torch.Tensor:
-    """A cached device buffer of at least ``nbytes`` (grown on demand)."""
-    key = str(device)
+    """A cached device buffer of at least ``nbytes`` (grown on demand), one
+    per (device, current stream): calls enqueued on different streams may run
+    at the same time and must not share scratch memory."""
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
     buf = _WS.get(key)
     if buf is None or buf.numel() < nbytes:
         _WS.pop(key, None)
