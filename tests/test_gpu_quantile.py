@@ -51,3 +51,19 @@ def test_quantile_buckets_ties_and_signed_zero():
     with pytest.raises(GeekError) as e:
         api.quantile_buckets(cuda(Xn), cuda(A), 5)
     assert e.value.code == 1
+
+
+def test_quantile_buckets_strided_rows():
+    # X as the first d columns of a wider row-major matrix (ldx > d)
+    api = gpu_api()
+    import torch
+
+    g = np.random.default_rng(7)
+    W = g.normal(size=(3000, 40)).astype(np.float32)
+    A = g.normal(size=(3, 33)).astype(np.float32)
+    announce("quantile strided n=3000 d=33 ldx=40")
+    mem, off, bof = oracle.quantile_buckets(W[:, :33], A, 50)
+    Wg = torch.from_numpy(W).cuda()
+    gm, go, gb = api.quantile_buckets(Wg[:, :33], torch.from_numpy(A).cuda(), 50)
+    assert np.array_equal(host_u32(gm), mem) and np.array_equal(host_u32(go), off)
+    assert np.array_equal(host_u32(gb), bof)

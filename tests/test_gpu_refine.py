@@ -104,3 +104,33 @@ def test_centroids_of_large_seeds(n, d, clusters, per, spare, seed):
     assert np.array_equal(out["centroids"].cpu().numpy(), C)
     assert np.array_equal(out["assign"].cpu().numpy(), a)
     assert np.array_equal(out["dist"].cpu().numpy(), dist)
+
+
+def test_regroup_two_jobs_one_call():
+    # two jobs in one geek_regroup call (through the C ABI) equal the oracle
+    api = gpu_api()
+    import torch
+    from paper_2106_10515_amd import _lib as L
+
+    g = np.random.default_rng(8)
+    cases = [(g.integers(0, 9, 5000).astype(np.int32), 12), (g.integers(0, 300, 777).astype(np.int32), 300)]
+    jobs, outs = [], []
+    for a, k in cases:
+        ag = cuda(a)
+        so = torch.empty(k + 1, dtype=torch.int32, device="cuda")
+        sm = torch.empty(len(a), dtype=torch.int32, device="cuda")
+        ko = torch.zeros(1, dtype=torch.int32, device="cuda")
+        lab = torch.empty(k, dtype=torch.int32, device="cuda")
+        outs.append((ag, so, sm, ko, lab))
+        jobs.append(L.RegroupJob(n=len(a), k=k, assign=ag.data_ptr(), seed_offsets=so.data_ptr(),
+                                 seed_members=sm.data_ptr(), k_out=ko.data_ptr(), label_of=lab.data_ptr()))
+    announce("regroup two jobs in one call")
+    status = api.new_status("cuda")
+    api._run(L.GEEK_OP_REGROUP, L.geek_regroup, jobs, torch.device("cuda:0"), status)
+    api.check_status(status, "geek_regroup (two jobs)")
+    for (a, k), (_, so, sm, ko, lab) in zip(cases, outs):
+        off, mem, lo = oracle.regroup(a, k)
+        kk = int(ko.item())
+        assert kk == len(lo)
+        assert np.array_equal(host_u32(so)[:kk + 1], off) and np.array_equal(host_u32(sm), mem)
+        assert np.array_equal(lab.cpu().numpy()[:kk], lo)
