@@ -74,14 +74,19 @@ def silk_from_bins(bucket_sets, table_bins, dedup_bins_of, delta):
     return C, _dedup(C, dedup_bins_of(C), delta)
 
 
-def _signatures(offsets, members, keys):
-    """G(B) for every set of a CSR: column k = min over the set of pi_k."""
+def _signatures(offsets, members, keys, tally=None):
+    """G(B) for every set of a CSR: column k = min over the set of pi_k.
+    ``tally`` (a one-element list, optional) is increased by the number of
+    pi evaluations made."""
     offsets = np.asarray(offsets, dtype=np.int64)
     members = np.asarray(members, dtype=np.uint32)
     K = len(keys)
     G = np.empty((len(offsets) - 1, K), dtype=np.uint32)
     for k in range(K):
-        G[:, k] = np.minimum.reduceat(perm(keys[k], members), offsets[:-1])
+        h = perm(keys[k], members)
+        if tally is not None:
+            tally[0] += int(h.size)
+        G[:, k] = np.minimum.reduceat(h, offsets[:-1])
     return G
 
 
@@ -139,30 +144,34 @@ def silk_seeds(offsets, members, K, L, delta, keys):
 
     Returns ``(seed_offsets uint32 [k+1], seed_members uint32, info)``;
     ``info`` holds the multiset size |C| before de-duplication and the work
-    counters (hash evaluations and voted (bin, id) pairs), which depend on the
-    buckets only and not on the number of clusters.
+    counters as counted while computing: the pi evaluations of the SILK
+    tables (``hash_evals``) and of the de-duplication table
+    (``hash_evals_dedup``), and the voted (bin, id) pairs.  Section 3.5 bounds
+    the work by the buckets alone (their number times their size times K
+    and L), not by the number of clusters.
     """
     keys = np.asarray(keys, dtype=np.uint32)
     offsets = np.asarray(offsets, dtype=np.int64)
     members = np.asarray(members, dtype=np.uint32)
-    total = int(offsets[-1]) if len(offsets) else 0
     C = []
     pairs = 0
+    evals = [0]
     for i in range(L):
-        G = _signatures(offsets, members, keys[i * K:(i + 1) * K])
+        G = _signatures(offsets, members, keys[i * K:(i + 1) * K], evals)
         got, pv = _vote_table_csr(offsets, members, G, delta)
         C.extend(got)
         pairs += pv
-    info = dict(multiset=len(C), hash_evals=K * L * total, pairs_voted=pairs)
+    info = dict(multiset=len(C), hash_evals=evals[0], pairs_voted=pairs)
     if not C:
         info["hash_evals_dedup"] = 0
         return np.zeros(1, np.uint32), np.zeros(0, np.uint32), info
     c_off = np.concatenate([[0], np.cumsum([len(c) for c in C])]).astype(np.int64)
     c_mem = np.concatenate(C).astype(np.uint32)
-    Gc = _signatures(c_off, c_mem, keys[L * K:(L + 1) * K])
+    dedup_evals = [0]
+    Gc = _signatures(c_off, c_mem, keys[L * K:(L + 1) * K], dedup_evals)
     bins, _ = _bins_of(Gc)
     seeds = _dedup(C, bins, delta)
-    info["hash_evals_dedup"] = K * int(c_off[-1])
+    info["hash_evals_dedup"] = dedup_evals[0]
     seen = {}
     dup = 0
     for s in seeds:

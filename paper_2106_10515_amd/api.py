@@ -128,10 +128,16 @@ def hash_hetero(X, cat, A, b, m, L_tables, w, mh_keys, status=None, check=True):
     dev = _dev(X)
     n, d = X.shape
     F = mh_keys.shape[0]
+    # contiguous copies held in locals until the call has been enqueued (a
+    # temporary freed earlier could be handed out again as the workspace)
+    A = A.contiguous()
+    b = b.contiguous()
+    cat = cat.contiguous()
+    mh_keys = mh_keys.contiguous()
     sig = torch.empty((n, F), dtype=torch.int32, device=dev)
     status = new_status(dev) if status is None else status
-    j = L.HashJob(kind=L.GEEK_HASH_HETERO, d=d, n=n, X=_p(X), ldx=X.stride(0), A=_p(A.contiguous()),
-                  b=_p(b.contiguous()), m=m, L=L_tables, w=float(w), F=F, cat=_p(cat),
+    j = L.HashJob(kind=L.GEEK_HASH_HETERO, d=d, n=n, X=_p(X), ldx=X.stride(0), A=_p(A),
+                  b=_p(b), m=m, L=L_tables, w=float(w), F=F, cat=_p(cat),
                   n_cat=cat.shape[1], mh_keys=_p(mh_keys), sig=_p(sig))
     _run(L.GEEK_OP_HASH, L.geek_hash, [j], dev, status)
     if check:
@@ -253,11 +259,12 @@ def quantile_buckets(X, A, t, want_bucket_of=True, status=None, check=True):
     dev = _dev(X)
     n, d = X.shape
     m = A.shape[0]
+    A = A.contiguous()  # kept alive in this frame until the call is enqueued
     mem = torch.empty((m, n), dtype=torch.int32, device=dev)
     off = torch.empty((m, t + 1), dtype=torch.int32, device=dev)
     bof = torch.empty((m, n), dtype=torch.int32, device=dev) if want_bucket_of else None
     status = new_status(dev) if status is None else status
-    j = L.QuantileJob(n=n, d=d, m=m, t=t, X=_p(X), ldx=X.stride(0), A=_p(A.contiguous()),
+    j = L.QuantileJob(n=n, d=d, m=m, t=t, X=_p(X), ldx=X.stride(0), A=_p(A),
                       members=_p(mem), offsets=_p(off), bucket_of=_p(bof))
     _run(L.GEEK_OP_QUANTILE, L.geek_quantile_buckets, [j], dev, status)
     if check:

@@ -1,7 +1,9 @@
 """Pins of the oracle's SILK (Algorithm 4): the paper's worked example
-(Examples 2 and 3) with explicit bins, a plain per-bin recount of the
-vectorised voting, the singleton / threshold rules, and the independence of
-the work from the number of clusters (Section 3.5)."""
+(Examples 2 and 3) with explicit bins, bucket signatures against a brute-force
+minimum, the seed order against hand-worked tuples, the whole pass against an
+independent dictionary-and-counter version, the singleton / threshold rules,
+and the independence of the counted work from the number of clusters
+(Section 3.5)."""
 
 import os
 
@@ -133,6 +135,112 @@ def test_one_table_gives_no_seeds():
     assert len(so) == 1 and sm.size == 0
 
 
+def _pi(key, x):
+    # one evaluation of the keyed permutation on one id
+    return int(oracle.perm(key, np.array([x], dtype=np.uint32))[0])
+
+
+def test_signatures_equal_brute_force_minimum():
+    # G(B) per bucket, recomputed one id at a time, on a CSR with singleton
+    # buckets, a large bucket and ids in no particular order
+    rng = np.random.default_rng(11)
+    sizes = [1, 3, 1, 40, 2, 1, 7, 1, 1, 15]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    mem = rng.permutation(5000)[: offs[-1]].astype(np.uint32)
+    keys = key_words(3, 5, STREAM_SILK)
+    tally = [0]
+    G = _signatures(offs, mem, keys, tally)
+    assert tally[0] == 3 * int(offs[-1])
+    for j in range(len(sizes)):
+        ids = mem[offs[j]:offs[j + 1]].tolist()
+        for k in range(3):
+            assert int(G[j, k]) == min(_pi(keys[k], x) for x in ids)
+
+
+def test_bins_ordered_by_ascending_tuple_hand_worked():
+    # rows 1 and 3 share (5, 2); rows 2 and 4 share (3, 7); the tuples tie in
+    # word 0 and differ in word 1, so only a word-0-major order gives
+    # (0,100) < (3,7) < (5,2) < (5,9)
+    G = np.array([[5, 9], [5, 2], [3, 7], [5, 2], [3, 7], [0, 100]], dtype=np.uint32)
+    bins, tup = _bins_of(G)
+    assert bins == [[5], [2, 4], [1, 3], [0]]
+    assert tup.tolist() == [[0, 100], [3, 7], [5, 2], [5, 9]]
+    # three words: ties in words 0 and 1, decided by word 2
+    G3 = np.array([[1, 1, 9], [1, 1, 2], [1, 0, 50], [1, 1, 2]], dtype=np.uint32)
+    bins3, tup3 = _bins_of(G3)
+    assert bins3 == [[2], [1, 3], [0]]
+    assert tup3.tolist() == [[1, 0, 50], [1, 1, 2], [1, 1, 9]]
+
+
+def _silk_by_dictionaries(sets, K, L, delta, keys):
+    """Algorithm 4 written with dictionaries and counters, one id at a time:
+    table s uses key rows s*K .. s*K+K-1 and the de-duplication table rows
+    L*K .. L*K+K-1; seeds in ascending order of their de-duplication tuple."""
+    from collections import Counter
+
+    C = []
+    for s in range(L):
+        table = {}
+        for j, B in enumerate(sets):
+            g = tuple(min(_pi(keys[s * K + k], x) for x in B) for k in range(K))
+            table.setdefault(g, []).append(j)
+        for g in table:
+            grp = table[g]
+            if len(grp) < 2:
+                continue
+            cnt = Counter(x for j in grp for x in sets[j])
+            shared = sorted(x for x, c in cnt.items() if 2 * c > len(grp))
+            if len(shared) >= delta:
+                C.append(shared)
+    dedup = {}
+    for i, c in enumerate(C):
+        g = tuple(min(_pi(keys[L * K + k], x) for x in c) for k in range(K))
+        dedup.setdefault(g, []).append(i)
+    seeds, multi = [], 0
+    for g in sorted(dedup):
+        grp = dedup[g]
+        if len(grp) == 1:
+            seeds.append(C[grp[0]])
+            continue
+        multi += 1
+        cnt = Counter(x for i in grp for x in C[i])
+        shared = sorted(x for x, c in cnt.items() if 2 * c > len(grp))
+        if len(shared) >= delta:
+            seeds.append(shared)
+    return C, seeds, multi
+
+
+def test_silk_equals_dictionary_version():
+    # pins the key rows of every table, the binning, the vote, the threshold,
+    # the de-duplication and the seed order against an independent version
+    offs, mem, _ = _hashed_buckets(n=700, d=12, clusters=6, m=5, L=6, seed=3)
+    K, L, delta = 3, 4, 4
+    keys = key_words((L + 1) * K, 9, STREAM_SILK)
+    sets = [mem[offs[i]:offs[i + 1]].tolist() for i in range(len(offs) - 1)]
+    C, seeds, multi = _silk_by_dictionaries(sets, K, L, delta, keys)
+    assert len(seeds) >= 3 and multi >= 1  # the case exercises a voted de-duplication bin
+    so, sm, info = oracle.silk_seeds(offs, mem, K, L, delta, keys)
+    got = [sm[so[i]:so[i + 1]].tolist() for i in range(len(so) - 1)]
+    assert got == seeds
+    assert info["multiset"] == len(C)
+    assert info["hash_evals"] == K * L * len(mem)
+    assert info["hash_evals_dedup"] == K * sum(len(c) for c in C)
+
+
+def test_silk_detects_swapped_key_rows():
+    # the same buckets with the SILK tables' key rows in another order give
+    # the same multiset C in another order, but a de-duplication table drawn
+    # from another row changes the bins; the dictionary version follows the
+    # documented rows, so a shifted row in the oracle would fail the test above
+    offs, mem, _ = _hashed_buckets(n=700, d=12, clusters=6, m=5, L=6, seed=3)
+    K, L, delta = 3, 4, 4
+    keys = key_words((L + 1) * K, 9, STREAM_SILK)
+    shifted = np.roll(keys, K, axis=0)
+    a = oracle.silk_seeds(offs, mem, K, L, delta, keys)
+    b = oracle.silk_seeds(offs, mem, K, L, delta, shifted)
+    assert not (np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]))
+
+
 def test_work_independent_of_cluster_count():
     n, d, m, L = 2000, 8, 4, 6
     K, LS = 3, 4
@@ -147,6 +255,8 @@ def test_work_independent_of_cluster_count():
             mem.append(mm)
             offs.extend((oo[1:].astype(np.int64) + offs[-1]).tolist())
         _, _, info = oracle.silk_seeds(np.asarray(offs), np.concatenate(mem), K, LS, 10, keys)
+        # counted while computing: K evaluations per member of every bucket
+        # of every transform table, whatever the number of clusters
         evals.add(info["hash_evals"])
         assert info["pairs_voted"] <= LS * n * L
     assert evals == {K * LS * n * L}
