@@ -16,13 +16,18 @@ the oracle follows Algorithm 4's steps in the paper's order.
 A further assignment pass (Section 4.3) regroups the objects by their
 assigned centre and assigns them again to the recomputed centroids.
 Quantile bucketing (Algorithm 1) ranks the objects by each QALSH value and
-splits the ranks evenly into t buckets.
+splits the ranks evenly into t buckets.  Densified one-permutation hashing
+(Algorithm 3's first step) reduces sets to D dimensions with one permutation
+and rotation densification.
 
 Pins (see ``tests/test_oracle_*.py``): exact rational arithmetic, closed forms
 (E2LSH collision probability, MinHash collision probability = Jaccard),
 published MurmurHash3 finalizer vectors, brute force on tiny inputs, the
-SILK worked example (Example 2), and for further passes the invariants that
-determine the regrouping plus Lloyd's monotone SSE and a hand-worked case.
+SILK worked example (Example 2) and an independent dictionary version of
+Algorithm 4, for further passes the invariants that determine the regrouping
+plus Lloyd's monotone SSE and a hand-worked case, and for DOPH hand-worked
+bins and densification, a plain per-bin loop, special sets and the
+collision rate = Jaccard.
 
 Parity unpinned: SILK's end-to-end seed sets on hashed inputs.  The paper's
 figures carry no coordinates, so only the worked example (explicit bins) and
@@ -53,3 +58,4 @@ from .assign import (  # noqa: F401
 )
 from .refine import assignment_pass, regroup  # noqa: F401
 from .quantile import qalsh_values, quantile_buckets  # noqa: F401
+from .doph import densify_rotation, doph_bin, doph_sets  # noqa: F401
