@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--clusters", type=int, default=10_000)
-    ap.add_argument("--cpu-rows", type=int, default=4096)
+    ap.add_argument("--cpu-rows", type=int, default=1024, help="oracle rows per CPU worker")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pipeline", type=int, default=0,
                     help="dense: bucketize the first half of the tables on a second stream while the second "
@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the installed tile shapes")
     ap.add_argument("--hetero-fp8", action="store_true", help="hetero: FP8 first pass instead of BF16")
+    ap.add_argument("--sets-hash", default="minhash", choices=["minhash", "doph"],
+                    help="sets: F = K*L MinHash functions per set, or DOPH to --doph-dims coordinates "
+                         "(bands and modes over the reduced rows)")
+    ap.add_argument("--doph-dims", type=int, default=400, help="sets with DOPH: reduced dimension D")
     return ap.parse_args()
 
 
@@ -239,7 +243,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(X, A, b, w, m, Lt, so, sm, a_bf16, args.cpu_rows, n, log)
+        cpu = cpu_baseline(X, A, b, w, m, Lt, so, sm, a_bf16, out_bf16["dist"], args.cpu_rows, n, log)
 
     stage_names = (("hash (bucketize of the first half overlapped)", "bucketize (second half)", "assign")
                    if args.pipeline else ("hash", "bucketize", "assign"))
@@ -282,33 +286,102 @@ def main():
     print(json.dumps(res))
 
 
-def cpu_baseline(X, A, b, w, m, Lt, so, sm, a_gpu, rows, n, log):
-    """The FP64 oracle on the first ``rows`` points of the same workload with
-    all k centroids (centroid cost prorated to the sample)."""
+_CPU_CTX = {}
+
+
+def _cpu_init(path):
+    """Pool initializer: the sample's shared inputs (projections, centroids)."""
+    import numpy as np
+
+    with np.load(path) as z:
+        _CPU_CTX.update({k: z[k] for k in z.files})
+
+
+def _cpu_task(Xs):
+    """One worker's share of the oracle run: E2LSH codes and buckets of its
+    rows, then their assignment to all centroids (float64, one thread)."""
     import numpy as np
 
     import oracle
 
-    Xs = X[:rows].cpu().numpy()
-    t0 = time.time()
-    codes = oracle.e2lsh_codes(Xs, A, b, w)
-    oracle.bucketize_tables(codes, m, Lt)
-    t_hb = time.time() - t0
+    c = _CPU_CTX
+    t0 = time.perf_counter()
+    codes = oracle.e2lsh_codes(Xs, c["A"], c["b"], float(c["w"]))
+    oracle.bucketize_tables(codes, int(c["m"]), int(c["L"]))
+    a, dist = oracle.assign_euclid(Xs, c["C"])
+    return a, dist, time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(X, A, b, w, m, Lt, so, sm, a_gpu, d_gpu, rows, n, log):
+    """The FP64 oracle on a bounded sample of the same workload, timed on the
+    host's cores: one worker process on ``rows`` points, then one worker per
+    core of the process's CPU share (at most 16) on ``rows`` points each,
+    started together; every worker hashes, buckets and assigns its own rows
+    against all k centroids (the centroid cost, measured once, is prorated to
+    the sample).  The oracle's arithmetic is unchanged; rows are split across
+    processes."""
+    import multiprocessing as mp
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    P = max(1, min(16, share))
+    Xh = X[:rows * (P + 1)].cpu().numpy()
     mem_rows = X[np.asarray(sm, dtype=np.int64)].cpu().numpy()
-    so_local = so.astype(np.int64)
-    t0 = time.time()
-    C = oracle.centroids(mem_rows, so_local, np.arange(len(sm), dtype=np.uint32))
-    t_c = time.time() - t0
-    t0 = time.time()
-    a, _ = oracle.assign_euclid(Xs, C)
-    t_a = time.time() - t0
-    agree = bool(np.array_equal(a, a_gpu[:rows].cpu().numpy()))
-    t = t_hb + t_a + t_c * rows / n
-    log(f"cpu oracle: {rows} rows hash+bucketize {t_hb:.1f}s assign {t_a:.1f}s centroids {t_c:.1f}s")
-    return {"value": rows / t, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {rows} of {n} points, all {len(so) - 1} centroids; centroid time "
-                      f"prorated by rows/n; numpy float64, single thread",
-            "seconds": t, "sample_assign_matches_gpu": agree}
+    t0 = time.perf_counter()
+    C = oracle.centroids(mem_rows, so.astype(np.int64), np.arange(len(sm), dtype=np.uint32))
+    t_c = time.perf_counter() - t0
+    fd, path = tempfile.mkstemp(suffix=".npz", dir="/tmp")
+    os.close(fd)
+    np.savez(path, A=A, b=b, w=np.float64(w), m=np.int64(m), L=np.int64(Lt), C=C)
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(P, initializer=_cpu_init, initargs=(path,)) as pool:
+            pool.map(_cpu_task, [Xh[:8]] * P)  # workers started and warm
+            t0 = time.perf_counter()
+            one = pool.map(_cpu_task, [Xh[:rows]])
+            t_one = time.perf_counter() - t0
+            parts = [Xh[rows * (q + 1):rows * (q + 2)] for q in range(P)]
+            t0 = time.perf_counter()
+            res = pool.map(_cpu_task, parts, chunksize=1)
+            t_all = time.perf_counter() - t0
+    finally:
+        os.unlink(path)
+    a_all = np.concatenate([one[0][0]] + [r[0] for r in res])
+    d_all = np.concatenate([one[0][1]] + [r[1] for r in res])
+    agree = bool(np.array_equal(a_all, a_gpu[:rows * (P + 1)].cpu().numpy()))
+    d_ref = d_gpu[:rows * (P + 1)].cpu().numpy()
+    sse_rel = abs(float(d_ref.sum()) - float(d_all.sum())) / max(float(d_all.sum()), 1e-300)
+    per_pt_c = t_c / n
+    v1 = rows / (t_one + per_pt_c * rows)
+    vP = rows * P / (t_all + per_pt_c * rows * P)
+    log(f"cpu oracle: 1 core {rows} rows {t_one:.1f}s; {P} cores {rows * P} rows {t_all:.1f}s; "
+        f"centroids {t_c:.1f}s")
+    return {"value": vP, "unit": "points/s", "cores": P, "kind": "oracle",
+            "sample": f"{rows} points per worker process (points {rows} .. {rows * (P + 1) - 1} of {n}), "
+                      f"{P} workers started together, each hashing, bucketing and assigning its rows to all "
+                      f"{len(so) - 1} centroids in numpy float64 (one thread each); centroid time prorated "
+                      f"by sample size / n",
+            "single_core": {"value": v1, "rows": rows, "seconds": t_one},
+            "seconds": t_all, "host": {"cpu_share": share, "nproc": os.cpu_count(), "model": _cpu_model()},
+            "sample_assign_matches_gpu": agree, "sample_sse_rel_err_vs_oracle": sse_rel}
 
 
 def _timed_graph(step, steps, warmup):
@@ -492,9 +565,17 @@ def bench_sets(args):
     cfg = CONFIGS["sets"]
     n = cfg["n"] if args.n == 10_000_000 else args.n
     K, Lb = cfg["K"], cfg["L"]
+    doph = args.sets_hash == "doph"
+    F = args.doph_dims if doph else K * Lb
+    assert F >= K * Lb, "the bands need K*L coordinates"
     t0 = time.time()
     off, tok, lab = sparse_sets(n, cfg["vocab"], cfg["clusters"], seed=0, device=dev)
-    mh = torch.from_numpy(key_words(K * Lb, 0, STREAM_MINHASH).view(np.int32)).to(dev)
+    mh = torch.from_numpy(key_words(1 if doph else K * Lb, 0, STREAM_MINHASH).view(np.int32)).to(dev)
+
+    def hash_fn(check):
+        if doph:
+            return api.hash_doph(off, tok, mh, F, status=status, check=check)
+        return api.hash_sets(off, tok, mh, status=status, check=check)
     so, sm = planted_seeds(lab, cfg["clusters"], 32)
     sog, smg = torch.from_numpy(so.view(np.int32)).to(dev), torch.from_numpy(sm.view(np.int32)).to(dev)
     k = len(so) - 1
@@ -504,36 +585,58 @@ def bench_sets(args):
     status = api.new_status(dev)
 
     def step(check):
-        sig = api.hash_sets(off, tok, mh, status=status, check=check)
-        bz = api.bucketize(sig, n, Lb, K, K, K * Lb, status=status, check=check)
+        sig = hash_fn(check)
+        bz = api.bucketize(sig, n, Lb, K, K, F, status=status, check=check)
         out = api.assign_sig(sig, sog, smg, k, status=status, check=check)
         return sig, bz, out
 
     ms, (sig, bz, out) = _timed_graph(step, args.steps, args.warmup)
     api.check_status(status, "graph replays")
-    # stage times (eager, events)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # stage times (eager, events; the hash and the assignment over a few
+    # launches each)
+    reps = 5
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
     ev[0].record()
-    sig2 = api.hash_sets(off, tok, mh, status=status, check=False)
+    for _ in range(reps):
+        sig2 = hash_fn(False)
     ev[1].record()
-    api.bucketize(sig2, n, Lb, K, K, K * Lb, status=status, check=False)
+    api.bucketize(sig2, n, Lb, K, K, F, status=status, check=False)
     ev[2].record()
-    api.assign_sig(sig2, sog, smg, k, status=status, check=False)
     ev[3].record()
+    for _ in range(2):
+        api.assign_sig(sig2, sog, smg, k, status=status, check=False)
+    ev[4].record()
     torch.cuda.synchronize()
-    stages = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    t_hash = ev[0].elapsed_time(ev[1]) / reps
+    t_bz = ev[1].elapsed_time(ev[2])
+    t_as = ev[3].elapsed_time(ev[4]) / 2
+    api.check_status(status, "stage runs")
+    # roofline of the dominant kernel, the signature assignment: one exact
+    # 32-bit compare-and-count per (set, seed, coordinate), two VALU lane
+    # operations each, against the chip's integer VALU rate
+    peak_alu = 256 * 64 * 2.4e9 / 2 / 1e12  # Tcompares/s
+    compares = float(n) * k * F
+    hash_bytes = nnz * 4 + (n + 1) * 8 + n * F * 4  # tokens + offsets read, rows written
+    name = f"DOPH D={F}" if doph else f"MinHash K={K} x L={Lb}"
     line = {
-        "metric": "sets/s (MinHash+bucketize+assign), sparse sets",
+        "metric": f"sets/s ({'DOPH' if doph else 'MinHash'}+bucketize+assign), sparse sets",
         "value": n / (ms * 1e-3), "unit": "sets/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"sets: n={n} sets, {nnz} tokens over a {cfg['vocab']}-token vocabulary, "
-                               f"{cfg['clusters']} planted clusters, MinHash K={K} x L={Lb}, k={k} planted seeds",
-                   "n": n, "nnz": nnz, "k": k},
-        "stages_ms": {"minhash": stages[0], "bucketize": stages[1], "assign": stages[2]},
-        "minhash_evals_per_s": nnz * K * Lb / (stages[0] * 1e-3),
+                               f"{cfg['clusters']} planted clusters, {name}, bands K={K} x L={Lb}, "
+                               f"k={k} planted seeds",
+                   "n": n, "nnz": nnz, "k": k, "F": F, "hash": args.sets_hash},
+        "roofline": {"bound": "alu", "achieved": compares / (t_as * 1e-3) / 1e12, "peak": peak_alu,
+                     "unit": "Tcompare/s", "frac": compares / (t_as * 1e-3) / 1e12 / peak_alu, "traffic": None,
+                     "kernel": "signature assignment (k_sig_dense)", "avg_launch_ms": t_as},
+        "stages_ms": {("doph" if doph else "minhash"): t_hash, "bucketize": t_bz, "assign": t_as},
+        "hash_hbm_gbs": hash_bytes / (t_hash * 1e-3) / 1e9,
+        "hash_hbm_frac": hash_bytes / (t_hash * 1e-3) / 8e12,
         "assign_counters": out["counters"].cpu().numpy().tolist(),
     }
+    if not doph:
+        line["minhash_evals_per_s"] = nnz * K * Lb / (t_hash * 1e-3)
     print(json.dumps(line), flush=True)
 
 

@@ -32,12 +32,11 @@
  *   ``geek_workspace_size`` returns for the same jobs, a device status word
  *   ``d_status`` (int32, device) and a HIP stream (``hipStream_t`` passed as
  *   ``void*``; NULL = the default stream).
- * - Calls are stream-ordered and return without waiting for the GPU, except
- *   ``geek_silk_seeds``, which synchronizes ``stream`` internally because the
- *   sizes of its intermediate collections are only known on the device.
- *   ``geek_hash``, ``geek_bucketize``, ``geek_assign``, ``geek_regroup`` and
- *   ``geek_quantile_buckets`` perform no host
- *   synchronization and no device allocation.
+ * - Calls are stream-ordered and return without waiting for the GPU: no
+ *   call performs a host synchronization or a device allocation, so every
+ *   call can be captured in a HIP graph.  Sizes that only the device knows
+ *   (the number of buckets, SILK's intermediate collections) are read by the
+ *   kernels from device memory; launches are sized by host upper bounds.
  * - Host-detectable errors (bad arguments, workspace too small, unsupported
  *   sizes, launch failure) return a negative status at once and enqueue no
  *   work.  Data-dependent errors (non-finite input, a hash code outside the
@@ -110,6 +109,23 @@ extern "C" {
 #define GEEK_HASH_DENSE 0
 #define GEEK_HASH_SETS 1
 #define GEEK_HASH_HETERO 2
+/* GEEK_HASH_DOPH: densified one-permutation hashing of sets, the dimension
+ *   reduction that Algorithm 3 applies first (Section 3.1, Sparse Data;
+ *   Section 3.3 represents sets by the reduced dimensions; Section 4.1
+ *   reduces URL to 400).  With pi(t) = (a * fmix32(t) + b) mod 2^32,
+ *   a = mh_keys[0][0] | 1, b = mh_keys[0][1] (one permutation, so mh_keys
+ *   holds one key pair), the permuted values of set i fall into D = F equal
+ *   ranges of [0, 2^32): value v lies in bin floor(v * D / 2^32).
+ *   sig[i][j] = the smallest permuted value of the set in bin j; an empty bin
+ *   takes the value of the first non-empty bin to its right, cyclically
+ *   (rotation densification, Shrivastava and Li, ICML 2014).  Every
+ *   coordinate collides for two sets with probability equal to their
+ *   Jaccard similarity, so the D coordinates serve as the MinHash values of
+ *   the (K, L) bands (band b = coordinates b*K .. b*K+K-1) and as the set's
+ *   reduced representation for modes.  1 <= F <= 4096.  Fields used:
+ *   n, offsets, tokens, mh_keys, F, sig [n][F].  An empty set sets
+ *   GEEK_ERR_EMPTY_SET (the row is then unspecified). */
+#define GEEK_HASH_DOPH 3
 
 typedef struct geek_hash_job {
   int32_t kind;             /* GEEK_HASH_* */
@@ -177,8 +193,15 @@ typedef struct geek_bucketize_job {
  * majority-voted and delta-filtered.  Seeds are ordered by the ascending
  * lexicographic K-tuple of their de-duplication bin, members ascending.
  * Output CSR: seed j = seed_members[seed_offsets[j] .. seed_offsets[j+1]).
- * If the capacities are too small, *needed = {seeds, members} and
- * GEEK_ERR_CAPACITY is set; no seed sets GEEK_ERR_NO_SEEDS.
+ * A bin contributes only a non-empty C_shared (delta < 1 acts as delta = 1).
+ * The intermediate multiset C is held in the workspace with room for
+ * 4 * cap_members sets and 4 * cap_members members.  If C or the outputs do
+ * not fit, *needed = {seeds, members} (for C: the cap_k and cap_members that
+ * make it fit) and GEEK_ERR_CAPACITY is set (outputs unspecified); no seed
+ * sets GEEK_ERR_NO_SEEDS.  The call never reads sizes back to the host.
+ * Requires 1 <= T <= 128 (GEEK_ERR_UNSUPPORTED above), T * n < 2^31 and
+ * 4 * cap_members < 2^31.  The workspace grows with T * n (about 100 bytes
+ * per (table, object)) and with cap_members (about 140 bytes each).
  */
 typedef struct geek_silk_job {
   int64_t n;                /* objects */

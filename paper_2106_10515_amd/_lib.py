@@ -24,7 +24,7 @@ GEEK_ERR_CAPACITY = 3
 GEEK_ERR_NO_SEEDS = 4
 GEEK_ERR_EMPTY_SET = 5
 
-GEEK_HASH_DENSE, GEEK_HASH_SETS, GEEK_HASH_HETERO = 0, 1, 2
+GEEK_HASH_DENSE, GEEK_HASH_SETS, GEEK_HASH_HETERO, GEEK_HASH_DOPH = 0, 1, 2, 3
 GEEK_METRIC_EUCLID, GEEK_METRIC_SIG, GEEK_METRIC_HETERO = 0, 1, 2
 GEEK_PREC_FP32, GEEK_PREC_BF16, GEEK_PREC_FP8 = 0, 1, 2
 GEEK_OP_HASH, GEEK_OP_BUCKETIZE, GEEK_OP_SILK, GEEK_OP_ASSIGN, GEEK_OP_REGROUP = 0, 1, 2, 3, 4

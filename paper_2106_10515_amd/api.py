@@ -122,6 +122,22 @@ def hash_sets(offsets, tokens, mh_keys, status=None, check=True):
     return sig
 
 
+def hash_doph(offsets, tokens, key, D, status=None, check=True):
+    """Densified one-permutation hashing of sets into D coordinates (one key
+    pair ``key`` [1, 2] or [2]).  Returns ``sig int32 [n, D]``."""
+    dev = _dev(tokens)
+    n = offsets.numel() - 1
+    key = key.reshape(-1).contiguous()
+    sig = torch.empty((n, D), dtype=torch.int32, device=dev)
+    status = new_status(dev) if status is None else status
+    j = L.HashJob(kind=L.GEEK_HASH_DOPH, n=n, F=D, offsets=_p(offsets), tokens=_p(tokens),
+                  mh_keys=_p(key), sig=_p(sig))
+    _run(L.GEEK_OP_HASH, L.geek_hash, [j], dev, status)
+    if check:
+        check_status(status, "geek_hash (DOPH)")
+    return sig
+
+
 def hash_hetero(X, cat, A, b, m, L_tables, w, mh_keys, status=None, check=True):
     """MinHash signatures of heterogeneous rows (numeric attributes turned
     into E2LSH code tokens).  Returns ``sig int32 [n, F]``."""
@@ -188,39 +204,55 @@ def bucketize_batch(problems, want_bucket_of=True, status=None, check=True):
 
 
 # ---------------------------------------------------------------- geek_silk_seeds
+def silk_seeds_async(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys, cap_k, cap_members,
+                     status):
+    """One geek_silk_seeds call with the given capacities; nothing is read
+    back to the host, so it may be recorded in a HIP graph.  Returns the
+    untrimmed device outputs ``dict(seed_offsets [cap_k+1], seed_members
+    [cap_members], k_out [1], needed [2], counters [4])``."""
+    dev = _dev(members)
+    out = dict(seed_offsets=torch.empty((cap_k + 1,), dtype=torch.int32, device=dev),
+               seed_members=torch.empty((cap_members,), dtype=torch.int32, device=dev),
+               k_out=torch.empty((1,), dtype=torch.int32, device=dev),
+               needed=torch.empty((2,), dtype=torch.int64, device=dev),
+               counters=torch.empty((4,), dtype=torch.int64, device=dev))
+    j = L.SilkJob(n=n, T=T, K=K, members=_p(members), offsets=_p(offsets), nbuckets=_p(nbuckets),
+                  L=L_silk, delta=delta, silk_keys=_p(silk_keys), cap_k=cap_k,
+                  cap_members=cap_members, seed_offsets=_p(out["seed_offsets"]),
+                  seed_members=_p(out["seed_members"]), k_out=_p(out["k_out"]), needed=_p(out["needed"]),
+                  counters=_p(out["counters"]))
+    _run(L.GEEK_OP_SILK, L.geek_silk_seeds, [j], dev, status)
+    return out
+
+
 def silk_seeds(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys,
                cap_k=None, cap_members=None, status=None, check=True):
     """SILK seeds.  Returns ``(seed_offsets [k+1], seed_members [N_C],
-    counters [4])`` trimmed to the k seeds found."""
+    counters [4])`` trimmed to the k seeds found (reads k back to the host;
+    with the default capacities a call that reports too little room is
+    repeated with the capacities it asked for)."""
     dev = _dev(members)
     auto = cap_k is None and cap_members is None
     cap_k = cap_k or max(1024, n // 4)
     cap_members = cap_members or max(4096, 2 * n)
     status = new_status(dev) if status is None else status
     for attempt in range(4):
-        so = torch.empty((cap_k + 1,), dtype=torch.int32, device=dev)
-        sm = torch.empty((cap_members,), dtype=torch.int32, device=dev)
-        k_out = torch.zeros((1,), dtype=torch.int32, device=dev)
-        needed = torch.zeros((2,), dtype=torch.int64, device=dev)
-        ctr = torch.zeros((4,), dtype=torch.int64, device=dev)
-        j = L.SilkJob(n=n, T=T, K=K, members=_p(members), offsets=_p(offsets), nbuckets=_p(nbuckets),
-                      L=L_silk, delta=delta, silk_keys=_p(silk_keys), cap_k=cap_k,
-                      cap_members=cap_members, seed_offsets=_p(so), seed_members=_p(sm),
-                      k_out=_p(k_out), needed=_p(needed), counters=_p(ctr))
-        _run(L.GEEK_OP_SILK, L.geek_silk_seeds, [j], dev, status)
+        out = silk_seeds_async(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys, cap_k,
+                               cap_members, status)
         # default capacities too small: the call reported what it needs (first
         # for the intermediate multiset, then for the seeds); call again
         if auto and attempt < 3 and int(status.item()) == L.GEEK_ERR_CAPACITY:
-            nk, nm = (int(v) for v in needed.cpu().tolist())
+            nk, nm = (int(v) for v in out["needed"].cpu().tolist())
             cap_k, cap_members = max(cap_k, nk), max(cap_members, nm)
             status.zero_()
             continue
         break
     if check:
         check_status(status, "geek_silk_seeds")
-    k = int(k_out.item())
+    so, sm = out["seed_offsets"], out["seed_members"]
+    k = int(out["k_out"].item())
     nm = int(so[k].item()) if k > 0 else 0
-    return so[:k + 1], sm[:nm], ctr
+    return so[:k + 1], sm[:nm], out["counters"]
 
 
 # ---------------------------------------------------------------- geek_assign

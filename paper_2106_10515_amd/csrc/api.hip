@@ -18,6 +18,7 @@ size_t bucketize_ws(const geek_bucketize_job& J);
 int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, int32_t* st,
                       hipStream_t s);
 size_t silk_ws(const geek_silk_job& J);
+int32_t silk_check(const geek_silk_job& J);
 int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s);
 size_t assign_euclid_ws(const geek_assign_job& J);
 int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32_t* st,
@@ -137,6 +138,10 @@ static int32_t check_hash(const geek_hash_job& J) {
   if (J.kind == GEEK_HASH_DENSE) {
     if (J.m > 32) return GEEK_ERR_UNSUPPORTED;  // at least 4 bits per packed code
     if (J.n > 0 && (!J.keys || !al16(J.keys))) return GEEK_ERR_ARG;
+  } else if (J.kind == GEEK_HASH_DOPH) {
+    if (J.F < 1 || !J.mh_keys) return GEEK_ERR_ARG;
+    if (J.F > 4096) return GEEK_ERR_UNSUPPORTED;
+    if (J.n > 0 && (!J.sig || !J.offsets || !J.tokens)) return GEEK_ERR_ARG;
   } else if (J.kind == GEEK_HASH_SETS || J.kind == GEEK_HASH_HETERO) {
     if (J.F < 1 || !J.mh_keys) return GEEK_ERR_ARG;
     if (J.F > 512) return GEEK_ERR_UNSUPPORTED;
@@ -297,6 +302,7 @@ int32_t geek_workspace_size(int32_t op, const void* jobs, int32_t njobs, size_t*
       }
       case GEEK_OP_SILK: {
         const geek_silk_job& J = static_cast<const geek_silk_job*>(jobs)[j];
+        if (int32_t rc = silk_check(J)) return rc;
         b = silk_ws(J);
         break;
       }

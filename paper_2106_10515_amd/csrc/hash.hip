@@ -428,6 +428,66 @@ __global__ __launch_bounds__(256) void k_minhash_hetero(const int32_t* __restric
   minhash_row<FPL>(i, n_cat + P, tok, mh_keys, F, sig);
 }
 
+// ---------------------------------------------------------------- DOPH
+// Densified one-permutation hashing (Algorithm 3's first step, after
+// Shrivastava and Li, ICML 2014): one keyed permutation pi of the 32-bit
+// token universe, D equal ranges of [0, 2^32) (value v lies in bin
+// floor(v * D / 2^32)), the smallest permuted value of the set in every bin,
+// and rotation densification: an empty bin takes the value of the first
+// non-empty bin to its right, cyclically.  A value names its own bin, so the
+// borrowed values of different distances never coincide.
+//
+// One wavefront per set: the lanes hash the set's tokens (one permutation
+// each) into a private LDS row of D minima plus an occupancy bit per bin
+// (LDS min / or atomics), then lane-strided over the bins each lane finds the
+// source bin from the occupancy words and writes the row (consecutive lanes,
+// consecutive words).
+
+__global__ __launch_bounds__(256) void k_doph(const int64_t* __restrict__ offsets,
+                                              const uint32_t* __restrict__ tokens, int64_t n,
+                                              const uint32_t* __restrict__ key, int D,
+                                              uint32_t* __restrict__ sig, int32_t* st) {
+  extern __shared__ uint32_t doph_lds[];
+  const int nw = (D + 31) >> 5;
+  const int stride = D + nw;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t* mins = doph_lds + wv * stride;
+  uint32_t* occ = mins + D;
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+  if (i >= n) return;  // the wave's LDS row is its own: no block barrier below
+  const int64_t s = offsets[i], e = offsets[i + 1];
+  if (e <= s) {
+    set_status(st, GEEK_ERR_EMPTY_SET);
+    return;
+  }
+  for (int j = lane; j < D; j += 64) mins[j] = 0xFFFFFFFFu;
+  for (int j = lane; j < nw; j += 64) occ[j] = 0u;
+  // lanes of one wave share the row: order the LDS accesses of the phases
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t a = key[0] | 1u, b = key[1];
+  const uint64_t Du = (uint64_t)D;
+  for (int64_t q = s + lane; q < e; q += 64) {
+    const uint32_t v = perm_premixed(a, b, fmix32(tokens[q]));
+    const uint32_t bin = (uint32_t)(((uint64_t)v * Du) >> 32);
+    atomicMin(&mins[bin], v);
+    atomicOr(&occ[bin >> 5], 1u << (bin & 31u));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  uint32_t* out = sig + i * (int64_t)D;
+  for (int j = lane; j < D; j += 64) {
+    int w = j >> 5;
+    uint32_t m = occ[w] & (0xFFFFFFFFu << (j & 31));
+    // the set is non-empty, so some word has a bit: at most nw + 1 steps
+    while (m == 0u) {
+      w = (w + 1 == nw) ? 0 : w + 1;
+      m = occ[w];
+    }
+    out[j] = mins[(w << 5) + __builtin_ctz(m)];
+  }
+}
+
 // ---------------------------------------------------------------- host side
 static int pick_dp_h(int d) { return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : d <= 256 ? 256 : 0; }
 
@@ -484,6 +544,13 @@ int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st,
   int32_t rc = GEEK_OK;
   if (J.kind == GEEK_HASH_DENSE) {
     rc = launch_e2lsh(J, anorm, J.keys, J.codes, J.n_fixup, st, s);
+  } else if (J.kind == GEEK_HASH_DOPH) {
+    if (J.n == 0) return GEEK_OK;
+    const size_t lds = sizeof(uint32_t) * 4 * (size_t)(J.F + (J.F + 31) / 32);
+    prof_begin(GEEK_PROF_MINHASH, s);
+    hipLaunchKernelGGL(k_doph, dim3(ceil_div(J.n, 4)), dim3(256), lds, s, J.offsets, J.tokens, J.n, J.mh_keys,
+                       J.F, J.sig, st);
+    prof_end(GEEK_PROF_MINHASH, s);
   } else if (J.kind == GEEK_HASH_SETS) {
     if (J.n == 0) return GEEK_OK;
     prof_begin(GEEK_PROF_MINHASH, s);

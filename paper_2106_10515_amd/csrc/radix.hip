@@ -41,9 +41,19 @@ __device__ uint32_t blk_exscan(uint32_t v, uint32_t* total, uint32_t* sh) {
   return res;
 }
 
+// Element count of a device-count call: *n_dev (when given) bounded by the
+// host bound n that sized the grid.
+GEEK_D int64_t dev_count(int64_t n, const uint32_t* n_dev) {
+  if (!n_dev) return n;
+  const int64_t v = (int64_t)*n_dev;
+  return v < n ? v : n;
+}
+
 __global__ __launch_bounds__(GS_THREADS) void k_gs_reduce(const uint32_t* __restrict__ in, int64_t n,
+                                                          const uint32_t* __restrict__ n_dev,
                                                           uint32_t* __restrict__ ctot) {
   __shared__ uint32_t sh[17];
+  n = dev_count(n, n_dev);
   const int64_t s = (int64_t)blockIdx.x * GS_CHUNK + threadIdx.x * GS_PER;
   uint32_t a = 0;
 #pragma unroll
@@ -75,9 +85,12 @@ __global__ __launch_bounds__(1024) void k_gs_scan_tot(uint32_t* ctot, int nch, u
 }
 
 __global__ __launch_bounds__(GS_THREADS) void k_gs_apply(const uint32_t* __restrict__ in, int64_t n,
+                                                         const uint32_t* __restrict__ n_dev,
                                                          const uint32_t* __restrict__ ctot,
                                                          uint32_t* __restrict__ out) {
   __shared__ uint32_t sh[17];
+  n = dev_count(n, n_dev);
+  if ((int64_t)blockIdx.x * GS_CHUNK >= n) return;  // uniform: the chunk lies past the count
   const int64_t s = (int64_t)blockIdx.x * GS_CHUNK + threadIdx.x * GS_PER;
   uint32_t v[GS_PER];
   uint32_t a = 0;
@@ -96,16 +109,21 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_apply(const uint32_t* __restr
 
 size_t exscan_tmp_words(int64_t n) { return (size_t)((n + GS_CHUNK - 1) / GS_CHUNK) + 1; }
 
-void exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
-                hipStream_t s) {
+void exscan_u32_dn(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev, uint32_t* tmp,
+                   uint32_t* total, hipStream_t s) {
   const int nch = (int)((n + GS_CHUNK - 1) / GS_CHUNK);
   if (nch == 0) {
     hipLaunchKernelGGL(k_gs_scan_tot, dim3(1), dim3(1024), 0, s, tmp, 0, total);
     return;
   }
-  hipLaunchKernelGGL(k_gs_reduce, dim3(nch), dim3(GS_THREADS), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(k_gs_reduce, dim3(nch), dim3(GS_THREADS), 0, s, in, n, n_dev, tmp);
   hipLaunchKernelGGL(k_gs_scan_tot, dim3(1), dim3(1024), 0, s, tmp, nch, total);
-  hipLaunchKernelGGL(k_gs_apply, dim3(nch), dim3(GS_THREADS), 0, s, in, n, tmp, out);
+  hipLaunchKernelGGL(k_gs_apply, dim3(nch), dim3(GS_THREADS), 0, s, in, n, n_dev, tmp, out);
+}
+
+void exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, uint32_t* total,
+                hipStream_t s) {
+  exscan_u32_dn(in, out, n, nullptr, tmp, total, s);
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -114,8 +132,10 @@ constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ kw, int64_t n,
-                                                        int shift, uint32_t* __restrict__ hist, int nblk) {
+                                                        const uint32_t* __restrict__ n_dev, int shift,
+                                                        uint32_t* __restrict__ hist, int nblk) {
   __shared__ uint32_t h[256];
+  n = dev_count(n, n_dev);
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t s = (int64_t)blockIdx.x * RS_TILE;
@@ -134,8 +154,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restri
 // digit counts come from the scanned histogram (the next entry of the
 // flattened [digit][tile] scan, or n for the last).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(RsView in, RsView out, int W, int64_t n,
-                                                           int word, int shift,
-                                                           const uint32_t* __restrict__ hist, int nblk) {
+                                                           const uint32_t* __restrict__ n_dev, int word,
+                                                           int shift, const uint32_t* __restrict__ hist,
+                                                           int nblk) {
+  n = dev_count(n, n_dev);
+  if ((int64_t)blockIdx.x * RS_TILE >= n) return;  // uniform: the tile lies past the count
   extern __shared__ uint32_t rs_stage[];  // [W (+1 with a payload)][RS_TILE]
   __shared__ uint32_t gstart[256], lstart[256], lrun[256];
   __shared__ uint32_t wcnt[RS_THREADS / 64][256];
@@ -214,18 +237,23 @@ size_t radix_tmp_words(int64_t n) {
 // Returns 1 if the sorted data ended in `alt`, 0 if in `buf`.
 int radix_sort(RsView buf, RsView alt, int W, int64_t n, const int* words, const int* shifts, int npass,
                uint32_t* tmp, hipStream_t s) {
+  return radix_sort_dn(buf, alt, W, n, nullptr, words, shifts, npass, tmp, s);
+}
+
+int radix_sort_dn(RsView buf, RsView alt, int W, int64_t n, const uint32_t* n_dev, const int* words,
+                  const int* shifts, int npass, uint32_t* tmp, hipStream_t s) {
   if (n <= 0 || npass == 0) return 0;
   const int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
   uint32_t* hist = tmp;
   uint32_t* stmp = tmp + (size_t)256 * nblk;
   RsView a = buf, b = alt;
   for (int p = 0; p < npass; ++p) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, s, a.k[words[p]], n, shifts[p], hist,
-                       nblk);
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, s, a.k[words[p]], n, n_dev, shifts[p],
+                       hist, nblk);
     exscan_u32(hist, hist, (int64_t)256 * nblk, stmp, nullptr, s);
     const size_t stage = sizeof(uint32_t) * RS_TILE * (size_t)(W + (a.v ? 1 : 0));
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), stage, s, a, b, W, n, words[p], shifts[p],
-                       hist, nblk);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), stage, s, a, b, W, n, n_dev, words[p],
+                       shifts[p], hist, nblk);
     RsView t = a;
     a = b;
     b = t;

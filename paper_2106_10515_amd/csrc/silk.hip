@@ -1,18 +1,31 @@
-// SILK seeding (paper Section 3.2, Algorithm 4) on gfx950.
+// SILK seeding (paper Section 3.2, Algorithm 4) on gfx950.  Every
+// intermediate size stays on the device: kernels read their counts from
+// device words and launches are sized by host upper bounds, so the call
+// never waits for the GPU and can be captured in a HIP graph.
 //
-// For each SILK table s:
-//   k_sig / k_sig_big   G(B) = (min_{x in B} pi_k(x))_k for every bucket
-//   bucketize_run       bins = buckets with identical G
-//   k_pair_count        pairs (bin, id) of the buckets of bins with >= 2 buckets
-//   radix_sort          sort the pairs by (bin, id)
-//   k_runs / k_keep     count each (bin, id); keep it when 2*count > |Bin|
-//   k_seg_*             C_shared per bin; append it to C when |C_shared| >= delta
-// De-duplication: the same steps once more over the sets of C (one table,
-// key rows L*K..), a bin holding a single set passes it through; bins are
-// then ordered by their K-tuple (radix sort) and emitted as the seeds.
-//
-// The sizes of the intermediate collections are only known on the device,
-// so the host reads them back between steps (the call synchronizes).
+// Once per call:
+//   k_silk_setup      global bucket ids (tables one after another), sizes of
+//                     the open-addressing table, zeroed counters
+//   k_extent          start and size of every bucket in the member array
+//   k_mark_starts, scan, k_bucket_of   the global bucket of every (table, object)
+// For each SILK table:
+//   k_sig / k_sig_big G(B) = (min_{x in B} pi_k(x))_k for every bucket, with the
+//                     hash evaluations counted as they are made
+//   k_ht_*            bins = buckets with identical G: an open-addressing table
+//                     on the exact G; a bin is named by its smallest bucket id
+//   k_vote            per object, over its T buckets: the bins of two or more
+//                     buckets in which it lies in more than half of the buckets.
+//                     The buckets of one table are disjoint, so an object lies
+//                     in exactly one bucket per table and its count in a bin is
+//                     the number of those T buckets that the bin holds.
+//   k_emit_flags, scans, k_commit   C_shared sizes, delta, room left in C
+//   k_count_kept, scan, k_kept_pairs, radix sort by bin, k_c_write
+//                     the new sets of C, ids ascending
+// De-duplication (one more table over the sets of C): sets sorted by their
+// K-tuple (radix sort) so that runs of equal tuples are the bins, in
+// ascending lexicographic order; a bin of one set passes it through, a bin of
+// several sets is majority-voted ((bin, id) pairs sorted and counted) and
+// delta-filtered; the seeds are written in bin order.
 #include <vector>
 
 #include "common.hpp"
@@ -20,78 +33,139 @@
 
 namespace geek {
 
-size_t bucketize_ws(const geek_bucketize_job& J);
-int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, int32_t* st,
-                      hipStream_t s);
+constexpr int SK_BIG = 64;       // buckets larger than this are hashed by a block
+constexpr int SG_GRID = 2048;    // blocks of the grid-stride kernels
+constexpr int SV_LDS = 8192;     // LDS entries (two words each) of a vote block
+constexpr int SILK_MAX_T = 128;  // transform tables the vote kernel holds in LDS
 
-constexpr int SK_BIG = 64;  // buckets larger than this are hashed by a block
+// Device-side sizes and counters of one call.
+struct SilkState {
+  unsigned long long hash_evals, pairs, multi, need_s, need_m;
+  uint32_t nb;       // buckets of all tables
+  uint32_t ht_mask;  // open-addressing table: mask + 1 slots in use
+  uint32_t big;      // buckets queued for k_sig_big
+  uint32_t es, em;   // this table's emitted sets / members
+  uint32_t kp;       // this table's kept (bin, id) pairs of emitted bins
+  uint32_t cs, cm;   // sets / members of C committed so far
+  uint32_t over;     // C ran out of room
+  uint32_t fit;      // this table's sets are written to C
+  uint32_t base_s, base_m;
+  // de-duplication
+  uint32_t nb2, P2, R2, kept2, k, tot_m, fit_out;
+};
 
-__global__ void k_tab_base(const uint32_t* nb, int T, uint32_t* base) {
+GEEK_D uint32_t gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
+GEEK_D uint32_t gstride() { return gridDim.x * blockDim.x; }
+
+// Block sum of one 64-bit value per thread, added to *dst by one thread.
+GEEK_D void block_add(unsigned long long v, unsigned long long* dst) {
+  __shared__ unsigned long long red[16];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) t += red[w];
+    if (t) atomicAdd(dst, t);
+  }
+}
+
+__global__ void k_silk_setup(const uint32_t* __restrict__ nbuckets, int T, int64_t n, uint32_t* __restrict__ base,
+                             SilkState* S) {
   if (blockIdx.x || threadIdx.x) return;
   uint32_t r = 0;
   for (int t = 0; t < T; ++t) {
     base[t] = r;
-    r += nb[t];
+    const uint32_t v = nbuckets[t];
+    r += v < (uint32_t)n ? v : (uint32_t)n;
   }
   base[T] = r;
+  uint32_t slots = 1024;
+  while (slots < 2u * r && slots < 0x80000000u) slots <<= 1;
+  *S = SilkState{};
+  S->nb = r;
+  S->ht_mask = slots - 1;
 }
 
-// Global extent of every bucket of every table: start position in the
-// flattened member array and size.
-__global__ void k_extent(const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ base, int T,
-                         int64_t n, int64_t NB, uint32_t* __restrict__ gstart,
-                         uint32_t* __restrict__ gsize) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= NB) return;
-  int lo = 0, hi = T;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (base[mid] <= (uint32_t)g) lo = mid; else hi = mid;
+// Start (in the flattened [T][n] member array) and size of every bucket.
+__global__ void k_extent(const uint32_t* __restrict__ offsets, const uint32_t* __restrict__ base, int T, int64_t n,
+                         const SilkState* S, uint32_t* __restrict__ gstart, uint32_t* __restrict__ gsize) {
+  const uint32_t NB = S->nb;
+  for (uint32_t g = gtid(); g < NB; g += gstride()) {
+    int lo = 0, hi = T;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (base[mid] <= g) lo = mid; else hi = mid;
+    }
+    const uint32_t j = g - base[lo];
+    const uint32_t o = offsets[(int64_t)lo * (n + 1) + j], e = offsets[(int64_t)lo * (n + 1) + j + 1];
+    gstart[g] = (uint32_t)((int64_t)lo * n + o);
+    gsize[g] = e - o;
   }
-  const uint32_t j = (uint32_t)g - base[lo];
-  const uint32_t o = offsets[(int64_t)lo * (n + 1) + j], e = offsets[(int64_t)lo * (n + 1) + j + 1];
-  gstart[g] = (uint32_t)((int64_t)lo * n + o);
-  gsize[g] = e - o;
 }
 
-__global__ void k_set_extent(const uint32_t* __restrict__ off, int64_t ns, uint32_t* __restrict__ gstart,
-                             uint32_t* __restrict__ gsize) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= ns) return;
-  gstart[g] = off[g];
-  gsize[g] = off[g + 1] - off[g];
+__global__ void k_sk_fill(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
 }
 
-// Signature of every set (thread per set); large sets go to k_sig_big.
-__global__ void k_sig(const uint32_t* __restrict__ mem, const uint32_t* __restrict__ gstart,
-                      const uint32_t* __restrict__ gsize, int64_t ns, const uint32_t* __restrict__ keys,
-                      int K, uint32_t* __restrict__ G, uint32_t* big_list, uint32_t* big_count) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= ns) return;
-  const uint32_t sz = gsize[g];
-  if (sz > SK_BIG) {
-    big_list[atomicAdd(big_count, 1u)] = (uint32_t)g;
-    return;
+__global__ void k_mark_starts(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ count,
+                              uint32_t* __restrict__ flag) {
+  const uint32_t ns = *count;
+  for (uint32_t g = gtid(); g < ns; g += gstride()) flag[gstart[g]] = 1u;
+}
+
+// Position q of the flattened member array lies in bucket fscan[q] + flag[q]
+// - 1 (buckets are numbered in member-array order); its object's entry of
+// table q / n gets that bucket.
+__global__ void k_bucket_of(const uint32_t* __restrict__ members, int64_t Tn, int64_t n,
+                            const uint32_t* __restrict__ flag, const uint32_t* __restrict__ fscan,
+                            uint32_t* __restrict__ bof) {
+  for (int64_t q = gtid(); q < Tn; q += gstride()) {
+    const int64_t t = q / n;
+    const uint32_t m = members[q];
+    if (m < (uint32_t)n) bof[t * n + m] = fscan[q] + flag[q] - 1u;
   }
-  uint32_t a[4], b[4], mn[4];
+}
+
+// Signature of every set (one thread per set of at most SK_BIG members;
+// larger sets are queued for k_sig_big).  *count sets, the K key pairs of
+// this table at keys.  Adds the pi evaluations made to *evals.
+__global__ __launch_bounds__(256) void k_sig(const uint32_t* __restrict__ mem, const uint32_t* __restrict__ gstart,
+                                             const uint32_t* __restrict__ gsize, const uint32_t* __restrict__ count,
+                                             const uint32_t* __restrict__ keys, int K, uint32_t* __restrict__ G,
+                                             uint32_t* __restrict__ big_list, uint32_t* big_count,
+                                             unsigned long long* evals) {
+  const uint32_t ns = *count;
+  uint32_t a[4], b[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     a[k] = k < K ? (keys[2 * k] | 1u) : 1u;
     b[k] = k < K ? keys[2 * k + 1] : 0u;
-    mn[k] = 0xFFFFFFFFu;
   }
-  const uint32_t* p = mem + gstart[g];
-  for (uint32_t q = 0; q < sz; ++q) {
-    const uint32_t y = fmix32(p[q]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t v = perm_premixed(a[k], b[k], y);
-      mn[k] = v < mn[k] ? v : mn[k];
+  unsigned long long done = 0;
+  for (uint32_t g = gtid(); g < ns; g += gstride()) {
+    const uint32_t sz = gsize[g];
+    if (sz > SK_BIG) {
+      big_list[atomicAdd(big_count, 1u)] = g;
+      continue;
     }
-  }
+    uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    const uint32_t* p = mem + gstart[g];
+    for (uint32_t q = 0; q < sz; ++q) {
+      const uint32_t y = fmix32(p[q]);
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (k < K) G[g * K + k] = mn[k];
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t v = perm_premixed(a[k], b[k], y);
+        mn[k] = v < mn[k] ? v : mn[k];
+      }
+    }
+    done += (unsigned long long)sz * K;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < K) G[(int64_t)g * K + k] = mn[k];
+  }
+  if (evals) block_add(done, evals);
 }
 
 __global__ __launch_bounds__(256) void k_sig_big(const uint32_t* __restrict__ mem,
@@ -99,18 +173,18 @@ __global__ __launch_bounds__(256) void k_sig_big(const uint32_t* __restrict__ me
                                                  const uint32_t* __restrict__ gsize,
                                                  const uint32_t* __restrict__ keys, int K,
                                                  uint32_t* __restrict__ G, const uint32_t* big_list,
-                                                 const uint32_t* big_count) {
+                                                 const uint32_t* big_count, unsigned long long* evals) {
   __shared__ uint32_t red[4][256];
   const uint32_t nbig = *big_count;
+  uint32_t a[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    a[k] = k < K ? (keys[2 * k] | 1u) : 1u;
+    b[k] = k < K ? keys[2 * k + 1] : 0u;
+  }
   for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
     const uint32_t g = big_list[bi];
-    uint32_t a[4], b[4], mn[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      a[k] = k < K ? (keys[2 * k] | 1u) : 1u;
-      b[k] = k < K ? keys[2 * k + 1] : 0u;
-      mn[k] = 0xFFFFFFFFu;
-    }
+    uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
     const uint32_t* p = mem + gstart[g];
     const uint32_t sz = gsize[g];
     for (uint32_t q = threadIdx.x; q < sz; q += blockDim.x) {
@@ -135,337 +209,524 @@ __global__ __launch_bounds__(256) void k_sig_big(const uint32_t* __restrict__ me
       __syncthreads();
     }
     if (threadIdx.x < (unsigned)K) G[(int64_t)g * K + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x == 0 && evals) atomicAdd(evals, (unsigned long long)sz * K);
     __syncthreads();
   }
 }
 
-// For each set: members to vote with when its bin holds >= 2 sets.
-__global__ void k_pair_count(const uint32_t* __restrict__ bin_of, const uint32_t* __restrict__ binoff,
-                             const uint32_t* __restrict__ binmem, const uint32_t* __restrict__ gsize, int64_t ns,
-                             uint32_t* __restrict__ cnt, uint32_t* multi_bins) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= ns) return;
-  const uint32_t b = bin_of[g];
-  const uint32_t bs = binoff[b + 1] - binoff[b];
-  cnt[g] = bs >= 2 ? gsize[g] : 0u;
-  if (bs >= 2 && binmem[binoff[b]] == (uint32_t)g) atomicAdd(multi_bins, 1u);
+// ---- bins of identical G (SILK tables) ---------------------------------------
+GEEK_D uint32_t g_hash(const uint32_t* __restrict__ G, uint32_t g, int K) {
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  for (int k = 0; k < K; ++k) w[k] = G[(int64_t)g * K + k];
+  return key_hash(w, 4);
+}
+GEEK_D bool g_eq(const uint32_t* __restrict__ G, uint32_t a, uint32_t b, int K) {
+  for (int k = 0; k < K; ++k)
+    if (G[(int64_t)a * K + k] != G[(int64_t)b * K + k]) return false;
+  return true;
 }
 
-__global__ void k_fill0(uint32_t* p, int64_t n) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+__global__ void k_ht_clear(const SilkState* S, uint32_t* __restrict__ ht, uint32_t* __restrict__ binmin,
+                           uint32_t* __restrict__ bcount, uint32_t* __restrict__ ksize) {
+  const uint32_t NB = S->nb, slots = S->ht_mask + 1u;
+  const uint32_t top = slots > NB ? slots : NB;
+  for (uint32_t i = gtid(); i < top; i += gstride()) {
+    if (i < slots) ht[i] = 0u;
+    if (i < NB) {
+      binmin[i] = 0xFFFFFFFFu;
+      bcount[i] = 0u;
+      ksize[i] = 0u;
+    }
+  }
 }
 
-__global__ void k_mark_starts(const uint32_t* __restrict__ gstart, int64_t ns, uint32_t base0,
-                              uint32_t* __restrict__ flag) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= ns) return;
-  flag[gstart[g] - base0] = 1u;
+// Open addressing with linear probing: a slot holds 1 + the bucket that
+// claimed it; a probe that meets another bucket compares the exact G (the
+// claimant's G is complete before this kernel starts), so no slot is ever
+// read before its key exists.  rep[g] = the claimant of g's G.
+__global__ void k_ht_insert(const uint32_t* __restrict__ G, int K, const SilkState* S, uint32_t* __restrict__ ht,
+                            uint32_t* __restrict__ rep) {
+  const uint32_t NB = S->nb, mask = S->ht_mask;
+  for (uint32_t g = gtid(); g < NB; g += gstride()) {
+    uint32_t h = g_hash(G, g, K) & mask;
+    uint32_t r = g;
+    for (;;) {  // at most mask + 1 > NB probes: the table is never full
+      const uint32_t prev = atomicCAS(&ht[h], 0u, g + 1u);
+      if (prev == 0u) break;
+      if (g_eq(G, prev - 1u, g, K)) {
+        r = prev - 1u;
+        break;
+      }
+      h = (h + 1u) & mask;
+    }
+    rep[g] = r;
+  }
 }
 
-// One thread per member position q of the flattened sets: set index of q is
-// (exclusive count of set starts) + flag - 1.
-__global__ void k_pairs(const uint32_t* __restrict__ mem, int64_t npos, uint32_t base0,
-                        const uint32_t* __restrict__ flag, const uint32_t* __restrict__ fscan,
-                        const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ cnt,
-                        const uint32_t* __restrict__ poff, const uint32_t* __restrict__ bin_of,
-                        uint32_t* __restrict__ hi, uint32_t* __restrict__ lo) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q >= npos) return;
-  const uint32_t g = fscan[q] + flag[q] - 1u;
-  if (cnt[g] == 0u) return;
-  const uint32_t p = poff[g] + ((uint32_t)q + base0 - gstart[g]);
-  hi[p] = bin_of[g];
-  lo[p] = mem[q];
+__global__ void k_ht_min(const uint32_t* __restrict__ rep, const SilkState* S, uint32_t* __restrict__ binmin,
+                         uint32_t* __restrict__ bcount) {
+  const uint32_t NB = S->nb;
+  for (uint32_t g = gtid(); g < NB; g += gstride()) {
+    const uint32_t r = rep[g];
+    atomicMin(&binmin[r], g);
+    atomicAdd(&bcount[r], 1u);
+  }
 }
 
-__global__ void k_run_heads(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo, int64_t P,
-                            uint32_t* __restrict__ h) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q >= P) return;
-  h[q] = (q == 0 || hi[q] != hi[q - 1] || lo[q] != lo[q - 1]) ? 1u : 0u;
+// info[g] = (bin id = smallest bucket of the bin, number of buckets in it);
+// counts the bins of two or more buckets.
+__global__ __launch_bounds__(256) void k_bin_info(const uint32_t* __restrict__ rep,
+                                                  const uint32_t* __restrict__ binmin,
+                                                  const uint32_t* __restrict__ bcount, SilkState* S,
+                                                  uint2* __restrict__ info) {
+  const uint32_t NB = S->nb;
+  unsigned long long multi = 0;
+  for (uint32_t g = gtid(); g < NB; g += gstride()) {
+    const uint32_t r = rep[g];
+    const uint32_t b = binmin[r], c = bcount[r];
+    info[g] = make_uint2(b, c);
+    multi += (b == g && c >= 2u) ? 1ull : 0ull;
+  }
+  block_add(multi, &S->multi);
 }
 
-__global__ void k_seg_heads(const uint32_t* __restrict__ hi, int64_t P, uint32_t* __restrict__ h) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q >= P) return;
-  h[q] = (q == 0 || hi[q] != hi[q - 1]) ? 1u : 0u;
+// Majority vote per object.  Object i lies in bucket bof[t][i] of table t;
+// the entries whose bin holds two or more buckets go to this thread's LDS
+// column, then each distinct bin is counted.  The object joins C_shared of a
+// bin when 2 * count > |Bin| (count >= 2, so at most T / 2 bins per object);
+// those bins are listed in kbin[j][i], their number in kc[i], and ksize[bin]
+// counts the bin's voted ids.  Adds the (bin, id) pairs voted to S->pairs.
+__global__ __launch_bounds__(256) void k_vote(const uint32_t* __restrict__ bof, const uint2* __restrict__ info,
+                                              int64_t n, int T, uint32_t* __restrict__ kbin,
+                                              uint32_t* __restrict__ kc, uint32_t* __restrict__ ksize,
+                                              SilkState* S) {
+  extern __shared__ uint32_t vl[];  // [2][T][blockDim.x]: bin id, bin size
+  const int VT = blockDim.x;
+  uint32_t* lb = vl;
+  uint32_t* ls = vl + (size_t)T * VT;
+  unsigned long long pairs = 0;
+  const int x = threadIdx.x;
+  const uint32_t NB = S->nb;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    int c = 0;
+    for (int t = 0; t < T; ++t) {
+      const uint32_t g = bof[(int64_t)t * n + i];
+      const uint2 e = g < NB ? info[g] : make_uint2(0u, 0u);  // bounded even for a malformed CSR
+      if (e.y >= 2u) {
+        lb[c * VT + x] = e.x;
+        ls[c * VT + x] = e.y;
+        ++c;
+      }
+    }
+    pairs += (unsigned long long)c;
+    uint32_t kept = 0;
+    for (int a = 0; a < c; ++a) {
+      const uint32_t b = lb[a * VT + x];
+      bool first = true;
+      for (int q = 0; q < a && first; ++q) first = lb[q * VT + x] != b;
+      if (!first) continue;
+      uint32_t cnt = 1;
+      for (int q = a + 1; q < c; ++q) cnt += lb[q * VT + x] == b ? 1u : 0u;
+      if (2u * cnt > ls[a * VT + x]) {
+        kbin[(int64_t)kept * n + i] = b;
+        ++kept;
+        atomicAdd(&ksize[b], 1u);
+      }
+    }
+    kc[i] = kept;
+  }
+  block_add(pairs, &S->pairs);
 }
 
-__global__ void k_starts(const uint32_t* __restrict__ h, const uint32_t* __restrict__ hs, int64_t P,
+// Bins that join C: named by their smallest bucket, two or more buckets,
+// C_shared non-empty and of at least delta ids.
+__global__ void k_emit_flags(const uint2* __restrict__ info, const uint32_t* __restrict__ ksize, int delta,
+                             const SilkState* S, uint32_t* __restrict__ eone, uint32_t* __restrict__ esz) {
+  const uint32_t NB = S->nb;
+  const uint32_t dmin = delta > 1 ? (uint32_t)delta : 1u;
+  for (uint32_t g = gtid(); g < NB; g += gstride()) {
+    const uint2 e = info[g];
+    const uint32_t ks = ksize[g];
+    const bool on = e.x == g && e.y >= 2u && ks >= dmin;
+    eone[g] = on ? 1u : 0u;
+    esz[g] = on ? ks : 0u;
+  }
+}
+
+// Room in C for this table's sets (C holds ccap sets and ccap members); once
+// C has run out of room no later table writes to it, but the sizes needed are
+// still counted.
+__global__ void k_commit(SilkState* S, uint32_t ccap) {
+  if (blockIdx.x || threadIdx.x) return;
+  const uint32_t es = S->es, em = S->em;
+  S->need_s += es;
+  S->need_m += em;
+  if (!S->over && (uint64_t)S->cs + es <= ccap && (uint64_t)S->cm + em <= ccap) {
+    S->fit = 1u;
+    S->base_s = S->cs;
+    S->base_m = S->cm;
+    S->cs += es;
+    S->cm += em;
+  } else {
+    S->fit = 0u;
+    S->over = 1u;
+  }
+}
+
+// Emitted bins per object (zero for every object when the table does not
+// fit in C, so the sort that follows has nothing to do).
+__global__ void k_count_kept(const uint32_t* __restrict__ kbin, const uint32_t* __restrict__ kc, int64_t n,
+                             const uint32_t* __restrict__ eone, const SilkState* S, uint32_t* __restrict__ kc2) {
+  const bool fit = S->fit != 0u;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    uint32_t m = 0;
+    if (fit) {
+      const uint32_t c = kc[i];
+      for (uint32_t j = 0; j < c; ++j) m += eone[kbin[(int64_t)j * n + i]];
+    }
+    kc2[i] = m;
+  }
+}
+
+// (emitted bin index, id) pairs in id order: a stable sort by the bin index
+// then lists every C_shared with its ids ascending.
+__global__ void k_kept_pairs(const uint32_t* __restrict__ kbin, const uint32_t* __restrict__ kc, int64_t n,
+                             const uint32_t* __restrict__ eone, const uint32_t* __restrict__ eidx,
+                             const uint32_t* __restrict__ kpos, const SilkState* S, uint32_t* __restrict__ phi,
+                             uint32_t* __restrict__ plo) {
+  if (!S->fit) return;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const uint32_t c = kc[i];
+    uint32_t p = kpos[i];
+    for (uint32_t j = 0; j < c; ++j) {
+      const uint32_t b = kbin[(int64_t)j * n + i];
+      if (eone[b]) {
+        phi[p] = eidx[b];
+        plo[p] = (uint32_t)i;
+        ++p;
+      }
+    }
+  }
+}
+
+__global__ void k_c_write(const uint32_t* __restrict__ sorted_ids, const uint32_t* __restrict__ eone,
+                          const uint32_t* __restrict__ eidx, const uint32_t* __restrict__ eoff, const SilkState* S,
+                          uint32_t* __restrict__ cmem, uint32_t* __restrict__ coff) {
+  if (!S->fit) return;
+  const uint32_t em = S->em, NB = S->nb, bs = S->base_s, bm = S->base_m;
+  for (uint32_t q = gtid(); q < em; q += gstride()) cmem[bm + q] = sorted_ids[q];
+  for (uint32_t g = gtid(); g < NB; g += gstride())
+    if (eone[g]) coff[bs + eidx[g]] = bm + eoff[g];
+}
+
+// ---- de-duplication ------------------------------------------------------------
+__global__ void k_dd_setup(SilkState* S, uint32_t* __restrict__ coff) {
+  if (blockIdx.x || threadIdx.x) return;
+  coff[S->cs] = S->cm;
+}
+
+__global__ void k_set_extent(const uint32_t* __restrict__ coff, const SilkState* S, uint32_t* __restrict__ gstart,
+                             uint32_t* __restrict__ gsize) {
+  const uint32_t cs = S->cs;
+  for (uint32_t s = gtid(); s < cs; s += gstride()) {
+    gstart[s] = coff[s];
+    gsize[s] = coff[s + 1] - coff[s];
+  }
+}
+
+// The K-tuples of C's sets as separate key words (word 0 most significant)
+// with the set index as payload.
+__global__ void k_dd_tuples(const uint32_t* __restrict__ G, int K, const SilkState* S, uint32_t* __restrict__ w0,
+                            uint32_t* __restrict__ w1, uint32_t* __restrict__ w2, uint32_t* __restrict__ w3,
+                            uint32_t* __restrict__ val) {
+  const uint32_t cs = S->cs;
+  for (uint32_t s = gtid(); s < cs; s += gstride()) {
+    w0[s] = G[(int64_t)s * K];
+    w1[s] = K > 1 ? G[(int64_t)s * K + 1] : 0u;
+    w2[s] = K > 2 ? G[(int64_t)s * K + 2] : 0u;
+    w3[s] = K > 3 ? G[(int64_t)s * K + 3] : 0u;
+    val[s] = s;
+  }
+}
+
+// Heads of runs of equal tuples in sorted order.
+__global__ void k_dd_heads(const uint32_t* __restrict__ w0, const uint32_t* __restrict__ w1,
+                           const uint32_t* __restrict__ w2, const uint32_t* __restrict__ w3, const SilkState* S,
+                           uint32_t* __restrict__ h) {
+  const uint32_t cs = S->cs;
+  for (uint32_t r = gtid(); r < cs; r += gstride())
+    h[r] = (r == 0 || w0[r] != w0[r - 1] || w1[r] != w1[r - 1] || w2[r] != w2[r - 1] || w3[r] != w3[r - 1]) ? 1u
+                                                                                                               : 0u;
+}
+
+// Bin of every sorted position, each bin's first position (bstart[nb2] =
+// cs), the voting pairs of every set in a bin of two or more sets, and the
+// sorted position of every set.
+__global__ void k_dd_bins(const uint32_t* __restrict__ h, const uint32_t* __restrict__ hs,
+                          const uint32_t* __restrict__ ord, const SilkState* S, uint32_t* __restrict__ binofr,
+                          uint32_t* __restrict__ bstart, uint32_t* __restrict__ inv) {
+  const uint32_t cs = S->cs;
+  for (uint32_t r = gtid(); r < cs; r += gstride()) {
+    const uint32_t b = hs[r] + h[r] - 1u;
+    binofr[r] = b;
+    if (h[r]) bstart[b] = r;
+    if (r == cs - 1u) bstart[b + 1u] = cs;
+    inv[ord[r]] = r;
+  }
+}
+
+__global__ void k_dd_cnt(const uint32_t* __restrict__ ord, const uint32_t* __restrict__ binofr,
+                         const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ gsize, const SilkState* S,
+                         uint32_t* __restrict__ cnt) {
+  const uint32_t cs = S->cs;
+  for (uint32_t r = gtid(); r < cs; r += gstride()) {
+    const uint32_t b = binofr[r];
+    cnt[r] = (bstart[b + 1] - bstart[b] >= 2u) ? gsize[ord[r]] : 0u;
+  }
+}
+
+// One thread per member position of C: (bin, id) of members of sets in bins
+// of two or more sets.
+__global__ void k_dd_pairs(const uint32_t* __restrict__ cmem, const uint32_t* __restrict__ flag,
+                           const uint32_t* __restrict__ fscan, const uint32_t* __restrict__ coff,
+                           const uint32_t* __restrict__ inv, const uint32_t* __restrict__ cnt,
+                           const uint32_t* __restrict__ poff, const uint32_t* __restrict__ binofr, const SilkState* S,
+                           uint32_t* __restrict__ hi, uint32_t* __restrict__ lo) {
+  const uint32_t cm = S->cm;
+  for (uint32_t q = gtid(); q < cm; q += gstride()) {
+    const uint32_t s = fscan[q] + flag[q] - 1u;
+    const uint32_t r = inv[s];
+    if (cnt[r] == 0u) continue;
+    const uint32_t p = poff[r] + (q - coff[s]);
+    hi[p] = binofr[r];
+    lo[p] = cmem[q];
+  }
+}
+
+__global__ void k_run_heads(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
+                            const uint32_t* __restrict__ count, uint32_t* __restrict__ h) {
+  const uint32_t P = *count;
+  for (uint32_t q = gtid(); q < P; q += gstride())
+    h[q] = (q == 0 || hi[q] != hi[q - 1] || lo[q] != lo[q - 1]) ? 1u : 0u;
+}
+
+__global__ void k_starts(const uint32_t* __restrict__ h, const uint32_t* __restrict__ hs,
+                         const uint32_t* __restrict__ count, const uint32_t* __restrict__ total,
                          uint32_t* __restrict__ start) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (q > P) return;
-  if (q == P) {
-    start[hs[P]] = (uint32_t)P;  // hs[P] = total heads
+  const uint32_t P = *count;
+  for (uint32_t q = gtid(); q <= P; q += gstride()) {
+    if (q == P) start[*total] = P;
+    else if (h[q]) start[hs[q]] = q;
+  }
+}
+
+// Majority of every (bin, id) run of the de-duplication pairs.
+__global__ void k_dd_keep(const uint32_t* __restrict__ rstart, const uint32_t* __restrict__ hi,
+                          const uint32_t* __restrict__ bstart, const SilkState* S, uint32_t* __restrict__ kept) {
+  const uint32_t R = S->R2;
+  for (uint32_t r = gtid(); r < R; r += gstride()) {
+    const uint32_t len = rstart[r + 1] - rstart[r];
+    const uint32_t b = hi[rstart[r]];
+    kept[r] = (2u * len > bstart[b + 1] - bstart[b]) ? 1u : 0u;
+  }
+}
+
+__global__ void k_dd_compact(const uint32_t* __restrict__ rstart, const uint32_t* __restrict__ kept,
+                             const uint32_t* __restrict__ kidx, const uint32_t* __restrict__ hi,
+                             const uint32_t* __restrict__ lo, const SilkState* S, uint32_t* __restrict__ klo,
+                             uint32_t* __restrict__ ksz, uint32_t* __restrict__ kstart) {
+  const uint32_t R = S->R2;
+  for (uint32_t r = gtid(); r < R; r += gstride()) {
+    if (!kept[r]) continue;
+    const uint32_t b = hi[rstart[r]];
+    klo[kidx[r]] = lo[rstart[r]];
+    atomicAdd(&ksz[b], 1u);
+    atomicMin(&kstart[b], kidx[r]);
+  }
+}
+
+// Seed size of every de-duplication bin (bins in ascending tuple order): a
+// single set passes through; several sets keep their voted ids when at least
+// delta (and at least one) of them remain.
+__global__ void k_dd_size(const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ ord,
+                          const uint32_t* __restrict__ gsize, const uint32_t* __restrict__ ksz, int delta,
+                          const SilkState* S, uint32_t* __restrict__ ssz, uint32_t* __restrict__ one) {
+  const uint32_t nb2 = S->nb2;
+  const uint32_t dmin = delta > 1 ? (uint32_t)delta : 1u;
+  for (uint32_t b = gtid(); b < nb2; b += gstride()) {
+    const uint32_t bs = bstart[b + 1] - bstart[b];
+    uint32_t v;
+    if (bs == 1u) v = gsize[ord[bstart[b]]];
+    else v = ksz[b] >= dmin ? ksz[b] : 0u;
+    ssz[b] = v;
+    one[b] = v ? 1u : 0u;
+  }
+}
+
+__global__ void k_silk_finish(SilkState* S, uint64_t cap_k, uint64_t cap_m, uint32_t* __restrict__ seed_off,
+                              uint32_t* k_out, unsigned long long* needed, unsigned long long* counters,
+                              int32_t* st) {
+  if (blockIdx.x || threadIdx.x) return;
+  S->fit_out = 0u;
+  if (counters) {
+    counters[0] = S->hash_evals;
+    counters[1] = S->pairs;
+    counters[2] = S->need_s;
+    counters[3] = S->multi;
+  }
+  if (S->over) {
+    // C did not fit (it holds 4 * cap_members sets and members): report the
+    // capacities that make it fit
+    const unsigned long long c = S->need_s > S->need_m ? S->need_s : S->need_m;
+    needed[0] = (S->need_s + 3) / 4;
+    needed[1] = (c + 3) / 4;
+    *k_out = 0;
+    set_status(st, GEEK_ERR_CAPACITY);
     return;
   }
-  if (h[q]) start[hs[q]] = (uint32_t)q;
+  const uint32_t k = S->cs ? S->k : 0u, m = S->cs ? S->tot_m : 0u;
+  needed[0] = k;
+  needed[1] = m;
+  if (k > cap_k || m > cap_m) {
+    *k_out = 0;
+    set_status(st, GEEK_ERR_CAPACITY);
+    return;
+  }
+  seed_off[k] = m;
+  *k_out = k;
+  S->fit_out = 1u;
+  if (k == 0) set_status(st, GEEK_ERR_NO_SEEDS);
 }
 
-// Majority vote of every (bin, id) run: keep iff 2 * count > |Bin|.
-__global__ void k_keep(const uint32_t* __restrict__ rstart, int64_t R, const uint32_t* __restrict__ hi,
-                       const uint32_t* __restrict__ binoff, uint32_t* __restrict__ kept) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  const uint32_t len = rstart[r + 1] - rstart[r];
-  const uint32_t b = hi[rstart[r]];
-  const uint32_t bs = binoff[b + 1] - binoff[b];
-  kept[r] = (2u * len > bs) ? 1u : 0u;
-}
-
-__global__ void k_compact_runs(const uint32_t* __restrict__ rstart, int64_t R, const uint32_t* __restrict__ kept,
-                               const uint32_t* __restrict__ kidx, const uint32_t* __restrict__ hi,
-                               const uint32_t* __restrict__ lo, uint32_t* __restrict__ khi,
-                               uint32_t* __restrict__ klo) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= R || !kept[r]) return;
-  khi[kidx[r]] = hi[rstart[r]];
-  klo[kidx[r]] = lo[rstart[r]];
-}
-
-// Segment (one bin's kept ids) sizes passing the threshold.
-__global__ void k_seg_emit_size(const uint32_t* __restrict__ sstart, int64_t S, int delta,
-                                uint32_t* __restrict__ esize, uint32_t* __restrict__ eone) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint32_t len = sstart[s + 1] - sstart[s];
-  const bool ok = (int64_t)len >= (int64_t)delta;
-  esize[s] = ok ? len : 0u;
-  eone[s] = ok ? 1u : 0u;
-}
-
-__global__ void k_seg_emit(const uint32_t* __restrict__ sstart, int64_t S, const uint32_t* __restrict__ esize,
-                           const uint32_t* __restrict__ eoff, const uint32_t* __restrict__ eidx,
-                           const uint32_t* __restrict__ klo, uint32_t m0, uint32_t s0,
-                           uint32_t* __restrict__ cmem, uint32_t* __restrict__ coff) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= S || esize[s] == 0u) return;
-  coff[s0 + eidx[s]] = m0 + eoff[s];  // the members are copied by k_seg_copy
+__global__ void k_emit_seeds(const uint32_t* __restrict__ ssz, const uint32_t* __restrict__ soff,
+                             const uint32_t* __restrict__ sidx, const SilkState* S, uint32_t* __restrict__ seed_off) {
+  if (!S->fit_out || !S->cs) return;
+  const uint32_t nb2 = S->nb2;
+  for (uint32_t b = gtid(); b < nb2; b += gstride())
+    if (ssz[b]) seed_off[sidx[b]] = soff[b];
 }
 
 // The last index r in [0, cnt) with off[r] <= e (off non-decreasing): the
 // non-empty entry whose output range holds position e.
-GEEK_D int64_t range_of(const uint32_t* __restrict__ off, int64_t cnt, uint32_t e) {
-  int64_t lo = 0, hi = cnt - 1;
+GEEK_D uint32_t range_of(const uint32_t* __restrict__ off, uint32_t cnt, uint32_t e) {
+  uint32_t lo = 0, hi = cnt - 1;
   while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
+    const uint32_t mid = (lo + hi + 1) >> 1;
     if (off[mid] <= e) lo = mid;
     else hi = mid - 1;
   }
   return lo;
 }
 
-// One thread per emitted member: C's members of this table, segment by
-// segment (a segment can hold a large share of the table, so the copy is
-// spread over threads rather than done by one thread per segment).
-__global__ void k_seg_copy(const uint32_t* __restrict__ sstart, int64_t S, const uint32_t* __restrict__ eoff,
-                           const uint32_t* __restrict__ klo, uint32_t m0, uint32_t em, uint32_t* __restrict__ cmem) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= em) return;
-  const int64_t s = range_of(eoff, S, (uint32_t)e);
-  cmem[m0 + e] = klo[sstart[s] + ((uint32_t)e - eoff[s])];
-}
-
-__global__ void k_put(uint32_t* p, int64_t i, uint32_t v) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) p[i] = v;
-}
-
-// ---- de-duplication output --------------------------------------------------
-// Seed size of every de-duplication bin: a single set passes through; a bin of
-// several sets keeps its voted C_shared when it meets the threshold.
-__global__ void k_dedup_size(const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ binmem,
-                             int64_t nbins, const uint32_t* __restrict__ gsize,
-                             uint32_t* __restrict__ ssize, uint32_t* __restrict__ src_kind) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
-  const uint32_t bs = binoff[b + 1] - binoff[b];
-  if (bs == 1) {
-    ssize[b] = gsize[binmem[binoff[b]]];
-    src_kind[b] = 1u;
-  } else {
-    ssize[b] = 0u;
-    src_kind[b] = 0u;
-  }
-}
-
-__global__ void k_dedup_multi(const uint32_t* __restrict__ sstart, int64_t S, const uint32_t* __restrict__ khi,
-                              int delta, uint32_t* __restrict__ ssize, uint32_t* __restrict__ segof) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint32_t len = sstart[s + 1] - sstart[s];
-  const uint32_t b = khi[sstart[s]];
-  if ((int64_t)len >= (int64_t)delta) ssize[b] = len;
-  segof[b] = (uint32_t)s;
-}
-
-// Tuple key words of every bin (the G of its first set), value = bin id.
-__global__ void k_bin_tuples(const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ binmem,
-                             int64_t nbins, const uint32_t* __restrict__ G, int K,
-                             uint32_t* __restrict__ w0, uint32_t* __restrict__ w1, uint32_t* __restrict__ w2,
-                             uint32_t* __restrict__ w3, uint32_t* __restrict__ val) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= nbins) return;
-  const uint32_t g = binmem[binoff[b]];
-  w0[b] = G[(int64_t)g * K];
-  w1[b] = K > 1 ? G[(int64_t)g * K + 1] : 0u;
-  w2[b] = K > 2 ? G[(int64_t)g * K + 2] : 0u;
-  w3[b] = K > 3 ? G[(int64_t)g * K + 3] : 0u;
-  val[b] = (uint32_t)b;
-}
-
-__global__ void k_order_sizes(const uint32_t* __restrict__ ord, int64_t nbins, const uint32_t* __restrict__ ssize,
-                              uint32_t* __restrict__ osz, uint32_t* __restrict__ oone) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= nbins) return;
-  const uint32_t v = ssize[ord[r]];
-  osz[r] = v;
-  oone[r] = v ? 1u : 0u;
-}
-
-__global__ void k_emit_seeds(const uint32_t* __restrict__ ord, int64_t nbins, const uint32_t* __restrict__ osz,
-                             const uint32_t* __restrict__ ooff, const uint32_t* __restrict__ oidx,
-                             const uint32_t* __restrict__ src_kind, const uint32_t* __restrict__ binoff,
-                             const uint32_t* __restrict__ binmem, const uint32_t* __restrict__ cmem,
-                             const uint32_t* __restrict__ coff, const uint32_t* __restrict__ segof,
-                             const uint32_t* __restrict__ sstart, const uint32_t* __restrict__ klo,
-                             uint32_t* __restrict__ seed_off, uint32_t* __restrict__ seed_mem) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= nbins || osz[r] == 0u) return;
-  seed_off[oidx[r]] = ooff[r];  // the members are copied by k_seed_copy
-}
-
-// One thread per seed member: from the set that passes through (C) or from
-// the voted ids of the bin.
-__global__ void k_seed_copy(const uint32_t* __restrict__ ord, int64_t nbins, const uint32_t* __restrict__ ooff,
-                            const uint32_t* __restrict__ src_kind, const uint32_t* __restrict__ binoff,
-                            const uint32_t* __restrict__ binmem, const uint32_t* __restrict__ cmem,
-                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ segof,
-                            const uint32_t* __restrict__ sstart, const uint32_t* __restrict__ klo, uint32_t tot,
+// One thread per seed member: from the set that passes through or from the
+// bin's voted ids.
+__global__ void k_seed_copy(const uint32_t* __restrict__ soff, const uint32_t* __restrict__ bstart,
+                            const uint32_t* __restrict__ ord, const uint32_t* __restrict__ cmem,
+                            const uint32_t* __restrict__ coff, const uint32_t* __restrict__ klo,
+                            const uint32_t* __restrict__ kstart, const SilkState* S,
                             uint32_t* __restrict__ seed_mem) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= tot) return;
-  const int64_t r = range_of(ooff, nbins, (uint32_t)e);
-  const uint32_t b = ord[r];
-  const uint32_t q = (uint32_t)e - ooff[r];
-  seed_mem[e] = src_kind[b] ? cmem[coff[binmem[binoff[b]]] + q] : klo[sstart[segof[b]] + q];
-}
-
-__global__ void k_silk_capacity(unsigned long long ns, unsigned long long nm, uint32_t* k_out,
-                                unsigned long long* needed, unsigned long long* counters,
-                                unsigned long long c0, unsigned long long c1, unsigned long long c2,
-                                unsigned long long c3, int32_t* st) {
-  if (blockIdx.x || threadIdx.x) return;
-  needed[0] = ns;
-  needed[1] = nm;
-  *k_out = 0;
-  set_status(st, GEEK_ERR_CAPACITY);
-  if (counters) {
-    counters[0] = c0;
-    counters[1] = c1;
-    counters[2] = c2;
-    counters[3] = c3;
-  }
-}
-
-__global__ void k_silk_finish(uint32_t k, uint32_t members, uint64_t cap_k, uint64_t cap_m,
-                              uint32_t* seed_off, uint32_t* k_out, unsigned long long* needed,
-                              unsigned long long* counters, unsigned long long c0, unsigned long long c1,
-                              unsigned long long c2, unsigned long long c3, int32_t* st) {
-  if (blockIdx.x || threadIdx.x) return;
-  needed[0] = k;
-  needed[1] = members;
-  if (k > cap_k || members > cap_m) {
-    set_status(st, GEEK_ERR_CAPACITY);
-    *k_out = 0;
-  } else {
-    seed_off[k] = members;
-    *k_out = k;
-    if (k == 0) set_status(st, GEEK_ERR_NO_SEEDS);
-  }
-  if (counters) {
-    counters[0] = c0;
-    counters[1] = c1;
-    counters[2] = c2;
-    counters[3] = c3;
+  if (!S->fit_out || !S->cs) return;
+  const uint32_t tot = S->tot_m, nb2 = S->nb2;
+  for (uint32_t e = gtid(); e < tot; e += gstride()) {
+    const uint32_t b = range_of(soff, nb2, e);
+    const uint32_t q = e - soff[b];
+    const uint32_t bs = bstart[b + 1] - bstart[b];
+    seed_mem[e] = bs == 1u ? cmem[coff[ord[bstart[b]]] + q] : klo[kstart[b] + q];
   }
 }
 
 // ---------------------------------------------------------------- host side
 struct SilkWs {
-  int64_t N1, Ccap;
-  uint32_t *base, *gstart, *gsize, *G, *binmem, *binoff, *nbins, *bin_of, *flag, *fscan, *cnt, *poff;
-  uint32_t *hi, *lo, *hi2, *lo2, *h, *hs, *rstart, *kept, *kidx, *khi, *klo;
-  uint32_t *sflag, *sscan, *sstart, *esize, *eoff, *eone, *eidx;
-  uint32_t *cmem, *coff, *ssize, *src_kind, *segof;
+  int64_t Tn, Ccap, KPmax, NS;  // NS = max(Tn, Ccap): sets of either phase
+  uint32_t ht_slots;
+  SilkState* S;
+  uint32_t *base, *gstart, *gsize, *G, *bof, *flag, *fscan, *ht, *rep, *binmin, *bcount, *ksize;
+  uint2* info;
+  uint32_t *eone, *esz, *eidx, *eoff, *kbin, *kc, *kc2, *kpos;
+  uint32_t *phi, *plo, *phi2, *plo2;
+  uint32_t *cmem, *coff;
   uint32_t *tw[4], *tv, *tw2[4], *tv2;
-  uint32_t *radix_tmp, *scan_tmp, *big_list, *small;
-  void* bz_ws;
-  size_t bz_bytes;
+  uint32_t *h, *hs, *binofr, *bstart, *inv, *cnt, *poff, *rstart, *kept, *kidx, *klo, *ksz2, *kstart;
+  uint32_t *ssz, *sone, *soff, *sidx;
+  uint32_t *big_list, *radix_tmp, *scan_tmp;
 };
-
-static geek_bucketize_job bz_job_for(int64_t n, int K) {
-  geek_bucketize_job b{};
-  b.n = n < 1 ? 1 : n;
-  b.T = 1;
-  b.key_words = K;
-  b.table_stride = 0;
-  b.row_stride = K;
-  return b;
-}
 
 static size_t carve_silk(const geek_silk_job& J, void* ws, SilkWs& W) {
   Carver c(ws);
-  const int64_t Tn = (int64_t)J.T * J.n;
+  W.Tn = (int64_t)J.T * J.n;
   W.Ccap = 4 * (J.cap_members > 0 ? J.cap_members : 1);
-  W.N1 = Tn > W.Ccap ? Tn : W.Ccap;
-  const int64_t N1 = W.N1;
+  W.KPmax = (int64_t)((J.T + 1) / 2) * J.n;
+  W.NS = W.Tn > W.Ccap ? W.Tn : W.Ccap;
+  uint64_t slots = 1024;
+  while (slots < 2u * (uint64_t)W.Tn && slots < 0x80000000ull) slots <<= 1;
+  W.ht_slots = (uint32_t)slots;
+  const int64_t NS = W.NS, Tn = W.Tn, Cc = W.Ccap;
+  const int64_t npairs = W.KPmax > Cc ? W.KPmax : Cc;
+  W.S = c.take<SilkState>(1);
   W.base = c.take<uint32_t>(J.T + 1);
-  W.gstart = c.take<uint32_t>(N1 + 1);
-  W.gsize = c.take<uint32_t>(N1 + 1);
-  W.G = c.take<uint32_t>(N1 * 4);
-  W.binmem = c.take<uint32_t>(N1);
-  W.binoff = c.take<uint32_t>(N1 + 1);
-  W.nbins = c.take<uint32_t>(4);
-  W.bin_of = c.take<uint32_t>(N1);
-  W.flag = c.take<uint32_t>(N1 + 1);
-  W.fscan = c.take<uint32_t>(N1 + 1);
-  W.cnt = c.take<uint32_t>(N1 + 1);
-  W.poff = c.take<uint32_t>(N1 + 1);
-  W.hi = c.take<uint32_t>(N1);
-  W.lo = c.take<uint32_t>(N1);
-  W.hi2 = c.take<uint32_t>(N1);
-  W.lo2 = c.take<uint32_t>(N1);
-  W.h = c.take<uint32_t>(N1 + 1);
-  W.hs = c.take<uint32_t>(N1 + 1);
-  W.rstart = c.take<uint32_t>(N1 + 1);
-  W.kept = c.take<uint32_t>(N1 + 1);
-  W.kidx = c.take<uint32_t>(N1 + 1);
-  W.khi = c.take<uint32_t>(N1);
-  W.klo = c.take<uint32_t>(N1);
-  W.sflag = c.take<uint32_t>(N1 + 1);
-  W.sscan = c.take<uint32_t>(N1 + 1);
-  W.sstart = c.take<uint32_t>(N1 + 1);
-  W.esize = c.take<uint32_t>(N1 + 1);
-  W.eoff = c.take<uint32_t>(N1 + 1);
-  W.eone = c.take<uint32_t>(N1 + 1);
-  W.eidx = c.take<uint32_t>(N1 + 1);
-  W.cmem = c.take<uint32_t>(W.Ccap);
-  W.coff = c.take<uint32_t>(W.Ccap + 1);
-  W.ssize = c.take<uint32_t>(N1 + 1);
-  W.src_kind = c.take<uint32_t>(N1 + 1);
-  W.segof = c.take<uint32_t>(N1 + 1);
-  for (int w = 0; w < 4; ++w) W.tw[w] = c.take<uint32_t>(N1);
-  W.tv = c.take<uint32_t>(N1);
-  for (int w = 0; w < 4; ++w) W.tw2[w] = c.take<uint32_t>(N1);
-  W.tv2 = c.take<uint32_t>(N1);
-  W.radix_tmp = c.take<uint32_t>(radix_tmp_words(N1));
-  W.scan_tmp = c.take<uint32_t>(exscan_tmp_words(N1 + 1) + 16);
-  W.big_list = c.take<uint32_t>(N1 + 1);
-  W.small = c.take<uint32_t>(64);
-  W.bz_bytes = bucketize_ws(bz_job_for(N1, 4));
-  W.bz_ws = c.take<char>(W.bz_bytes);
+  W.gstart = c.take<uint32_t>(NS + 1);
+  W.gsize = c.take<uint32_t>(NS + 1);
+  W.G = c.take<uint32_t>(NS * J.K);
+  W.bof = c.take<uint32_t>(Tn);
+  W.flag = c.take<uint32_t>(NS + 1);
+  W.fscan = c.take<uint32_t>(NS + 1);
+  W.ht = c.take<uint32_t>(slots);
+  W.rep = c.take<uint32_t>(Tn);
+  W.binmin = c.take<uint32_t>(Tn);
+  W.bcount = c.take<uint32_t>(Tn);
+  W.ksize = c.take<uint32_t>(Tn);
+  W.info = c.take<uint2>(Tn);
+  W.eone = c.take<uint32_t>(Tn + 1);
+  W.esz = c.take<uint32_t>(Tn + 1);
+  W.eidx = c.take<uint32_t>(Tn + 1);
+  W.eoff = c.take<uint32_t>(Tn + 1);
+  W.kbin = c.take<uint32_t>(W.KPmax);
+  W.kc = c.take<uint32_t>(J.n + 1);
+  W.kc2 = c.take<uint32_t>(J.n + 1);
+  W.kpos = c.take<uint32_t>(J.n + 1);
+  W.phi = c.take<uint32_t>(npairs);
+  W.plo = c.take<uint32_t>(npairs);
+  W.phi2 = c.take<uint32_t>(npairs);
+  W.plo2 = c.take<uint32_t>(npairs);
+  W.cmem = c.take<uint32_t>(Cc);
+  W.coff = c.take<uint32_t>(Cc + 1);
+  for (int w = 0; w < 4; ++w) W.tw[w] = c.take<uint32_t>(Cc);
+  W.tv = c.take<uint32_t>(Cc);
+  for (int w = 0; w < 4; ++w) W.tw2[w] = c.take<uint32_t>(Cc);
+  W.tv2 = c.take<uint32_t>(Cc);
+  W.h = c.take<uint32_t>(Cc + 1);
+  W.hs = c.take<uint32_t>(Cc + 1);
+  W.binofr = c.take<uint32_t>(Cc + 1);
+  W.bstart = c.take<uint32_t>(Cc + 2);
+  W.inv = c.take<uint32_t>(Cc + 1);
+  W.cnt = c.take<uint32_t>(Cc + 1);
+  W.poff = c.take<uint32_t>(Cc + 1);
+  W.rstart = c.take<uint32_t>(Cc + 1);
+  W.kept = c.take<uint32_t>(Cc + 1);
+  W.kidx = c.take<uint32_t>(Cc + 1);
+  W.klo = c.take<uint32_t>(Cc);
+  W.ksz2 = c.take<uint32_t>(Cc);
+  W.kstart = c.take<uint32_t>(Cc);
+  W.ssz = c.take<uint32_t>(Cc + 1);
+  W.sone = c.take<uint32_t>(Cc + 1);
+  W.soff = c.take<uint32_t>(Cc + 1);
+  W.sidx = c.take<uint32_t>(Cc + 1);
+  W.big_list = c.take<uint32_t>(NS + 1);
+  W.radix_tmp = c.take<uint32_t>(radix_tmp_words(npairs > NS ? npairs : NS));
+  W.scan_tmp = c.take<uint32_t>(exscan_tmp_words(NS + 1) + 16);
   return c.used + 256;
+}
+
+int32_t silk_check(const geek_silk_job& J) {
+  if (J.n < 1 || J.n >= (1ll << 31) || J.T < 1 || J.K < 1 || J.K > 4 || J.L < 0 || !J.members || !J.offsets ||
+      !J.nbuckets || !J.silk_keys || !J.seed_offsets || !J.seed_members || !J.k_out || !J.needed ||
+      J.cap_k < 0 || J.cap_members < 0)
+    return GEEK_ERR_ARG;
+  if (J.T > SILK_MAX_T) return GEEK_ERR_UNSUPPORTED;
+  if ((int64_t)J.T * J.n >= (1ll << 31) || 4 * (J.cap_members > 0 ? J.cap_members : 1) >= (1ll << 31) ||
+      J.cap_k >= (1ll << 32) - 1)
+    return GEEK_ERR_UNSUPPORTED;
+  return GEEK_OK;
 }
 
 size_t silk_ws(const geek_silk_job& J) {
@@ -473,17 +734,10 @@ size_t silk_ws(const geek_silk_job& J) {
   return carve_silk(J, nullptr, W);
 }
 
-static inline int nblk(int64_t n) { return (int)((n + 255) / 256) > 0 ? (int)((n + 255) / 256) : 1; }
-
-struct Host {
-  hipStream_t s;
-  uint32_t read(const uint32_t* p) {
-    uint32_t v = 0;
-    hipMemcpyAsync(&v, p, 4, hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
-    return v;
-  }
-};
+static inline int ggrid(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return b < 1 ? 1 : b > SG_GRID ? SG_GRID : (int)b;
+}
 
 static int bits_for(uint64_t maxval) {
   int b = 0;
@@ -491,192 +745,123 @@ static int bits_for(uint64_t maxval) {
   return b;
 }
 
-// One voting round over `ns` sets (start/size in gstart/gsize, members in
-// mem starting at position base0 covering npos positions) whose signatures are
-// in W.G: bins, pairs, majority.  Leaves the kept (bin, id) pairs in khi/klo
-// (sorted) and their bin segments in sstart; returns the segment count.
-struct VoteOut {
-  uint32_t nbins, P, R, Kept, S, multi;
-};
-
-
-
-static int32_t vote_round(SilkWs& W, const uint32_t* mem, int64_t ns, uint32_t base0, int64_t npos, int K,
-                          int id_bits, Host& H, int32_t* st, VoteOut& o) {
-  hipStream_t s = H.s;
-  // bins of identical signatures
-  geek_bucketize_job bj = bz_job_for(ns, K);
-  bj.keys = W.G;
-  bj.members = W.binmem;
-  bj.offsets = W.binoff;
-  bj.nbuckets = W.nbins;
-  bj.bucket_of = W.bin_of;
-  if (int32_t rc = bucketize_run(bj, W.bz_ws, W.bz_bytes, st, s)) return rc;
-  o.nbins = H.read(W.nbins);
-  // pairs of multi-set bins
-  hipLaunchKernelGGL(k_put, dim3(1), dim3(1), 0, s, W.small, 9, 0u);
-  hipLaunchKernelGGL(k_pair_count, dim3(nblk(ns)), dim3(256), 0, s, W.bin_of, W.binoff, W.binmem, W.gsize, ns,
-                     W.cnt, W.small + 9);
-  o.multi = H.read(W.small + 9);
-  exscan_u32(W.cnt, W.poff, ns, W.scan_tmp, W.small + 0, s);
-  o.P = H.read(W.small + 0);
-  o.R = o.Kept = o.S = 0;
-  if (o.P == 0) return GEEK_OK;
-  hipLaunchKernelGGL(k_fill0, dim3(nblk(npos)), dim3(256), 0, s, W.flag, npos);
-  hipLaunchKernelGGL(k_mark_starts, dim3(nblk(ns)), dim3(256), 0, s, W.gstart, ns, base0, W.flag);
-  exscan_u32(W.flag, W.fscan, npos, W.scan_tmp, nullptr, s);
-  hipLaunchKernelGGL(k_pairs, dim3(nblk(npos)), dim3(256), 0, s, mem, npos, base0, W.flag, W.fscan, W.gstart,
-                     W.cnt, W.poff, W.bin_of, W.hi, W.lo);
-  // sort by (bin, id): lo is word 0, hi is word 1
-  int words[12], shifts[12], np = 0;
-  for (int sh = 0; sh < id_bits; sh += 8) {
-    words[np] = 0;
-    shifts[np++] = sh;
-  }
-  const int bb = bits_for(o.nbins ? o.nbins - 1 : 0);
-  for (int sh = 0; sh < bb; sh += 8) {
-    words[np] = 1;
-    shifts[np++] = sh;
-  }
-  RsView A{{W.lo, W.hi, nullptr, nullptr}, nullptr}, B{{W.lo2, W.hi2, nullptr, nullptr}, nullptr};
-  const int in_alt = radix_sort(A, B, 2, o.P, words, shifts, np, W.radix_tmp, s);
-  uint32_t* hi = in_alt ? W.hi2 : W.hi;
-  uint32_t* lo = in_alt ? W.lo2 : W.lo;
-  // runs of equal (bin, id) and the majority vote
-  hipLaunchKernelGGL(k_run_heads, dim3(nblk(o.P)), dim3(256), 0, s, hi, lo, (int64_t)o.P, W.h);
-  exscan_u32(W.h, W.hs, o.P, W.scan_tmp, W.hs + o.P, s);
-  hipLaunchKernelGGL(k_starts, dim3(nblk(o.P + 1)), dim3(256), 0, s, W.h, W.hs, (int64_t)o.P, W.rstart);
-  o.R = H.read(W.hs + o.P);
-  hipLaunchKernelGGL(k_keep, dim3(nblk(o.R)), dim3(256), 0, s, W.rstart, (int64_t)o.R, hi, W.binoff, W.kept);
-  exscan_u32(W.kept, W.kidx, o.R, W.scan_tmp, W.kidx + o.R, s);
-  hipLaunchKernelGGL(k_compact_runs, dim3(nblk(o.R)), dim3(256), 0, s, W.rstart, (int64_t)o.R, W.kept, W.kidx,
-                     hi, lo, W.khi, W.klo);
-  o.Kept = H.read(W.kidx + o.R);
-  if (o.Kept == 0) return GEEK_OK;
-  hipLaunchKernelGGL(k_seg_heads, dim3(nblk(o.Kept)), dim3(256), 0, s, W.khi, (int64_t)o.Kept, W.sflag);
-  exscan_u32(W.sflag, W.sscan, o.Kept, W.scan_tmp, W.sscan + o.Kept, s);
-  hipLaunchKernelGGL(k_starts, dim3(nblk(o.Kept + 1)), dim3(256), 0, s, W.sflag, W.sscan, (int64_t)o.Kept,
-                     W.sstart);
-  o.S = H.read(W.sscan + o.Kept);
-  return GEEK_OK;
-}
-
 int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s) {
-  if (J.n < 1 || J.T < 1 || J.K < 1 || J.K > 4 || J.L < 0 || !J.members || !J.offsets || !J.nbuckets ||
-      !J.silk_keys || !J.seed_offsets || !J.seed_members || !J.k_out || !J.needed || J.cap_k < 0 ||
-      J.cap_members < 0)
-    return GEEK_ERR_ARG;
-  if ((int64_t)J.T * J.n >= (1ll << 32) - 2) return GEEK_ERR_UNSUPPORTED;
+  if (int32_t rc = silk_check(J)) return rc;
   SilkWs W;
   if (!ws || ws_bytes < carve_silk(J, ws, W)) return GEEK_ERR_WORKSPACE;
-  Host H{s};
   prof_begin(GEEK_PROF_SILK, s);
-  const int K = J.K;
-  const int64_t Tn = (int64_t)J.T * J.n;
-  hipLaunchKernelGGL(k_tab_base, dim3(1), dim3(1), 0, s, J.nbuckets, J.T, W.base);
-  const uint32_t NB = H.read(W.base + J.T);
-  unsigned long long pairs = 0, multi = 0;
-  uint32_t cm = 0, cs = 0;  // members / sets of C so far
-  bool overflow = false;
-  uint64_t need_m = 0, need_s = 0;
-  const int id_bits = bits_for((uint64_t)(J.n - 1));
-  hipLaunchKernelGGL(k_extent, dim3(nblk(NB)), dim3(256), 0, s, J.offsets, W.base, J.T, J.n, (int64_t)NB,
-                     W.gstart, W.gsize);
+  const int K = J.K, T = J.T;
+  const int64_t n = J.n, Tn = W.Tn, Cc = W.Ccap;
+  SilkState* S = W.S;
+  // ---- setup: global buckets and the bucket of every (table, object)
+  hipLaunchKernelGGL(k_silk_setup, dim3(1), dim3(1), 0, s, J.nbuckets, T, n, W.base, S);
+  hipLaunchKernelGGL(k_extent, dim3(ggrid(Tn)), dim3(256), 0, s, J.offsets, W.base, T, n, S, W.gstart, W.gsize);
+  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Tn)), dim3(256), 0, s, W.flag, Tn, 0u);
+  hipLaunchKernelGGL(k_mark_starts, dim3(ggrid(Tn)), dim3(256), 0, s, W.gstart, &S->nb, W.flag);
+  exscan_u32(W.flag, W.fscan, Tn, W.scan_tmp, nullptr, s);
+  hipLaunchKernelGGL(k_bucket_of, dim3(ggrid(Tn)), dim3(256), 0, s, J.members, Tn, n, W.flag, W.fscan, W.bof);
+  // vote blocks: T LDS entries per thread
+  int VT = 256;
+  while (VT > 64 && VT * T > SV_LDS) VT >>= 1;
+  const size_t vlds = sizeof(uint32_t) * 2 * (size_t)T * VT;
+  const int vgrid = (int)std::min<int64_t>((n + VT - 1) / VT, 4096);
+  // kept pairs sorted by the emitted bin index (< number of buckets)
+  int kw[4], ksh[4], knp = 0;
+  for (int sh = 0; sh < bits_for((uint64_t)(Tn - 1)); sh += 8) {
+    kw[knp] = 0;
+    ksh[knp++] = sh;
+  }
   for (int t = 0; t < J.L; ++t) {
-    hipLaunchKernelGGL(k_put, dim3(1), dim3(1), 0, s, W.small + 8, 0, 0u);
-    hipLaunchKernelGGL(k_sig, dim3(nblk(NB)), dim3(256), 0, s, J.members, W.gstart, W.gsize, (int64_t)NB,
-                       J.silk_keys + 2 * t * K, K, W.G, W.big_list, W.small + 8);
-    hipLaunchKernelGGL(k_sig_big, dim3(512), dim3(256), 0, s, J.members, W.gstart, W.gsize,
-                       J.silk_keys + 2 * t * K, K, W.G, W.big_list, W.small + 8);
-    VoteOut o;
-    if (int32_t rc = vote_round(W, J.members, NB, 0u, Tn, K, id_bits, H, st, o)) return rc;
-    pairs += o.P;
-    multi += o.multi;
-    if (o.S == 0) continue;
-    hipLaunchKernelGGL(k_seg_emit_size, dim3(nblk(o.S)), dim3(256), 0, s, W.sstart, (int64_t)o.S, J.delta,
-                       W.esize, W.eone);
-    exscan_u32(W.esize, W.eoff, o.S, W.scan_tmp, W.eoff + o.S, s);
-    exscan_u32(W.eone, W.eidx, o.S, W.scan_tmp, W.eidx + o.S, s);
-    const uint32_t em = H.read(W.eoff + o.S), es = H.read(W.eidx + o.S);
-    need_m += em;
-    need_s += es;
-    if ((int64_t)cm + em > W.Ccap || (int64_t)cs + es > W.Ccap) {
-      overflow = true;
-      continue;
-    }
-    hipLaunchKernelGGL(k_seg_emit, dim3(nblk(o.S)), dim3(256), 0, s, W.sstart, (int64_t)o.S, W.esize, W.eoff,
-                       W.eidx, W.klo, cm, cs, W.cmem, W.coff);
-    if (em)
-      hipLaunchKernelGGL(k_seg_copy, dim3(nblk(em)), dim3(256), 0, s, W.sstart, (int64_t)o.S, W.eoff, W.klo, cm, em,
-                         W.cmem);
-    cm += em;
-    cs += es;
-  }
-  const unsigned long long hash_evals = (unsigned long long)K * J.L * Tn;
-  if (overflow) {
-    // C did not fit: report the capacities that make it fit (C holds up to
-    // 4 * cap_members members and sets)
-    hipLaunchKernelGGL(k_silk_capacity, dim3(1), dim3(1), 0, s, (unsigned long long)((need_s + 3) / 4),
-                       (unsigned long long)((need_m + 3) / 4), J.k_out, J.needed, J.counters, hash_evals,
-                       pairs, (unsigned long long)need_s, multi, st);
-    hipStreamSynchronize(s);
-    prof_end(GEEK_PROF_SILK, s);
-    return GEEK_OK;
-  }
-  if (cs == 0) {
-    hipLaunchKernelGGL(k_silk_finish, dim3(1), dim3(1), 0, s, 0u, 0u, (unsigned long long)J.cap_k,
-                       (unsigned long long)J.cap_members, J.seed_offsets, J.k_out, J.needed, J.counters,
-                       hash_evals, pairs, 0ull, multi, st);
-    hipLaunchKernelGGL(k_put, dim3(1), dim3(1), 0, s, J.seed_offsets, 0, 0u);
-    hipStreamSynchronize(s);
-    prof_end(GEEK_PROF_SILK, s);
-    return GEEK_OK;
+    const uint32_t* keys = J.silk_keys + 2 * (int64_t)t * K;
+    hipLaunchKernelGGL(k_sk_fill, dim3(1), dim3(64), 0, s, &S->big, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_sig, dim3(ggrid(Tn)), dim3(256), 0, s, J.members, W.gstart, W.gsize, &S->nb, keys, K, W.G,
+                       W.big_list, &S->big, &S->hash_evals);
+    hipLaunchKernelGGL(k_sig_big, dim3(512), dim3(256), 0, s, J.members, W.gstart, W.gsize, keys, K, W.G,
+                       W.big_list, &S->big, &S->hash_evals);
+    // bins of identical G
+    hipLaunchKernelGGL(k_ht_clear, dim3(SG_GRID), dim3(256), 0, s, S, W.ht, W.binmin, W.bcount, W.ksize);
+    hipLaunchKernelGGL(k_ht_insert, dim3(ggrid(Tn)), dim3(256), 0, s, W.G, K, S, W.ht, W.rep);
+    hipLaunchKernelGGL(k_ht_min, dim3(ggrid(Tn)), dim3(256), 0, s, W.rep, S, W.binmin, W.bcount);
+    hipLaunchKernelGGL(k_bin_info, dim3(ggrid(Tn)), dim3(256), 0, s, W.rep, W.binmin, W.bcount, S, W.info);
+    // majority votes and the bins that join C
+    hipLaunchKernelGGL(k_vote, dim3(vgrid), dim3(VT), vlds, s, W.bof, W.info, n, T, W.kbin, W.kc, W.ksize, S);
+    hipLaunchKernelGGL(k_emit_flags, dim3(ggrid(Tn)), dim3(256), 0, s, W.info, W.ksize, J.delta, S, W.eone, W.esz);
+    exscan_u32_dn(W.eone, W.eidx, Tn, &S->nb, W.scan_tmp, &S->es, s);
+    exscan_u32_dn(W.esz, W.eoff, Tn, &S->nb, W.scan_tmp, &S->em, s);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, S, (uint32_t)Cc);
+    // this table's sets of C, ids ascending
+    hipLaunchKernelGGL(k_count_kept, dim3(ggrid(n)), dim3(256), 0, s, W.kbin, W.kc, n, W.eone, S, W.kc2);
+    exscan_u32(W.kc2, W.kpos, n, W.scan_tmp, &S->kp, s);
+    hipLaunchKernelGGL(k_kept_pairs, dim3(ggrid(n)), dim3(256), 0, s, W.kbin, W.kc, n, W.eone, W.eidx, W.kpos, S,
+                       W.phi, W.plo);
+    RsView A{{W.phi, nullptr, nullptr, nullptr}, W.plo}, B{{W.phi2, nullptr, nullptr, nullptr}, W.plo2};
+    const int alt = radix_sort_dn(A, B, 1, W.KPmax, &S->kp, kw, ksh, knp, W.radix_tmp, s);
+    hipLaunchKernelGGL(k_c_write, dim3(ggrid(Tn)), dim3(256), 0, s, alt ? W.plo2 : W.plo, W.eone, W.eidx, W.eoff, S,
+                       W.cmem, W.coff);
   }
   // ---- de-duplication: one more table over the sets of C
-  hipLaunchKernelGGL(k_put, dim3(1), dim3(1), 0, s, W.coff, (int64_t)cs, cm);
-  hipLaunchKernelGGL(k_set_extent, dim3(nblk(cs)), dim3(256), 0, s, W.coff, (int64_t)cs, W.gstart, W.gsize);
-  hipLaunchKernelGGL(k_put, dim3(1), dim3(1), 0, s, W.small + 8, 0, 0u);
-  hipLaunchKernelGGL(k_sig, dim3(nblk(cs)), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, (int64_t)cs,
-                     J.silk_keys + 2 * J.L * K, K, W.G, W.big_list, W.small + 8);
-  hipLaunchKernelGGL(k_sig_big, dim3(512), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, J.silk_keys + 2 * J.L * K,
-                     K, W.G, W.big_list, W.small + 8);
-  VoteOut o;
-  if (int32_t rc = vote_round(W, W.cmem, cs, 0u, cm, K, id_bits, H, st, o)) return rc;
-  const int64_t nb2 = o.nbins;
-  hipLaunchKernelGGL(k_dedup_size, dim3(nblk(nb2)), dim3(256), 0, s, W.binoff, W.binmem, nb2, W.gsize, W.ssize,
-                     W.src_kind);
-  if (o.S)
-    hipLaunchKernelGGL(k_dedup_multi, dim3(nblk(o.S)), dim3(256), 0, s, W.sstart, (int64_t)o.S, W.khi, J.delta,
-                       W.ssize, W.segof);
-  // order bins by their K-tuple (word 0 most significant)
-  hipLaunchKernelGGL(k_bin_tuples, dim3(nblk(nb2)), dim3(256), 0, s, W.binoff, W.binmem, nb2, W.G, K, W.tw[0],
-                     W.tw[1], W.tw[2], W.tw[3], W.tv);
-  int words[16], shifts[16], np = 0;
+  const uint32_t* dkeys = J.silk_keys + 2 * (int64_t)J.L * K;
+  hipLaunchKernelGGL(k_dd_setup, dim3(1), dim3(1), 0, s, S, W.coff);
+  hipLaunchKernelGGL(k_set_extent, dim3(ggrid(Cc)), dim3(256), 0, s, W.coff, S, W.gstart, W.gsize);
+  hipLaunchKernelGGL(k_sk_fill, dim3(1), dim3(64), 0, s, &S->big, (int64_t)1, 0u);
+  hipLaunchKernelGGL(k_sig, dim3(ggrid(Cc)), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, &S->cs, dkeys, K, W.G,
+                     W.big_list, &S->big, (unsigned long long*)nullptr);
+  hipLaunchKernelGGL(k_sig_big, dim3(512), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, dkeys, K, W.G, W.big_list,
+                     &S->big, (unsigned long long*)nullptr);
+  hipLaunchKernelGGL(k_dd_tuples, dim3(ggrid(Cc)), dim3(256), 0, s, W.G, K, S, W.tw[0], W.tw[1], W.tw[2], W.tw[3],
+                     W.tv);
+  int tw[16], tsh[16], tnp = 0;
   for (int k = K - 1; k >= 0; --k)
     for (int sh = 0; sh < 32; sh += 8) {
-      words[np] = k;
-      shifts[np++] = sh;
+      tw[tnp] = k;
+      tsh[tnp++] = sh;
     }
-  RsView A{{W.tw[0], W.tw[1], W.tw[2], W.tw[3]}, W.tv}, B{{W.tw2[0], W.tw2[1], W.tw2[2], W.tw2[3]}, W.tv2};
-  const int in_alt = radix_sort(A, B, 4, nb2, words, shifts, np, W.radix_tmp, s);
-  const uint32_t* ord = in_alt ? W.tv2 : W.tv;
-  hipLaunchKernelGGL(k_order_sizes, dim3(nblk(nb2)), dim3(256), 0, s, ord, nb2, W.ssize, W.esize, W.eone);
-  exscan_u32(W.esize, W.eoff, nb2, W.scan_tmp, W.eoff + nb2, s);
-  exscan_u32(W.eone, W.eidx, nb2, W.scan_tmp, W.eidx + nb2, s);
-  const uint32_t tot_m = H.read(W.eoff + nb2), k = H.read(W.eidx + nb2);
-  if ((int64_t)k <= J.cap_k && (int64_t)tot_m <= J.cap_members) {
-    hipLaunchKernelGGL(k_emit_seeds, dim3(nblk(nb2)), dim3(256), 0, s, ord, nb2, W.esize, W.eoff, W.eidx,
-                       W.src_kind, W.binoff, W.binmem, W.cmem, W.coff, W.segof, W.sstart, W.klo, J.seed_offsets,
-                       J.seed_members);
-    if (tot_m)
-      hipLaunchKernelGGL(k_seed_copy, dim3(nblk(tot_m)), dim3(256), 0, s, ord, nb2, W.eoff, W.src_kind, W.binoff,
-                         W.binmem, W.cmem, W.coff, W.segof, W.sstart, W.klo, tot_m, J.seed_members);
+  RsView TA{{W.tw[0], W.tw[1], W.tw[2], W.tw[3]}, W.tv}, TB{{W.tw2[0], W.tw2[1], W.tw2[2], W.tw2[3]}, W.tv2};
+  const int talt = radix_sort_dn(TA, TB, 4, Cc, &S->cs, tw, tsh, tnp, W.radix_tmp, s);
+  const RsView& TS = talt ? TB : TA;
+  const uint32_t* ord = TS.v;
+  hipLaunchKernelGGL(k_dd_heads, dim3(ggrid(Cc)), dim3(256), 0, s, TS.k[0], TS.k[1], TS.k[2], TS.k[3], S, W.h);
+  exscan_u32_dn(W.h, W.hs, Cc, &S->cs, W.scan_tmp, &S->nb2, s);
+  hipLaunchKernelGGL(k_dd_bins, dim3(ggrid(Cc)), dim3(256), 0, s, W.h, W.hs, ord, S, W.binofr, W.bstart, W.inv);
+  hipLaunchKernelGGL(k_dd_cnt, dim3(ggrid(Cc)), dim3(256), 0, s, ord, W.binofr, W.bstart, W.gsize, S, W.cnt);
+  exscan_u32_dn(W.cnt, W.poff, Cc, &S->cs, W.scan_tmp, &S->P2, s);
+  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cc)), dim3(256), 0, s, W.flag, Cc + 1, 0u);
+  hipLaunchKernelGGL(k_mark_starts, dim3(ggrid(Cc)), dim3(256), 0, s, W.gstart, &S->cs, W.flag);
+  exscan_u32_dn(W.flag, W.fscan, Cc, &S->cm, W.scan_tmp, nullptr, s);
+  hipLaunchKernelGGL(k_dd_pairs, dim3(ggrid(Cc)), dim3(256), 0, s, W.cmem, W.flag, W.fscan, W.coff, W.inv, W.cnt,
+                     W.poff, W.binofr, S, W.phi, W.plo);
+  int pw[12], psh[12], pnp = 0;
+  for (int sh = 0; sh < bits_for((uint64_t)(n - 1)); sh += 8) {
+    pw[pnp] = 0;
+    psh[pnp++] = sh;
   }
-  hipLaunchKernelGGL(k_silk_finish, dim3(1), dim3(1), 0, s, k, tot_m, (unsigned long long)J.cap_k,
-                     (unsigned long long)J.cap_members, J.seed_offsets, J.k_out, J.needed, J.counters, hash_evals,
-                     pairs, (unsigned long long)cs, multi, st);
+  for (int sh = 0; sh < bits_for((uint64_t)(Cc - 1)); sh += 8) {
+    pw[pnp] = 1;
+    psh[pnp++] = sh;
+  }
+  RsView PA{{W.plo, W.phi, nullptr, nullptr}, nullptr}, PB{{W.plo2, W.phi2, nullptr, nullptr}, nullptr};
+  const int palt = radix_sort_dn(PA, PB, 2, Cc, &S->P2, pw, psh, pnp, W.radix_tmp, s);
+  const uint32_t* phi = palt ? W.phi2 : W.phi;
+  const uint32_t* plo = palt ? W.plo2 : W.plo;
+  hipLaunchKernelGGL(k_run_heads, dim3(ggrid(Cc)), dim3(256), 0, s, phi, plo, &S->P2, W.kept);
+  exscan_u32_dn(W.kept, W.kidx, Cc, &S->P2, W.scan_tmp, &S->R2, s);
+  hipLaunchKernelGGL(k_starts, dim3(ggrid(Cc + 1)), dim3(256), 0, s, W.kept, W.kidx, &S->P2, &S->R2, W.rstart);
+  hipLaunchKernelGGL(k_dd_keep, dim3(ggrid(Cc)), dim3(256), 0, s, W.rstart, phi, W.bstart, S, W.kept);
+  exscan_u32_dn(W.kept, W.kidx, Cc, &S->R2, W.scan_tmp, &S->kept2, s);
+  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cc)), dim3(256), 0, s, W.ksz2, Cc, 0u);
+  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cc)), dim3(256), 0, s, W.kstart, Cc, 0xFFFFFFFFu);
+  hipLaunchKernelGGL(k_dd_compact, dim3(ggrid(Cc)), dim3(256), 0, s, W.rstart, W.kept, W.kidx, phi, plo, S, W.klo,
+                     W.ksz2, W.kstart);
+  hipLaunchKernelGGL(k_dd_size, dim3(ggrid(Cc)), dim3(256), 0, s, W.bstart, ord, W.gsize, W.ksz2, J.delta, S,
+                     W.ssz, W.sone);
+  exscan_u32_dn(W.ssz, W.soff, Cc, &S->nb2, W.scan_tmp, &S->tot_m, s);
+  exscan_u32_dn(W.sone, W.sidx, Cc, &S->nb2, W.scan_tmp, &S->k, s);
+  hipLaunchKernelGGL(k_silk_finish, dim3(1), dim3(1), 0, s, S, (uint64_t)J.cap_k, (uint64_t)J.cap_members,
+                     J.seed_offsets, J.k_out, J.needed, J.counters, st);
+  hipLaunchKernelGGL(k_emit_seeds, dim3(ggrid(Cc)), dim3(256), 0, s, W.ssz, W.soff, W.sidx, S, J.seed_offsets);
+  hipLaunchKernelGGL(k_seed_copy, dim3(ggrid(Cc)), dim3(256), 0, s, W.soff, W.bstart, ord, W.cmem, W.coff, W.klo,
+                     W.kstart, S, J.seed_members);
   prof_end(GEEK_PROF_SILK, s);
-  hipStreamSynchronize(s);
   GEEK_LAUNCH_CHECK();
   return GEEK_OK;
 }

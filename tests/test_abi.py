@@ -63,6 +63,12 @@ def test_argument_errors_need_no_gpu():
     assert lib.geek_workspace_size(L.GEEK_OP_HASH, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_UNSUPPORTED
     bad = L.HashJob(kind=L.GEEK_HASH_DENSE, n=10, d=4, X=16, ldx=4, A=16, b=16, m=4, L=1, w=0.0, keys=16)
     assert lib.geek_hash(C.byref(bad), 1, None, 0, None, None) == L.GEEK_ERR_ARG
+    bad = L.HashJob(kind=L.GEEK_HASH_DOPH, n=10, F=4097, offsets=16, tokens=16, mh_keys=16, sig=16)
+    assert lib.geek_workspace_size(L.GEEK_OP_HASH, C.byref(bad), 1, C.byref(nb)) == L.GEEK_ERR_UNSUPPORTED
+    bad = L.HashJob(kind=L.GEEK_HASH_DOPH, n=10, F=400, offsets=16, tokens=16, mh_keys=None, sig=16)
+    assert lib.geek_hash(C.byref(bad), 1, None, 0, None, None) == L.GEEK_ERR_ARG
+    bad = L.HashJob(kind=7, n=10, F=400, offsets=16, tokens=16, mh_keys=16, sig=16)
+    assert lib.geek_hash(C.byref(bad), 1, None, 0, None, None) == L.GEEK_ERR_ARG
     assert lib.geek_status_string(L.GEEK_ERR_RANGE).decode() == "value outside the packable range"
     ok = L.BucketizeJob(n=1000, T=3, key_words=4, keys=16, table_stride=4000, row_stride=4,
                         members=16, offsets=16, nbuckets=16)

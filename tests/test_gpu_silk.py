@@ -101,3 +101,51 @@ def test_silk_over_minhash_bands():
     so, sm, ctr = api.silk_seeds(bm, bo, bn, n, Lb, 3, 20, 10, cuda(sk), check=len(ro) > 1)
     assert np.array_equal(host_u32(so), ro)
     assert np.array_equal(host_u32(sm), rm)
+
+
+def test_silk_pass_captured_in_one_graph():
+    # hash -> bucketize -> SILK recorded in one HIP graph (the SILK call reads
+    # nothing back to the host); every replay, with eager work and
+    # synchronizations between replays, gives the eager seeds bit for bit
+    api = gpu_api()
+    n, d, m, L, K, LS, delta = 4000, 32, 8, 16, 3, 20, 10
+    w = 4.0 * math.sqrt(d)
+    X, _, _ = dense_mixture(n, d, 20, -10, 10, 1.0, "equal", 0)
+    A, b = e2lsh_params(m * L, d, w, 0)
+    keys = cuda(key_words((LS + 1) * K, 0, STREAM_SILK))
+    Xg, Ag, bg = cuda(X), cuda(A), cuda(b)
+    cap_k, cap_m = 4096, 16000
+    announce(f"silk graph capture n={n}")
+
+    def chain(status):
+        kg, _ = api.hash_dense(Xg, Ag, bg, m, L, w, status=status, check=False)
+        bm, bo, bn, _ = api.bucketize(kg, n, L, 4, n * 4, 4, want_bucket_of=False, status=status, check=False)
+        return api.silk_seeds_async(bm, bo, bn, n, L, K, LS, delta, keys, cap_k, cap_m, status)
+
+    def seeds(out):
+        k = int(out["k_out"].item())
+        so = host_u32(out["seed_offsets"][:k + 1])
+        return so, host_u32(out["seed_members"][:int(so[-1])]), out["counters"].cpu().numpy()
+
+    st_e = api.new_status("cuda")
+    ref = seeds(chain(st_e))
+    assert int(st_e.item()) == 0 and len(ref[0]) > 2
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    st_g = api.new_status("cuda")
+    with torch.cuda.stream(side):
+        chain(st_g)  # warm-up on the side stream (workspace for that stream)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = chain(st_g)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        got = seeds(out)
+        assert int(st_g.item()) == 0, rep
+        for a, r in zip(got, ref):
+            assert np.array_equal(a, r), rep
+        chain(api.new_status("cuda"))  # eager work between replays
+        torch.cuda.synchronize()
