@@ -51,7 +51,9 @@ from .assign import (  # noqa: F401
     assign_hetero,
     assign_sig,
     centroids,
+    euclid_dist_pairs,
     euclid_dist_rows,
+    hetero_dist_pairs,
     modes,
     radius,
     sse,

@@ -66,6 +66,39 @@ def euclid_dist_rows(X, C):
     return acc
 
 
+def euclid_dist_pairs(X, C, idx, chunk=262144):
+    """Squared Euclidean distance of every row to one given centre,
+    ``D[i] = sum_t (x_it - c_{idx_i, t})^2``, in exactly the arithmetic of
+    ``euclid_dist_rows`` (t ascending, ``delta = x_it - c_jt``, ``acc <- acc +
+    delta * delta``, each operation rounded), so ``D[i] ==
+    euclid_dist_rows(X, C)[i, idx[i]]`` bit for bit.  Returns float64 [n]."""
+    X = np.asarray(X, dtype=np.float32)
+    C = np.asarray(C, dtype=np.float64)
+    idx = np.asarray(idx, dtype=np.int64)
+    n = X.shape[0]
+    out = np.empty(n, dtype=np.float64)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        Xc = np.ascontiguousarray(X[s:e].T).astype(np.float64)
+        Cc = np.ascontiguousarray(C[idx[s:e]].T)
+        acc = np.zeros(e - s, dtype=np.float64)
+        for t in range(X.shape[1]):
+            delta = Xc[t] - Cc[t]
+            acc += delta * delta
+        out[s:e] = acc
+    return out
+
+
+def hetero_dist_pairs(Xn, cat, Cn, Mc, idx, gamma=1.0):
+    """The heterogeneous distance of every row to one given seed, in the
+    arithmetic of ``assign_hetero``: ``euclid_dist_pairs`` of the numeric
+    attributes plus ``gamma * mismatches`` (float64).  Returns float64 [n]."""
+    idx = np.asarray(idx, dtype=np.int64)
+    dn = euclid_dist_pairs(Xn, Cn, idx)
+    mism = (np.asarray(cat) != np.asarray(Mc)[idx]).sum(axis=1).astype(np.float64)
+    return dn + np.float64(gamma) * mism
+
+
 def assign_euclid(X, C, chunk=2048):
     """One-pass assignment to the nearest centroid (Eq. (1)): returns
     ``(assign int32 [n], dist float64 [n])`` where dist is the squared

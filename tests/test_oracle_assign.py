@@ -135,3 +135,31 @@ def test_radius():
     dist = np.array([4.0, 9.0, 1.0, 0.0])
     a = np.array([0, 0, 2, 2])
     assert oracle.radius(dist, a, 4).tolist() == [3.0, 0.0, 1.0, 0.0]
+
+
+def test_dist_pairs_equal_full_rows_and_exact_values():
+    # the per-row distance to one given centre is the same number as the full
+    # distance matrix's entry (same arithmetic), and within the dot-product
+    # rounding bound of the exact rational value
+    g = np.random.default_rng(12)
+    X = g.uniform(-30, 30, size=(700, 13)).astype(np.float32)
+    C = g.uniform(-30, 30, size=(9, 13))
+    idx = g.integers(0, 9, size=700)
+    D = oracle.euclid_dist_rows(X, C)
+    got = oracle.euclid_dist_pairs(X, C, idx, chunk=128)
+    assert np.array_equal(got, D[np.arange(700), idx])
+    for i in range(0, 700, 97):
+        ex = _exact_d2(X[i], C[idx[i]])
+        assert abs(got[i] - float(ex)) <= _gamma(15) * float(ex) + 1e-300
+    # a 3-4-5 triangle and a zero distance
+    X2 = np.array([[3.0, 0.0], [1.5, -2.0]], dtype=np.float32)
+    C2 = np.array([[0.0, 4.0], [1.5, -2.0]])
+    assert oracle.euclid_dist_pairs(X2, C2, np.array([0, 1])).tolist() == [25.0, 0.0]
+    cat = g.integers(0, 3, size=(700, 5)).astype(np.int32)
+    Mc = g.integers(0, 3, size=(9, 5)).astype(np.int32)
+    for gamma in (1.0, 0.25):
+        h = oracle.hetero_dist_pairs(X, cat, C, Mc, idx, gamma)
+        a, dist = oracle.assign_hetero(X, cat, C, Mc, gamma)
+        assert np.array_equal(oracle.hetero_dist_pairs(X, cat, C, Mc, a, gamma), dist)
+        mism = (cat != Mc[idx]).sum(axis=1)
+        assert np.array_equal(h, D[np.arange(700), idx] + gamma * mism)
