@@ -370,6 +370,21 @@ int32_t geek_hash(const geek_hash_job* jobs, int32_t njobs, void* ws, size_t ws_
                   int32_t* d_status, void* stream);
 int32_t geek_bucketize(const geek_bucketize_job* jobs, int32_t njobs, void* ws,
                        size_t ws_bytes, int32_t* d_status, void* stream);
+
+/* geek_hash without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same jobs, outputs, status words and
+ * errors as geek_hash; the kernels' scratch is a library-owned device array
+ * of GEEK_NOALLOC_SCRATCH_BYTES per GPU (each GPU the call runs on holds it
+ * until the process ends).  A job whose workspace (geek_workspace_size)
+ * exceeds it -- e.g. heterogeneous rows with n * m * L above about 2^18 --
+ * returns GEEK_ERR_WORKSPACE before any work is enqueued.  The jobs run one
+ * after another on `stream`.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race, so the caller must order them. */
+#define GEEK_NOALLOC_SCRATCH_BYTES 1048576
+int32_t geek_hash_noalloc(const geek_hash_job* jobs, int32_t njobs, int32_t* d_status, void* stream);
 int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                         int32_t* d_status, void* stream);
 /* geek_assign with njobs > 1 and every job GEEK_METRIC_EUCLID in one

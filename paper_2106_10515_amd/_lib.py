@@ -104,7 +104,7 @@ class QuantileJob(C.Structure):
 EXPORTS = ("geek_workspace_size", "geek_hash", "geek_bucketize", "geek_silk_seeds",
            "geek_assign", "geek_regroup", "geek_quantile_buckets", "geek_status_string", "geek_version", "geek_last_hip_error",
            "geek_profile", "geek_profile_read", "geek_wallclock_hz", "geek_set_scan_tiles",
-           "geek_get_scan_tiles")
+           "geek_get_scan_tiles", "geek_hash_noalloc")
 
 GEEK_PROF_E2LSH, GEEK_PROF_BUCKETIZE, GEEK_PROF_ASSIGN_SCAN, GEEK_PROF_ASSIGN = 0, 1, 2, 3
 GEEK_PROF_MINHASH, GEEK_PROF_SILK, GEEK_PROF_BZ_SORT = 4, 5, 6
@@ -127,6 +127,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [C.POINTER(jt), C.c_int32, P, C.c_size_t, P, P]
         f.restype = C.c_int32
+    lib.geek_hash_noalloc.argtypes = [C.POINTER(HashJob), C.c_int32, P, P]
+    lib.geek_hash_noalloc.restype = C.c_int32
     lib.geek_status_string.argtypes = [C.c_int32]
     lib.geek_status_string.restype = C.c_char_p
     lib.geek_version.restype = C.c_char_p

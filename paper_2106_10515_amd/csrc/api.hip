@@ -157,6 +157,8 @@ static int32_t check_hash(const geek_hash_job& J) {
   return GEEK_OK;
 }
 
+int32_t hash_check(const geek_hash_job& J) { return check_hash(J); }
+
 static int32_t check_bz(const geek_bucketize_job& J) {
   if (J.n < 1 || J.n >= (1ll << 31) || J.T < 1 || J.T > 65535) return GEEK_ERR_ARG;
   if (J.key_words < 1 || J.key_words > 4) return GEEK_ERR_ARG;

@@ -19,6 +19,8 @@
 
 #include <type_traits>
 
+#include <mutex>
+
 #include "common.hpp"
 
 namespace geek {
@@ -580,4 +582,54 @@ int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st,
   return GEEK_OK;
 }
 
+// ---------------------------------------------------------------- no allocation
+// geek_hash_noalloc keeps its scratch (the projections' norms, the codes of
+// heterogeneous rows) in this file-scope device array instead of a caller
+// workspace.  Each GPU holds its own copy; host code takes the copy's device
+// address from hipGetSymbolAddress once per device and never passes the
+// array's name itself to a kernel.
+__device__ __align__(256) unsigned char scratch[GEEK_NOALLOC_SCRATCH_BYTES];
+
+int32_t hash_check(const geek_hash_job& J);
+
+namespace {
+constexpr int NA_DEVS = 64;
+std::mutex g_na_mu;
+void* g_na_ptr[NA_DEVS];  // scratch's device address per device, null until looked up
+
+int32_t scratch_ptr(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= NA_DEVS) return GEEK_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> g(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    g_na_ptr[dev] = p;
+  }
+  *out = g_na_ptr[dev];
+  return GEEK_OK;
+}
+}  // namespace
+
 }  // namespace geek
+
+extern "C" int32_t geek_hash_noalloc(const geek_hash_job* jobs, int32_t njobs, int32_t* d_status, void* stream) {
+  using namespace geek;
+  if (!jobs || njobs < 1) return GEEK_ERR_ARG;
+  for (int j = 0; j < njobs; ++j) {
+    if (int32_t rc = hash_check(jobs[j])) return rc;
+    if (ws_slice(hash_ws(jobs[j])) > (size_t)GEEK_NOALLOC_SCRATCH_BYTES) return GEEK_ERR_WORKSPACE;
+  }
+  void* ws = nullptr;
+  if (int32_t rc = scratch_ptr(&ws)) return rc;
+  // the jobs share the scratch, so they run one after another on `stream`;
+  // every kernel writes the scratch words it reads, nothing needs clearing
+  for (int j = 0; j < njobs; ++j) {
+    int32_t rc = hash_run(jobs[j], ws, GEEK_NOALLOC_SCRATCH_BYTES, d_status, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return GEEK_OK;
+}
