@@ -117,7 +117,14 @@ def test_full_assign_sampled_rows(big, prec):
     assert np.array_equal(out["assign"].cpu().numpy()[rows], a)
     got_dist = out["dist"].cpu().numpy()
     assert np.array_equal(got_dist[rows], dist)
-    assert out["sse"].item() == oracle.sse(got_dist)
+    # every row's distance to its assigned centroid, and the SSE, from the
+    # oracle's own arithmetic over all 10^7 rows
+    if "Xh" not in big:
+        big["Xh"] = big["X"].cpu().numpy()
+    announce(f"full size: oracle distances of all rows prec={prec}")
+    d_all = oracle.euclid_dist_pairs(big["Xh"], C, out["assign"].cpu().numpy())
+    assert np.array_equal(got_dist, d_all)
+    assert out["sse"].item() == oracle.sse(d_all)
     if prec == 1:
         big["assign"] = out["assign"]
 

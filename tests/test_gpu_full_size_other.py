@@ -92,19 +92,27 @@ def test_full_hetero():
     announce("full size hetero: bucketize")
     mem, boff, nb, _ = api.bucketize(sig, n, L, K, K, K * L, want_bucket_of=False)
     _band_csr_properties(sig, mem[0], boff[0], nb[0], 0, K)
-    announce("full size hetero: assign (BF16 numeric part)")
     so, sm = planted_seeds(lab, cfg["clusters"], 32)
     k = len(so) - 1
-    out = api.assign_hetero(Xg, catg, torch.from_numpy(so.view(np.int32)).cuda(),
-                            torch.from_numpy(sm.view(np.int32)).cuda(), k, 1.0, 1)
     Cn = oracle.centroids(X, so, sm)
     Mc = oracle.modes(cat, so, sm)
-    assert np.array_equal(out["centroids"].cpu().numpy(), Cn)
-    assert np.array_equal(out["modes"].cpu().numpy(), Mc)
     a, dist = oracle.assign_hetero(X[rows], cat[rows], Cn, Mc, 1.0)
-    assert np.array_equal(out["assign"].cpu().numpy()[rows], a)
-    assert np.array_equal(out["dist"].cpu().numpy()[rows], dist)
-    assert out["sse"].item() == oracle.sse(out["dist"].cpu().numpy())
+    # FP8 (e4m3) numeric part as the workload states it, then BF16
+    for prec in (2, 1):
+        announce(f"full size hetero: assign prec={prec}")
+        out = api.assign_hetero(Xg, catg, torch.from_numpy(so.view(np.int32)).cuda(),
+                                torch.from_numpy(sm.view(np.int32)).cuda(), k, 1.0, prec)
+        assert np.array_equal(out["centroids"].cpu().numpy(), Cn)
+        assert np.array_equal(out["modes"].cpu().numpy(), Mc)
+        got_a = out["assign"].cpu().numpy()
+        assert np.array_equal(got_a[rows], a)
+        got_d = out["dist"].cpu().numpy()
+        assert np.array_equal(got_d[rows], dist)
+        # every row's distance to its assigned seed and the SSE from the
+        # oracle's arithmetic over all rows
+        d_all = oracle.hetero_dist_pairs(X, cat, Cn, Mc, got_a, 1.0)
+        assert np.array_equal(got_d, d_all)
+        assert out["sse"].item() == oracle.sse(d_all)
 
 
 def test_full_batched_jobs():
@@ -177,3 +185,41 @@ def test_full_silk_pass_properties():
     seg = np.repeat(np.arange(k), sizes)
     inner = seg[1:] == seg[:-1]
     assert (sm[1:][inner].astype(np.int64) > sm[:-1][inner].astype(np.int64)).all()
+
+
+def test_full_silk_pass_matches_oracle_digest(golden_dir):
+    # the SILK pass at 10^6 points (numpy-drawn mixture, 32 tables, K_S = 3,
+    # L_S = 20, delta = 10) against the oracle's seed CSR, stored as digests
+    # by tests/golden/make_silk_dense_1e6.py (oracle only)
+    import hashlib
+    import json
+    import os
+
+    from workloads import dense_mixture
+    from workloads.gen import STREAM_SILK
+
+    api = gpu_api()
+    with open(os.path.join(golden_dir, "silk_dense_1e6.json")) as f:
+        ref = json.load(f)
+    cfg = CONFIGS["dense_large"]
+    n, d, m, L = ref["n"], cfg["d"], cfg["m"], cfg["L"]
+    w = cfg["w"] * d ** 0.5
+    K, LS, delta = cfg["K_S"], cfg["L_S"], cfg["delta"]
+    announce(f"full size silk vs oracle digest: n={n}")
+    X, _, _ = dense_mixture(n, d, cfg["clusters"] * n // cfg["n"], cfg["lo"], cfg["hi"], cfg["sigma"], cfg["sizes"],
+                            seed=0)
+    A, b = e2lsh_params(m * L, d, w, 0)
+    keys = torch.from_numpy(key_words((LS + 1) * K, 0, STREAM_SILK).view(np.int32)).cuda()
+    kg, _ = api.hash_dense(torch.from_numpy(X).cuda(), torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda(), m, L, w)
+    bm, bo, bn, _ = api.bucketize(kg, n, L, 4, n * 4, 4, want_bucket_of=False)
+    assert int(bn.sum()) == ref["buckets_total"]
+    so, sm, ctr = api.silk_seeds(bm, bo, bn, n, L, K, LS, delta, keys)
+    so, sm, ctr = host_u32(so), host_u32(sm), ctr.cpu().numpy()
+    assert len(so) - 1 == ref["k"] and len(sm) == ref["members"]
+    assert ctr[0] == ref["hash_evals"] and ctr[1] == ref["pairs_voted"] and ctr[2] == ref["multiset"]
+    for j, seed in ref["sample_seeds"].items():
+        j = int(j)
+        assert int(so[j + 1] - so[j]) == seed["size"], j
+        assert sm[so[j]:so[j + 1]][:64].tolist() == seed["first"], j
+    assert hashlib.sha256(so.astype("<u4").tobytes()).hexdigest() == ref["sha256_seed_offsets"]
+    assert hashlib.sha256(sm.astype("<u4").tobytes()).hexdigest() == ref["sha256_seed_members"]
