@@ -194,14 +194,16 @@ typedef struct geek_bucketize_job {
  * lexicographic K-tuple of their de-duplication bin, members ascending.
  * Output CSR: seed j = seed_members[seed_offsets[j] .. seed_offsets[j+1]).
  * A bin contributes only a non-empty C_shared (delta < 1 acts as delta = 1).
- * The intermediate multiset C is held in the workspace with room for
- * 4 * cap_members sets and 4 * cap_members members.  If C or the outputs do
- * not fit, *needed = {seeds, members} (for C: the cap_k and cap_members that
- * make it fit) and GEEK_ERR_CAPACITY is set (outputs unspecified); no seed
- * sets GEEK_ERR_NO_SEEDS.  The call never reads sizes back to the host.
- * Requires 1 <= T <= 128 (GEEK_ERR_UNSUPPORTED above), T * n < 2^31 and
- * 4 * cap_members < 2^31.  The workspace grows with T * n (about 100 bytes
- * per (table, object)) and with cap_members (about 140 bytes each).
+ * The intermediate multiset C is held in the workspace with room for cap_c
+ * members (4 * cap_members when cap_c is 0) and cap_c / max(delta, 1) + 1
+ * sets.  needed [3] = {seeds, seed members, members of C}; if C does not fit,
+ * needed = {0, 0, the cap_c that fits} and GEEK_ERR_CAPACITY is set; if the
+ * seeds do not fit cap_k / cap_members, needed holds their sizes and
+ * GEEK_ERR_CAPACITY is set (outputs unspecified either way); no seed sets
+ * GEEK_ERR_NO_SEEDS.  The call never reads sizes back to the host.
+ * Requires 1 <= T <= 128 (GEEK_ERR_UNSUPPORTED above), T * n < 2^31 and a C
+ * capacity below 2^31.  The workspace grows with T * n (about 100 bytes per
+ * (table, object)) and with the C capacity (about 50 bytes per member).
  */
 typedef struct geek_silk_job {
   int64_t n;                /* objects */
@@ -218,10 +220,12 @@ typedef struct geek_silk_job {
   uint32_t* seed_offsets;   /* out [cap_k+1] */
   uint32_t* seed_members;   /* out [cap_members] */
   uint32_t* k_out;          /* out [1] number of seeds */
-  unsigned long long* needed;   /* out [2] seeds, members needed */
+  unsigned long long* needed;   /* out [3] seeds, seed members, members of C */
   unsigned long long* counters; /* optional out [4]: hash evaluations,
                                    voted (bin, id) pairs, |C| before
                                    de-duplication, multi-bucket bins */
+  int64_t cap_c;            /* room of the multiset C in members (workspace);
+                               0 = 4 * cap_members */
 } geek_silk_job;
 
 /* ---- geek_assign --------------------------------------------------------

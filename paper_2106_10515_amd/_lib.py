@@ -72,6 +72,7 @@ class SilkJob(C.Structure):
         ("L", C.c_int32), ("delta", C.c_int32), ("silk_keys", P),
         ("cap_k", C.c_int64), ("cap_members", C.c_int64),
         ("seed_offsets", P), ("seed_members", P), ("k_out", P), ("needed", P), ("counters", P),
+        ("cap_c", C.c_int64),
     ]
 
 

@@ -205,45 +205,46 @@ def bucketize_batch(problems, want_bucket_of=True, status=None, check=True):
 
 # ---------------------------------------------------------------- geek_silk_seeds
 def silk_seeds_async(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys, cap_k, cap_members,
-                     status):
+                     status, cap_c=0):
     """One geek_silk_seeds call with the given capacities; nothing is read
     back to the host, so it may be recorded in a HIP graph.  Returns the
     untrimmed device outputs ``dict(seed_offsets [cap_k+1], seed_members
-    [cap_members], k_out [1], needed [2], counters [4])``."""
+    [cap_members], k_out [1], needed [3], counters [4])``."""
     dev = _dev(members)
     out = dict(seed_offsets=torch.empty((cap_k + 1,), dtype=torch.int32, device=dev),
                seed_members=torch.empty((cap_members,), dtype=torch.int32, device=dev),
                k_out=torch.empty((1,), dtype=torch.int32, device=dev),
-               needed=torch.empty((2,), dtype=torch.int64, device=dev),
+               needed=torch.empty((3,), dtype=torch.int64, device=dev),
                counters=torch.empty((4,), dtype=torch.int64, device=dev))
     j = L.SilkJob(n=n, T=T, K=K, members=_p(members), offsets=_p(offsets), nbuckets=_p(nbuckets),
                   L=L_silk, delta=delta, silk_keys=_p(silk_keys), cap_k=cap_k,
                   cap_members=cap_members, seed_offsets=_p(out["seed_offsets"]),
                   seed_members=_p(out["seed_members"]), k_out=_p(out["k_out"]), needed=_p(out["needed"]),
-                  counters=_p(out["counters"]))
+                  counters=_p(out["counters"]), cap_c=cap_c)
     _run(L.GEEK_OP_SILK, L.geek_silk_seeds, [j], dev, status)
     return out
 
 
 def silk_seeds(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys,
-               cap_k=None, cap_members=None, status=None, check=True):
+               cap_k=None, cap_members=None, cap_c=None, status=None, check=True):
     """SILK seeds.  Returns ``(seed_offsets [k+1], seed_members [N_C],
     counters [4])`` trimmed to the k seeds found (reads k back to the host;
     with the default capacities a call that reports too little room is
     repeated with the capacities it asked for)."""
     dev = _dev(members)
-    auto = cap_k is None and cap_members is None
+    auto = cap_k is None and cap_members is None and cap_c is None
     cap_k = cap_k or max(1024, n // 4)
-    cap_members = cap_members or max(4096, 2 * n)
+    cap_members = cap_members or max(4096, 16 * n)
+    cap_c = cap_c if cap_c is not None else max(16384, 24 * n)
     status = new_status(dev) if status is None else status
     for attempt in range(4):
         out = silk_seeds_async(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys, cap_k,
-                               cap_members, status)
+                               cap_members, status, cap_c)
         # default capacities too small: the call reported what it needs (first
         # for the intermediate multiset, then for the seeds); call again
         if auto and attempt < 3 and int(status.item()) == L.GEEK_ERR_CAPACITY:
-            nk, nm = (int(v) for v in out["needed"].cpu().tolist())
-            cap_k, cap_members = max(cap_k, nk), max(cap_members, nm)
+            nk, nm, nc = (int(v) for v in out["needed"].cpu().tolist())
+            cap_k, cap_members, cap_c = max(cap_k, nk), max(cap_members, nm), max(cap_c, nc)
             status.zero_()
             continue
         break

@@ -372,10 +372,14 @@ __device__ __forceinline__ void scan_tiles(
     auto t2_update = [&](int cb, const f32x16& t, int gb) {
       const float a1_prev = a1[cb];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const float tb = __uint_as_float((__float_as_uint(t[r]) & ~15u) | (uint32_t)r);
-        a2[cb] = __builtin_amdgcn_fmed3f(a1[cb], a2[cb], tb);            // second best
-        a1[cb] = __builtin_amdgcn_fmed3f(a1[cb], tb, 3.402823466e38f);  // best
+      for (int r = 0; r < 16; r += 2) {
+        const float u = __uint_as_float((__float_as_uint(t[r]) & ~15u) | (uint32_t)r);
+        const float v = __uint_as_float((__float_as_uint(t[r + 1]) & ~15u) | (uint32_t)(r + 1));
+        // with a1 >= a2: the second best of {a1, a2, u, v} is
+        // max(a2, median(a1, u, v)); the best is max(a1, u, v)
+        const float mid = __builtin_amdgcn_fmed3f(a1[cb], u, v);
+        a1[cb] = fmaxf(fmaxf(a1[cb], u), v);
+        a2[cb] = fmaxf(a2[cb], mid);
       }
       blk[cb] = a1[cb] != a1_prev ? gb : blk[cb];
     };

@@ -33,7 +33,7 @@
 
 namespace geek {
 
-constexpr int SK_BIG = 64;       // buckets larger than this are hashed by a block
+constexpr int SK_BIG = 64;       // buckets larger than this are hashed by a wavefront
 constexpr int SG_GRID = 2048;    // blocks of the grid-stride kernels
 constexpr int SV_LDS = 8192;     // LDS entries (two words each) of a vote block
 constexpr int SILK_MAX_T = 128;  // transform tables the vote kernel holds in LDS
@@ -168,26 +168,31 @@ __global__ __launch_bounds__(256) void k_sig(const uint32_t* __restrict__ mem, c
   if (evals) block_add(done, evals);
 }
 
+// Signatures of the queued large sets: one wavefront per set, the lanes
+// striding over its members, then a shuffle reduction of the K minima.
 __global__ __launch_bounds__(256) void k_sig_big(const uint32_t* __restrict__ mem,
                                                  const uint32_t* __restrict__ gstart,
                                                  const uint32_t* __restrict__ gsize,
                                                  const uint32_t* __restrict__ keys, int K,
                                                  uint32_t* __restrict__ G, const uint32_t* big_list,
                                                  const uint32_t* big_count, unsigned long long* evals) {
-  __shared__ uint32_t red[4][256];
   const uint32_t nbig = *big_count;
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwave = (gridDim.x * blockDim.x) >> 6;
   uint32_t a[4], b[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     a[k] = k < K ? (keys[2 * k] | 1u) : 1u;
     b[k] = k < K ? keys[2 * k + 1] : 0u;
   }
-  for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+  unsigned long long done = 0;
+  for (uint32_t bi = wave; bi < nbig; bi += nwave) {
     const uint32_t g = big_list[bi];
     uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
     const uint32_t* p = mem + gstart[g];
     const uint32_t sz = gsize[g];
-    for (uint32_t q = threadIdx.x; q < sz; q += blockDim.x) {
+    for (uint32_t q = lane; q < sz; q += 64) {
       const uint32_t y = fmix32(p[q]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -196,22 +201,18 @@ __global__ __launch_bounds__(256) void k_sig_big(const uint32_t* __restrict__ me
       }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = mn[k];
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if ((int)threadIdx.x < o) {
+    for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t v = red[k][threadIdx.x + o];
-          if (v < red[k][threadIdx.x]) red[k][threadIdx.x] = v;
-        }
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t v = (uint32_t)__shfl_xor((int)mn[k], o);
+        mn[k] = v < mn[k] ? v : mn[k];
       }
-      __syncthreads();
-    }
-    if (threadIdx.x < (unsigned)K) G[(int64_t)g * K + threadIdx.x] = red[threadIdx.x][0];
-    if (threadIdx.x == 0 && evals) atomicAdd(evals, (unsigned long long)sz * K);
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (lane == k && k < K) G[(int64_t)g * K + k] = mn[k];
+    done += (unsigned long long)sz * K;
   }
+  if (evals && lane == 0 && done) atomicAdd(evals, done);
 }
 
 // ---- bins of identical G (SILK tables) ---------------------------------------
@@ -338,6 +339,56 @@ __global__ __launch_bounds__(256) void k_vote(const uint32_t* __restrict__ bof, 
   block_add(pairs, &S->pairs);
 }
 
+// The same vote with the object's T <= TT bin ids in registers
+// (compile-time indices, no LDS round trips): entries of bins with fewer than
+// two buckets, and entries past T, hold no bin.  A bin's size is read back
+// from its smallest bucket's entry (info[bin] = (bin, size)) once per
+// distinct bin.
+template <int TT>
+__global__ __launch_bounds__(256) void k_vote_reg(const uint32_t* __restrict__ bof, const uint2* __restrict__ info,
+                                                  int64_t n, int T, uint32_t* __restrict__ kbin,
+                                                  uint32_t* __restrict__ kc, uint32_t* __restrict__ ksize,
+                                                  SilkState* S) {
+  constexpr uint32_t NONE = 0xFFFFFFFFu;
+  const uint32_t NB = S->nb;
+  unsigned long long pairs = 0;
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    uint32_t lb[TT];
+#pragma unroll
+    for (int t = 0; t < TT; ++t) {
+      lb[t] = NONE;
+      if (t < T) {
+        const uint32_t g = bof[(int64_t)t * n + i];
+        const uint2 e = g < NB ? info[g] : make_uint2(0u, 0u);  // bounded even for a malformed CSR
+        if (e.y >= 2u) {
+          lb[t] = e.x;
+          ++pairs;
+        }
+      }
+    }
+    uint32_t kept = 0;
+#pragma unroll
+    for (int a = 0; a < TT; ++a) {
+      uint32_t cnt = 0;
+      bool first = true;
+#pragma unroll
+      for (int q = 0; q < TT; ++q) {
+        const bool eq = lb[q] == lb[a];
+        cnt += eq ? 1u : 0u;
+        if (q < a) first = first && !eq;
+      }
+      // a majority needs cnt >= 2 (2 * cnt > size >= 2)
+      if (lb[a] != NONE && first && cnt >= 2u && 2u * cnt > info[lb[a]].y) {
+        kbin[(int64_t)kept * n + i] = lb[a];
+        ++kept;
+        atomicAdd(&ksize[lb[a]], 1u);
+      }
+    }
+    kc[i] = kept;
+  }
+  block_add(pairs, &S->pairs);
+}
+
 // Bins that join C: named by their smallest bucket, two or more buckets,
 // C_shared non-empty and of at least delta ids.
 __global__ void k_emit_flags(const uint2* __restrict__ info, const uint32_t* __restrict__ ksize, int delta,
@@ -353,15 +404,15 @@ __global__ void k_emit_flags(const uint2* __restrict__ info, const uint32_t* __r
   }
 }
 
-// Room in C for this table's sets (C holds ccap sets and ccap members); once
+// Room in C for this table's sets (C holds scap sets and mcap members); once
 // C has run out of room no later table writes to it, but the sizes needed are
 // still counted.
-__global__ void k_commit(SilkState* S, uint32_t ccap) {
+__global__ void k_commit(SilkState* S, uint32_t scap, uint32_t mcap) {
   if (blockIdx.x || threadIdx.x) return;
   const uint32_t es = S->es, em = S->em;
   S->need_s += es;
   S->need_m += em;
-  if (!S->over && (uint64_t)S->cs + es <= ccap && (uint64_t)S->cm + em <= ccap) {
+  if (!S->over && (uint64_t)S->cs + es <= scap && (uint64_t)S->cm + em <= mcap) {
     S->fit = 1u;
     S->base_s = S->cs;
     S->base_m = S->cm;
@@ -534,14 +585,24 @@ __global__ void k_dd_keep(const uint32_t* __restrict__ rstart, const uint32_t* _
 __global__ void k_dd_compact(const uint32_t* __restrict__ rstart, const uint32_t* __restrict__ kept,
                              const uint32_t* __restrict__ kidx, const uint32_t* __restrict__ hi,
                              const uint32_t* __restrict__ lo, const SilkState* S, uint32_t* __restrict__ klo,
-                             uint32_t* __restrict__ ksz, uint32_t* __restrict__ kstart) {
+                             uint32_t* __restrict__ khi) {
   const uint32_t R = S->R2;
   for (uint32_t r = gtid(); r < R; r += gstride()) {
     if (!kept[r]) continue;
-    const uint32_t b = hi[rstart[r]];
+    khi[kidx[r]] = hi[rstart[r]];
     klo[kidx[r]] = lo[rstart[r]];
-    atomicAdd(&ksz[b], 1u);
-    atomicMin(&kstart[b], kidx[r]);
+  }
+}
+
+// The kept ids are sorted by bin: each bin's run [kstart, kend) from the run
+// boundaries (bins with no kept id keep 0, 0).
+__global__ void k_dd_kruns(const uint32_t* __restrict__ khi, const SilkState* S, uint32_t* __restrict__ kstart,
+                           uint32_t* __restrict__ kend) {
+  const uint32_t K2 = S->kept2;
+  for (uint32_t q = gtid(); q < K2; q += gstride()) {
+    const uint32_t b = khi[q];
+    if (q == 0 || khi[q - 1] != b) kstart[b] = q;
+    if (q + 1 == K2 || khi[q + 1] != b) kend[b] = q + 1;
   }
 }
 
@@ -549,15 +610,17 @@ __global__ void k_dd_compact(const uint32_t* __restrict__ rstart, const uint32_t
 // single set passes through; several sets keep their voted ids when at least
 // delta (and at least one) of them remain.
 __global__ void k_dd_size(const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ ord,
-                          const uint32_t* __restrict__ gsize, const uint32_t* __restrict__ ksz, int delta,
-                          const SilkState* S, uint32_t* __restrict__ ssz, uint32_t* __restrict__ one) {
+                          const uint32_t* __restrict__ gsize, const uint32_t* __restrict__ kstart,
+                          const uint32_t* __restrict__ kend, int delta, const SilkState* S,
+                          uint32_t* __restrict__ ssz, uint32_t* __restrict__ one) {
   const uint32_t nb2 = S->nb2;
   const uint32_t dmin = delta > 1 ? (uint32_t)delta : 1u;
   for (uint32_t b = gtid(); b < nb2; b += gstride()) {
     const uint32_t bs = bstart[b + 1] - bstart[b];
+    const uint32_t kz = kend[b] - kstart[b];
     uint32_t v;
     if (bs == 1u) v = gsize[ord[bstart[b]]];
-    else v = ksz[b] >= dmin ? ksz[b] : 0u;
+    else v = kz >= dmin ? kz : 0u;
     ssz[b] = v;
     one[b] = v ? 1u : 0u;
   }
@@ -575,11 +638,11 @@ __global__ void k_silk_finish(SilkState* S, uint64_t cap_k, uint64_t cap_m, uint
     counters[3] = S->multi;
   }
   if (S->over) {
-    // C did not fit (it holds 4 * cap_members sets and members): report the
-    // capacities that make it fit
-    const unsigned long long c = S->need_s > S->need_m ? S->need_s : S->need_m;
-    needed[0] = (S->need_s + 3) / 4;
-    needed[1] = (c + 3) / 4;
+    // C did not fit: report the room for its members that makes it fit (the
+    // seeds are not known yet)
+    needed[0] = 0;
+    needed[1] = 0;
+    needed[2] = S->need_m;
     *k_out = 0;
     set_status(st, GEEK_ERR_CAPACITY);
     return;
@@ -587,6 +650,7 @@ __global__ void k_silk_finish(SilkState* S, uint64_t cap_k, uint64_t cap_m, uint
   const uint32_t k = S->cs ? S->k : 0u, m = S->cs ? S->tot_m : 0u;
   needed[0] = k;
   needed[1] = m;
+  needed[2] = S->cm;
   if (k > cap_k || m > cap_m) {
     *k_out = 0;
     set_status(st, GEEK_ERR_CAPACITY);
@@ -637,7 +701,7 @@ __global__ void k_seed_copy(const uint32_t* __restrict__ soff, const uint32_t* _
 
 // ---------------------------------------------------------------- host side
 struct SilkWs {
-  int64_t Tn, Ccap, KPmax, NS;  // NS = max(Tn, Ccap): sets of either phase
+  int64_t Tn, Ccap, Cs, KPmax, NS, NM;  // C's members / sets; NS, NM: sets, positions of either phase
   uint32_t ht_slots;
   SilkState* S;
   uint32_t *base, *gstart, *gsize, *G, *bof, *flag, *fscan, *ht, *rep, *binmin, *bcount, *ksize;
@@ -646,21 +710,29 @@ struct SilkWs {
   uint32_t *phi, *plo, *phi2, *plo2;
   uint32_t *cmem, *coff;
   uint32_t *tw[4], *tv, *tw2[4], *tv2;
-  uint32_t *h, *hs, *binofr, *bstart, *inv, *cnt, *poff, *rstart, *kept, *kidx, *klo, *ksz2, *kstart;
+  uint32_t *h, *hs, *binofr, *bstart, *inv, *cnt, *poff, *rstart, *kept, *kidx, *klo, *khi, *kend, *kstart;
   uint32_t *ssz, *sone, *soff, *sidx;
   uint32_t *big_list, *radix_tmp, *scan_tmp;
 };
 
+// Room of the multiset C: cap_c members (4 * cap_members when cap_c is 0);
+// every set of C holds at least max(delta, 1) members, which bounds its sets.
+static int64_t c_members(const geek_silk_job& J) {
+  return J.cap_c > 0 ? J.cap_c : 4 * (J.cap_members > 0 ? J.cap_members : 1);
+}
+
 static size_t carve_silk(const geek_silk_job& J, void* ws, SilkWs& W) {
   Carver c(ws);
   W.Tn = (int64_t)J.T * J.n;
-  W.Ccap = 4 * (J.cap_members > 0 ? J.cap_members : 1);
+  W.Ccap = c_members(J);
+  W.Cs = W.Ccap / (J.delta > 1 ? J.delta : 1) + 1;
   W.KPmax = (int64_t)((J.T + 1) / 2) * J.n;
-  W.NS = W.Tn > W.Ccap ? W.Tn : W.Ccap;
+  W.NS = W.Tn > W.Cs ? W.Tn : W.Cs;
+  W.NM = W.Tn > W.Ccap ? W.Tn : W.Ccap;
   uint64_t slots = 1024;
   while (slots < 2u * (uint64_t)W.Tn && slots < 0x80000000ull) slots <<= 1;
   W.ht_slots = (uint32_t)slots;
-  const int64_t NS = W.NS, Tn = W.Tn, Cc = W.Ccap;
+  const int64_t NS = W.NS, Tn = W.Tn, Cc = W.Ccap, Cs = W.Cs;
   const int64_t npairs = W.KPmax > Cc ? W.KPmax : Cc;
   W.S = c.take<SilkState>(1);
   W.base = c.take<uint32_t>(J.T + 1);
@@ -668,8 +740,8 @@ static size_t carve_silk(const geek_silk_job& J, void* ws, SilkWs& W) {
   W.gsize = c.take<uint32_t>(NS + 1);
   W.G = c.take<uint32_t>(NS * J.K);
   W.bof = c.take<uint32_t>(Tn);
-  W.flag = c.take<uint32_t>(NS + 1);
-  W.fscan = c.take<uint32_t>(NS + 1);
+  W.flag = c.take<uint32_t>(W.NM + 1);
+  W.fscan = c.take<uint32_t>(W.NM + 1);
   W.ht = c.take<uint32_t>(slots);
   W.rep = c.take<uint32_t>(Tn);
   W.binmin = c.take<uint32_t>(Tn);
@@ -688,32 +760,35 @@ static size_t carve_silk(const geek_silk_job& J, void* ws, SilkWs& W) {
   W.plo = c.take<uint32_t>(npairs);
   W.phi2 = c.take<uint32_t>(npairs);
   W.plo2 = c.take<uint32_t>(npairs);
+  // C and the de-duplication table: member-indexed, then set-indexed
   W.cmem = c.take<uint32_t>(Cc);
-  W.coff = c.take<uint32_t>(Cc + 1);
-  for (int w = 0; w < 4; ++w) W.tw[w] = c.take<uint32_t>(Cc);
-  W.tv = c.take<uint32_t>(Cc);
-  for (int w = 0; w < 4; ++w) W.tw2[w] = c.take<uint32_t>(Cc);
-  W.tv2 = c.take<uint32_t>(Cc);
-  W.h = c.take<uint32_t>(Cc + 1);
-  W.hs = c.take<uint32_t>(Cc + 1);
-  W.binofr = c.take<uint32_t>(Cc + 1);
-  W.bstart = c.take<uint32_t>(Cc + 2);
-  W.inv = c.take<uint32_t>(Cc + 1);
-  W.cnt = c.take<uint32_t>(Cc + 1);
-  W.poff = c.take<uint32_t>(Cc + 1);
   W.rstart = c.take<uint32_t>(Cc + 1);
   W.kept = c.take<uint32_t>(Cc + 1);
   W.kidx = c.take<uint32_t>(Cc + 1);
   W.klo = c.take<uint32_t>(Cc);
-  W.ksz2 = c.take<uint32_t>(Cc);
-  W.kstart = c.take<uint32_t>(Cc);
-  W.ssz = c.take<uint32_t>(Cc + 1);
-  W.sone = c.take<uint32_t>(Cc + 1);
-  W.soff = c.take<uint32_t>(Cc + 1);
-  W.sidx = c.take<uint32_t>(Cc + 1);
+  W.khi = c.take<uint32_t>(Cc);
+  W.coff = c.take<uint32_t>(Cs + 1);
+  for (int w = 0; w < 4; ++w) W.tw[w] = c.take<uint32_t>(Cs);
+  W.tv = c.take<uint32_t>(Cs);
+  for (int w = 0; w < 4; ++w) W.tw2[w] = c.take<uint32_t>(Cs);
+  W.tv2 = c.take<uint32_t>(Cs);
+  W.h = c.take<uint32_t>(Cs + 1);
+  W.hs = c.take<uint32_t>(Cs + 1);
+  W.binofr = c.take<uint32_t>(Cs + 1);
+  W.bstart = c.take<uint32_t>(Cs + 2);
+  W.inv = c.take<uint32_t>(Cs + 1);
+  W.cnt = c.take<uint32_t>(Cs + 1);
+  W.poff = c.take<uint32_t>(Cs + 1);
+  W.kend = c.take<uint32_t>(Cs);
+  W.kstart = c.take<uint32_t>(Cs);
+  W.ssz = c.take<uint32_t>(Cs + 1);
+  W.sone = c.take<uint32_t>(Cs + 1);
+  W.soff = c.take<uint32_t>(Cs + 1);
+  W.sidx = c.take<uint32_t>(Cs + 1);
   W.big_list = c.take<uint32_t>(NS + 1);
-  W.radix_tmp = c.take<uint32_t>(radix_tmp_words(npairs > NS ? npairs : NS));
-  W.scan_tmp = c.take<uint32_t>(exscan_tmp_words(NS + 1) + 16);
+  const int64_t nsort = npairs > NS ? npairs : NS;
+  W.radix_tmp = c.take<uint32_t>(radix_tmp_words(nsort));
+  W.scan_tmp = c.take<uint32_t>(exscan_tmp_words((W.NM > NS ? W.NM : NS) + 1) + 16);
   return c.used + 256;
 }
 
@@ -723,7 +798,7 @@ int32_t silk_check(const geek_silk_job& J) {
       J.cap_k < 0 || J.cap_members < 0)
     return GEEK_ERR_ARG;
   if (J.T > SILK_MAX_T) return GEEK_ERR_UNSUPPORTED;
-  if ((int64_t)J.T * J.n >= (1ll << 31) || 4 * (J.cap_members > 0 ? J.cap_members : 1) >= (1ll << 31) ||
+  if ((int64_t)J.T * J.n >= (1ll << 31) || J.cap_c < 0 || c_members(J) >= (1ll << 31) ||
       J.cap_k >= (1ll << 32) - 1)
     return GEEK_ERR_UNSUPPORTED;
   return GEEK_OK;
@@ -776,7 +851,7 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
     hipLaunchKernelGGL(k_sk_fill, dim3(1), dim3(64), 0, s, &S->big, (int64_t)1, 0u);
     hipLaunchKernelGGL(k_sig, dim3(ggrid(Tn)), dim3(256), 0, s, J.members, W.gstart, W.gsize, &S->nb, keys, K, W.G,
                        W.big_list, &S->big, &S->hash_evals);
-    hipLaunchKernelGGL(k_sig_big, dim3(512), dim3(256), 0, s, J.members, W.gstart, W.gsize, keys, K, W.G,
+    hipLaunchKernelGGL(k_sig_big, dim3(SG_GRID), dim3(256), 0, s, J.members, W.gstart, W.gsize, keys, K, W.G,
                        W.big_list, &S->big, &S->hash_evals);
     // bins of identical G
     hipLaunchKernelGGL(k_ht_clear, dim3(SG_GRID), dim3(256), 0, s, S, W.ht, W.binmin, W.bcount, W.ksize);
@@ -784,11 +859,18 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
     hipLaunchKernelGGL(k_ht_min, dim3(ggrid(Tn)), dim3(256), 0, s, W.rep, S, W.binmin, W.bcount);
     hipLaunchKernelGGL(k_bin_info, dim3(ggrid(Tn)), dim3(256), 0, s, W.rep, W.binmin, W.bcount, S, W.info);
     // majority votes and the bins that join C
-    hipLaunchKernelGGL(k_vote, dim3(vgrid), dim3(VT), vlds, s, W.bof, W.info, n, T, W.kbin, W.kc, W.ksize, S);
+    if (T <= 16)
+      hipLaunchKernelGGL(k_vote_reg<16>, dim3(ggrid(n)), dim3(256), 0, s, W.bof, W.info, n, T, W.kbin, W.kc,
+                         W.ksize, S);
+    else if (T <= 32)
+      hipLaunchKernelGGL(k_vote_reg<32>, dim3(ggrid(n)), dim3(256), 0, s, W.bof, W.info, n, T, W.kbin, W.kc,
+                         W.ksize, S);
+    else
+      hipLaunchKernelGGL(k_vote, dim3(vgrid), dim3(VT), vlds, s, W.bof, W.info, n, T, W.kbin, W.kc, W.ksize, S);
     hipLaunchKernelGGL(k_emit_flags, dim3(ggrid(Tn)), dim3(256), 0, s, W.info, W.ksize, J.delta, S, W.eone, W.esz);
     exscan_u32_dn(W.eone, W.eidx, Tn, &S->nb, W.scan_tmp, &S->es, s);
     exscan_u32_dn(W.esz, W.eoff, Tn, &S->nb, W.scan_tmp, &S->em, s);
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, S, (uint32_t)Cc);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, S, (uint32_t)W.Cs, (uint32_t)Cc);
     // this table's sets of C, ids ascending
     hipLaunchKernelGGL(k_count_kept, dim3(ggrid(n)), dim3(256), 0, s, W.kbin, W.kc, n, W.eone, S, W.kc2);
     exscan_u32(W.kc2, W.kpos, n, W.scan_tmp, &S->kp, s);
@@ -799,16 +881,18 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
     hipLaunchKernelGGL(k_c_write, dim3(ggrid(Tn)), dim3(256), 0, s, alt ? W.plo2 : W.plo, W.eone, W.eidx, W.eoff, S,
                        W.cmem, W.coff);
   }
-  // ---- de-duplication: one more table over the sets of C
+  // ---- de-duplication: one more table over the sets of C (Cs bounds its
+  // sets and bins, Cc its members and voting pairs)
+  const int64_t Cs = W.Cs;
   const uint32_t* dkeys = J.silk_keys + 2 * (int64_t)J.L * K;
   hipLaunchKernelGGL(k_dd_setup, dim3(1), dim3(1), 0, s, S, W.coff);
-  hipLaunchKernelGGL(k_set_extent, dim3(ggrid(Cc)), dim3(256), 0, s, W.coff, S, W.gstart, W.gsize);
+  hipLaunchKernelGGL(k_set_extent, dim3(ggrid(Cs)), dim3(256), 0, s, W.coff, S, W.gstart, W.gsize);
   hipLaunchKernelGGL(k_sk_fill, dim3(1), dim3(64), 0, s, &S->big, (int64_t)1, 0u);
-  hipLaunchKernelGGL(k_sig, dim3(ggrid(Cc)), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, &S->cs, dkeys, K, W.G,
+  hipLaunchKernelGGL(k_sig, dim3(ggrid(Cs)), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, &S->cs, dkeys, K, W.G,
                      W.big_list, &S->big, (unsigned long long*)nullptr);
-  hipLaunchKernelGGL(k_sig_big, dim3(512), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, dkeys, K, W.G, W.big_list,
+  hipLaunchKernelGGL(k_sig_big, dim3(SG_GRID), dim3(256), 0, s, W.cmem, W.gstart, W.gsize, dkeys, K, W.G, W.big_list,
                      &S->big, (unsigned long long*)nullptr);
-  hipLaunchKernelGGL(k_dd_tuples, dim3(ggrid(Cc)), dim3(256), 0, s, W.G, K, S, W.tw[0], W.tw[1], W.tw[2], W.tw[3],
+  hipLaunchKernelGGL(k_dd_tuples, dim3(ggrid(Cs)), dim3(256), 0, s, W.G, K, S, W.tw[0], W.tw[1], W.tw[2], W.tw[3],
                      W.tv);
   int tw[16], tsh[16], tnp = 0;
   for (int k = K - 1; k >= 0; --k)
@@ -817,16 +901,16 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
       tsh[tnp++] = sh;
     }
   RsView TA{{W.tw[0], W.tw[1], W.tw[2], W.tw[3]}, W.tv}, TB{{W.tw2[0], W.tw2[1], W.tw2[2], W.tw2[3]}, W.tv2};
-  const int talt = radix_sort_dn(TA, TB, 4, Cc, &S->cs, tw, tsh, tnp, W.radix_tmp, s);
+  const int talt = radix_sort_dn(TA, TB, 4, Cs, &S->cs, tw, tsh, tnp, W.radix_tmp, s);
   const RsView& TS = talt ? TB : TA;
   const uint32_t* ord = TS.v;
-  hipLaunchKernelGGL(k_dd_heads, dim3(ggrid(Cc)), dim3(256), 0, s, TS.k[0], TS.k[1], TS.k[2], TS.k[3], S, W.h);
-  exscan_u32_dn(W.h, W.hs, Cc, &S->cs, W.scan_tmp, &S->nb2, s);
-  hipLaunchKernelGGL(k_dd_bins, dim3(ggrid(Cc)), dim3(256), 0, s, W.h, W.hs, ord, S, W.binofr, W.bstart, W.inv);
-  hipLaunchKernelGGL(k_dd_cnt, dim3(ggrid(Cc)), dim3(256), 0, s, ord, W.binofr, W.bstart, W.gsize, S, W.cnt);
-  exscan_u32_dn(W.cnt, W.poff, Cc, &S->cs, W.scan_tmp, &S->P2, s);
+  hipLaunchKernelGGL(k_dd_heads, dim3(ggrid(Cs)), dim3(256), 0, s, TS.k[0], TS.k[1], TS.k[2], TS.k[3], S, W.h);
+  exscan_u32_dn(W.h, W.hs, Cs, &S->cs, W.scan_tmp, &S->nb2, s);
+  hipLaunchKernelGGL(k_dd_bins, dim3(ggrid(Cs)), dim3(256), 0, s, W.h, W.hs, ord, S, W.binofr, W.bstart, W.inv);
+  hipLaunchKernelGGL(k_dd_cnt, dim3(ggrid(Cs)), dim3(256), 0, s, ord, W.binofr, W.bstart, W.gsize, S, W.cnt);
+  exscan_u32_dn(W.cnt, W.poff, Cs, &S->cs, W.scan_tmp, &S->P2, s);
   hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cc)), dim3(256), 0, s, W.flag, Cc + 1, 0u);
-  hipLaunchKernelGGL(k_mark_starts, dim3(ggrid(Cc)), dim3(256), 0, s, W.gstart, &S->cs, W.flag);
+  hipLaunchKernelGGL(k_mark_starts, dim3(ggrid(Cs)), dim3(256), 0, s, W.gstart, &S->cs, W.flag);
   exscan_u32_dn(W.flag, W.fscan, Cc, &S->cm, W.scan_tmp, nullptr, s);
   hipLaunchKernelGGL(k_dd_pairs, dim3(ggrid(Cc)), dim3(256), 0, s, W.cmem, W.flag, W.fscan, W.coff, W.inv, W.cnt,
                      W.poff, W.binofr, S, W.phi, W.plo);
@@ -835,7 +919,7 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
     pw[pnp] = 0;
     psh[pnp++] = sh;
   }
-  for (int sh = 0; sh < bits_for((uint64_t)(Cc - 1)); sh += 8) {
+  for (int sh = 0; sh < bits_for((uint64_t)(Cs - 1)); sh += 8) {
     pw[pnp] = 1;
     psh[pnp++] = sh;
   }
@@ -848,17 +932,18 @@ int32_t silk_run(const geek_silk_job& J, void* ws, size_t ws_bytes, int32_t* st,
   hipLaunchKernelGGL(k_starts, dim3(ggrid(Cc + 1)), dim3(256), 0, s, W.kept, W.kidx, &S->P2, &S->R2, W.rstart);
   hipLaunchKernelGGL(k_dd_keep, dim3(ggrid(Cc)), dim3(256), 0, s, W.rstart, phi, W.bstart, S, W.kept);
   exscan_u32_dn(W.kept, W.kidx, Cc, &S->R2, W.scan_tmp, &S->kept2, s);
-  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cc)), dim3(256), 0, s, W.ksz2, Cc, 0u);
-  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cc)), dim3(256), 0, s, W.kstart, Cc, 0xFFFFFFFFu);
   hipLaunchKernelGGL(k_dd_compact, dim3(ggrid(Cc)), dim3(256), 0, s, W.rstart, W.kept, W.kidx, phi, plo, S, W.klo,
-                     W.ksz2, W.kstart);
-  hipLaunchKernelGGL(k_dd_size, dim3(ggrid(Cc)), dim3(256), 0, s, W.bstart, ord, W.gsize, W.ksz2, J.delta, S,
-                     W.ssz, W.sone);
-  exscan_u32_dn(W.ssz, W.soff, Cc, &S->nb2, W.scan_tmp, &S->tot_m, s);
-  exscan_u32_dn(W.sone, W.sidx, Cc, &S->nb2, W.scan_tmp, &S->k, s);
+                     W.khi);
+  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cs)), dim3(256), 0, s, W.kstart, Cs, 0u);
+  hipLaunchKernelGGL(k_sk_fill, dim3(ggrid(Cs)), dim3(256), 0, s, W.kend, Cs, 0u);
+  hipLaunchKernelGGL(k_dd_kruns, dim3(ggrid(Cc)), dim3(256), 0, s, W.khi, S, W.kstart, W.kend);
+  hipLaunchKernelGGL(k_dd_size, dim3(ggrid(Cs)), dim3(256), 0, s, W.bstart, ord, W.gsize, W.kstart, W.kend, J.delta,
+                     S, W.ssz, W.sone);
+  exscan_u32_dn(W.ssz, W.soff, Cs, &S->nb2, W.scan_tmp, &S->tot_m, s);
+  exscan_u32_dn(W.sone, W.sidx, Cs, &S->nb2, W.scan_tmp, &S->k, s);
   hipLaunchKernelGGL(k_silk_finish, dim3(1), dim3(1), 0, s, S, (uint64_t)J.cap_k, (uint64_t)J.cap_members,
                      J.seed_offsets, J.k_out, J.needed, J.counters, st);
-  hipLaunchKernelGGL(k_emit_seeds, dim3(ggrid(Cc)), dim3(256), 0, s, W.ssz, W.soff, W.sidx, S, J.seed_offsets);
+  hipLaunchKernelGGL(k_emit_seeds, dim3(ggrid(Cs)), dim3(256), 0, s, W.ssz, W.soff, W.sidx, S, J.seed_offsets);
   hipLaunchKernelGGL(k_seed_copy, dim3(ggrid(Cc)), dim3(256), 0, s, W.soff, W.bstart, ord, W.cmem, W.coff, W.klo,
                      W.kstart, S, J.seed_members);
   prof_end(GEEK_PROF_SILK, s);

@@ -23,6 +23,7 @@ int main(void) {
   F(geek_silk_job, delta); F(geek_silk_job, silk_keys); F(geek_silk_job, cap_k);
   F(geek_silk_job, cap_members); F(geek_silk_job, seed_offsets); F(geek_silk_job, seed_members);
   F(geek_silk_job, k_out); F(geek_silk_job, needed); F(geek_silk_job, counters);
+  F(geek_silk_job, cap_c);
   printf("geek_assign_job sizeof %zu\n", sizeof(geek_assign_job));
   F(geek_assign_job, metric); F(geek_assign_job, precision); F(geek_assign_job, n);
   F(geek_assign_job, d); F(geek_assign_job, k); F(geek_assign_job, X); F(geek_assign_job, ldx);

@@ -149,3 +149,34 @@ def test_silk_pass_captured_in_one_graph():
             assert np.array_equal(a, r), rep
         chain(api.new_status("cuda"))  # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_silk_multiset_capacity_reported_then_fits():
+    # too little room for the intermediate multiset C: the call reports the
+    # room C needs (needed[2]); called again with it, the seeds equal those of
+    # a call with ample room
+    api = gpu_api()
+    from paper_2106_10515_amd import _lib as L
+
+    n, d, m, Lt, w = 4000, 32, 8, 16, 4.0 * math.sqrt(32)
+    X, _, _ = dense_mixture(n, d, 20, -10, 10, 1.0, "equal", 0)
+    A, b = e2lsh_params(m * Lt, d, w, 0)
+    keys = cuda(key_words(21 * 3, 0, STREAM_SILK))
+    kg, _ = api.hash_dense(cuda(X), cuda(A), cuda(b), m, Lt, w)
+    bm, bo, bn, _ = api.bucketize(kg, n, Lt, 4, n * 4, 4, want_bucket_of=False)
+    announce("silk multiset capacity")
+    st = api.new_status("cuda")
+    out = api.silk_seeds_async(bm, bo, bn, n, Lt, 3, 20, 10, keys, 4096, 64000, st, cap_c=100)
+    torch.cuda.synchronize()
+    assert int(st.item()) == L.GEEK_ERR_CAPACITY
+    need = out["needed"].cpu().numpy()
+    assert need[0] == 0 and need[1] == 0 and need[2] > 100
+    st.zero_()
+    out2 = api.silk_seeds_async(bm, bo, bn, n, Lt, 3, 20, 10, keys, 4096, 64000, st, cap_c=int(need[2]))
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    ref_o, ref_m, _ = api.silk_seeds(bm, bo, bn, n, Lt, 3, 20, 10, keys)
+    k = int(out2["k_out"].item())
+    assert torch.equal(out2["seed_offsets"][:k + 1], ref_o)
+    assert torch.equal(out2["seed_members"][:int(ref_o[-1])], ref_m)
+    assert int(out2["needed"][2]) == int(need[2])
