@@ -55,7 +55,8 @@ def parse():
                          "with SILK seeds on the dense mixture at the scaled width")
     ap.add_argument("--jobs", type=int, default=256, help="batched: number of jobs")
     ap.add_argument("--no-tune", action="store_true", help="batched: keep the installed tile shapes")
-    ap.add_argument("--hetero-fp8", action="store_true", help="hetero: FP8 first pass instead of BF16")
+    ap.add_argument("--hetero-prec", default="fp8", choices=["fp8", "bf16"],
+                    help="hetero: matrix-core type of the numeric part (the workload states FP8 e4m3)")
     ap.add_argument("--sets-hash", default="minhash", choices=["minhash", "doph"],
                     help="sets: F = K*L MinHash functions per set, or DOPH to --doph-dims coordinates "
                          "(bands and modes over the reduced rows)")
@@ -494,6 +495,15 @@ def bench_batched(args):
         "assign_one_call_per_job_ms": single_ms,
         "batched_equals_single_calls": bool(same),
     }
+    if tiles:
+        # the persistent first pass of every padded depth, timed by the
+        # autotuner with its chosen shape: 2 n d k flops per job
+        fp_ms = sum(v["first_pass_ms"] for v in tiles.values())
+        ach = flops / (fp_ms * 1e-3) / 1e12
+        line["roofline"] = {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16, "unit": "TFLOP/s",
+                            "frac": ach / PEAK_BF16, "traffic": None,
+                            "kernel": "k_scan_batch (persistent BF16 first pass, one launch per padded depth)",
+                            "avg_launch_ms": fp_ms, "flop_per_launch": flops}
     print(json.dumps(line), flush=True)
 
 
@@ -526,7 +536,8 @@ def bench_hetero(args):
     torch.cuda.synchronize()
     log(f"hetero workload ready n={n} k={k} in {time.time() - t0:.1f}s")
     status = api.new_status(dev)
-    prec = L.GEEK_PREC_FP8 if args.hetero_fp8 else L.GEEK_PREC_BF16
+    fp8 = args.hetero_prec == "fp8"
+    prec = L.GEEK_PREC_FP8 if fp8 else L.GEEK_PREC_BF16
 
     def step(check):
         sig = api.hash_hetero(Xg, catg, Ag, bg, cfg["P_h"], 1, cfg["w"], mhg, status=status, check=check)
@@ -536,15 +547,61 @@ def bench_hetero(args):
 
     ms, (sig, bz, out) = _timed_graph(step, args.steps, args.warmup)
     api.check_status(status, "graph replays")
+    # stage times (eager, events) and the scan kernel's launch time
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    L.geek_profile(True)
+    ev[0].record()
+    sig2 = api.hash_hetero(Xg, catg, Ag, bg, cfg["P_h"], 1, cfg["w"], mhg, status=status, check=False)
+    ev[1].record()
+    api.bucketize(sig2, n, Lb, K, K, K * Lb, status=status, check=False)
+    ev[2].record()
+    out2 = api.assign_hetero(Xg, catg, sog, smg, k, 1.0, prec, status=status, check=False)
+    ev[3].record()
+    torch.cuda.synchronize()
+    scan_ms, scan_n = L.geek_profile_read(L.GEEK_PROF_ASSIGN_SCAN)
+    L.geek_profile(False)
+    api.check_status(status, "stage runs")
+    stages = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    d_num = cfg["d_num"]
+    flops = 2.0 * n * d_num * k
+    peak = 5000.0 if fp8 else PEAK_BF16
+    ach = flops / (scan_ms / max(scan_n, 1) * 1e-3) / 1e12
+    # oracle on a bounded sample: the assignment of the first rows to every
+    # seed's centroid and mode, one thread
+    import oracle
+
+    rows = min(512, n)
+    t0 = time.perf_counter()
+    Cn = oracle.centroids(X, so, sm)
+    Mc = oracle.modes(cat, so, sm)
+    t_c = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    a_ref, d_ref = oracle.assign_hetero(X[:rows], cat[:rows], Cn, Mc, 1.0)
+    t_a = time.perf_counter() - t0
+    a_gpu = out2["assign"][:rows].cpu().numpy()
+    d_gpu = out2["dist"][:rows].cpu().numpy()
     line = {
         "metric": "points/s (hash+bucketize+assign), heterogeneous rows",
         "value": n / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp8" if args.hetero_fp8 else "bf16", "data": "synthetic",
+        "vs_baseline": None, "dtype": "fp8" if fp8 else "bf16", "data": "synthetic",
         "config": {"workload": f"hetero: n={n}, 20 numeric + 10 categorical attributes, "
                                f"{cfg['clusters']} clusters, MinHash K={K} x L={Lb}, k={k} planted seeds",
                    "n": n, "k": k},
-        "assign_counters": out["counters"].cpu().numpy().tolist(),
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                     "traffic": None, "kernel": "k_scan (heterogeneous first pass)",
+                     "avg_launch_ms": scan_ms / max(scan_n, 1), "flop_per_launch": flops,
+                     "note": "d = 20 numeric attributes pad to the 64-deep FP8 (32-deep BF16) matrix step and "
+                             "every (row, seed) pair also counts 10 categorical mismatches on the VALU"},
+        "stages_ms": {"hash": stages[0], "bucketize": stages[1], "assign": stages[2]},
+        "assign_counters": out2["counters"].cpu().numpy().tolist(),
+        "cpu_baseline": {"value": rows / (t_a + t_c * rows / n), "unit": "points/s", "cores": 1,
+                         "kind": "oracle",
+                         "sample": f"first {rows} of {n} rows assigned to all {k} seeds (numpy float64, one "
+                                   "thread; centroid and mode time prorated by rows / n); hashing not included",
+                         "sample_assign_matches_gpu": bool(np.array_equal(a_ref, a_gpu)),
+                         "sample_sse_rel_err_vs_oracle": abs(float(d_gpu.sum()) - float(d_ref.sum()))
+                         / max(float(d_ref.sum()), 1e-300)},
     }
     print(json.dumps(line), flush=True)
 
@@ -644,8 +701,9 @@ def bench_silk(args):
     """The whole GEEK pass on the dense mixture (d = 128, Zipf cluster sizes,
     clusters scaled with n) at the scaled E2LSH width w * sqrt(d): hash,
     buckets of 32 tables, SILK seeds (K_S = 3, L_S = 20, delta = 10), then the
-    BF16 assignment to the SILK seeds.  SILK reads sizes back to the host
-    between its steps, so the pass is timed eagerly with events."""
+    BF16 assignment to the SILK seeds.  The binding reads the seed count k
+    back to the host between SILK and the assignment (geek_assign takes k on
+    the host), so the pass is timed eagerly with events."""
     import numpy as np
     import torch
 
@@ -701,6 +759,14 @@ def bench_silk(args):
         "stages_ms": {"hash": float(st[0]), "bucketize": float(st[1]), "silk": float(st[2]),
                       "assign": float(st[3])},
         "silk_counters": ctr.cpu().numpy().tolist(),
+        # SILK's algorithmic work: K hash evaluations per (table, object) and
+        # SILK table (the counters' first entry), about 6 integer VALU
+        # operations each (the member's finalizer mix shared by its K
+        # evaluations, then multiply, add and min per evaluation)
+        "roofline": {"bound": "alu", "achieved": float(ctr[0]) * 6 / (st[2] * 1e-3) / 1e12,
+                     "peak": 256 * 64 * 2.4e9 / 1e12, "unit": "Tops/s",
+                     "frac": float(ctr[0]) * 6 / (st[2] * 1e-3) / (256 * 64 * 2.4e9), "traffic": None,
+                     "kernel": "geek_silk_seeds (all kernels of the call)", "avg_launch_ms": float(st[2])},
         "assign_counters": out["counters"].cpu().numpy().tolist() if out is not None else None,
         "sse": float(out["sse"].item()) if out is not None else None,
     }

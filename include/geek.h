@@ -76,6 +76,9 @@ extern "C" {
 #define GEEK_ERR_CAPACITY 3       /* output capacity too small (see `needed`) */
 #define GEEK_ERR_NO_SEEDS 4       /* SILK found no seed */
 #define GEEK_ERR_EMPTY_SET 5      /* a set (or seed) with no element */
+#define GEEK_ERR_KEYS 6           /* bucketize: over 1792 distinct keys of one bin
+                                     share a 32-bit fingerprint and 24 bits of an
+                                     independent second hash (not handled) */
 
 /* ---- geek_hash ----------------------------------------------------------
  * The data transformation's LSH values (paper Section 3.1).

@@ -23,6 +23,7 @@ GEEK_ERR_RANGE = 2
 GEEK_ERR_CAPACITY = 3
 GEEK_ERR_NO_SEEDS = 4
 GEEK_ERR_EMPTY_SET = 5
+GEEK_ERR_KEYS = 6
 
 GEEK_HASH_DENSE, GEEK_HASH_SETS, GEEK_HASH_HETERO, GEEK_HASH_DOPH = 0, 1, 2, 3
 GEEK_METRIC_EUCLID, GEEK_METRIC_SIG, GEEK_METRIC_HETERO = 0, 1, 2

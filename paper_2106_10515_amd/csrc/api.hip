@@ -222,6 +222,7 @@ const char* geek_status_string(int32_t s) {
     case GEEK_ERR_CAPACITY: return "output capacity too small";
     case GEEK_ERR_NO_SEEDS: return "no seeds";
     case GEEK_ERR_EMPTY_SET: return "empty set";
+    case GEEK_ERR_KEYS: return "too many distinct keys collide in one bucketize bin";
     default: return "unknown status";
   }
 }

@@ -1,36 +1,38 @@
 // Buckets of every table (paper Algorithms 2 and 3: T[G(x_j)].push(j)) on
 // gfx950: group the objects whose table keys are identical.
 //
-//  1. A partition of (key, id) records into 2^nb bins per table, the bin
-//     being the top bits of a 32-bit mix of the exact key (equal keys always
-//     share a bin).  Up to 2^PT_B1 bins it is one pass (k_bin_count, the
-//     scans, k_p1_scatter); beyond, a second pass splits every first-pass bin
-//     by the next bits (k_p2_*).  Each scatter sorts rounds of PT_ROUND
-//     records by bin in LDS before writing, so the stores are runs of
-//     consecutive records instead of single scattered records.
-//  2. k_bin_group: one workgroup per bin groups its records with an LDS hash
-//     table on the exact key; objects sharing a key get (head = smallest id,
-//     rank among the bucket's ids, bucket size at the head) in id-indexed
-//     arrays plus a flag bit.  Bins too large for LDS are sorted by
-//     k_big_sort (workgroup LSD radix sort in global memory) and their runs
-//     recorded by k_big_runs.
-//  3. k_bz_reduce / k_scan_chunks / k_bz_apply: a scan over ids in id order
+//  1. k_fp_count: a 32-bit fingerprint f of every exact key (written once)
+//     and the histogram of its top bits per chunk of ids.
+//  2. A stable partition of (f, id) records into 2^nb bins per table by the
+//     top nb bits of f (equal keys always share a bin): up to 2^PT_B1 bins in
+//     one pass, else a second pass splits every first-pass bin by the next
+//     bits.  Each scatter ranks the records of a round in index order
+//     (wavefront ballots on the bin) and writes every bin's run contiguously,
+//     so each bin keeps its ids ascending.
+//  3. k_group: one workgroup per (bin, table) streams the bin's records in
+//     order through an LDS table keyed by the exact key (fingerprint first,
+//     the exact keys compared only when fingerprints match).  With the ids in
+//     order, a record's rank in its bucket is the number of earlier records of
+//     that bucket: per step, wavefront ballots on the slot give the ranks
+//     within the step and a per-slot counter carries them across steps; the
+//     rank-0 record is the bucket's head (smallest id).  Objects that share
+//     their key record (head, rank) -- or (head, size) at the head -- in
+//     id-indexed arrays plus a flag bit; objects alone in their bucket write
+//     nothing.  A bin with more distinct keys than the table holds is
+//     processed in sub-ranges of a second hash of the exact key.
+//  4. k_bz_reduce / k_scan_chunks / k_bz_apply: a scan over ids in id order
 //     gives every bucket its rank in smallest-member order and its CSR
 //     offset; every head (including objects alone in their bucket) is
 //     written to its slot at once.
-//  4. k_bz_members: the remaining members of buckets of two or more go to
+//  5. k_bz_members: the remaining members of buckets of two or more go to
 //     head offset + rank.
 #include "common.hpp"
 
 namespace geek {
 
 constexpr int BZ_THREADS = 256;
-constexpr int BZ_CAP = 2048;      // largest bin grouped in LDS
-constexpr int BZ_HT = 4096;       // LDS hash slots per bin
-constexpr int BZ_SMALL = 32;      // largest group ranked by walking its member list
 constexpr int BZ_MAXBITS = 14;    // at most 16384 bins per table
 constexpr int SC_CHUNK = 4096;    // elements per block in the scans
-constexpr int BIG_THREADS = 1024;
 
 struct BzArgs {
   const uint32_t* keys;
@@ -50,23 +52,26 @@ GEEK_D uint4 load_key(const BzArgs& a, int t, int64_t i) {
   r.w = a.kw > 3 ? k[3] : 0u;
   return r;
 }
-GEEK_D uint32_t bin_of(const uint4& k, int nb) {
+GEEK_D uint32_t fp_of(const uint4& k) {
   const uint32_t w[4] = {k.x, k.y, k.z, k.w};
-  return nb ? key_hash(w, 4) >> (32 - nb) : 0u;
+  return key_hash(w, 4);
 }
+// A second hash of the exact key (independent of the fingerprint): splits a
+// bin whose distinct keys overflow the grouping table.
+GEEK_D uint32_t fp2_of(const uint4& k) {
+  const uint32_t w[4] = {k.x ^ 0x3C6EF372u, k.y ^ 0xA54FF53Au, k.z ^ 0x510E527Fu, k.w ^ 0x9B05688Cu};
+  return fmix32(key_hash(w, 4) + 0x1F83D9ABu);
+}
+GEEK_D uint32_t bin_bits_of(uint32_t f, int nb) { return nb ? f >> (32 - nb) : 0u; }
 GEEK_D bool key_eq(const uint4& a, const uint4& b) {
   return a.x == b.x && a.y == b.y && a.z == b.z && a.w == b.w;
 }
-GEEK_D bool rec_less(const uint4& a, uint32_t ia, const uint4& b, uint32_t ib) {
-  if (a.x != b.x) return a.x < b.x;
-  if (a.y != b.y) return a.y < b.y;
-  if (a.z != b.z) return a.z < b.z;
-  if (a.w != b.w) return a.w < b.w;
-  return ia < ib;
-}
 
 // ---------------------------------------------------------------- partition
-__global__ __launch_bounds__(BZ_THREADS) void k_bin_count(BzArgs a, int nblk, int chunk, uint32_t* counts) {
+// Fingerprint of every (table, id) and the per-chunk histogram of its top nb
+// bits.
+__global__ __launch_bounds__(BZ_THREADS) void k_fp_count(BzArgs a, int nblk, int chunk, uint32_t* counts,
+                                                         uint32_t* fp) {
   extern __shared__ uint32_t hist[];
   const int t = blockIdx.y, blk = blockIdx.x;
   const int nbins = 1 << a.nb;
@@ -74,8 +79,11 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bin_count(BzArgs a, int nblk, in
   __syncthreads();
   const int64_t s = (int64_t)blk * chunk;
   const int64_t e = s + chunk < a.n ? s + chunk : a.n;
-  for (int64_t i = s + threadIdx.x; i < e; i += BZ_THREADS)
-    atomicAdd(&hist[bin_of(load_key(a, t, i), a.nb)], 1u);
+  for (int64_t i = s + threadIdx.x; i < e; i += BZ_THREADS) {
+    const uint32_t f = fp_of(load_key(a, t, i));
+    fp[(int64_t)t * a.n + i] = f;
+    atomicAdd(&hist[bin_bits_of(f, a.nb)], 1u);
+  }
   __syncthreads();
   uint32_t* out = counts + ((int64_t)t * nblk + blk) * nbins;
   for (int b = threadIdx.x; b < nbins; b += BZ_THREADS) out[b] = hist[b];
@@ -154,89 +162,119 @@ __global__ __launch_bounds__(1024) void k_bin_rowscan(int nbins, const uint32_t*
     }
   }
 }
-
 constexpr int PT_B1 = 6;          // bits of the first partition pass (64 bins)
-constexpr int PT_ROUND = 2048;    // records sorted by bin in LDS per round
+constexpr int PT_ROUND = 2048;    // records placed in LDS per round
 constexpr int PT_SUPER = 16384;   // records per workgroup of a partition pass
 constexpr int PT_RPT = PT_ROUND / BZ_THREADS;
 
-// One round of a partition scatter: the block's `cnt` records (key, id,
-// bin) are counted per bin, placed in LDS in bin order, and written out so
+// One round of a stable partition scatter: the round's `cnt` records
+// (fingerprint, id, bin), taken in index order, get their place among the
+// round's records of the same bin (sub-rounds of BZ_THREADS records in order;
+// within a sub-round wavefront ballots match the bin bits, earlier waves'
+// counts come from LDS), are staged in LDS in bin order and written out so
 // that consecutive threads store consecutive records of a bin.  cur[b] is
 // the global position of bin b's next record and advances by the round's
-// count.  Records of a bin keep no particular order (the grouping that
-// follows does not depend on it).
+// count; every bin receives its records in index order.
 struct PartLds {
-  uint4 key[PT_ROUND];
+  uint32_t f[PT_ROUND];
   uint32_t id[PT_ROUND];
   uint16_t bin[PT_ROUND];
-  uint32_t hist[256], lst[256], cur[256], sh[17];
+  uint32_t hist[256], lst[256], lrun[256], cur[256], sh[17];
+  uint32_t wcnt[BZ_THREADS / 64][256];
 };
 
 template <class Load>
-__device__ void part_round(PartLds& L, int nbins, int cnt, const Load& load, uint4* out_keys,
-                           uint32_t* out_ids) {
-  const int tid = threadIdx.x;
+__device__ void part_round(PartLds& L, int nbins, int nbits, int cnt, const Load& load, uint32_t* out_f,
+                           uint32_t* out_id) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int b = tid; b < nbins; b += BZ_THREADS) L.hist[b] = 0u;
+  for (int w = 0; w < BZ_THREADS / 64; ++w)
+    for (int b = tid; b < nbins; b += BZ_THREADS) L.wcnt[w][b] = 0u;
   __syncthreads();
-  uint4 k[PT_RPT];
-  uint32_t id[PT_RPT], rk[PT_RPT];
+  uint32_t f[PT_RPT], id[PT_RPT];
   int bn[PT_RPT];
 #pragma unroll
   for (int u = 0; u < PT_RPT; ++u) {
-    const int q = tid + u * BZ_THREADS;
+    const int q = u * BZ_THREADS + tid;
+    bn[u] = 0;
     if (q < cnt) {
-      load(q, k[u], id[u], bn[u]);
-      rk[u] = atomicAdd(&L.hist[bn[u]], 1u);
+      load(q, f[u], id[u], bn[u]);
+      atomicAdd(&L.hist[bn[u]], 1u);
     }
   }
   __syncthreads();
   // exclusive scan of the round's bin counts (nbins <= 256 = one per thread)
   const uint32_t hv = tid < nbins ? L.hist[tid] : 0u;
   const uint32_t ex = block_exscan(hv, nullptr, L.sh);
-  if (tid < nbins) L.lst[tid] = ex;
+  if (tid < nbins) {
+    L.lst[tid] = ex;
+    L.lrun[tid] = ex;
+  }
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < PT_RPT; ++u) {
-    const int q = tid + u * BZ_THREADS;
-    if (q < cnt) {
-      const uint32_t p = L.lst[bn[u]] + rk[u];
-      L.key[p] = k[u];
-      L.id[p] = id[u];
-      L.bin[p] = (uint16_t)bn[u];
+    const int q = u * BZ_THREADS + tid;
+    const bool has = q < cnt;
+    const uint32_t dg = has ? (uint32_t)bn[u] : 0u;
+    uint64_t mask = __ballot(has);
+    for (int b = 0; b < nbits; ++b) {
+      const uint64_t bb = __ballot(has && ((dg >> b) & 1u));
+      mask &= ((dg >> b) & 1u) ? bb : ~bb;
     }
+    const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    const bool leader = has && below == 0;
+    if (leader) L.wcnt[wv][dg] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    if (has) {
+      uint32_t before = 0;
+      for (int w2 = 0; w2 < wv; ++w2) before += L.wcnt[w2][dg];
+      const uint32_t p = L.lrun[dg] + before + below;
+      L.f[p] = f[u];
+      L.id[p] = id[u];
+      L.bin[p] = (uint16_t)dg;
+    }
+    __syncthreads();
+    if (tid < nbins) {
+      uint32_t tot = 0;
+      for (int w2 = 0; w2 < BZ_THREADS / 64; ++w2) tot += L.wcnt[w2][tid];
+      L.lrun[tid] += tot;
+    }
+    __syncthreads();
+    if (leader) L.wcnt[wv][dg] = 0u;
+    __syncthreads();
   }
-  __syncthreads();
   for (int p = tid; p < cnt; p += BZ_THREADS) {
     const int b = L.bin[p];
     const uint32_t gp = L.cur[b] + (uint32_t)p - L.lst[b];
-    out_keys[gp] = L.key[p];
-    out_ids[gp] = L.id[p];
+    out_f[gp] = L.f[p];
+    out_id[gp] = L.id[p];
   }
   __syncthreads();
   for (int b = tid; b < nbins; b += BZ_THREADS) L.cur[b] += L.hist[b];
 }
 
-// First pass: block (chunk of PT_SUPER ids, table) -> 2^a.nb bins (a.nb <= PT_B1).
-__global__ __launch_bounds__(BZ_THREADS) void k_p1_scatter(BzArgs a, int nblk, const uint32_t* counts,
-                                                           const uint32_t* binstart, uint4* out_keys,
-                                                           uint32_t* out_ids) {
+// First pass: block (chunk of PT_SUPER ids, table) -> 2^nb1 bins by the top
+// nb1 bits of the fingerprint (nb1 <= PT_B1).
+__global__ __launch_bounds__(BZ_THREADS) void k_p1_scatter(BzArgs a, int nb1, int nblk, const uint32_t* counts,
+                                                           const uint32_t* binstart, const uint32_t* fp,
+                                                           uint32_t* out_f, uint32_t* out_id) {
   __shared__ PartLds L;
   const int t = blockIdx.y, blk = blockIdx.x;
-  const int nbins = 1 << a.nb;
+  const int nbins = 1 << nb1;
   for (int b = threadIdx.x; b < nbins; b += BZ_THREADS)
     L.cur[b] = binstart[(int64_t)t * nbins + b] + counts[((int64_t)t * nblk + blk) * nbins + b];
   const int64_t s = (int64_t)blk * PT_SUPER;
   const int64_t e = s + PT_SUPER < a.n ? s + PT_SUPER : a.n;
+  const uint32_t* fpt = fp + (int64_t)t * a.n;
   for (int64_t r0 = s; r0 < e; r0 += PT_ROUND) {
     const int cnt = (int)(e - r0 < PT_ROUND ? e - r0 : PT_ROUND);
-    part_round(L, nbins, cnt,
-               [&](int q, uint4& k, uint32_t& id, int& bn) {
-                 k = load_key(a, t, r0 + q);
+    part_round(L, nbins, nb1, cnt,
+               [&](int q, uint32_t& f, uint32_t& id, int& bn) {
+                 f = fpt[r0 + q];
                  id = (uint32_t)(r0 + q);
-                 bn = (int)bin_of(k, a.nb);
+                 bn = (int)bin_bits_of(f, nb1);
                },
-               out_keys + (int64_t)t * a.n, out_ids + (int64_t)t * a.n);
+               out_f + (int64_t)t * a.n, out_id + (int64_t)t * a.n);
   }
 }
 
@@ -276,7 +314,7 @@ GEEK_D int p2_bin_of_chunk(const uint32_t* cbase, int nb1bins, uint32_t g) {
 // Per chunk: counts of the second-pass bins (the next nb - PT_B1 bits).
 __global__ __launch_bounds__(BZ_THREADS) void k_p2_count(int64_t n, int nb, const uint32_t* cbase, int nb1bins,
                                                          const uint32_t* bintot1, const uint32_t* binstart1,
-                                                         const uint4* keys1, uint32_t* counts2) {
+                                                         const uint32_t* f1, uint32_t* counts2) {
   __shared__ uint32_t hist[256];
   const uint32_t g = blockIdx.x;
   if (g >= cbase[nb1bins]) return;
@@ -285,13 +323,11 @@ __global__ __launch_bounds__(BZ_THREADS) void k_p2_count(int64_t n, int nb, cons
   const int t = tb >> PT_B1;
   const uint32_t off = (g - cbase[tb]) * (uint32_t)PT_SUPER;
   const uint32_t cnt = min((uint32_t)PT_SUPER, bintot1[tb] - off);
-  const uint4* src = keys1 + (int64_t)t * n + binstart1[tb] + off;
+  const uint32_t* src = f1 + (int64_t)t * n + binstart1[tb] + off;
   for (int b = threadIdx.x; b < F; b += BZ_THREADS) hist[b] = 0u;
   __syncthreads();
-  for (uint32_t q = threadIdx.x; q < cnt; q += BZ_THREADS) {
-    const uint4 k = src[q];
-    atomicAdd(&hist[bin_of(k, nb) & (uint32_t)(F - 1)], 1u);
-  }
+  for (uint32_t q = threadIdx.x; q < cnt; q += BZ_THREADS)
+    atomicAdd(&hist[bin_bits_of(src[q], nb) & (uint32_t)(F - 1)], 1u);
   __syncthreads();
   for (int b = threadIdx.x; b < F; b += BZ_THREADS) counts2[(int64_t)g * F + b] = hist[b];
 }
@@ -313,9 +349,9 @@ __global__ void k_p2_colscan(int nb1bins, int F, const uint32_t* cbase, uint32_t
 
 __global__ __launch_bounds__(BZ_THREADS) void k_p2_scatter(int64_t n, int nb, const uint32_t* cbase, int nb1bins,
                                                            const uint32_t* bintot1, const uint32_t* binstart1,
-                                                           const uint4* keys1, const uint32_t* ids1,
+                                                           const uint32_t* f1, const uint32_t* ids1,
                                                            const uint32_t* counts2, const uint32_t* binstart,
-                                                           uint4* out_keys, uint32_t* out_ids) {
+                                                           uint32_t* out_f, uint32_t* out_id) {
   __shared__ PartLds L;
   const uint32_t g = blockIdx.x;
   if (g >= cbase[nb1bins]) return;
@@ -329,13 +365,13 @@ __global__ __launch_bounds__(BZ_THREADS) void k_p2_scatter(int64_t n, int nb, co
     L.cur[b] = binstart[(int64_t)tb * F + b] + counts2[(int64_t)g * F + b];
   for (uint32_t r0 = 0; r0 < cnt_all; r0 += PT_ROUND) {
     const int cnt = (int)min((uint32_t)PT_ROUND, cnt_all - r0);
-    part_round(L, F, cnt,
-               [&](int q, uint4& k, uint32_t& id, int& bn) {
-                 k = keys1[s + r0 + q];
+    part_round(L, F, nb - PT_B1, cnt,
+               [&](int q, uint32_t& f, uint32_t& id, int& bn) {
+                 f = f1[s + r0 + q];
                  id = ids1[s + r0 + q];
-                 bn = (int)(bin_of(k, nb) & (uint32_t)(F - 1));
+                 bn = (int)(bin_bits_of(f, nb) & (uint32_t)(F - 1));
                },
-               out_keys + (int64_t)t * n, out_ids + (int64_t)t * n);
+               out_f + (int64_t)t * n, out_id + (int64_t)t * n);
   }
 }
 
@@ -358,293 +394,164 @@ GEEK_D void group_record(const GroupOut& go, int t, int64_t n, uint32_t id, uint
   atomicOr(&go.flags[(int64_t)t * go.flag_words + (id >> 5)], 1u << (id & 31));
 }
 
-// One workgroup per (bin, table).  Each thread keeps its records (key, id,
-// slot) in registers; an LDS hash table keyed by the exact key gives each
-// record its group (slot) and the group sizes; keys of slot owners are
-// re-read from the bin's staging copy (cache-resident) for comparisons.
-// Ranks inside groups of at most BZ_SMALL come from a walk of the group's
-// member list; bins with a larger group sort (slot, id) pairs in LDS
-// (bitonic) and rank by position.  A slot word holds the group size in its
-// high 16 bits and, in its low 16 bits, first the owning record + 1
-// (0: empty), then the member-list head + 1, then the first sorted position
-// + 1.  LDS stays small enough for four workgroups per CU.
-constexpr int BZ_RPT = BZ_CAP / BZ_THREADS;  // records per thread
-__global__ __launch_bounds__(BZ_THREADS) void k_bin_group(int64_t n, int nb, const uint32_t* bintot,
-                                                          const uint32_t* binstart, const uint4* st_keys,
-                                                          const uint32_t* st_ids, GroupOut go,
-                                                          uint32_t* big_list, uint32_t* big_count) {
-  __shared__ uint32_t hw[BZ_HT];
-  __shared__ int16_t nxt[BZ_CAP];
-  __shared__ unsigned long long sc[BZ_CAP];  // (slot, id) sort array
-  __shared__ uint32_t smax;
+// One workgroup per (bin, table).  The bin's records (fingerprint, id) are in
+// ascending id order.  An LDS table maps each distinct exact key to a slot:
+// a slot word holds the fingerprint and 1 + the bin position of the record
+// that claimed it; a record whose fingerprint matches a slot compares its
+// exact key with the claimant's (both read from the keys array), so only
+// records that share a fingerprint touch the keys.  Records go through in
+// steps of BZ_THREADS in order; ranks come from ballots on the slot within
+// each wavefront, the per-wavefront counts of earlier wavefronts (cleared at
+// the end of each step) and the slot's count of earlier steps.  Bins of at most GB_FILL records fit the
+// table whatever their keys (one pass); larger bins build the table first and
+// are processed in sub-ranges of a second key hash (1, 64, 4096, ... of them)
+// if their distinct keys do not fit.
+constexpr int GB_HT = 2048;             // slots of the table
+constexpr int GB_FILL = 1792;           // distinct keys per (sub-)range
+constexpr int GB_SBITS = 11;            // bits of a slot index
+constexpr int GB_LEVELS = 5;            // sub-range splits: 1, 2^6, 2^12, 2^18, 2^24
+struct GroupLds {
+  unsigned long long slot[GB_HT];
+  uint32_t cnt[GB_HT];
+  uint32_t head[GB_HT];
+  uint16_t wc[BZ_THREADS / 64][GB_HT];  // records of each wavefront in the slot, this step
+  uint32_t nslot, over;
+};
+
+// Slot of a record's exact key; inserts it when `ins`.  -1: the table has no
+// room (or, without insertion, the key is absent).
+GEEK_D int gb_slot(GroupLds& G, const BzArgs& a, int t, uint32_t f, uint32_t pos, uint32_t id,
+                   const uint32_t* __restrict__ bin_ids, bool ins) {
+  uint32_t h = f & (GB_HT - 1);
+  uint4 mine = make_uint4(0u, 0u, 0u, 0u);
+  bool have = false;
+  for (int probe = 0; probe < GB_HT; ++probe) {
+    unsigned long long s = G.slot[h];
+    if (s == 0ull) {
+      if (!ins) return -1;
+      const unsigned long long v = ((unsigned long long)f << 32) | (unsigned long long)(pos + 1u);
+      const unsigned long long prev = atomicCAS(&G.slot[h], 0ull, v);
+      if (prev == 0ull) {
+        atomicAdd(&G.nslot, 1u);
+        return (int)h;
+      }
+      s = prev;
+    }
+    if ((uint32_t)(s >> 32) == f) {
+      const uint32_t opos = (uint32_t)s - 1u;
+      if (opos == pos) return (int)h;
+      if (!have) {
+        mine = load_key(a, t, id);
+        have = true;
+      }
+      if (key_eq(load_key(a, t, bin_ids[opos]), mine)) return (int)h;
+    }
+    h = (h + 1u) & (GB_HT - 1);
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* bintot, const uint32_t* binstart,
+                                                      const uint32_t* st_f, const uint32_t* st_id, GroupOut go,
+                                                      int32_t* st) {
+  __shared__ GroupLds G;
   const int t = blockIdx.y, bin = blockIdx.x;
-  const int nbins = 1 << nb;
+  const int nbins = 1 << a.nb;
   const uint32_t size = bintot[(int64_t)t * nbins + bin];
   if (size <= 1) return;  // empty, or one record: a bucket of its own
-  if (size > BZ_CAP) {
-    if (threadIdx.x == 0) big_list[atomicAdd(big_count, 1u)] = (uint32_t)(t * nbins + bin);
-    return;
-  }
+  const int64_t n = a.n;
   const uint32_t s0 = binstart[(int64_t)t * nbins + bin];
-  const uint4* gk = st_keys + (int64_t)t * n + s0;
-  const uint32_t* gi = st_ids + (int64_t)t * n + s0;
-  uint4 kr[BZ_RPT];
-  uint32_t idr[BZ_RPT];
-  int slot[BZ_RPT];
-#pragma unroll
-  for (int u = 0; u < BZ_RPT; ++u) {
-    const int q = threadIdx.x + u * BZ_THREADS;
-    if (q < (int)size) {
-      kr[u] = gk[q];
-      idr[u] = gi[q];
-    }
-  }
-  for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] = 0u;
-  if (threadIdx.x == 0) smax = 0;
-  __syncthreads();
-  // insert with linear probing; an owned slot's key is already in memory
-#pragma unroll
-  for (int u = 0; u < BZ_RPT; ++u) {
-    const int q = threadIdx.x + u * BZ_THREADS;
-    slot[u] = 0;
-    if (q >= (int)size) continue;
-    const uint4 k = kr[u];
-    const uint32_t w[4] = {k.x, k.y, k.z, k.w};
-    int h = (int)(key_hash(w, 4) & (BZ_HT - 1));
-    for (;;) {
-      uint32_t cur = hw[h] & 0xFFFFu;
-      if (cur == 0u) {
-        const uint32_t prev = atomicCAS(&hw[h], 0u, (uint32_t)(q + 1));
-        if (prev == 0u) break;
-        cur = prev & 0xFFFFu;
-      }
-      if (key_eq(gk[cur - 1], k)) break;
-      h = (h + 1) & (BZ_HT - 1);
-    }
-    slot[u] = h;
-    atomicAdd(&hw[h], 0x10000u);
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] &= 0xFFFF0000u;
-  __syncthreads();
-  // member lists (order arbitrary)
-#pragma unroll
-  for (int u = 0; u < BZ_RPT; ++u) {
-    const int q = threadIdx.x + u * BZ_THREADS;
-    if (q >= (int)size) continue;
-    const int g = slot[u];
-    uint32_t old = hw[g];
-    for (;;) {
-      const uint32_t prev = atomicCAS(&hw[g], old, (old & 0xFFFF0000u) | (uint32_t)(q + 1));
-      if (prev == old) break;
-      old = prev;
-    }
-    nxt[q] = (int16_t)((int)(old & 0xFFFFu) - 1);
-    if ((old >> 16) > 1u) atomicMax(&smax, old >> 16);
-  }
-  __syncthreads();
-  const uint32_t big = smax;
-  if (big <= 1) return;  // all keys distinct
-  if (big <= BZ_SMALL) {
-#pragma unroll
-    for (int u = 0; u < BZ_RPT; ++u) {
-      const int q = threadIdx.x + u * BZ_THREADS;
-      if (q >= (int)size) continue;
-      const uint32_t v = hw[slot[u]];
-      const uint32_t c = v >> 16;
-      if (c == 1) continue;
-      const uint32_t me = idr[u];
-      uint32_t r = 0, head = me;
-      for (int e = (int)(v & 0xFFFFu) - 1; e >= 0; e = nxt[e]) {
-        const uint32_t o = gi[e];
-        r += o < me;
-        head = min(head, o);
-      }
-      group_record(go, t, n, me, head, r == 0 ? c : r);
-    }
-    return;
-  }
-  // a larger group: sort (slot, id) pairs, rank by position
-  int P2 = 1;
-  while (P2 < (int)size) P2 <<= 1;
-#pragma unroll
-  for (int u = 0; u < BZ_RPT; ++u) {
-    const int q = threadIdx.x + u * BZ_THREADS;
-    if (q < P2) sc[q] = q < (int)size ? ((unsigned long long)slot[u] << 32) | idr[u] : ~0ull;
-  }
-  for (int q = threadIdx.x; q < BZ_HT; q += BZ_THREADS) hw[q] |= 0xFFFFu;
-  __syncthreads();
-  for (int kk = 2; kk <= P2; kk <<= 1) {
-    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-      for (int q = threadIdx.x; q < P2; q += BZ_THREADS) {
-        const int o = q ^ jj;
-        if (o > q) {
-          const unsigned long long a = sc[q], b = sc[o];
-          const bool up = (q & kk) == 0;
-          if (up ? (b < a) : (a < b)) {
-            sc[q] = b;
-            sc[o] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
-    const int g = (int)(sc[q] >> 32);
-    atomicMin(&hw[g], (hw[g] & 0xFFFF0000u) | (uint32_t)(q + 1));
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < (int)size; q += BZ_THREADS) {
-    const uint32_t v = hw[(int)(sc[q] >> 32)];
-    const uint32_t c = v >> 16;
-    if (c == 1) continue;
-    const int f = (int)(v & 0xFFFFu) - 1;
-    const uint32_t me = (uint32_t)sc[q], head = (uint32_t)sc[f];
-    group_record(go, t, n, me, head, q == f ? c : (uint32_t)(q - f));
-  }
-}
-
-// Oversize bins: LSD radix sort (8-bit digits, stable) of the bin's records
-// by (key, id) in global memory, one workgroup per bin; passes whose digit is
-// constant over the bin are skipped.
-__global__ __launch_bounds__(BIG_THREADS) void k_big_sort(int64_t n, int nb, int kw, const uint32_t* bintot,
-                                                          const uint32_t* binstart, uint4* st_keys,
-                                                          uint32_t* st_ids, uint4* alt_keys,
-                                                          uint32_t* alt_ids, const uint32_t* big_list,
-                                                          const uint32_t* big_count) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[16][256];
-  __shared__ int skip;
-  const int nbins = 1 << nb;
-  const uint32_t nbig = *big_count;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
-    const uint32_t tb = big_list[bi];
-    const int t = (int)(tb / nbins);
-    const uint32_t size = bintot[tb], s0 = binstart[tb];
-    uint4* k0 = st_keys + (int64_t)t * n + s0;
-    uint32_t* i0 = st_ids + (int64_t)t * n + s0;
-    uint4* k1 = alt_keys + (int64_t)t * n + s0;
-    uint32_t* i1 = alt_ids + (int64_t)t * n + s0;
-    const int npass = 4 + 4 * kw;  // id bytes first (least significant), then key words
-    for (int pass = 0; pass < npass; ++pass) {
-      // digit extractor: passes 0..3 id bytes; then word (kw-1 .. 0) bytes
-      auto digit = [&](const uint4& k, uint32_t id) -> uint32_t {
-        if (pass < 4) return (id >> (8 * pass)) & 255u;
-        const int wp = (pass - 4) >> 2, by = (pass - 4) & 3;
-        const int word = kw - 1 - wp;
-        const uint32_t w = word == 0 ? k.x : word == 1 ? k.y : word == 2 ? k.z : k.w;
-        return (w >> (8 * by)) & 255u;
+  const uint32_t* fptr = st_f + (int64_t)t * n + s0;
+  const uint32_t* iptr = st_id + (int64_t)t * n + s0;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int level = 0; level < GB_LEVELS; ++level) {
+    const int sbits = 6 * level;
+    const uint32_t nsub = 1u << sbits;
+    bool done = true;
+    for (uint32_t r = 0; r < nsub; ++r) {
+      // the records of this sub-range: all records at level 0, else those
+      // whose second key hash has r in its low sbits bits
+      auto in_range = [&](uint32_t q) -> bool {
+        if (level == 0) return true;
+        return (fp2_of(load_key(a, t, iptr[q])) & (nsub - 1u)) == r;
       };
-      for (int q = threadIdx.x; q < 256; q += BIG_THREADS) hist[q] = 0;
-      __syncthreads();
-      for (uint32_t q = threadIdx.x; q < size; q += BIG_THREADS) atomicAdd(&hist[digit(k0[q], i0[q])], 1u);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t r = 0;
-        int sk = 0;
-        for (int b = 0; b < 256; ++b) {
-          base[b] = r;
-          r += hist[b];
-          sk |= (hist[b] == size);
-        }
-        skip = sk;
+      for (int h = tid; h < GB_HT; h += BZ_THREADS) {
+        G.slot[h] = 0ull;
+        G.cnt[h] = 0u;
+#pragma unroll
+        for (int w = 0; w < BZ_THREADS / 64; ++w) G.wc[w][h] = 0;
+      }
+      if (tid == 0) {
+        G.nslot = 0u;
+        G.over = 0u;
       }
       __syncthreads();
-      if (skip) continue;
-      // stable scatter, BIG_THREADS records per round in thread order
-      for (uint32_t r0 = 0; r0 < size; r0 += BIG_THREADS) {
-        const uint32_t q = r0 + threadIdx.x;
-        const bool has = q < size;
-        uint4 kk = make_uint4(0, 0, 0, 0);
-        uint32_t id = 0, dg = 0;
-        if (has) {
-          kk = k0[q];
-          id = i0[q];
-          dg = digit(kk, id);
+      // a range that could hold more distinct keys than fit: build the table first
+      const bool build = level > 0 || size > (uint32_t)GB_FILL;
+      if (build) {
+        for (uint32_t q0 = 0; q0 < size; q0 += BZ_THREADS) {
+          const uint32_t q = q0 + tid;
+          if (q < size && in_range(q)) {
+            const int g = gb_slot(G, a, t, fptr[q], q, iptr[q], iptr, true);
+            if (g < 0) G.over = 1u;
+          }
+          __syncthreads();
+          if (G.over || G.nslot > (uint32_t)GB_FILL) break;  // uniform: read after the barrier
+          __syncthreads();
         }
-        // lanes of this wave with the same digit
-        uint64_t mask = __ballot(has);
-        for (int b = 0; b < 8; ++b) {
-          const uint64_t bb = __ballot(has && ((dg >> b) & 1u));
-          mask &= ((dg >> b) & 1u) ? bb : ~bb;
+        __syncthreads();
+        if (G.over || G.nslot > (uint32_t)GB_FILL) {
+          done = false;
+          __syncthreads();
+          break;  // split this bin more finely
+        }
+      }
+      for (uint32_t q0 = 0; q0 < size; q0 += BZ_THREADS) {
+        const uint32_t q = q0 + tid;
+        bool valid = q < size && in_range(q);
+        uint32_t id = 0u;
+        int g = -1;
+        if (valid) {
+          id = iptr[q];
+          g = gb_slot(G, a, t, fptr[q], q, id, iptr, !build);
+          valid = g >= 0;
+        }
+        __syncthreads();  // every insertion of the step is done
+        uint64_t mask = __ballot(valid);
+        for (int b = 0; b < GB_SBITS; ++b) {
+          const uint64_t bb = __ballot(valid && ((g >> b) & 1));
+          mask &= ((g >> b) & 1) ? bb : ~bb;
         }
         const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-        for (int b = threadIdx.x; b < 16 * 256; b += BIG_THREADS) (&wcnt[0][0])[b] = 0;
+        const uint32_t wcount = (uint32_t)__popcll(mask);
+        const bool leader = valid && below == 0;
+        if (leader) G.wc[wv][g] = (uint16_t)wcount;
         __syncthreads();
-        if (has && below == 0) wcnt[wv][dg] = (uint32_t)__popcll(mask);
-        __syncthreads();
-        if (has) {
-          uint32_t before = 0;
-          for (int w2 = 0; w2 < wv; ++w2) before += wcnt[w2][dg];
-          const uint32_t pos = base[dg] + before + below;
-          k1[pos] = kk;
-          i1[pos] = id;
+        uint32_t rank = 0u;
+        if (valid) {
+          uint32_t before = 0u;
+          for (int w2 = 0; w2 < wv; ++w2) before += G.wc[w2][g];
+          rank = G.cnt[g] + before + below;
+          if (rank == 0u) G.head[g] = id;
         }
         __syncthreads();
-        if (threadIdx.x < 256) {
-          uint32_t tot = 0;
-          for (int w2 = 0; w2 < 16; ++w2) tot += wcnt[w2][threadIdx.x];
-          base[threadIdx.x] += tot;
+        if (valid && rank > 0u) group_record(go, t, n, id, G.head[g], rank);
+        if (leader) {
+          atomicAdd(&G.cnt[g], wcount);
+          G.wc[wv][g] = 0;
         }
         __syncthreads();
       }
-      // copy back so the sorted data is always in (k0, i0)
-      for (uint32_t q = threadIdx.x; q < size; q += BIG_THREADS) {
-        k0[q] = k1[q];
-        i0[q] = i1[q];
-      }
+      // heads of buckets of two or more: (head, size)
+      for (int h = tid; h < GB_HT; h += BZ_THREADS)
+        if (G.slot[h] != 0ull && G.cnt[h] >= 2u) group_record(go, t, n, G.head[h], G.head[h], G.cnt[h]);
       __syncthreads();
     }
+    if (done) return;
   }
-}
-
-// Run detection of a sorted oversize bin (one workgroup per bin); records
-// the runs of two or more in the grouping output.
-__global__ __launch_bounds__(BIG_THREADS) void k_big_runs(int64_t n, int nb, const uint32_t* bintot,
-                                                          const uint32_t* binstart, const uint4* st_keys,
-                                                          const uint32_t* st_ids, GroupOut go,
-                                                          const uint32_t* big_list, const uint32_t* big_count) {
-  __shared__ int ss[BIG_THREADS];
-  __shared__ int carry;
-  const int nbins = 1 << nb;
-  const uint32_t nbig = *big_count;
-  for (uint32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
-    const uint32_t tb = big_list[bi];
-    const int t = (int)(tb / nbins);
-    const uint32_t size = bintot[tb], s0 = binstart[tb];
-    const uint4* k = st_keys + (int64_t)t * n + s0;
-    const uint32_t* ids = st_ids + (int64_t)t * n + s0;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (uint32_t r0 = 0; r0 < size; r0 += BIG_THREADS) {
-      const uint32_t q = r0 + threadIdx.x;
-      int v = -1;
-      if (q < size) v = (q == 0 || !key_eq(k[q], k[q - 1])) ? (int)q : -1;
-      ss[threadIdx.x] = v;
-      __syncthreads();
-      for (int o = 1; o < BIG_THREADS; o <<= 1) {
-        const int y = threadIdx.x >= (unsigned)o ? ss[threadIdx.x - o] : -1;
-        __syncthreads();
-        ss[threadIdx.x] = max(ss[threadIdx.x], y);
-        __syncthreads();
-      }
-      const int rs = max(ss[threadIdx.x], carry);
-      if (q < size) {
-        const uint32_t f = ids[rs];
-        const bool last = (q == size - 1) || !key_eq(k[q + 1], k[q]);
-        if ((int)q != rs) {
-          group_record(go, t, n, ids[q], f, q - (uint32_t)rs);
-          if (last) group_record(go, t, n, f, f, q - (uint32_t)rs + 1u);
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x == BIG_THREADS - 1) carry = rs;
-      __syncthreads();
-    }
-  }
+  // more than GB_FILL distinct keys share 24 bits of the second hash in one
+  // bin: not handled
+  if (tid == 0) set_status(st, GEEK_ERR_KEYS);
 }
 
 // ---------------------------------------------------------------- scans and emission
@@ -821,11 +728,9 @@ static int bin_bits(int64_t n) {
 }
 
 struct BzWs {
-  uint32_t *counts, *bintot, *binstart, *st_ids, *alt_ids, *flags;
+  uint32_t *counts, *bintot, *binstart, *fp, *st_f, *st_id, *alt_f, *alt_id, *flags;
   uint32_t *counts2, *bintot1, *binstart1, *cbase;  // second partition pass
-  uint4 *st_keys, *alt_keys;
   uint2 *info, *hs, *ctot;
-  uint32_t *big_list, *big_count;
 };
 
 static size_t carve_bz(const geek_bucketize_job& J, void* ws, BzWs& W) {
@@ -846,16 +751,15 @@ static size_t carve_bz(const geek_bucketize_job& J, void* ws, BzWs& W) {
   W.cbase = c.take<uint32_t>((size_t)J.T * nb1bins + 1);
   W.bintot = c.take<uint32_t>((size_t)J.T * nbins);
   W.binstart = c.take<uint32_t>((size_t)J.T * nbins);
-  W.st_keys = c.take<uint4>(Tn);
-  W.alt_keys = c.take<uint4>(Tn);
-  W.hs = reinterpret_cast<uint2*>(W.alt_keys);  // used after the oversize-bin sorts
-  W.st_ids = c.take<uint32_t>(Tn);
-  W.alt_ids = c.take<uint32_t>(Tn);
+  W.fp = c.take<uint32_t>(Tn);
+  W.st_f = c.take<uint32_t>(Tn);
+  W.st_id = c.take<uint32_t>(Tn);
+  W.alt_f = two ? c.take<uint32_t>(Tn) : nullptr;
+  W.alt_id = two ? c.take<uint32_t>(Tn) : nullptr;
   W.flags = c.take<uint32_t>((size_t)J.T * fw);
   W.info = c.take<uint2>(Tn);
+  W.hs = c.take<uint2>(Tn);
   W.ctot = c.take<uint2>((size_t)J.T * nch);
-  W.big_list = c.take<uint32_t>((size_t)J.T * nbins);
-  W.big_count = c.take<uint32_t>(4);
   return c.used + 256;
 }
 
@@ -871,7 +775,6 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
 
 int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, int32_t* st,
                       hipStream_t s) {
-  (void)st;
   BzWs W;
   if (ws_bytes < carve_bz(J, ws, W)) return GEEK_ERR_WORKSPACE;
   const int nb = bin_bits(J.n);
@@ -881,18 +784,17 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   const int64_t fw = ceil_div(J.n, 32);
   BzArgs a{J.keys, J.n, J.T, J.key_words, J.table_stride, J.row_stride, nb};
   GroupOut go{W.flags, W.info, fw};
-  const size_t hbytes = (size_t)nbins * 4;
   prof_begin(GEEK_PROF_BUCKETIZE, s);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, W.big_count, (int64_t)4);
   hipLaunchKernelGGL(k_zero_u32, dim3(ceil_div((int64_t)J.T * fw, 256)), dim3(256), 0, s, W.flags,
                      (int64_t)J.T * fw);
   if (nb <= PT_B1) {
-    hipLaunchKernelGGL(k_bin_count, dim3(nblk, J.T), dim3(BZ_THREADS), hbytes, s, a, nblk, PT_SUPER, W.counts);
+    hipLaunchKernelGGL(k_fp_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)nbins * 4, s, a, nblk, PT_SUPER,
+                       W.counts, W.fp);
     hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div((int64_t)J.T * nbins, 256)), dim3(256), 0, s, J.T,
                        nblk, nbins, W.counts, W.bintot);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
-    hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a, nblk, W.counts, W.binstart,
-                       W.st_keys, W.st_ids);
+    hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a, nb, nblk, W.counts, W.binstart,
+                       W.fp, W.st_f, W.st_id);
   } else {
     // first pass into the alternate buffers by the top PT_B1 bits, second
     // pass by the next nb - PT_B1 bits into the staging buffers
@@ -901,30 +803,26 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
     const int nb1bins = J.T << PT_B1;
     const int F = 1 << (nb - PT_B1);
     const int maxchunks = (int)p2_max_chunks(J.n, J.T);
-    hipLaunchKernelGGL(k_bin_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)4 << PT_B1, s, a1, nblk, PT_SUPER,
-                       W.counts);
+    hipLaunchKernelGGL(k_fp_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)4 << PT_B1, s, a1, nblk, PT_SUPER,
+                       W.counts, W.fp);
     hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div(nb1bins, 256)), dim3(256), 0, s, J.T, nblk, 1 << PT_B1,
                        W.counts, W.bintot1);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, 1 << PT_B1, W.bintot1, W.binstart1);
-    hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a1, nblk, W.counts, W.binstart1,
-                       W.alt_keys, W.alt_ids);
+    hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a1, PT_B1, nblk, W.counts,
+                       W.binstart1, W.fp, W.alt_f, W.alt_id);
     hipLaunchKernelGGL(k_p2_chunks, dim3(1), dim3(1024), 0, s, nb1bins, W.bintot1, W.cbase);
     hipLaunchKernelGGL(k_p2_count, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, nb1bins, W.bintot1,
-                       W.binstart1, W.alt_keys, W.counts2);
+                       W.binstart1, W.alt_f, W.counts2);
     hipLaunchKernelGGL(k_p2_colscan, dim3(ceil_div((int64_t)nb1bins * F, 256)), dim3(256), 0, s, nb1bins, F,
                        W.cbase, W.counts2, W.bintot);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
     hipLaunchKernelGGL(k_p2_scatter, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, nb1bins,
-                       W.bintot1, W.binstart1, W.alt_keys, W.alt_ids, W.counts2, W.binstart, W.st_keys, W.st_ids);
+                       W.bintot1, W.binstart1, W.alt_f, W.alt_id, W.counts2, W.binstart, W.st_f, W.st_id);
   }
   prof_begin(GEEK_PROF_BZ_SORT, s);
-  hipLaunchKernelGGL(k_bin_group, dim3(nbins, J.T), dim3(BZ_THREADS), 0, s, J.n, nb, W.bintot, W.binstart,
-                     W.st_keys, W.st_ids, go, W.big_list, W.big_count);
+  hipLaunchKernelGGL(k_group, dim3(nbins, J.T), dim3(BZ_THREADS), 0, s, a, W.bintot, W.binstart, W.st_f,
+                     W.st_id, go, st);
   prof_end(GEEK_PROF_BZ_SORT, s);
-  hipLaunchKernelGGL(k_big_sort, dim3(256), dim3(BIG_THREADS), 0, s, J.n, nb, J.key_words, W.bintot,
-                     W.binstart, W.st_keys, W.st_ids, W.alt_keys, W.alt_ids, W.big_list, W.big_count);
-  hipLaunchKernelGGL(k_big_runs, dim3(256), dim3(BIG_THREADS), 0, s, J.n, nb, W.bintot, W.binstart,
-                     W.st_keys, W.st_ids, go, W.big_list, W.big_count);
   hipLaunchKernelGGL(k_bz_reduce, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, go, W.ctot);
   hipLaunchKernelGGL(k_scan_chunks, dim3(J.T), dim3(1024), 0, s, nch, W.ctot, J.nbuckets);
   hipLaunchKernelGGL(k_bz_apply, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, go, W.ctot, W.hs,

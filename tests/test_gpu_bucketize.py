@@ -83,3 +83,101 @@ def test_bucketize_minhash_band_layout():
     sig = g.integers(0, 3, size=(n, F)).astype(np.uint32)
     tuples = [sig[:, b * K:(b + 1) * K] for b in range(Lb)]
     _compare(api, sig, n, Lb, K, K, F, tuples, "bands")
+
+
+def test_bucketize_two_streams_at_once():
+    # the two halves of the tables bucketized on two streams at the same time
+    # (each stream has its own cached workspace in the binding) equal one
+    # call over all tables; entries of offsets past nbuckets are unspecified
+    # and not compared
+    import torch
+
+    api = gpu_api()
+    n, d, m, L = 200_000, 32, 8, 16
+    X, _, _ = dense_mixture(n, d, 40, -10, 10, 1.0, "equal", 5)
+    w = 4.0 * math.sqrt(d)
+    A, b = e2lsh_params(m * L, d, w, 5)
+    keys, _ = api.hash_dense(cuda(X), cuda(A), cuda(b), m, L, w)
+    announce(f"bucketize two streams n={n} L={L}")
+    ref = api.bucketize(keys, n, L, 4, n * 4, 4)
+    torch.cuda.synchronize()
+    h = L // 2
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    st1, st2 = api.new_status("cuda"), api.new_status("cuda")
+    torch.cuda.synchronize()
+    for rep in range(2):
+        with torch.cuda.stream(s1):
+            a = api.bucketize(keys[:h], n, h, 4, n * 4, 4, status=st1, check=False)
+        with torch.cuda.stream(s2):
+            bb = api.bucketize(keys[h:], n, L - h, 4, n * 4, 4, status=st2, check=False)
+        torch.cuda.synchronize()
+        assert int(st1.item()) == 0 and int(st2.item()) == 0
+        for part, t0 in ((a, 0), (bb, h)):
+            for t in range(part[0].shape[0]):
+                nb = int(ref[2][t0 + t])
+                assert int(part[2][t]) == nb, (rep, t0 + t)
+                assert torch.equal(part[0][t], ref[0][t0 + t]), (rep, t0 + t)
+                assert torch.equal(part[1][t, :nb + 1], ref[1][t0 + t, :nb + 1]), (rep, t0 + t)
+                assert torch.equal(part[3][t], ref[3][t0 + t]), (rep, t0 + t)
+
+
+def _fmix32(x):
+    x = x & 0xFFFFFFFF
+    x ^= x >> 16
+    x = (x * 0x85EBCA6B) & 0xFFFFFFFF
+    x ^= x >> 13
+    x = (x * 0xC2B2AE35) & 0xFFFFFFFF
+    x ^= x >> 16
+    return x
+
+
+def _bin_hash(words):
+    # the library's bin selector (a 32-bit mix of the four key words, missing
+    # words zero); test-side only, to aim keys at one bin
+    h = 0x9E3779B9
+    for i, w in enumerate(list(words) + [0] * (4 - len(words))):
+        h = (_fmix32(h ^ int(w)) + 0x7F4A7C15 * (i + 1)) & 0xFFFFFFFF
+    return _fmix32(h)
+
+
+def test_bucketize_huge_buckets():
+    # a few keys shared by tens of thousands of objects, among singletons
+    api = gpu_api()
+    g = np.random.default_rng(3)
+    n = 300_000
+    big = g.integers(0, 7, size=n).astype(np.uint32)
+    single = g.random(n) < 0.1
+    keys = np.stack([np.where(single, np.arange(n, dtype=np.uint32) + 100, big),
+                     np.zeros(n, np.uint32)], axis=1)
+    _compare(api, keys.reshape(-1), n, 1, 2, 0, 2, [keys], "huge buckets")
+
+
+def test_bucketize_bin_beyond_the_table():
+    # every key aimed at bin 0 (the top bits of the bin selector): more
+    # distinct keys in one bin than the grouping table holds, some repeated
+    api = gpu_api()
+    n = 3600  # 4 bins of about 900 records each
+    cand = []
+    v = 1
+    while len(cand) < 2600:
+        if (_bin_hash([v, 7]) >> 30) == 0:
+            cand.append(v)
+        v += 1
+    g = np.random.default_rng(4)
+    pick = np.concatenate([np.arange(2600), g.integers(0, 2600, n - 2600)])
+    g.shuffle(pick)
+    k0 = np.asarray(cand, dtype=np.uint32)[pick]
+    keys = np.stack([k0, np.full(n, 7, np.uint32)], axis=1)
+    _compare(api, keys.reshape(-1), n, 1, 2, 0, 2, [keys], "one bin over the table")
+
+
+def test_bucketize_large_bin_few_keys():
+    # one bin far above the one-pass size holding three keys
+    api = gpu_api()
+    n = 20_000
+    g = np.random.default_rng(5)
+    k0 = g.choice(np.asarray([11, 12, 13], np.uint32), size=n)
+    keys = np.stack([k0, k0 ^ 0x55AA55AA, np.arange(n, dtype=np.uint32) % 1], axis=1).astype(np.uint32)
+    _compare(api, keys.reshape(-1), n, 1, 3, 0, 3, [keys], "large bin, three keys")
