@@ -6,20 +6,20 @@
 //  2. A stable partition of (f, id) records into 2^nb bins per table by the
 //     top nb bits of f (equal keys always share a bin): up to 2^PT_B1 bins in
 //     one pass, else a second pass splits every first-pass bin by the next
-//     bits.  Each scatter ranks the records of a round in index order
-//     (wavefront ballots on the bin) and writes every bin's run contiguously,
-//     so each bin keeps its ids ascending.
-//  3. k_group: one workgroup per (bin, table) streams the bin's records in
+//     bits.  Each scatter ranks a round's records in index order (per
+//     wavefront: ballots on the bin and a running count; one scan over
+//     (bin, wavefront) joins the wavefronts) and writes every bin's run
+//     contiguously, so each bin keeps its ids ascending.
+//  3. k_group: one workgroup per (bin, table) takes the bin's records in
 //     order through an LDS table keyed by the exact key (fingerprint first,
 //     the exact keys compared only when fingerprints match).  With the ids in
 //     order, a record's rank in its bucket is the number of earlier records of
-//     that bucket: per step, wavefront ballots on the slot give the ranks
-//     within the step and a per-slot counter carries them across steps; the
-//     rank-0 record is the bucket's head (smallest id).  Objects that share
-//     their key record (head, rank) -- or (head, size) at the head -- in
-//     id-indexed arrays plus a flag bit; objects alone in their bucket write
-//     nothing.  A bin with more distinct keys than the table holds is
-//     processed in sub-ranges of a second hash of the exact key.
+//     that bucket, counted per wavefront and joined per chunk; the rank-0
+//     record is the bucket's head (smallest id).  Objects that share their key
+//     record (head, rank) -- or (head, size) at the head -- in id-indexed
+//     arrays plus a flag byte; objects alone in their bucket write nothing.
+//     A bin with more distinct keys than the table holds is processed in
+//     sub-ranges of further fingerprint bits.
 //  4. k_bz_reduce / k_scan_chunks / k_bz_apply: a scan over ids in id order
 //     gives every bucket its rank in smallest-member order and its CSR
 //     offset; every head (including objects alone in their bucket) is
@@ -166,83 +166,101 @@ constexpr int PT_B1 = 6;          // bits of the first partition pass (64 bins)
 constexpr int PT_ROUND = 2048;    // records placed in LDS per round
 constexpr int PT_SUPER = 16384;   // records per workgroup of a partition pass
 constexpr int PT_RPT = PT_ROUND / BZ_THREADS;
+constexpr int PT_SEG = PT_ROUND / (BZ_THREADS / 64);  // records of one wavefront per round
 
-// One round of a stable partition scatter: the round's `cnt` records
-// (fingerprint, id, bin), taken in index order, get their place among the
-// round's records of the same bin (sub-rounds of BZ_THREADS records in order;
-// within a sub-round wavefront ballots match the bin bits, earlier waves'
-// counts come from LDS), are staged in LDS in bin order and written out so
-// that consecutive threads store consecutive records of a bin.  cur[b] is
-// the global position of bin b's next record and advances by the round's
-// count; every bin receives its records in index order.
+// One round of a stable partition scatter.  The round's `cnt` records
+// (fingerprint, id, bin) are in index order; wavefront w holds the
+// contiguous segment [w * PT_SEG, (w + 1) * PT_SEG), 64 records per step.
+// Each wavefront ranks its records among its own records of the same bin
+// (ballots on the bin bits, a per-wavefront running count in LDS, no
+// barrier); one exclusive scan over (bin, wavefront) then gives every record
+// its place among the round's records of its bin.  The records are staged in
+// LDS in bin order and written out so that consecutive threads store
+// consecutive records of a bin.  cur[b] is the global position of bin b's
+// next record and advances by the round's count, so every bin receives its
+// records in index order.
 struct PartLds {
   uint32_t f[PT_ROUND];
   uint32_t id[PT_ROUND];
   uint16_t bin[PT_ROUND];
-  uint32_t hist[256], lst[256], lrun[256], cur[256], sh[17];
-  uint32_t wcnt[BZ_THREADS / 64][256];
+  uint32_t wc[BZ_THREADS / 64][256];  // records of each bin in the wavefront, then its first place
+  uint32_t hist[256], lst[256], cur[256], sh[17];
 };
 
-template <class Load>
-__device__ void part_round(PartLds& L, int nbins, int nbits, int cnt, const Load& load, uint32_t* out_f,
-                           uint32_t* out_id) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int b = tid; b < nbins; b += BZ_THREADS) L.hist[b] = 0u;
-  for (int w = 0; w < BZ_THREADS / 64; ++w)
-    for (int b = tid; b < nbins; b += BZ_THREADS) L.wcnt[w][b] = 0u;
-  __syncthreads();
+struct PartRecs {
   uint32_t f[PT_RPT], id[PT_RPT];
   int bn[PT_RPT];
+};
+
+// Records of one round: record q = wave * PT_SEG + step * 64 + lane.
+template <class Load>
+GEEK_D void part_load(int cnt, const Load& load, PartRecs& R) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int u = 0; u < PT_RPT; ++u) {
-    const int q = u * BZ_THREADS + tid;
-    bn[u] = 0;
-    if (q < cnt) {
-      load(q, f[u], id[u], bn[u]);
-      atomicAdd(&L.hist[bn[u]], 1u);
-    }
+    const int q = wv * PT_SEG + u * 64 + lane;
+    R.bn[u] = 0;
+    R.f[u] = 0u;
+    R.id[u] = 0u;
+    if (q < cnt) load(q, R.f[u], R.id[u], R.bn[u]);
   }
-  __syncthreads();
-  // exclusive scan of the round's bin counts (nbins <= 256 = one per thread)
-  const uint32_t hv = tid < nbins ? L.hist[tid] : 0u;
-  const uint32_t ex = block_exscan(hv, nullptr, L.sh);
-  if (tid < nbins) {
-    L.lst[tid] = ex;
-    L.lrun[tid] = ex;
-  }
-  __syncthreads();
+}
+
+__device__ void part_round(PartLds& L, int nbins, int nbits, int cnt, const PartRecs& R, uint32_t* out_f,
+                           uint32_t* out_id) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = BZ_THREADS / 64;
+  for (int b = lane; b < nbins; b += 64) L.wc[wv][b] = 0u;  // this wavefront's row only
+  uint32_t lr[PT_RPT];
 #pragma unroll
   for (int u = 0; u < PT_RPT; ++u) {
-    const int q = u * BZ_THREADS + tid;
+    const int q = wv * PT_SEG + u * 64 + lane;
     const bool has = q < cnt;
-    const uint32_t dg = has ? (uint32_t)bn[u] : 0u;
+    const uint32_t dg = has ? (uint32_t)R.bn[u] : 0u;
     uint64_t mask = __ballot(has);
     for (int b = 0; b < nbits; ++b) {
       const uint64_t bb = __ballot(has && ((dg >> b) & 1u));
       mask &= ((dg >> b) & 1u) ? bb : ~bb;
     }
     const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    const bool leader = has && below == 0;
-    if (leader) L.wcnt[wv][dg] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    if (has) {
-      uint32_t before = 0;
-      for (int w2 = 0; w2 < wv; ++w2) before += L.wcnt[w2][dg];
-      const uint32_t p = L.lrun[dg] + before + below;
-      L.f[p] = f[u];
-      L.id[p] = id[u];
-      L.bin[p] = (uint16_t)dg;
-    }
-    __syncthreads();
-    if (tid < nbins) {
-      uint32_t tot = 0;
-      for (int w2 = 0; w2 < BZ_THREADS / 64; ++w2) tot += L.wcnt[w2][tid];
-      L.lrun[tid] += tot;
-    }
-    __syncthreads();
-    if (leader) L.wcnt[wv][dg] = 0u;
-    __syncthreads();
+    lr[u] = L.wc[wv][dg] + below;
+    __builtin_amdgcn_wave_barrier();
+    if (has && below == 0) L.wc[wv][dg] += (uint32_t)__popcll(mask);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
+  __syncthreads();
+  // per bin: the round's count, its start among the round's records, and
+  // the first place of each wavefront's records of the bin
+  uint32_t c[NW], tot = 0u;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    c[w] = tid < nbins ? L.wc[w][tid] : 0u;
+    tot += c[w];
+  }
+  const uint32_t ex = block_exscan(tot, nullptr, L.sh);
+  if (tid < nbins) {
+    L.hist[tid] = tot;
+    L.lst[tid] = ex;
+    uint32_t run = ex;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      L.wc[w][tid] = run;
+      run += c[w];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PT_RPT; ++u) {
+    const int q = wv * PT_SEG + u * 64 + lane;
+    if (q < cnt) {
+      const uint32_t p = L.wc[wv][R.bn[u]] + lr[u];
+      L.f[p] = R.f[u];
+      L.id[p] = R.id[u];
+      L.bin[p] = (uint16_t)R.bn[u];
+    }
+  }
+  __syncthreads();
   for (int p = tid; p < cnt; p += BZ_THREADS) {
     const int b = L.bin[p];
     const uint32_t gp = L.cur[b] + (uint32_t)p - L.lst[b];
@@ -250,7 +268,19 @@ __device__ void part_round(PartLds& L, int nbins, int nbits, int cnt, const Load
     out_id[gp] = L.id[p];
   }
   __syncthreads();
-  for (int b = tid; b < nbins; b += BZ_THREADS) L.cur[b] += L.hist[b];
+  if (tid < nbins) L.cur[tid] += L.hist[tid];
+}
+
+// Rounds of one workgroup.
+template <class Load>
+__device__ void part_rounds(PartLds& L, int nbins, int nbits, int64_t total, const Load& load, uint32_t* out_f,
+                            uint32_t* out_id) {
+  for (int64_t r0 = 0; r0 < total; r0 += PT_ROUND) {
+    const int cnt = (int)(total - r0 < PT_ROUND ? total - r0 : PT_ROUND);
+    PartRecs cur;
+    part_load(cnt, [&](int q, uint32_t& f, uint32_t& id, int& bn) { load(r0 + q, f, id, bn); }, cur);
+    part_round(L, nbins, nbits, cnt, cur, out_f, out_id);
+  }
 }
 
 // First pass: block (chunk of PT_SUPER ids, table) -> 2^nb1 bins by the top
@@ -266,16 +296,13 @@ __global__ __launch_bounds__(BZ_THREADS) void k_p1_scatter(BzArgs a, int nb1, in
   const int64_t s = (int64_t)blk * PT_SUPER;
   const int64_t e = s + PT_SUPER < a.n ? s + PT_SUPER : a.n;
   const uint32_t* fpt = fp + (int64_t)t * a.n;
-  for (int64_t r0 = s; r0 < e; r0 += PT_ROUND) {
-    const int cnt = (int)(e - r0 < PT_ROUND ? e - r0 : PT_ROUND);
-    part_round(L, nbins, nb1, cnt,
-               [&](int q, uint32_t& f, uint32_t& id, int& bn) {
-                 f = fpt[r0 + q];
-                 id = (uint32_t)(r0 + q);
-                 bn = (int)bin_bits_of(f, nb1);
-               },
-               out_f + (int64_t)t * a.n, out_id + (int64_t)t * a.n);
-  }
+  part_rounds(L, nbins, nb1, e - s,
+              [&](int64_t q, uint32_t& f, uint32_t& id, int& bn) {
+                f = fpt[s + q];
+                id = (uint32_t)(s + q);
+                bn = (int)bin_bits_of(f, nb1);
+              },
+              out_f + (int64_t)t * a.n, out_id + (int64_t)t * a.n);
 }
 
 // Second pass.  The records of first-pass bin (t, B) are cut into chunks of
@@ -363,195 +390,485 @@ __global__ __launch_bounds__(BZ_THREADS) void k_p2_scatter(int64_t n, int nb, co
   const int64_t s = (int64_t)t * n + binstart1[tb] + off;
   for (int b = threadIdx.x; b < F; b += BZ_THREADS)
     L.cur[b] = binstart[(int64_t)tb * F + b] + counts2[(int64_t)g * F + b];
-  for (uint32_t r0 = 0; r0 < cnt_all; r0 += PT_ROUND) {
-    const int cnt = (int)min((uint32_t)PT_ROUND, cnt_all - r0);
-    part_round(L, F, nb - PT_B1, cnt,
-               [&](int q, uint32_t& f, uint32_t& id, int& bn) {
-                 f = f1[s + r0 + q];
-                 id = ids1[s + r0 + q];
-                 bn = (int)(bin_bits_of(f, nb) & (uint32_t)(F - 1));
-               },
-               out_f + (int64_t)t * n, out_id + (int64_t)t * n);
-  }
+  part_rounds(L, F, nb - PT_B1, (int64_t)cnt_all,
+              [&](int64_t q, uint32_t& f, uint32_t& id, int& bn) {
+                f = f1[s + q];
+                id = ids1[s + q];
+                bn = (int)(bin_bits_of(f, nb) & (uint32_t)(F - 1));
+              },
+              out_f + (int64_t)t * n, out_id + (int64_t)t * n);
 }
 
 // ---------------------------------------------------------------- per-bin grouping
 // Id-indexed results of the grouping, per table (only objects that share
 // their key with another object are recorded; every other object is a
 // bucket of its own):
-//   flags  bit i set iff object i is in a bucket of two or more
+//   flag8  byte i is 1 iff object i is in a bucket of two or more (plain byte
+//          stores: no atomics)
 //   info   for flagged i: x = head (smallest id of the bucket),
 //          y = bucket size if i is the head, else the rank of i in its bucket
 //          (number of smaller ids)
 struct GroupOut {
-  uint32_t* flags;  // [T][flag_words]
+  uint8_t* flag8;   // [T][fstride]
   uint2* info;      // [T][n]
-  int64_t flag_words;
+  int64_t fstride;  // n rounded up to 16
 };
 
 GEEK_D void group_record(const GroupOut& go, int t, int64_t n, uint32_t id, uint32_t head, uint32_t y) {
   go.info[(int64_t)t * n + id] = make_uint2(head, y);
-  atomicOr(&go.flags[(int64_t)t * go.flag_words + (id >> 5)], 1u << (id & 31));
+  go.flag8[(int64_t)t * go.fstride + id] = 1;
 }
 
-// One workgroup per (bin, table).  The bin's records (fingerprint, id) are in
-// ascending id order.  An LDS table maps each distinct exact key to a slot:
-// a slot word holds the fingerprint and 1 + the bin position of the record
-// that claimed it; a record whose fingerprint matches a slot compares its
-// exact key with the claimant's (both read from the keys array), so only
-// records that share a fingerprint touch the keys.  Records go through in
-// steps of BZ_THREADS in order; ranks come from ballots on the slot within
-// each wavefront, the per-wavefront counts of earlier wavefronts (cleared at
-// the end of each step) and the slot's count of earlier steps.  Bins of at most GB_FILL records fit the
-// table whatever their keys (one pass); larger bins build the table first and
-// are processed in sub-ranges of a second key hash (1, 64, 4096, ... of them)
-// if their distinct keys do not fit.
-constexpr int GB_HT = 2048;             // slots of the table
-constexpr int GB_FILL = 1792;           // distinct keys per (sub-)range
-constexpr int GB_SBITS = 11;            // bits of a slot index
-constexpr int GB_LEVELS = 5;            // sub-range splits: 1, 2^6, 2^12, 2^18, 2^24
+// Grouping of one bin's records (fingerprint, id), taken in ascending id
+// order.  An LDS table maps each distinct exact key to a slot: a slot word
+// holds the fingerprint and 1 + the id of the record that claimed it; a
+// record whose fingerprint matches a slot claimed by another id compares its
+// exact key with the claimant's (the key loads of a chunk are issued
+// together).  Records are taken in chunks of GB_CAP, lane-private in LDS
+// while they probe; wavefront w holds the contiguous segment
+// [w * GB_SEG, (w + 1) * GB_SEG) of a chunk, 64 records per step.
+//  * Fast path (a bin of at most GB_FILL records, the common case): after the
+//    probes, the slots that some record joined are marked; only their
+//    records (usually a handful) are listed, and each listed record's rank
+//    (number of smaller ids with its key), bucket size and head come from
+//    one pass over the list.
+//  * General path (a larger bin, or more than GB_LIST shared records):
+//    every wavefront counts its records per slot in order (ballots on the
+//    slot bits and a running count), one pass over the slots turns the
+//    counts into the first rank of each wavefront's records (plus the
+//    slot's count of earlier chunks); the rank-0 record is the head.  A bin
+//    larger than GB_FILL inserts every record first (its slot kept in a
+//    bin-ordered scratch array); one whose distinct keys do not fit is done
+//    in sub-ranges of further fingerprint bits (equal keys have equal
+//    fingerprints, so a key never spans two sub-ranges).
+constexpr int GB_HT = 1024;                 // slots of the table
+constexpr int GB_FILL = 896;                // distinct keys per (sub-)range
+constexpr int GB_SBITS = 10;                // bits of a slot index
+constexpr int GB_CAP = 1024;                // records per chunk
+constexpr int GB_RPL = GB_CAP / BZ_THREADS; // records per lane and chunk
+constexpr int GB_SEG = GB_CAP / (BZ_THREADS / 64);
+constexpr int GB_LIST = BZ_THREADS;         // shared-key records of the fast path
+constexpr int GB_SUBBITS = 5;               // sub-range bits added per level
+constexpr int GB_LEVELS = 4;                // 1, 2^5, 2^10, 2^15 sub-ranges
+constexpr uint16_t GB_NONE = 0xFFFFu;
+// Probe results of a record (16 bits): a slot (bits 0-9) with GB_CLAIM set
+// when this record inserted it; GB_PEND | slot: the slot's claimant has the
+// same fingerprint, keys not compared yet; GB_CONT | slot: it holds another
+// key, probe on after it; GB_FULL: no room; GB_NONE: no record.
+constexpr uint16_t GB_CLAIM = 0x0800u, GB_PEND = 0x8000u, GB_CONT = 0x4000u, GB_FULL = 0xFFFEu;
+constexpr uint32_t GB_SLOTMASK = GB_HT - 1;
 struct GroupLds {
   unsigned long long slot[GB_HT];
-  uint32_t cnt[GB_HT];
-  uint32_t head[GB_HT];
-  uint16_t wc[BZ_THREADS / 64][GB_HT];  // records of each wavefront in the slot, this step
-  uint32_t nslot, over;
+  union {
+    struct {             // probing: the lane's records, thread-private
+      uint32_t f[GB_CAP];
+      uint32_t id[GB_CAP];
+      uint16_t res[GB_CAP];
+    } rec;
+    struct {             // general-path ranks
+      uint32_t wc[BZ_THREADS / 64][GB_HT];  // per wavefront: records this chunk, then first rank
+      uint32_t cnt[GB_HT];                  // records of the slot's key so far
+      uint32_t head[GB_HT];                 // the key's smallest id
+    } rk;
+  };
+  uint32_t mark[GB_HT / 32];                // fast path: slots another record joined
+  uint32_t lslot[GB_LIST], lid[GB_LIST];    // fast path: their records
+  uint32_t nslot, over, nlist;
 };
 
-// Slot of a record's exact key; inserts it when `ins`.  -1: the table has no
-// room (or, without insertion, the key is absent).
-GEEK_D int gb_slot(GroupLds& G, const BzArgs& a, int t, uint32_t f, uint32_t pos, uint32_t id,
-                   const uint32_t* __restrict__ bin_ids, bool ins) {
-  uint32_t h = f & (GB_HT - 1);
-  uint4 mine = make_uint4(0u, 0u, 0u, 0u);
-  bool have = false;
+// A slot word: (fingerprint << 32) | (claimant id + 1); 0 = free.
+// Probe for the slot of (f, id) from slot h on.  Returns the slot (*claimed:
+// this call inserted it); -1: no room; -2: slot *ph holds the same
+// fingerprint for another id, the exact keys decide.
+GEEK_D int gb_probe(GroupLds& G, uint32_t f, uint32_t id, uint32_t h, uint32_t* ph, bool* claimed) {
+  const unsigned long long v = ((unsigned long long)f << 32) | (unsigned long long)(id + 1u);
+#pragma unroll 1
   for (int probe = 0; probe < GB_HT; ++probe) {
     unsigned long long s = G.slot[h];
     if (s == 0ull) {
-      if (!ins) return -1;
-      const unsigned long long v = ((unsigned long long)f << 32) | (unsigned long long)(pos + 1u);
-      const unsigned long long prev = atomicCAS(&G.slot[h], 0ull, v);
-      if (prev == 0ull) {
-        atomicAdd(&G.nslot, 1u);
+      s = atomicCAS(&G.slot[h], 0ull, v);
+      if (s == 0ull) {
+        *claimed = true;
         return (int)h;
       }
-      s = prev;
     }
     if ((uint32_t)(s >> 32) == f) {
-      const uint32_t opos = (uint32_t)s - 1u;
-      if (opos == pos) return (int)h;
-      if (!have) {
-        mine = load_key(a, t, id);
-        have = true;
-      }
-      if (key_eq(load_key(a, t, bin_ids[opos]), mine)) return (int)h;
+      if ((uint32_t)s == id + 1u) return (int)h;
+      *ph = h;
+      return -2;
     }
-    h = (h + 1u) & (GB_HT - 1);
+    h = (h + 1u) & GB_SLOTMASK;
   }
   return -1;
 }
 
-__global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* bintot, const uint32_t* binstart,
-                                                      const uint32_t* st_f, const uint32_t* st_id, GroupOut go,
-                                                      int32_t* st) {
-  __shared__ GroupLds G;
-  const int t = blockIdx.y, bin = blockIdx.x;
-  const int nbins = 1 << a.nb;
-  const uint32_t size = bintot[(int64_t)t * nbins + bin];
-  if (size <= 1) return;  // empty, or one record: a bucket of its own
-  const int64_t n = a.n;
-  const uint32_t s0 = binstart[(int64_t)t * nbins + bin];
-  const uint32_t* fptr = st_f + (int64_t)t * n + s0;
-  const uint32_t* iptr = st_id + (int64_t)t * n + s0;
+GEEK_D uint16_t gb_code(int r, bool claimed, uint32_t ph) {
+  if (r >= 0) return (uint16_t)((uint32_t)r | (claimed ? GB_CLAIM : 0u));
+  return r == -1 ? GB_FULL : (uint16_t)(GB_PEND | ph);
+}
+GEEK_D uint32_t gb_claimant(const GroupLds& G, uint32_t h) { return (uint32_t)G.slot[h] - 1u; }
+
+// Slots of the lane's records of one chunk, left in G.rec.res: probes first
+// (one loop over the lane's records), then the exact-key comparisons of all
+// pending records with their loads issued together, then the rare records
+// whose fingerprint met another key, probing on one by one.
+GEEK_D void gb_slots(GroupLds& G, const BzArgs& a, int t) {
+  const int tid = threadIdx.x;
+#pragma unroll 1
+  for (int u = 0; u < GB_RPL; ++u) {
+    const int i = u * BZ_THREADS + tid;
+    if (G.rec.res[i] == GB_NONE) continue;
+    uint32_t ph = 0u;
+    bool cl = false;
+    const uint32_t f = G.rec.f[i];
+    const int r = gb_probe(G, f, G.rec.id[i], f & GB_SLOTMASK, &ph, &cl);
+    G.rec.res[i] = gb_code(r, cl, ph);
+  }
+  uint4 mk[GB_RPL], ck[GB_RPL];
+#pragma unroll
+  for (int u = 0; u < GB_RPL; ++u) {
+    const int i = u * BZ_THREADS + tid;
+    const uint16_t c = G.rec.res[i];
+    if ((c & 0xC000u) == GB_PEND) {
+      mk[u] = load_key(a, t, G.rec.id[i]);
+      ck[u] = load_key(a, t, gb_claimant(G, c & GB_SLOTMASK));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < GB_RPL; ++u) {
+    const int i = u * BZ_THREADS + tid;
+    const uint16_t c = G.rec.res[i];
+    if ((c & 0xC000u) == GB_PEND)
+      G.rec.res[i] = key_eq(mk[u], ck[u]) ? (uint16_t)(c & GB_SLOTMASK) : (uint16_t)(GB_CONT | (c & GB_SLOTMASK));
+  }
+#pragma unroll 1
+  for (int u = 0; u < GB_RPL; ++u) {
+    const int i = u * BZ_THREADS + tid;
+    uint16_t c = G.rec.res[i];
+    if ((c & 0xC000u) != GB_CONT) continue;
+    const uint32_t f = G.rec.f[i], id = G.rec.id[i];
+    const uint4 mine = load_key(a, t, id);
+    while ((c & 0xC000u) == GB_CONT) {
+      uint32_t ph = 0u;
+      bool cl = false;
+      const int r = gb_probe(G, f, id, ((c & GB_SLOTMASK) + 1u) & GB_SLOTMASK, &ph, &cl);
+      c = gb_code(r, cl, ph);
+      if ((c & 0xC000u) == GB_PEND)
+        c = key_eq(mine, load_key(a, t, gb_claimant(G, ph))) ? (uint16_t)ph : (uint16_t)(GB_CONT | ph);
+    }
+    G.rec.res[i] = c;
+  }
+}
+
+// The lane's records of one chunk into G.rec (res = 0: to probe, GB_NONE: none).
+GEEK_D void gb_stage(GroupLds& G, const uint32_t* f, const uint32_t* id, const bool* in) {
+#pragma unroll
+  for (int u = 0; u < GB_RPL; ++u) {
+    const int i = u * BZ_THREADS + threadIdx.x;
+    G.rec.f[i] = f[u];
+    G.rec.id[i] = id[u];
+    G.rec.res[i] = in[u] ? (uint16_t)0u : GB_NONE;
+  }
+}
+
+// General-path ranks of one chunk (g < 0: no record) and their records;
+// G.rk.cnt / G.rk.head carry across chunks, G.rk.wc is zero on entry and
+// on exit.
+GEEK_D void gb_rank_chunk(GroupLds& G, const GroupOut& go, int t, int64_t n, const int* g, const uint32_t* id) {
+  constexpr int NW = BZ_THREADS / 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t lr[GB_RPL];
+#pragma unroll
+  for (int u = 0; u < GB_RPL; ++u) {
+    const bool v = g[u] >= 0;
+    const uint32_t gg = v ? (uint32_t)g[u] : 0u;
+    uint64_t mask = __ballot(v);
+    for (int b = 0; b < GB_SBITS; ++b) {
+      const uint64_t bb = __ballot(v && ((gg >> b) & 1u));
+      mask &= ((gg >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    lr[u] = G.rk.wc[wv][gg] + below;
+    __builtin_amdgcn_wave_barrier();
+    if (v && below == 0) G.rk.wc[wv][gg] += (uint32_t)__popcll(mask);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  for (int h = tid; h < GB_HT; h += BZ_THREADS) {
+    uint32_t run = G.rk.cnt[h];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t cw = G.rk.wc[w][h];
+      G.rk.wc[w][h] = run;
+      run += cw;
+    }
+    G.rk.cnt[h] = run;
+  }
+  __syncthreads();
+  uint32_t rank[GB_RPL];
+#pragma unroll
+  for (int u = 0; u < GB_RPL; ++u) {
+    rank[u] = 0u;
+    if (g[u] >= 0) {
+      rank[u] = G.rk.wc[wv][g[u]] + lr[u];
+      if (rank[u] == 0u) G.rk.head[g[u]] = id[u];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < GB_RPL; ++u)
+    if (g[u] >= 0 && rank[u] > 0u) group_record(go, t, n, id[u], G.rk.head[g[u]], rank[u]);
+  for (int h = tid; h < GB_HT; h += BZ_THREADS) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) G.rk.wc[w][h] = 0u;
+  }
+  __syncthreads();
+}
+
+GEEK_D void gb_rank_clear(GroupLds& G) {
+  constexpr int NW = BZ_THREADS / 64;
+  for (int h = threadIdx.x; h < GB_HT; h += BZ_THREADS) {
+    G.rk.cnt[h] = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) G.rk.wc[w][h] = 0u;
+  }
+}
+
+// Heads of buckets of two or more: (head, size).
+GEEK_D void gb_heads(GroupLds& G, const GroupOut& go, int t, int64_t n) {
+  for (int h = threadIdx.x; h < GB_HT; h += BZ_THREADS)
+    if (G.slot[h] != 0ull && G.rk.cnt[h] >= 2u) group_record(go, t, n, G.rk.head[h], G.rk.head[h], G.rk.cnt[h]);
+}
+
+// One bin by the general path: inserts first (slots kept in sptr), in
+// sub-ranges of further fingerprint bits if its distinct keys do not fit,
+// then ranks chunk by chunk.
+__device__ void gb_large_bin(GroupLds& G, const BzArgs& a, int t, uint32_t size, const uint32_t* fptr,
+                             const uint32_t* iptr, uint16_t* sptr, const GroupOut& go, int32_t* st) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t n = a.n;
   for (int level = 0; level < GB_LEVELS; ++level) {
-    const int sbits = 6 * level;
+    const int sbits = GB_SUBBITS * level;
     const uint32_t nsub = 1u << sbits;
     bool done = true;
     for (uint32_t r = 0; r < nsub; ++r) {
-      // the records of this sub-range: all records at level 0, else those
-      // whose second key hash has r in its low sbits bits
-      auto in_range = [&](uint32_t q) -> bool {
-        if (level == 0) return true;
-        return (fp2_of(load_key(a, t, iptr[q])) & (nsub - 1u)) == r;
-      };
-      for (int h = tid; h < GB_HT; h += BZ_THREADS) {
-        G.slot[h] = 0ull;
-        G.cnt[h] = 0u;
-#pragma unroll
-        for (int w = 0; w < BZ_THREADS / 64; ++w) G.wc[w][h] = 0;
-      }
+      for (int h = tid; h < GB_HT; h += BZ_THREADS) G.slot[h] = 0ull;
       if (tid == 0) {
         G.nslot = 0u;
         G.over = 0u;
       }
       __syncthreads();
-      // a range that could hold more distinct keys than fit: build the table first
-      const bool build = level > 0 || size > (uint32_t)GB_FILL;
-      if (build) {
-        for (uint32_t q0 = 0; q0 < size; q0 += BZ_THREADS) {
-          const uint32_t q = q0 + tid;
-          if (q < size && in_range(q)) {
-            const int g = gb_slot(G, a, t, fptr[q], q, iptr[q], iptr, true);
-            if (g < 0) G.over = 1u;
-          }
-          __syncthreads();
-          if (G.over || G.nslot > (uint32_t)GB_FILL) break;  // uniform: read after the barrier
-          __syncthreads();
+      bool anydup = false, full = false;
+      for (uint32_t c0 = 0; c0 < size; c0 += GB_CAP) {
+        uint32_t f[GB_RPL], id[GB_RPL];
+        bool in[GB_RPL];
+#pragma unroll
+        for (int u = 0; u < GB_RPL; ++u) {
+          const uint32_t q = c0 + wv * GB_SEG + u * 64 + lane;
+          in[u] = q < size;
+          f[u] = in[u] ? fptr[q] : 0u;
+          id[u] = in[u] ? iptr[q] : 0u;
+          in[u] = in[u] && (level == 0 || ((f[u] << a.nb) >> (32 - sbits)) == r);
         }
+        gb_stage(G, f, id, in);
+        gb_slots(G, a, t);
+        uint32_t nc = 0u;
+#pragma unroll
+        for (int u = 0; u < GB_RPL; ++u) {
+          const uint32_t q = c0 + wv * GB_SEG + u * 64 + lane;
+          const uint16_t c = G.rec.res[u * BZ_THREADS + tid];
+          const bool ok = c < GB_CONT;
+          anydup |= ok && !(c & GB_CLAIM);
+          nc += (uint32_t)__popcll(__ballot(ok && (c & GB_CLAIM)));
+          if (c == GB_FULL) G.over = 1u;
+          if (q < size) sptr[q] = ok ? (uint16_t)(c & GB_SLOTMASK) : GB_NONE;
+        }
+        if (lane == 0) atomicAdd(&G.nslot, nc);
         __syncthreads();
-        if (G.over || G.nslot > (uint32_t)GB_FILL) {
-          done = false;
-          __syncthreads();
-          break;  // split this bin more finely
-        }
+        full = G.over || G.nslot > (uint32_t)GB_FILL;  // uniform: read between two barriers
+        __syncthreads();
+        if (full) break;
       }
-      for (uint32_t q0 = 0; q0 < size; q0 += BZ_THREADS) {
-        const uint32_t q = q0 + tid;
-        bool valid = q < size && in_range(q);
-        uint32_t id = 0u;
-        int g = -1;
-        if (valid) {
-          id = iptr[q];
-          g = gb_slot(G, a, t, fptr[q], q, id, iptr, !build);
-          valid = g >= 0;
-        }
-        __syncthreads();  // every insertion of the step is done
-        uint64_t mask = __ballot(valid);
-        for (int b = 0; b < GB_SBITS; ++b) {
-          const uint64_t bb = __ballot(valid && ((g >> b) & 1));
-          mask &= ((g >> b) & 1) ? bb : ~bb;
-        }
-        const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-        const uint32_t wcount = (uint32_t)__popcll(mask);
-        const bool leader = valid && below == 0;
-        if (leader) G.wc[wv][g] = (uint16_t)wcount;
-        __syncthreads();
-        uint32_t rank = 0u;
-        if (valid) {
-          uint32_t before = 0u;
-          for (int w2 = 0; w2 < wv; ++w2) before += G.wc[w2][g];
-          rank = G.cnt[g] + before + below;
-          if (rank == 0u) G.head[g] = id;
-        }
-        __syncthreads();
-        if (valid && rank > 0u) group_record(go, t, n, id, G.head[g], rank);
-        if (leader) {
-          atomicAdd(&G.cnt[g], wcount);
-          G.wc[wv][g] = 0;
-        }
-        __syncthreads();
+      if (full) {
+        done = false;
+        break;  // split this bin more finely
       }
-      // heads of buckets of two or more: (head, size)
-      for (int h = tid; h < GB_HT; h += BZ_THREADS)
-        if (G.slot[h] != 0ull && G.cnt[h] >= 2u) group_record(go, t, n, G.head[h], G.head[h], G.cnt[h]);
+      // every key of the (sub-)range alone: nothing to record
+      if (!__syncthreads_or(anydup)) continue;
+      gb_rank_clear(G);
+      __syncthreads();
+      for (uint32_t c0 = 0; c0 < size; c0 += GB_CAP) {
+        int g[GB_RPL];
+        uint32_t id[GB_RPL];
+#pragma unroll
+        for (int u = 0; u < GB_RPL; ++u) {
+          const uint32_t q = c0 + wv * GB_SEG + u * 64 + lane;
+          const uint16_t sl = q < size ? sptr[q] : GB_NONE;
+          id[u] = sl != GB_NONE ? iptr[q] : 0u;
+          g[u] = sl != GB_NONE ? (int)sl : -1;
+        }
+        gb_rank_chunk(G, go, t, n, g, id);
+      }
+      gb_heads(G, go, t, n);
       __syncthreads();
     }
     if (done) return;
   }
-  // more than GB_FILL distinct keys share 24 bits of the second hash in one
-  // bin: not handled
+  // more than GB_FILL distinct keys share every fingerprint bit the
+  // sub-ranges can split on: not handled
   if (tid == 0) set_status(st, GEEK_ERR_KEYS);
+}
+
+// Fast grouping of the bins that hold few shared keys (the common case), a
+// persistent kernel: workgroup b takes the (table, bin) items b, b + grid,
+// ...; the next item's records and the one after's extent are loaded while
+// the current one is grouped.  A record sets bit (f mod 2^16) of a "seen"
+// bitmap; a bit that was already set also goes into "seen twice".  Records
+// whose bit is in "seen twice" -- every record of a key shared in the bin,
+// plus a few whose 16 bits merely coincide -- are listed with their exact
+// keys, and each listed record's rank (number of smaller listed ids with
+// the same key), bucket size and head come from one pass over the list.
+// Every other record is alone in its bucket.  Bins larger than GB_FILL or
+// with more than GB_LIST listed records go to a list of hard items for
+// k_group_hard.
+constexpr int GF_BITS = 1 << 16;
+struct FastLds {
+  uint32_t seen[GF_BITS / 32];
+  uint32_t twice[GF_BITS / 32];
+  uint32_t lid[GB_LIST], lf[GB_LIST];
+  uint4 lkey[GB_LIST];
+  uint32_t nlist;
+};
+
+__global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* bintot, const uint32_t* binstart,
+                                                      const uint32_t* st_f, const uint32_t* st_id, GroupOut go,
+                                                      uint32_t* hard, uint32_t* nhard) {
+  __shared__ FastLds S;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nbins = 1 << a.nb;
+  const int64_t nwork = (int64_t)a.T * nbins;
+  const int64_t n = a.n;
+  const int64_t step = gridDim.x;
+  auto extent = [&](int64_t w, uint32_t& size, uint32_t& s0) {
+    size = 0u;
+    s0 = 0u;
+    if (w < nwork) {
+      size = bintot[w];
+      s0 = binstart[w];
+    }
+  };
+  auto records = [&](int64_t w, uint32_t size, uint32_t s0, uint32_t* f, uint32_t* id) {
+    const int64_t base = (w / nbins) * n + s0;
+#pragma unroll
+    for (int u = 0; u < GB_RPL; ++u) {
+      const uint32_t q = wv * GB_SEG + u * 64 + lane;
+      const bool in = size > 1u && size <= (uint32_t)GB_FILL && q < size;
+      f[u] = in ? st_f[base + q] : 0u;
+      id[u] = in ? st_id[base + q] : 0u;
+    }
+  };
+  int64_t w = blockIdx.x;
+  uint32_t sz0, b0, sz1, b1;
+  extent(w, sz0, b0);
+  extent(w + step, sz1, b1);
+  uint32_t f0[GB_RPL], i0[GB_RPL];
+  records(w, sz0, b0, f0, i0);
+  for (; w < nwork; w += step) {
+    const uint32_t size = sz0;
+    uint32_t f[GB_RPL], id[GB_RPL];
+#pragma unroll
+    for (int u = 0; u < GB_RPL; ++u) {
+      f[u] = f0[u];
+      id[u] = i0[u];
+    }
+    uint32_t sz2, b2;
+    extent(w + 2 * step, sz2, b2);
+    records(w + step, sz1, b1, f0, i0);
+    sz0 = sz1;
+    b0 = b1;
+    sz1 = sz2;
+    b1 = b2;
+    if (size <= 1u) continue;  // empty, or one record: a bucket of its own
+    if (size > (uint32_t)GB_FILL) {
+      if (tid == 0) hard[atomicAdd(nhard, 1u)] = (uint32_t)w;
+      continue;
+    }
+    const int t = (int)(w / nbins);
+    bool in[GB_RPL];
+#pragma unroll
+    for (int u = 0; u < GB_RPL; ++u) in[u] = (uint32_t)(wv * GB_SEG + u * 64 + lane) < size;
+    {
+      uint4* s4 = reinterpret_cast<uint4*>(S.seen);  // seen and twice are adjacent
+      for (int i = tid; i < GF_BITS / 64; i += BZ_THREADS) s4[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    if (tid == 0) S.nlist = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < GB_RPL; ++u) {
+      if (!in[u]) continue;
+      const uint32_t b = f[u] & (GF_BITS - 1), m = 1u << (b & 31);
+      if (atomicOr(&S.seen[b >> 5], m) & m) atomicOr(&S.twice[b >> 5], m);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < GB_RPL; ++u) {
+      const uint32_t b = f[u] & (GF_BITS - 1);
+      if (in[u] && ((S.twice[b >> 5] >> (b & 31)) & 1u)) {
+        const uint32_t p = atomicAdd(&S.nlist, 1u);
+        if (p < (uint32_t)GB_LIST) {
+          S.lid[p] = id[u];
+          S.lf[p] = f[u];
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t k = S.nlist;
+    __syncthreads();        // read by every thread before the next item resets it
+    if (k == 0u) continue;  // every key alone
+    if (k > (uint32_t)GB_LIST) {
+      if (tid == 0) hard[atomicAdd(nhard, 1u)] = (uint32_t)w;
+      continue;
+    }
+    if ((uint32_t)tid < k) S.lkey[tid] = load_key(a, t, S.lid[tid]);
+    __syncthreads();
+    if ((uint32_t)tid < k) {
+      const uint32_t me = S.lid[tid], mf = S.lf[tid];
+      const uint4 mk = S.lkey[tid];
+      uint32_t rank = 0u, cnt = 0u, head = me;
+      for (uint32_t j = 0; j < k; ++j) {
+        if (S.lf[j] == mf && key_eq(S.lkey[j], mk)) {
+          const uint32_t ij = S.lid[j];
+          ++cnt;
+          rank += ij < me;
+          head = min(head, ij);
+        }
+      }
+      if (cnt >= 2u) group_record(go, t, n, me, head, rank ? rank : cnt);
+    }
+    __syncthreads();
+  }
+}
+
+// The hard items: the general path (insertion into the slot table, ranks by
+// ballots), persistent over the list k_group left.
+__global__ __launch_bounds__(BZ_THREADS) void k_group_hard(BzArgs a, const uint32_t* bintot,
+                                                           const uint32_t* binstart, const uint32_t* st_f,
+                                                           const uint32_t* st_id, uint16_t* sc_slot, GroupOut go,
+                                                           const uint32_t* hard, const uint32_t* nhard,
+                                                           int32_t* st) {
+  __shared__ GroupLds G;
+  const int nbins = 1 << a.nb;
+  const int64_t n = a.n;
+  const uint32_t cnt = *nhard;
+  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const uint32_t w = hard[i];
+    const int t = (int)(w / (uint32_t)nbins);
+    const uint32_t size = bintot[w], s0 = binstart[w];
+    gb_large_bin(G, a, t, size, st_f + (int64_t)t * n + s0, st_id + (int64_t)t * n + s0,
+                 sc_slot + (int64_t)t * n + s0, go, st);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- scans and emission
@@ -573,8 +890,11 @@ GEEK_D void id_bucket(const GroupOut& go, int t, int64_t n, int64_t i, bool flag
   len = is_head ? inf.y : 0u;
 }
 
+// Flags of ids i0 .. i0 + 15 (i0 a multiple of 16) as bits.
 GEEK_D uint32_t flag_bits16(const GroupOut& go, int t, int64_t i0) {
-  return (go.flags[(int64_t)t * go.flag_words + (i0 >> 5)] >> (i0 & 31)) & 0xFFFFu;
+  const uint4 v = *reinterpret_cast<const uint4*>(go.flag8 + (int64_t)t * go.fstride + i0);
+  auto nib = [](uint32_t w) { return (w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u); };
+  return nib(v.x) | (nib(v.y) << 4) | (nib(v.z) << 8) | (nib(v.w) << 12);
 }
 
 __global__ __launch_bounds__(BZ_THREADS) void k_bz_reduce(int64_t n, int nch, GroupOut go, uint2* ctot) {
@@ -723,12 +1043,14 @@ static size_t p2_max_chunks(int64_t n, int T) {
 
 static int bin_bits(int64_t n) {
   int nb = 0;
-  while (nb < BZ_MAXBITS && (n >> nb) > 1536) ++nb;
+  while (nb < BZ_MAXBITS && (n >> nb) > 768) ++nb;
   return nb;
 }
 
 struct BzWs {
-  uint32_t *counts, *bintot, *binstart, *fp, *st_f, *st_id, *alt_f, *alt_id, *flags;
+  uint32_t *counts, *bintot, *binstart, *fp, *st_f, *st_id, *alt_f, *alt_id;
+  uint8_t* flag8;
+  uint32_t* hard;
   uint32_t *counts2, *bintot1, *binstart1, *cbase;  // second partition pass
   uint2 *info, *hs, *ctot;
 };
@@ -740,7 +1062,7 @@ static size_t carve_bz(const geek_bucketize_job& J, void* ws, BzWs& W) {
   const int nblk = ceil_div(J.n, PT_SUPER);
   const int nch = ceil_div(J.n, SC_CHUNK);
   const size_t Tn = (size_t)J.T * J.n;
-  const int64_t fw = ceil_div(J.n, 32);
+  const int64_t fw = ceil_div(J.n, 16) * 16;
   const bool two = nb > PT_B1;
   const int nb1bins = 1 << (two ? PT_B1 : nb);
   W.counts = c.take<uint32_t>((size_t)J.T * nblk * nb1bins);
@@ -756,7 +1078,8 @@ static size_t carve_bz(const geek_bucketize_job& J, void* ws, BzWs& W) {
   W.st_id = c.take<uint32_t>(Tn);
   W.alt_f = two ? c.take<uint32_t>(Tn) : nullptr;
   W.alt_id = two ? c.take<uint32_t>(Tn) : nullptr;
-  W.flags = c.take<uint32_t>((size_t)J.T * fw);
+  W.flag8 = c.take<uint8_t>((size_t)J.T * fw + 16);  // + the hard-item counter, cleared with the flags
+  W.hard = c.take<uint32_t>((size_t)J.T * nbins);
   W.info = c.take<uint2>(Tn);
   W.hs = c.take<uint2>(Tn);
   W.ctot = c.take<uint2>((size_t)J.T * nch);
@@ -768,9 +1091,9 @@ size_t bucketize_ws(const geek_bucketize_job& J) {
   return carve_bz(J, nullptr, W);
 }
 
-__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+__global__ void k_zero_u4(uint4* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+  if (i < n) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, int32_t* st,
@@ -781,12 +1104,13 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   const int nbins = 1 << nb;
   const int nblk = ceil_div(J.n, PT_SUPER);
   const int nch = ceil_div(J.n, SC_CHUNK);
-  const int64_t fw = ceil_div(J.n, 32);
+  const int64_t fw = ceil_div(J.n, 16) * 16;
   BzArgs a{J.keys, J.n, J.T, J.key_words, J.table_stride, J.row_stride, nb};
-  GroupOut go{W.flags, W.info, fw};
+  GroupOut go{W.flag8, W.info, fw};
   prof_begin(GEEK_PROF_BUCKETIZE, s);
-  hipLaunchKernelGGL(k_zero_u32, dim3(ceil_div((int64_t)J.T * fw, 256)), dim3(256), 0, s, W.flags,
-                     (int64_t)J.T * fw);
+  hipLaunchKernelGGL(k_zero_u4, dim3(ceil_div((int64_t)J.T * fw / 16 + 1, 256)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(W.flag8), (int64_t)J.T * fw / 16 + 1);
+  uint32_t* nhard = reinterpret_cast<uint32_t*>(W.flag8 + (size_t)J.T * fw);
   if (nb <= PT_B1) {
     hipLaunchKernelGGL(k_fp_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)nbins * 4, s, a, nblk, PT_SUPER,
                        W.counts, W.fp);
@@ -820,8 +1144,16 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
                        W.bintot1, W.binstart1, W.alt_f, W.alt_id, W.counts2, W.binstart, W.st_f, W.st_id);
   }
   prof_begin(GEEK_PROF_BZ_SORT, s);
-  hipLaunchKernelGGL(k_group, dim3(nbins, J.T), dim3(BZ_THREADS), 0, s, a, W.bintot, W.binstart, W.st_f,
-                     W.st_id, go, st);
+  {
+    const int64_t items = (int64_t)J.T * nbins;
+    const int grid = (int)(items < 1792 ? items : 1792);  // persistent: 7 per CU are resident
+    hipLaunchKernelGGL(k_group, dim3(grid), dim3(BZ_THREADS), 0, s, a, W.bintot, W.binstart, W.st_f, W.st_id, go,
+                       W.hard, nhard);
+    // the fingerprints are dead after the first scatter: their space keeps
+    // the general path's slots
+    hipLaunchKernelGGL(k_group_hard, dim3(grid < 1024 ? grid : 1024), dim3(BZ_THREADS), 0, s, a, W.bintot,
+                       W.binstart, W.st_f, W.st_id, reinterpret_cast<uint16_t*>(W.fp), go, W.hard, nhard, st);
+  }
   prof_end(GEEK_PROF_BZ_SORT, s);
   hipLaunchKernelGGL(k_bz_reduce, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, go, W.ctot);
   hipLaunchKernelGGL(k_scan_chunks, dim3(J.T), dim3(1024), 0, s, nch, W.ctot, J.nbuckets);
