@@ -63,6 +63,11 @@ GEEK_D uint32_t fp2_of(const uint4& k) {
   return fmix32(key_hash(w, 4) + 0x1F83D9ABu);
 }
 GEEK_D uint32_t bin_bits_of(uint32_t f, int nb) { return nb ? f >> (32 - nb) : 0u; }
+// A partitioned record: fingerprint in the low word, id in the high word.
+typedef unsigned long long BzRec;
+GEEK_D BzRec rec_make(uint32_t f, uint32_t id) { return ((BzRec)id << 32) | (BzRec)f; }
+GEEK_D uint32_t rec_f(BzRec r) { return (uint32_t)r; }
+GEEK_D uint32_t rec_id(BzRec r) { return (uint32_t)(r >> 32); }
 GEEK_D bool key_eq(const uint4& a, const uint4& b) {
   return a.x == b.x && a.y == b.y && a.z == b.z && a.w == b.w;
 }
@@ -180,43 +185,41 @@ constexpr int PT_SEG = PT_ROUND / (BZ_THREADS / 64);  // records of one wavefron
 // next record and advances by the round's count, so every bin receives its
 // records in index order.
 struct PartLds {
-  uint32_t f[PT_ROUND];
-  uint32_t id[PT_ROUND];
-  uint16_t bin[PT_ROUND];
+  BzRec rec[PT_ROUND];
   uint32_t wc[BZ_THREADS / 64][256];  // records of each bin in the wavefront, then its first place
   uint32_t hist[256], lst[256], cur[256], sh[17];
 };
 
 struct PartRecs {
   uint32_t f[PT_RPT], id[PT_RPT];
-  int bn[PT_RPT];
 };
 
-// Records of one round: record q = wave * PT_SEG + step * 64 + lane.
+// Records of one round: record q = wave * PT_SEG + step * 64 + lane.  The
+// loads are unconditional (lanes past the end read record cnt - 1 and are
+// ignored), so all of a round's loads are in flight at once.
 template <class Load>
 GEEK_D void part_load(int cnt, const Load& load, PartRecs& R) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int u = 0; u < PT_RPT; ++u) {
     const int q = wv * PT_SEG + u * 64 + lane;
-    R.bn[u] = 0;
-    R.f[u] = 0u;
-    R.id[u] = 0u;
-    if (q < cnt) load(q, R.f[u], R.id[u], R.bn[u]);
+    load(q < cnt ? q : cnt - 1, R.f[u], R.id[u]);
   }
 }
 
-__device__ void part_round(PartLds& L, int nbins, int nbits, int cnt, const PartRecs& R, uint32_t* out_f,
-                           uint32_t* out_id) {
+// A record's bin is (f >> shift) & (nbins - 1).
+__device__ void part_round(PartLds& L, int nbins, int nbits, int shift, int cnt, const PartRecs& R, BzRec* out) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = BZ_THREADS / 64;
   for (int b = lane; b < nbins; b += 64) L.wc[wv][b] = 0u;  // this wavefront's row only
-  uint32_t lr[PT_RPT];
+  uint32_t lr[PT_RPT], bn[PT_RPT];
+#pragma unroll
+  for (int u = 0; u < PT_RPT; ++u) bn[u] = nbins > 1 ? (R.f[u] >> shift) & (uint32_t)(nbins - 1) : 0u;
 #pragma unroll
   for (int u = 0; u < PT_RPT; ++u) {
     const int q = wv * PT_SEG + u * 64 + lane;
     const bool has = q < cnt;
-    const uint32_t dg = has ? (uint32_t)R.bn[u] : 0u;
+    const uint32_t dg = has ? bn[u] : 0u;
     uint64_t mask = __ballot(has);
     for (int b = 0; b < nbits; ++b) {
       const uint64_t bb = __ballot(has && ((dg >> b) & 1u));
@@ -253,19 +256,13 @@ __device__ void part_round(PartLds& L, int nbins, int nbits, int cnt, const Part
 #pragma unroll
   for (int u = 0; u < PT_RPT; ++u) {
     const int q = wv * PT_SEG + u * 64 + lane;
-    if (q < cnt) {
-      const uint32_t p = L.wc[wv][R.bn[u]] + lr[u];
-      L.f[p] = R.f[u];
-      L.id[p] = R.id[u];
-      L.bin[p] = (uint16_t)R.bn[u];
-    }
+    if (q < cnt) L.rec[L.wc[wv][bn[u]] + lr[u]] = rec_make(R.f[u], R.id[u]);
   }
   __syncthreads();
   for (int p = tid; p < cnt; p += BZ_THREADS) {
-    const int b = L.bin[p];
-    const uint32_t gp = L.cur[b] + (uint32_t)p - L.lst[b];
-    out_f[gp] = L.f[p];
-    out_id[gp] = L.id[p];
+    const BzRec r = L.rec[p];
+    const int b = nbins > 1 ? (int)((rec_f(r) >> shift) & (uint32_t)(nbins - 1)) : 0;
+    out[L.cur[b] + (uint32_t)p - L.lst[b]] = r;
   }
   __syncthreads();
   if (tid < nbins) L.cur[tid] += L.hist[tid];
@@ -273,13 +270,13 @@ __device__ void part_round(PartLds& L, int nbins, int nbits, int cnt, const Part
 
 // Rounds of one workgroup.
 template <class Load>
-__device__ void part_rounds(PartLds& L, int nbins, int nbits, int64_t total, const Load& load, uint32_t* out_f,
-                            uint32_t* out_id) {
+__device__ void part_rounds(PartLds& L, int nbins, int nbits, int shift, int64_t total, const Load& load,
+                            BzRec* out) {
   for (int64_t r0 = 0; r0 < total; r0 += PT_ROUND) {
     const int cnt = (int)(total - r0 < PT_ROUND ? total - r0 : PT_ROUND);
     PartRecs cur;
-    part_load(cnt, [&](int q, uint32_t& f, uint32_t& id, int& bn) { load(r0 + q, f, id, bn); }, cur);
-    part_round(L, nbins, nbits, cnt, cur, out_f, out_id);
+    part_load(cnt, [&](int q, uint32_t& f, uint32_t& id) { load(r0 + q, f, id); }, cur);
+    part_round(L, nbins, nbits, shift, cnt, cur, out);
   }
 }
 
@@ -287,7 +284,7 @@ __device__ void part_rounds(PartLds& L, int nbins, int nbits, int64_t total, con
 // nb1 bits of the fingerprint (nb1 <= PT_B1).
 __global__ __launch_bounds__(BZ_THREADS) void k_p1_scatter(BzArgs a, int nb1, int nblk, const uint32_t* counts,
                                                            const uint32_t* binstart, const uint32_t* fp,
-                                                           uint32_t* out_f, uint32_t* out_id) {
+                                                           BzRec* out) {
   __shared__ PartLds L;
   const int t = blockIdx.y, blk = blockIdx.x;
   const int nbins = 1 << nb1;
@@ -296,18 +293,19 @@ __global__ __launch_bounds__(BZ_THREADS) void k_p1_scatter(BzArgs a, int nb1, in
   const int64_t s = (int64_t)blk * PT_SUPER;
   const int64_t e = s + PT_SUPER < a.n ? s + PT_SUPER : a.n;
   const uint32_t* fpt = fp + (int64_t)t * a.n;
-  part_rounds(L, nbins, nb1, e - s,
-              [&](int64_t q, uint32_t& f, uint32_t& id, int& bn) {
+  part_rounds(L, nbins, nb1, 32 - nb1, e - s,
+              [&](int64_t q, uint32_t& f, uint32_t& id) {
                 f = fpt[s + q];
                 id = (uint32_t)(s + q);
-                bn = (int)bin_bits_of(f, nb1);
               },
-              out_f + (int64_t)t * a.n, out_id + (int64_t)t * a.n);
+              out + (int64_t)t * a.n);
 }
 
 // Second pass.  The records of first-pass bin (t, B) are cut into chunks of
-// PT_SUPER; cbase[t * 2^PT_B1 + B] is the first global chunk of that bin.
-__global__ __launch_bounds__(1024) void k_p2_chunks(int nb1bins, const uint32_t* bintot1, uint32_t* cbase) {
+// PT_SUPER; cbase[t * 2^PT_B1 + B] is the first global chunk of that bin and
+// cbin[g] the first-pass bin of global chunk g.
+__global__ __launch_bounds__(1024) void k_p2_chunks(int nb1bins, const uint32_t* bintot1, uint32_t* cbase,
+                                                    uint32_t* cbin) {
   __shared__ uint32_t sh[17];
   const int per = (nb1bins + 1023) / 1024;
   uint32_t loc = 0;
@@ -321,40 +319,32 @@ __global__ __launch_bounds__(1024) void k_p2_chunks(int nb1bins, const uint32_t*
     const int i = threadIdx.x * per + q;
     if (i < nb1bins) {
       cbase[i] = base;
-      base += (bintot1[i] + PT_SUPER - 1) / PT_SUPER;
+      const uint32_t nc = (bintot1[i] + PT_SUPER - 1) / PT_SUPER;
+      for (uint32_t j = 0; j < nc; ++j) cbin[base + j] = (uint32_t)i;
+      base += nc;
     }
   }
   if (threadIdx.x == 0) cbase[nb1bins] = total;
 }
 
-// The first-pass bin of global chunk g (the last i with cbase[i] <= g).
-GEEK_D int p2_bin_of_chunk(const uint32_t* cbase, int nb1bins, uint32_t g) {
-  int lo = 0, hi = nb1bins - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (cbase[mid] <= g) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Per chunk: counts of the second-pass bins (the next nb - PT_B1 bits).
-__global__ __launch_bounds__(BZ_THREADS) void k_p2_count(int64_t n, int nb, const uint32_t* cbase, int nb1bins,
+__global__ __launch_bounds__(BZ_THREADS) void k_p2_count(int64_t n, int nb, const uint32_t* cbase,
+                                                         const uint32_t* cbin, int nb1bins,
                                                          const uint32_t* bintot1, const uint32_t* binstart1,
-                                                         const uint32_t* f1, uint32_t* counts2) {
+                                                         const BzRec* r1, uint32_t* counts2) {
   __shared__ uint32_t hist[256];
   const uint32_t g = blockIdx.x;
   if (g >= cbase[nb1bins]) return;
   const int F = 1 << (nb - PT_B1);
-  const int tb = p2_bin_of_chunk(cbase, nb1bins, g);
+  const int tb = (int)cbin[g];
   const int t = tb >> PT_B1;
   const uint32_t off = (g - cbase[tb]) * (uint32_t)PT_SUPER;
   const uint32_t cnt = min((uint32_t)PT_SUPER, bintot1[tb] - off);
-  const uint32_t* src = f1 + (int64_t)t * n + binstart1[tb] + off;
+  const BzRec* src = r1 + (int64_t)t * n + binstart1[tb] + off;
   for (int b = threadIdx.x; b < F; b += BZ_THREADS) hist[b] = 0u;
   __syncthreads();
   for (uint32_t q = threadIdx.x; q < cnt; q += BZ_THREADS)
-    atomicAdd(&hist[bin_bits_of(src[q], nb) & (uint32_t)(F - 1)], 1u);
+    atomicAdd(&hist[bin_bits_of(rec_f(src[q]), nb) & (uint32_t)(F - 1)], 1u);
   __syncthreads();
   for (int b = threadIdx.x; b < F; b += BZ_THREADS) counts2[(int64_t)g * F + b] = hist[b];
 }
@@ -374,29 +364,29 @@ __global__ void k_p2_colscan(int nb1bins, int F, const uint32_t* cbase, uint32_t
   bintot[(int64_t)tb * F + f] = run;
 }
 
-__global__ __launch_bounds__(BZ_THREADS) void k_p2_scatter(int64_t n, int nb, const uint32_t* cbase, int nb1bins,
+__global__ __launch_bounds__(BZ_THREADS) void k_p2_scatter(int64_t n, int nb, const uint32_t* cbase,
+                                                           const uint32_t* cbin, int nb1bins,
                                                            const uint32_t* bintot1, const uint32_t* binstart1,
-                                                           const uint32_t* f1, const uint32_t* ids1,
-                                                           const uint32_t* counts2, const uint32_t* binstart,
-                                                           uint32_t* out_f, uint32_t* out_id) {
+                                                           const BzRec* r1, const uint32_t* counts2,
+                                                           const uint32_t* binstart, BzRec* out) {
   __shared__ PartLds L;
   const uint32_t g = blockIdx.x;
   if (g >= cbase[nb1bins]) return;
   const int F = 1 << (nb - PT_B1);
-  const int tb = p2_bin_of_chunk(cbase, nb1bins, g);
+  const int tb = (int)cbin[g];
   const int t = tb >> PT_B1;
   const uint32_t off = (g - cbase[tb]) * (uint32_t)PT_SUPER;
   const uint32_t cnt_all = min((uint32_t)PT_SUPER, bintot1[tb] - off);
   const int64_t s = (int64_t)t * n + binstart1[tb] + off;
   for (int b = threadIdx.x; b < F; b += BZ_THREADS)
     L.cur[b] = binstart[(int64_t)tb * F + b] + counts2[(int64_t)g * F + b];
-  part_rounds(L, F, nb - PT_B1, (int64_t)cnt_all,
-              [&](int64_t q, uint32_t& f, uint32_t& id, int& bn) {
-                f = f1[s + q];
-                id = ids1[s + q];
-                bn = (int)(bin_bits_of(f, nb) & (uint32_t)(F - 1));
+  part_rounds(L, F, nb - PT_B1, 32 - nb, (int64_t)cnt_all,
+              [&](int64_t q, uint32_t& f, uint32_t& id) {
+                const BzRec r = r1[s + q];
+                f = rec_f(r);
+                id = rec_id(r);
               },
-              out_f + (int64_t)t * n, out_id + (int64_t)t * n);
+              out + (int64_t)t * n);
 }
 
 // ---------------------------------------------------------------- per-bin grouping
@@ -419,35 +409,30 @@ GEEK_D void group_record(const GroupOut& go, int t, int64_t n, uint32_t id, uint
   go.flag8[(int64_t)t * go.fstride + id] = 1;
 }
 
-// Grouping of one bin's records (fingerprint, id), taken in ascending id
-// order.  An LDS table maps each distinct exact key to a slot: a slot word
-// holds the fingerprint and 1 + the id of the record that claimed it; a
-// record whose fingerprint matches a slot claimed by another id compares its
-// exact key with the claimant's (the key loads of a chunk are issued
-// together).  Records are taken in chunks of GB_CAP, lane-private in LDS
-// while they probe; wavefront w holds the contiguous segment
-// [w * GB_SEG, (w + 1) * GB_SEG) of a chunk, 64 records per step.
-//  * Fast path (a bin of at most GB_FILL records, the common case): after the
-//    probes, the slots that some record joined are marked; only their
-//    records (usually a handful) are listed, and each listed record's rank
-//    (number of smaller ids with its key), bucket size and head come from
-//    one pass over the list.
-//  * General path (a larger bin, or more than GB_LIST shared records):
-//    every wavefront counts its records per slot in order (ballots on the
-//    slot bits and a running count), one pass over the slots turns the
-//    counts into the first rank of each wavefront's records (plus the
-//    slot's count of earlier chunks); the rank-0 record is the head.  A bin
-//    larger than GB_FILL inserts every record first (its slot kept in a
-//    bin-ordered scratch array); one whose distinct keys do not fit is done
-//    in sub-ranges of further fingerprint bits (equal keys have equal
-//    fingerprints, so a key never spans two sub-ranges).
+// General-path grouping of one bin's records (fingerprint, id), taken in
+// ascending id order -- the bins the fast path below leaves (more than
+// GF_MAXREC records, or many records sharing keys).  An LDS table maps each
+// distinct exact key to a slot: a slot word holds the fingerprint and 1 +
+// the id of the record that claimed it; a record whose fingerprint matches a
+// slot claimed by another id compares its exact key with the claimant's (the
+// key loads of a chunk are issued together).  Records are taken in chunks of
+// GB_CAP, lane-private in LDS while they probe; wavefront w holds the
+// contiguous segment [w * GB_SEG, (w + 1) * GB_SEG) of a chunk, 64 records
+// per step.  Every record is inserted first (its slot kept in a bin-ordered
+// scratch array); then every wavefront counts its records per slot in order
+// (ballots on the slot bits and a running count), one pass over the slots
+// turns the counts into the first rank of each wavefront's records (plus the
+// slot's count of earlier chunks), and the rank-0 record is the head.  A bin
+// whose distinct keys do not fit the table is done in sub-ranges of further
+// fingerprint bits (equal keys have equal fingerprints, so a key never spans
+// two sub-ranges).
 constexpr int GB_HT = 1024;                 // slots of the table
 constexpr int GB_FILL = 896;                // distinct keys per (sub-)range
 constexpr int GB_SBITS = 10;                // bits of a slot index
 constexpr int GB_CAP = 1024;                // records per chunk
 constexpr int GB_RPL = GB_CAP / BZ_THREADS; // records per lane and chunk
 constexpr int GB_SEG = GB_CAP / (BZ_THREADS / 64);
-constexpr int GB_LIST = BZ_THREADS;         // shared-key records of the fast path
+constexpr int GB_LIST = BZ_THREADS;         // listed records of the fast path
 constexpr int GB_SUBBITS = 5;               // sub-range bits added per level
 constexpr int GB_LEVELS = 4;                // 1, 2^5, 2^10, 2^15 sub-ranges
 constexpr uint16_t GB_NONE = 0xFFFFu;
@@ -471,19 +456,20 @@ struct GroupLds {
       uint32_t head[GB_HT];                 // the key's smallest id
     } rk;
   };
-  uint32_t mark[GB_HT / 32];                // fast path: slots another record joined
-  uint32_t lslot[GB_LIST], lid[GB_LIST];    // fast path: their records
-  uint32_t nslot, over, nlist;
+  uint32_t nslot, over;
 };
 
 // A slot word: (fingerprint << 32) | (claimant id + 1); 0 = free.
-// Probe for the slot of (f, id) from slot h on.  Returns the slot (*claimed:
-// this call inserted it); -1: no room; -2: slot *ph holds the same
-// fingerprint for another id, the exact keys decide.
-GEEK_D int gb_probe(GroupLds& G, uint32_t f, uint32_t id, uint32_t h, uint32_t* ph, bool* claimed) {
+// Probe for the slot of (f, id) from slot h on, visiting at most `budget`
+// slots.  Returns the slot (*claimed: this call inserted it); -1: no room
+// within the budget; -2: slot *ph holds the same fingerprint for another id,
+// the exact keys decide.  A record's probes, continued past fingerprints of
+// other keys, share one budget of GB_HT slots: the walk from its home slot
+// covers the table at most once, so it ends even when the table is full.
+GEEK_D int gb_probe(GroupLds& G, uint32_t f, uint32_t id, uint32_t h, int budget, uint32_t* ph, bool* claimed) {
   const unsigned long long v = ((unsigned long long)f << 32) | (unsigned long long)(id + 1u);
 #pragma unroll 1
-  for (int probe = 0; probe < GB_HT; ++probe) {
+  for (int probe = 0; probe < budget; ++probe) {
     unsigned long long s = G.slot[h];
     if (s == 0ull) {
       s = atomicCAS(&G.slot[h], 0ull, v);
@@ -521,7 +507,7 @@ GEEK_D void gb_slots(GroupLds& G, const BzArgs& a, int t) {
     uint32_t ph = 0u;
     bool cl = false;
     const uint32_t f = G.rec.f[i];
-    const int r = gb_probe(G, f, G.rec.id[i], f & GB_SLOTMASK, &ph, &cl);
+    const int r = gb_probe(G, f, G.rec.id[i], f & GB_SLOTMASK, GB_HT, &ph, &cl);
     G.rec.res[i] = gb_code(r, cl, ph);
   }
   uint4 mk[GB_RPL], ck[GB_RPL];
@@ -551,7 +537,9 @@ GEEK_D void gb_slots(GroupLds& G, const BzArgs& a, int t) {
     while ((c & 0xC000u) == GB_CONT) {
       uint32_t ph = 0u;
       bool cl = false;
-      const int r = gb_probe(G, f, id, ((c & GB_SLOTMASK) + 1u) & GB_SLOTMASK, &ph, &cl);
+      // slots left of the record's walk from its home slot f & GB_SLOTMASK
+      const int left = GB_HT - 1 - (int)(((c & GB_SLOTMASK) - f) & GB_SLOTMASK);
+      const int r = gb_probe(G, f, id, ((c & GB_SLOTMASK) + 1u) & GB_SLOTMASK, left, &ph, &cl);
       c = gb_code(r, cl, ph);
       if ((c & 0xC000u) == GB_PEND)
         c = key_eq(mine, load_key(a, t, gb_claimant(G, ph))) ? (uint16_t)ph : (uint16_t)(GB_CONT | ph);
@@ -644,8 +632,8 @@ GEEK_D void gb_heads(GroupLds& G, const GroupOut& go, int t, int64_t n) {
 // One bin by the general path: inserts first (slots kept in sptr), in
 // sub-ranges of further fingerprint bits if its distinct keys do not fit,
 // then ranks chunk by chunk.
-__device__ void gb_large_bin(GroupLds& G, const BzArgs& a, int t, uint32_t size, const uint32_t* fptr,
-                             const uint32_t* iptr, uint16_t* sptr, const GroupOut& go, int32_t* st) {
+__device__ void gb_large_bin(GroupLds& G, const BzArgs& a, int t, uint32_t size, const BzRec* rptr,
+                             uint16_t* sptr, const GroupOut& go, int32_t* st) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t n = a.n;
   for (int level = 0; level < GB_LEVELS; ++level) {
@@ -667,8 +655,9 @@ __device__ void gb_large_bin(GroupLds& G, const BzArgs& a, int t, uint32_t size,
         for (int u = 0; u < GB_RPL; ++u) {
           const uint32_t q = c0 + wv * GB_SEG + u * 64 + lane;
           in[u] = q < size;
-          f[u] = in[u] ? fptr[q] : 0u;
-          id[u] = in[u] ? iptr[q] : 0u;
+          const BzRec rr = in[u] ? rptr[q] : 0ull;
+          f[u] = rec_f(rr);
+          id[u] = rec_id(rr);
           in[u] = in[u] && (level == 0 || ((f[u] << a.nb) >> (32 - sbits)) == r);
         }
         gb_stage(G, f, id, in);
@@ -705,7 +694,7 @@ __device__ void gb_large_bin(GroupLds& G, const BzArgs& a, int t, uint32_t size,
         for (int u = 0; u < GB_RPL; ++u) {
           const uint32_t q = c0 + wv * GB_SEG + u * 64 + lane;
           const uint16_t sl = q < size ? sptr[q] : GB_NONE;
-          id[u] = sl != GB_NONE ? iptr[q] : 0u;
+          id[u] = sl != GB_NONE ? rec_id(rptr[q]) : 0u;
           g[u] = sl != GB_NONE ? (int)sl : -1;
         }
         gb_rank_chunk(G, go, t, n, g, id);
@@ -729,10 +718,13 @@ __device__ void gb_large_bin(GroupLds& G, const BzArgs& a, int t, uint32_t size,
 // plus a few whose 16 bits merely coincide -- are listed with their exact
 // keys, and each listed record's rank (number of smaller listed ids with
 // the same key), bucket size and head come from one pass over the list.
-// Every other record is alone in its bucket.  Bins larger than GB_FILL or
+// Every other record is alone in its bucket.  Bins larger than GF_MAXREC or
 // with more than GB_LIST listed records go to a list of hard items for
 // k_group_hard.
 constexpr int GF_BITS = 1 << 16;
+constexpr int GF_MAXREC = 2048;                   // records of a fast-path bin
+constexpr int GF_RPL = GF_MAXREC / BZ_THREADS;    // per lane
+constexpr int GF_SEG = GF_MAXREC / (BZ_THREADS / 64);
 struct FastLds {
   uint32_t seen[GF_BITS / 32];
   uint32_t twice[GF_BITS / 32];
@@ -742,8 +734,8 @@ struct FastLds {
 };
 
 __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* bintot, const uint32_t* binstart,
-                                                      const uint32_t* st_f, const uint32_t* st_id, GroupOut go,
-                                                      uint32_t* hard, uint32_t* nhard) {
+                                                      const BzRec* recs, GroupOut go, uint32_t* hard,
+                                                      uint32_t* nhard) {
   __shared__ FastLds S;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nbins = 1 << a.nb;
@@ -761,24 +753,25 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
   auto records = [&](int64_t w, uint32_t size, uint32_t s0, uint32_t* f, uint32_t* id) {
     const int64_t base = (w / nbins) * n + s0;
 #pragma unroll
-    for (int u = 0; u < GB_RPL; ++u) {
-      const uint32_t q = wv * GB_SEG + u * 64 + lane;
-      const bool in = size > 1u && size <= (uint32_t)GB_FILL && q < size;
-      f[u] = in ? st_f[base + q] : 0u;
-      id[u] = in ? st_id[base + q] : 0u;
+    for (int u = 0; u < GF_RPL; ++u) {
+      const uint32_t q = wv * GF_SEG + u * 64 + lane;
+      const bool in = size > 1u && size <= (uint32_t)GF_MAXREC && q < size;
+      const BzRec r = in ? recs[base + q] : 0ull;
+      f[u] = rec_f(r);
+      id[u] = rec_id(r);
     }
   };
   int64_t w = blockIdx.x;
   uint32_t sz0, b0, sz1, b1;
   extent(w, sz0, b0);
   extent(w + step, sz1, b1);
-  uint32_t f0[GB_RPL], i0[GB_RPL];
+  uint32_t f0[GF_RPL], i0[GF_RPL];
   records(w, sz0, b0, f0, i0);
   for (; w < nwork; w += step) {
     const uint32_t size = sz0;
-    uint32_t f[GB_RPL], id[GB_RPL];
+    uint32_t f[GF_RPL], id[GF_RPL];
 #pragma unroll
-    for (int u = 0; u < GB_RPL; ++u) {
+    for (int u = 0; u < GF_RPL; ++u) {
       f[u] = f0[u];
       id[u] = i0[u];
     }
@@ -790,14 +783,14 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
     sz1 = sz2;
     b1 = b2;
     if (size <= 1u) continue;  // empty, or one record: a bucket of its own
-    if (size > (uint32_t)GB_FILL) {
+    if (size > (uint32_t)GF_MAXREC) {
       if (tid == 0) hard[atomicAdd(nhard, 1u)] = (uint32_t)w;
       continue;
     }
     const int t = (int)(w / nbins);
-    bool in[GB_RPL];
+    bool in[GF_RPL];
 #pragma unroll
-    for (int u = 0; u < GB_RPL; ++u) in[u] = (uint32_t)(wv * GB_SEG + u * 64 + lane) < size;
+    for (int u = 0; u < GF_RPL; ++u) in[u] = (uint32_t)(wv * GF_SEG + u * 64 + lane) < size;
     {
       uint4* s4 = reinterpret_cast<uint4*>(S.seen);  // seen and twice are adjacent
       for (int i = tid; i < GF_BITS / 64; i += BZ_THREADS) s4[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -805,14 +798,14 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
     if (tid == 0) S.nlist = 0u;
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < GB_RPL; ++u) {
+    for (int u = 0; u < GF_RPL; ++u) {
       if (!in[u]) continue;
       const uint32_t b = f[u] & (GF_BITS - 1), m = 1u << (b & 31);
       if (atomicOr(&S.seen[b >> 5], m) & m) atomicOr(&S.twice[b >> 5], m);
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < GB_RPL; ++u) {
+    for (int u = 0; u < GF_RPL; ++u) {
       const uint32_t b = f[u] & (GF_BITS - 1);
       if (in[u] && ((S.twice[b >> 5] >> (b & 31)) & 1u)) {
         const uint32_t p = atomicAdd(&S.nlist, 1u);
@@ -853,8 +846,8 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
 // The hard items: the general path (insertion into the slot table, ranks by
 // ballots), persistent over the list k_group left.
 __global__ __launch_bounds__(BZ_THREADS) void k_group_hard(BzArgs a, const uint32_t* bintot,
-                                                           const uint32_t* binstart, const uint32_t* st_f,
-                                                           const uint32_t* st_id, uint16_t* sc_slot, GroupOut go,
+                                                           const uint32_t* binstart, const BzRec* recs,
+                                                           uint16_t* sc_slot, GroupOut go,
                                                            const uint32_t* hard, const uint32_t* nhard,
                                                            int32_t* st) {
   __shared__ GroupLds G;
@@ -865,8 +858,7 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group_hard(BzArgs a, const uint3
     const uint32_t w = hard[i];
     const int t = (int)(w / (uint32_t)nbins);
     const uint32_t size = bintot[w], s0 = binstart[w];
-    gb_large_bin(G, a, t, size, st_f + (int64_t)t * n + s0, st_id + (int64_t)t * n + s0,
-                 sc_slot + (int64_t)t * n + s0, go, st);
+    gb_large_bin(G, a, t, size, recs + (int64_t)t * n + s0, sc_slot + (int64_t)t * n + s0, go, st);
     __syncthreads();
   }
 }
@@ -877,15 +869,23 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group_hard(BzArgs a, const uint3
 constexpr int BZ_PER = SC_CHUNK / BZ_THREADS;
 static_assert(BZ_PER == 16, "16 ids per thread: one half flag word");
 
-// Bucket head / bucket length of id i (0 length for non-head members).
-GEEK_D void id_bucket(const GroupOut& go, int t, int64_t n, int64_t i, bool flagged, uint32_t& is_head,
-                      uint32_t& len, uint2& inf) {
+// The grouping records of ids i0 .. i0 + 15 that have one (flag bit set).
+// All loads are issued before any is used.
+GEEK_D void load_infos(const GroupOut& go, int t, int64_t n, int64_t i0, uint32_t fb, uint2* inf) {
+#pragma unroll
+  for (int u = 0; u < BZ_PER; ++u) {
+    inf[u] = make_uint2(0u, 0u);
+    if ((fb >> u) & 1u) inf[u] = go.info[(int64_t)t * n + i0 + u];
+  }
+}
+// Bucket head / bucket length of id i (0 length for non-head members); ids
+// past n (never flagged) count as nothing.
+GEEK_D void id_bucket(int64_t n, int64_t i, bool flagged, const uint2& inf, uint32_t& is_head, uint32_t& len) {
   if (!flagged) {
-    is_head = 1;
-    len = 1;
+    is_head = i < n ? 1u : 0u;
+    len = is_head;
     return;
   }
-  inf = go.info[(int64_t)t * n + i];
   is_head = inf.x == (uint32_t)i;
   len = is_head ? inf.y : 0u;
 }
@@ -904,13 +904,12 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bz_reduce(int64_t n, int nch, Gr
   uint32_t h = 0, l = 0;
   if (i0 < n) {
     const uint32_t fb = flag_bits16(go, t, i0);
+    uint2 inf[BZ_PER];
+    load_infos(go, t, n, i0, fb, inf);
 #pragma unroll
     for (int u = 0; u < BZ_PER; ++u) {
-      const int64_t i = i0 + u;
-      if (i >= n) break;
       uint32_t ih, len;
-      uint2 inf;
-      id_bucket(go, t, n, i, (fb >> u) & 1u, ih, len, inf);
+      id_bucket(n, i0 + u, (fb >> u) & 1u, inf[u], ih, len);
       h += ih;
       l += len;
     }
@@ -954,14 +953,18 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(int nch, uint2* ctot, uint
 // buckets leave (start, rank) for their members.  Each thread scans 16
 // consecutive ids; the chunk's heads (consecutive ranks) are staged in LDS
 // and written by consecutive threads, so the offsets and the member slots of
-// buckets of one are stored as contiguous runs.
+// buckets of one are stored as contiguous runs.  The staging arrays skip one
+// word in 17 (bz_pad), so the 16-word strides of the scan do not fall into
+// one LDS bank.
+GEEK_D int bz_pad(int x) { return x + (x >> 4); }
+constexpr int SC_PADDED = SC_CHUNK + SC_CHUNK / 16;
 __global__ __launch_bounds__(BZ_THREADS) void k_bz_apply(int64_t n, int nch, GroupOut go, const uint2* ctot,
                                                          uint2* hs, uint32_t* members, uint32_t* offsets,
                                                          uint32_t* bucket_of, const uint32_t* nbuckets) {
   __shared__ uint32_t sh[17];
-  __shared__ uint32_t s_slot[SC_CHUNK];  // member slot of the chunk's q-th head
-  __shared__ uint32_t s_id[SC_CHUNK];    // its id
-  __shared__ uint32_t s_bof[SC_CHUNK];   // bucket rank of each head id of the chunk, else ~0
+  __shared__ uint32_t s_slot[SC_PADDED];  // member slot of the chunk's q-th head
+  __shared__ uint32_t s_id[SC_PADDED];    // its id
+  __shared__ uint32_t s_bof[SC_PADDED];   // bucket rank of each head id of the chunk, else ~0
   const int t = blockIdx.y, c = blockIdx.x;
   const int64_t c0 = (int64_t)c * SC_CHUNK;
   const int64_t i0 = c0 + (int64_t)threadIdx.x * BZ_PER;
@@ -969,17 +972,15 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bz_apply(int64_t n, int nch, Gro
   uint32_t fb = 0, lh = 0, ll = 0;
   uint32_t ihv[BZ_PER], lenv[BZ_PER];
   if (i0 < n) fb = flag_bits16(go, t, i0);
+  {
+    uint2 inf[BZ_PER];
+    load_infos(go, t, n, i0, fb, inf);
 #pragma unroll
-  for (int u = 0; u < BZ_PER; ++u) {
-    const int64_t i = i0 + u;
-    ihv[u] = 0;
-    lenv[u] = 0;
-    if (i < n) {
-      uint2 inf;
-      id_bucket(go, t, n, i, (fb >> u) & 1u, ihv[u], lenv[u], inf);
+    for (int u = 0; u < BZ_PER; ++u) {
+      id_bucket(n, i0 + u, (fb >> u) & 1u, inf[u], ihv[u], lenv[u]);
+      lh += ihv[u];
+      ll += lenv[u];
     }
-    lh += ihv[u];
-    ll += lenv[u];
   }
   const uint2 base = ctot[(int64_t)t * nch + c];
   uint32_t nh;
@@ -989,11 +990,11 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bz_apply(int64_t n, int nch, Gro
 #pragma unroll
   for (int u = 0; u < BZ_PER; ++u) {
     const int l = threadIdx.x * BZ_PER + u;
-    if (bucket_of) s_bof[l] = ihv[u] ? base.x + q : 0xFFFFFFFFu;
+    if (bucket_of) s_bof[bz_pad(l)] = ihv[u] ? base.x + q : 0xFFFFFFFFu;
     if (!ihv[u]) continue;
     const uint32_t i = (uint32_t)(i0 + u);
-    s_slot[q] = bl;
-    s_id[q] = i;
+    s_slot[bz_pad((int)q)] = bl;
+    s_id[bz_pad((int)q)] = i;
     if ((fb >> u) & 1u) hs[tn + i] = make_uint2(bl, base.x + q);
     ++q;
     bl += lenv[u];
@@ -1001,36 +1002,53 @@ __global__ __launch_bounds__(BZ_THREADS) void k_bz_apply(int64_t n, int nch, Gro
   __syncthreads();
   uint32_t* off = offsets + (int64_t)t * (n + 1);
   for (uint32_t k = threadIdx.x; k < nh; k += BZ_THREADS) {
-    const uint32_t sl = s_slot[k];
+    const uint32_t sl = s_slot[bz_pad((int)k)];
     off[base.x + k] = sl;
-    members[tn + sl] = s_id[k];
+    members[tn + sl] = s_id[bz_pad((int)k)];
   }
   if (bucket_of) {
     const int64_t cl = n - c0 < SC_CHUNK ? n - c0 : SC_CHUNK;
     for (int l = threadIdx.x; l < cl; l += BZ_THREADS)
-      if (s_bof[l] != 0xFFFFFFFFu) bucket_of[tn + c0 + l] = s_bof[l];
+      if (s_bof[bz_pad(l)] != 0xFFFFFFFFu) bucket_of[tn + c0 + l] = s_bof[bz_pad(l)];
   }
   if (c == 0 && threadIdx.x == 0) off[nbuckets[t]] = (uint32_t)n;
 }
 
-// Members of buckets of two or more, other than the head.
+// The members of ids i0 .. i0 + 15 other than heads (fb: their flags).
+GEEK_D void bz_members16(int64_t n, const GroupOut& go, const uint2* hs, uint32_t* members, uint32_t* bucket_of,
+                         int t, int64_t i0, uint32_t fb) {
+  const int64_t tn = (int64_t)t * n;
+  uint2 inf[BZ_PER], h[BZ_PER];
+  load_infos(go, t, n, i0, fb, inf);
+  uint32_t mem = 0u;  // members other than the head
+#pragma unroll
+  for (int u = 0; u < BZ_PER; ++u) {
+    h[u] = make_uint2(0u, 0u);
+    if (((fb >> u) & 1u) && inf[u].x != (uint32_t)(i0 + u)) {
+      mem |= 1u << u;
+      h[u] = hs[tn + inf[u].x];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < BZ_PER; ++u) {
+    if (!((mem >> u) & 1u)) continue;
+    members[tn + h[u].x + inf[u].y] = (uint32_t)(i0 + u);
+    if (bucket_of) bucket_of[tn + i0 + u] = h[u].y;
+  }
+}
+
+
+// Members of buckets of two or more, other than the head; BZ_MEMCH chunks
+// of ids per workgroup.
+constexpr int BZ_MEMCH = 4;
 __global__ __launch_bounds__(BZ_THREADS) void k_bz_members(int64_t n, GroupOut go, const uint2* hs,
                                                            uint32_t* members, uint32_t* bucket_of) {
   const int t = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * SC_CHUNK + (int64_t)threadIdx.x * BZ_PER;
-  if (i0 >= n) return;
-  const uint32_t fb = flag_bits16(go, t, i0);
-  if (!fb) return;
-  const int64_t tn = (int64_t)t * n;
-#pragma unroll
-  for (int u = 0; u < BZ_PER; ++u) {
-    const int64_t i = i0 + u;
-    if (i >= n || !((fb >> u) & 1u)) continue;
-    const uint2 inf = go.info[tn + i];
-    if (inf.x == (uint32_t)i) continue;  // head: already written
-    const uint2 h = hs[tn + inf.x];
-    members[tn + h.x + inf.y] = (uint32_t)i;
-    if (bucket_of) bucket_of[tn + i] = h.y;
+  for (int j = 0; j < BZ_MEMCH; ++j) {
+    const int64_t i0 = ((int64_t)blockIdx.x * BZ_MEMCH + j) * SC_CHUNK + (int64_t)threadIdx.x * BZ_PER;
+    if (i0 >= n) return;
+    const uint32_t fb = flag_bits16(go, t, i0);
+    if (fb) bz_members16(n, go, hs, members, bucket_of, t, i0, fb);
   }
 }
 
@@ -1043,15 +1061,16 @@ static size_t p2_max_chunks(int64_t n, int T) {
 
 static int bin_bits(int64_t n) {
   int nb = 0;
-  while (nb < BZ_MAXBITS && (n >> nb) > 768) ++nb;
+  while (nb < BZ_MAXBITS && (n >> nb) > 1536) ++nb;
   return nb;
 }
 
 struct BzWs {
-  uint32_t *counts, *bintot, *binstart, *fp, *st_f, *st_id, *alt_f, *alt_id;
+  uint32_t *counts, *bintot, *binstart, *fp;
+  BzRec *st, *alt;  // partitioned records: final bins, first-pass bins
   uint8_t* flag8;
   uint32_t* hard;
-  uint32_t *counts2, *bintot1, *binstart1, *cbase;  // second partition pass
+  uint32_t *counts2, *bintot1, *binstart1, *cbase, *cbin;  // second partition pass
   uint2 *info, *hs, *ctot;
 };
 
@@ -1071,13 +1090,12 @@ static size_t carve_bz(const geek_bucketize_job& J, void* ws, BzWs& W) {
   W.bintot1 = c.take<uint32_t>((size_t)J.T * nb1bins);
   W.binstart1 = c.take<uint32_t>((size_t)J.T * nb1bins);
   W.cbase = c.take<uint32_t>((size_t)J.T * nb1bins + 1);
+  W.cbin = c.take<uint32_t>(two ? maxchunks : 1);
   W.bintot = c.take<uint32_t>((size_t)J.T * nbins);
   W.binstart = c.take<uint32_t>((size_t)J.T * nbins);
   W.fp = c.take<uint32_t>(Tn);
-  W.st_f = c.take<uint32_t>(Tn);
-  W.st_id = c.take<uint32_t>(Tn);
-  W.alt_f = two ? c.take<uint32_t>(Tn) : nullptr;
-  W.alt_id = two ? c.take<uint32_t>(Tn) : nullptr;
+  W.st = c.take<BzRec>(Tn);
+  W.alt = two ? c.take<BzRec>(Tn) : nullptr;
   W.flag8 = c.take<uint8_t>((size_t)J.T * fw + 16);  // + the hard-item counter, cleared with the flags
   W.hard = c.take<uint32_t>((size_t)J.T * nbins);
   W.info = c.take<uint2>(Tn);
@@ -1118,7 +1136,7 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
                        nblk, nbins, W.counts, W.bintot);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
     hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a, nb, nblk, W.counts, W.binstart,
-                       W.fp, W.st_f, W.st_id);
+                       W.fp, W.st);
   } else {
     // first pass into the alternate buffers by the top PT_B1 bits, second
     // pass by the next nb - PT_B1 bits into the staging buffers
@@ -1133,33 +1151,35 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
                        W.counts, W.bintot1);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, 1 << PT_B1, W.bintot1, W.binstart1);
     hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a1, PT_B1, nblk, W.counts,
-                       W.binstart1, W.fp, W.alt_f, W.alt_id);
-    hipLaunchKernelGGL(k_p2_chunks, dim3(1), dim3(1024), 0, s, nb1bins, W.bintot1, W.cbase);
-    hipLaunchKernelGGL(k_p2_count, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, nb1bins, W.bintot1,
-                       W.binstart1, W.alt_f, W.counts2);
+                       W.binstart1, W.fp, W.alt);
+    hipLaunchKernelGGL(k_p2_chunks, dim3(1), dim3(1024), 0, s, nb1bins, W.bintot1, W.cbase, W.cbin);
+    hipLaunchKernelGGL(k_p2_count, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, W.cbin, nb1bins,
+                       W.bintot1,
+                       W.binstart1, W.alt, W.counts2);
     hipLaunchKernelGGL(k_p2_colscan, dim3(ceil_div((int64_t)nb1bins * F, 256)), dim3(256), 0, s, nb1bins, F,
                        W.cbase, W.counts2, W.bintot);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
-    hipLaunchKernelGGL(k_p2_scatter, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, nb1bins,
-                       W.bintot1, W.binstart1, W.alt_f, W.alt_id, W.counts2, W.binstart, W.st_f, W.st_id);
+    hipLaunchKernelGGL(k_p2_scatter, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, W.cbin, nb1bins,
+                       W.bintot1, W.binstart1, W.alt, W.counts2, W.binstart, W.st);
   }
   prof_begin(GEEK_PROF_BZ_SORT, s);
   {
     const int64_t items = (int64_t)J.T * nbins;
     const int grid = (int)(items < 1792 ? items : 1792);  // persistent: 7 per CU are resident
-    hipLaunchKernelGGL(k_group, dim3(grid), dim3(BZ_THREADS), 0, s, a, W.bintot, W.binstart, W.st_f, W.st_id, go,
+    hipLaunchKernelGGL(k_group, dim3(grid), dim3(BZ_THREADS), 0, s, a, W.bintot, W.binstart, W.st, go,
                        W.hard, nhard);
     // the fingerprints are dead after the first scatter: their space keeps
     // the general path's slots
     hipLaunchKernelGGL(k_group_hard, dim3(grid < 1024 ? grid : 1024), dim3(BZ_THREADS), 0, s, a, W.bintot,
-                       W.binstart, W.st_f, W.st_id, reinterpret_cast<uint16_t*>(W.fp), go, W.hard, nhard, st);
+                       W.binstart, W.st, reinterpret_cast<uint16_t*>(W.fp), go, W.hard, nhard, st);
   }
   prof_end(GEEK_PROF_BZ_SORT, s);
   hipLaunchKernelGGL(k_bz_reduce, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, go, W.ctot);
   hipLaunchKernelGGL(k_scan_chunks, dim3(J.T), dim3(1024), 0, s, nch, W.ctot, J.nbuckets);
   hipLaunchKernelGGL(k_bz_apply, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, nch, go, W.ctot, W.hs,
                      J.members, J.offsets, J.bucket_of, J.nbuckets);
-  hipLaunchKernelGGL(k_bz_members, dim3(nch, J.T), dim3(BZ_THREADS), 0, s, J.n, go, W.hs, J.members,
+  hipLaunchKernelGGL(k_bz_members, dim3(ceil_div(nch, BZ_MEMCH), J.T), dim3(BZ_THREADS), 0, s, J.n, go, W.hs,
+                     J.members,
                      J.bucket_of);
   prof_end(GEEK_PROF_BUCKETIZE, s);
   GEEK_LAUNCH_CHECK();

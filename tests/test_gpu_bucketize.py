@@ -181,3 +181,56 @@ def test_bucketize_large_bin_few_keys():
     k0 = g.choice(np.asarray([11, 12, 13], np.uint32), size=n)
     keys = np.stack([k0, k0 ^ 0x55AA55AA, np.arange(n, dtype=np.uint32) % 1], axis=1).astype(np.uint32)
     _compare(api, keys.reshape(-1), n, 1, 3, 0, 3, [keys], "large bin, three keys")
+
+
+def _bin_hash_np(v, w1):
+    # _bin_hash over keys [v, w1] for vectors v, w1 (uint64 arithmetic, masked)
+    M = np.uint64(0xFFFFFFFF)
+
+    def fm(x):
+        x = x & M
+        x ^= x >> np.uint64(16)
+        x = (x * np.uint64(0x85EBCA6B)) & M
+        x ^= x >> np.uint64(13)
+        x = (x * np.uint64(0xC2B2AE35)) & M
+        x ^= x >> np.uint64(16)
+        return x
+
+    h = np.full(v.shape, 0x9E3779B9, np.uint64)
+    for i, wd in enumerate([v.astype(np.uint64), np.asarray(w1, np.uint64) + np.zeros(v.shape, np.uint64),
+                            np.zeros(v.shape, np.uint64), np.zeros(v.shape, np.uint64)]):
+        h = (fm(h ^ wd) + np.uint64(0x7F4A7C15 * (i + 1))) & M
+    return fm(h).astype(np.uint32)
+
+
+def test_bucketize_full_table_with_fingerprint_collision():
+    # One bin on the general path whose second chunk overfills the grouping
+    # table while one of its new keys shares the full 32-bit fingerprint with
+    # a key already there: that record must give up (the bin is then split)
+    # rather than keep walking the full table.
+    # (with one word fixed the selector is a bijection of the other, so the
+    # keys [v, v] are searched for a collision instead)
+    api = gpu_api()
+    v = np.arange(1, 1 << 18, dtype=np.uint32)
+    f = _bin_hash_np(v, v)
+    keep = (f >> 31) == 0                      # all in bin 0 of 2
+    v, f = v[keep], f[keep]
+    order = np.argsort(f, kind="stable")
+    fs = f[order]
+    dup = np.nonzero(fs[1:] == fs[:-1])[0]
+    assert len(dup) > 0
+    a_key, b_key = int(v[order[dup[0]]]), int(v[order[dup[0] + 1]])
+    assert _bin_hash([a_key, a_key]) == _bin_hash([b_key, b_key]) and a_key != b_key
+    rest = [int(x) for x in v if int(x) not in (a_key, b_key)]
+    g = np.random.default_rng(6)
+    first = np.asarray([a_key] + rest[:799], np.uint32)        # 800 keys, chunk one
+    second = np.asarray([b_key] + rest[799:799 + 1023], np.uint32)  # 1024 new keys, chunk two
+    c1 = first[np.concatenate([np.arange(800), g.integers(0, 800, 224)])]
+    g.shuffle(c1)
+    c2 = second.copy()
+    g.shuffle(c2)
+    tail = first[g.integers(0, 800, 60)]      # beyond the fast-path size
+    k0 = np.concatenate([c1, c2, tail]).astype(np.uint32)
+    n = len(k0)
+    keys = np.stack([k0, k0], axis=1)
+    _compare(api, keys.reshape(-1), n, 1, 2, 0, 2, [keys], "full table, fingerprint collision")
