@@ -426,9 +426,9 @@ GEEK_D void group_record(const GroupOut& go, int t, int64_t n, uint32_t id, uint
 // whose distinct keys do not fit the table is done in sub-ranges of further
 // fingerprint bits (equal keys have equal fingerprints, so a key never spans
 // two sub-ranges).
-constexpr int GB_HT = 1024;                 // slots of the table
-constexpr int GB_FILL = 896;                // distinct keys per (sub-)range
-constexpr int GB_SBITS = 10;                // bits of a slot index
+constexpr int GB_HT = 2048;                 // slots of the table
+constexpr int GB_FILL = 1792;               // distinct keys per (sub-)range
+constexpr int GB_SBITS = 11;                // bits of a slot index
 constexpr int GB_CAP = 1024;                // records per chunk
 constexpr int GB_RPL = GB_CAP / BZ_THREADS; // records per lane and chunk
 constexpr int GB_SEG = GB_CAP / (BZ_THREADS / 64);
@@ -436,11 +436,11 @@ constexpr int GB_LIST = BZ_THREADS;         // listed records of the fast path
 constexpr int GB_SUBBITS = 5;               // sub-range bits added per level
 constexpr int GB_LEVELS = 4;                // 1, 2^5, 2^10, 2^15 sub-ranges
 constexpr uint16_t GB_NONE = 0xFFFFu;
-// Probe results of a record (16 bits): a slot (bits 0-9) with GB_CLAIM set
+// Probe results of a record (16 bits): a slot (bits 0-10) with GB_CLAIM set
 // when this record inserted it; GB_PEND | slot: the slot's claimant has the
 // same fingerprint, keys not compared yet; GB_CONT | slot: it holds another
 // key, probe on after it; GB_FULL: no room; GB_NONE: no record.
-constexpr uint16_t GB_CLAIM = 0x0800u, GB_PEND = 0x8000u, GB_CONT = 0x4000u, GB_FULL = 0xFFFEu;
+constexpr uint16_t GB_CLAIM = 0x1000u, GB_PEND = 0x8000u, GB_CONT = 0x4000u, GB_FULL = 0xFFFEu;
 constexpr uint32_t GB_SLOTMASK = GB_HT - 1;
 struct GroupLds {
   unsigned long long slot[GB_HT];
@@ -451,8 +451,8 @@ struct GroupLds {
       uint16_t res[GB_CAP];
     } rec;
     struct {             // general-path ranks
-      uint32_t wc[BZ_THREADS / 64][GB_HT];  // per wavefront: records this chunk, then first rank
-      uint32_t cnt[GB_HT];                  // records of the slot's key so far
+      uint16_t wc[BZ_THREADS / 64][GB_HT];  // per wavefront: records this chunk, then first rank in it
+      uint32_t cnt[GB_HT];                  // records of the slot's key in earlier chunks
       uint32_t head[GB_HT];                 // the key's smallest id
     } rk;
   };
@@ -561,7 +561,8 @@ GEEK_D void gb_stage(GroupLds& G, const uint32_t* f, const uint32_t* id, const b
 
 // General-path ranks of one chunk (g < 0: no record) and their records;
 // G.rk.cnt / G.rk.head carry across chunks, G.rk.wc is zero on entry and
-// on exit.
+// on exit (a wavefront's count of one slot in one chunk is at most GB_SEG,
+// so 16 bits hold it).
 GEEK_D void gb_rank_chunk(GroupLds& G, const GroupOut& go, int t, int64_t n, const int* g, const uint32_t* id) {
   constexpr int NW = BZ_THREADS / 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -576,22 +577,28 @@ GEEK_D void gb_rank_chunk(GroupLds& G, const GroupOut& go, int t, int64_t n, con
       mask &= ((gg >> b) & 1u) ? bb : ~bb;
     }
     const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    lr[u] = G.rk.wc[wv][gg] + below;
+    lr[u] = (uint32_t)G.rk.wc[wv][gg] + below;
     __builtin_amdgcn_wave_barrier();
-    if (v && below == 0) G.rk.wc[wv][gg] += (uint32_t)__popcll(mask);
+    if (v && below == 0) G.rk.wc[wv][gg] = (uint16_t)(G.rk.wc[wv][gg] + __popcll(mask));
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  for (int h = tid; h < GB_HT; h += BZ_THREADS) {
-    uint32_t run = G.rk.cnt[h];
+  // the chunk's count of each slot stays with the thread that owns the slot
+  // until the ranks have read the earlier chunks' counts
+  constexpr int SPT = GB_HT / BZ_THREADS;
+  uint32_t tot[SPT];
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int h = j * BZ_THREADS + tid;
+    uint32_t run = 0u;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
       const uint32_t cw = G.rk.wc[w][h];
-      G.rk.wc[w][h] = run;
+      G.rk.wc[w][h] = (uint16_t)run;
       run += cw;
     }
-    G.rk.cnt[h] = run;
+    tot[j] = run;
   }
   __syncthreads();
   uint32_t rank[GB_RPL];
@@ -599,7 +606,7 @@ GEEK_D void gb_rank_chunk(GroupLds& G, const GroupOut& go, int t, int64_t n, con
   for (int u = 0; u < GB_RPL; ++u) {
     rank[u] = 0u;
     if (g[u] >= 0) {
-      rank[u] = G.rk.wc[wv][g[u]] + lr[u];
+      rank[u] = G.rk.cnt[g[u]] + G.rk.wc[wv][g[u]] + lr[u];
       if (rank[u] == 0u) G.rk.head[g[u]] = id[u];
     }
   }
@@ -607,7 +614,10 @@ GEEK_D void gb_rank_chunk(GroupLds& G, const GroupOut& go, int t, int64_t n, con
 #pragma unroll
   for (int u = 0; u < GB_RPL; ++u)
     if (g[u] >= 0 && rank[u] > 0u) group_record(go, t, n, id[u], G.rk.head[g[u]], rank[u]);
-  for (int h = tid; h < GB_HT; h += BZ_THREADS) {
+#pragma unroll
+  for (int j = 0; j < SPT; ++j) {
+    const int h = j * BZ_THREADS + tid;
+    G.rk.cnt[h] += tot[j];
 #pragma unroll
     for (int w = 0; w < NW; ++w) G.rk.wc[w][h] = 0u;
   }
@@ -1170,7 +1180,7 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
                        W.hard, nhard);
     // the fingerprints are dead after the first scatter: their space keeps
     // the general path's slots
-    hipLaunchKernelGGL(k_group_hard, dim3(grid < 1024 ? grid : 1024), dim3(BZ_THREADS), 0, s, a, W.bintot,
+    hipLaunchKernelGGL(k_group_hard, dim3(grid < 768 ? grid : 768), dim3(BZ_THREADS), 0, s, a, W.bintot,
                        W.binstart, W.st, reinterpret_cast<uint16_t*>(W.fp), go, W.hard, nhard, st);
   }
   prof_end(GEEK_PROF_BZ_SORT, s);

@@ -192,12 +192,23 @@ __global__ __launch_bounds__(256) void k_sig_big(const uint32_t* __restrict__ me
     uint32_t mn[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
     const uint32_t* p = mem + gstart[g];
     const uint32_t sz = gsize[g];
-    for (uint32_t q = lane; q < sz; q += 64) {
-      const uint32_t y = fmix32(p[q]);
+    // four members per lane and step, their loads issued together
+    for (uint32_t q0 = 0; q0 < sz; q0 += 256) {
+      uint32_t x[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t v = perm_premixed(a[k], b[k], y);
-        mn[k] = v < mn[k] ? v : mn[k];
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t q = q0 + u * 64 + lane;
+        x[u] = q < sz ? p[q] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (q0 + u * 64 + lane >= sz) continue;
+        const uint32_t y = fmix32(x[u]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t v = perm_premixed(a[k], b[k], y);
+          mn[k] = v < mn[k] ? v : mn[k];
+        }
       }
     }
 #pragma unroll
@@ -343,7 +354,10 @@ __global__ __launch_bounds__(256) void k_vote(const uint32_t* __restrict__ bof, 
 // (compile-time indices, no LDS round trips): entries of bins with fewer than
 // two buckets, and entries past T, hold no bin.  A bin's size is read back
 // from its smallest bucket's entry (info[bin] = (bin, size)) once per
-// distinct bin.
+// distinct bin.  The per-table loads go in batches of VB tables (their
+// buckets, then those buckets' bin entries), each batch issued whole before
+// its values are used.
+constexpr int VB = 8;
 template <int TT>
 __global__ __launch_bounds__(256) void k_vote_reg(const uint32_t* __restrict__ bof, const uint2* __restrict__ info,
                                                   int64_t n, int T, uint32_t* __restrict__ kbin,
@@ -355,34 +369,46 @@ __global__ __launch_bounds__(256) void k_vote_reg(const uint32_t* __restrict__ b
   for (int64_t i = gtid(); i < n; i += gstride()) {
     uint32_t lb[TT];
 #pragma unroll
-    for (int t = 0; t < TT; ++t) {
-      lb[t] = NONE;
-      if (t < T) {
-        const uint32_t g = bof[(int64_t)t * n + i];
-        const uint2 e = g < NB ? info[g] : make_uint2(0u, 0u);  // bounded even for a malformed CSR
-        if (e.y >= 2u) {
-          lb[t] = e.x;
-          ++pairs;
-        }
+    for (int t0 = 0; t0 < TT; t0 += VB) {
+      uint32_t g[VB];
+#pragma unroll
+      for (int u = 0; u < VB; ++u) g[u] = t0 + u < T ? bof[(int64_t)(t0 + u) * n + i] : NONE;
+      uint2 e[VB];
+#pragma unroll
+      for (int u = 0; u < VB; ++u) {
+        e[u] = make_uint2(0u, 0u);
+        if (g[u] < NB) e[u] = info[g[u]];  // bounded even for a malformed CSR
+      }
+#pragma unroll
+      for (int u = 0; u < VB; ++u) {
+        lb[t0 + u] = e[u].y >= 2u ? e[u].x : NONE;
+        pairs += e[u].y >= 2u ? 1u : 0u;
       }
     }
+    // entry a is taken at lb[0]; the array turns left by one per step, so
+    // the entries before a sit at positions TT - a .. TT - 1 (each step's
+    // comparisons are used at once instead of kept for later steps)
     uint32_t kept = 0;
-#pragma unroll
-    for (int a = 0; a < TT; ++a) {
+#pragma unroll 1
+    for (int a = 0; a < T; ++a) {
+      const uint32_t h = lb[0];
       uint32_t cnt = 0;
       bool first = true;
 #pragma unroll
       for (int q = 0; q < TT; ++q) {
-        const bool eq = lb[q] == lb[a];
+        const bool eq = lb[q] == h;
         cnt += eq ? 1u : 0u;
-        if (q < a) first = first && !eq;
+        if (q >= TT - a) first = first && !eq;
       }
       // a majority needs cnt >= 2 (2 * cnt > size >= 2)
-      if (lb[a] != NONE && first && cnt >= 2u && 2u * cnt > info[lb[a]].y) {
-        kbin[(int64_t)kept * n + i] = lb[a];
+      if (h != NONE && first && cnt >= 2u && 2u * cnt > info[h].y) {
+        kbin[(int64_t)kept * n + i] = h;
         ++kept;
-        atomicAdd(&ksize[lb[a]], 1u);
+        atomicAdd(&ksize[h], 1u);
       }
+#pragma unroll
+      for (int q = 0; q < TT - 1; ++q) lb[q] = lb[q + 1];
+      lb[TT - 1] = h;
     }
     kc[i] = kept;
   }

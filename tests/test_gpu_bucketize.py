@@ -204,16 +204,18 @@ def _bin_hash_np(v, w1):
 
 
 def test_bucketize_full_table_with_fingerprint_collision():
-    # One bin on the general path whose second chunk overfills the grouping
-    # table while one of its new keys shares the full 32-bit fingerprint with
-    # a key already there: that record must give up (the bin is then split)
+    # One bin on the general path (more than 2,048 records) whose third chunk
+    # of 1,024 records overfills the 2,048-slot grouping table (the first two
+    # chunks leave it at most 1,792 keys full, so the bin goes on), while one
+    # of the third chunk's new keys shares the full 32-bit fingerprint with a
+    # key already there: that record must give up (the bin is then split)
     # rather than keep walking the full table.
     # (with one word fixed the selector is a bijection of the other, so the
     # keys [v, v] are searched for a collision instead)
     api = gpu_api()
-    v = np.arange(1, 1 << 18, dtype=np.uint32)
+    v = np.arange(1, 1 << 20, dtype=np.uint32)
     f = _bin_hash_np(v, v)
-    keep = (f >> 31) == 0                      # all in bin 0 of 2
+    keep = (f >> 30) == 0                      # all in bin 0 of 4
     v, f = v[keep], f[keep]
     order = np.argsort(f, kind="stable")
     fs = f[order]
@@ -221,16 +223,18 @@ def test_bucketize_full_table_with_fingerprint_collision():
     assert len(dup) > 0
     a_key, b_key = int(v[order[dup[0]]]), int(v[order[dup[0] + 1]])
     assert _bin_hash([a_key, a_key]) == _bin_hash([b_key, b_key]) and a_key != b_key
-    rest = [int(x) for x in v if int(x) not in (a_key, b_key)]
+    rest = [int(x) for x in v[:5000] if int(x) not in (a_key, b_key)]
     g = np.random.default_rng(6)
-    first = np.asarray([a_key] + rest[:799], np.uint32)        # 800 keys, chunk one
-    second = np.asarray([b_key] + rest[799:799 + 1023], np.uint32)  # 1024 new keys, chunk two
-    c1 = first[np.concatenate([np.arange(800), g.integers(0, 800, 224)])]
-    g.shuffle(c1)
-    c2 = second.copy()
-    g.shuffle(c2)
-    tail = first[g.integers(0, 800, 60)]      # beyond the fast-path size
-    k0 = np.concatenate([c1, c2, tail]).astype(np.uint32)
+    k1 = np.asarray([a_key] + rest[:999], np.uint32)            # 1,000 keys
+    k2 = np.asarray(rest[999:999 + 792], np.uint32)             # 792 new keys
+    k3 = np.asarray([b_key] + rest[1791:1791 + 1023], np.uint32)  # 1,024 new keys
+    c1 = k1[np.concatenate([np.arange(1000), g.integers(0, 1000, 24)])]
+    c2 = k2[np.concatenate([np.arange(792), g.integers(0, 792, 232)])]
+    c3 = k3.copy()
+    for c in (c1, c2, c3):
+        g.shuffle(c)
+    tail = k1[g.integers(0, 1000, 60)]
+    k0 = np.concatenate([c1, c2, c3, tail]).astype(np.uint32)
     n = len(k0)
     keys = np.stack([k0, k0], axis=1)
     _compare(api, keys.reshape(-1), n, 1, 2, 0, 2, [keys], "full table, fingerprint collision")
