@@ -395,6 +395,83 @@ __device__ __forceinline__ void scan_tiles(
         if (NBUF == 2 && more) GEEK_LOAD_REGS(c0 + SCAN_BC);
       }
 
+      // A fragments of a 32-row block: all S of them in registers, the next
+      // block's loaded while this block's epilogue runs (modes with at most
+      // eight K steps per block; float32's 64 steps read them one by one)
+      constexpr bool PF = !BLK && S <= 8;
+      auto afrag_rb = [&](int rb, int s) {
+        const int R = rb * 32 + p;
+        if constexpr (DMA) {
+          const char* rowp = reinterpret_cast<const char*>(cbuf(IC<cur>{})) + R * CH * 16;
+          const int off = (h * (DP / 2) + s * M::KPER) * (int)sizeof(CE);
+          return M::load_lds(reinterpret_cast<const CE*>(rowp + (((off >> 4) ^ (R & (CH - 1))) << 4) + (off & 15)));
+        } else {
+          return M::load_lds(cbuf(IC<cur>{}) + R * STR + h * (DP / 2) + s * M::KPER);
+        }
+      };
+      typename M::frag af[PF ? S : 1];
+      if constexpr (PF) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) af[s] = afrag_rb(0, s);
+      }
+      // first pass of point rows (top two, no categorical part): both 32-row
+      // blocks of the stage go to the matrix cores back to back, into two
+      // accumulator sets, so the first block's epilogue runs while the
+      // second block's products are still in the matrix pipe
+      if constexpr (T2 && PF && !HET && SCAN_BC == 64) {
+        f32x16 accA[NCB], accB[NCB];
+        f32x16 initA, initB;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          initA[r] = lds_nc[cur][(r >> 2) * 8 + h * 4 + (r & 3)];
+          initB[r] = lds_nc[cur][32 + (r >> 2) * 8 + h * 4 + (r & 3)];
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          accA[cb] = initA;
+          accB[cb] = initB;
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) accA[cb] = M::mma(af[s], xb[cb][s], accA[cb]);
+#pragma unroll
+        for (int s = 0; s < S; ++s) af[s] = afrag_rb(1, s);
+        const int g0 = it * (SCAN_BC / 32);
+        // block B's products step by step, each step followed by its share
+        // of block A's eight value pairs per column block: the vector
+        // instructions issue while the matrix pipe works on B
+        float a1p[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) a1p[cb] = a1[cb];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) accB[cb] = M::mma(af[s], xb[cb][s], accB[cb]);
+#pragma unroll
+          for (int q = 8 * s / S; q < 8 * (s + 1) / S; ++q) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+              const int r = 2 * q;
+              const float u = __uint_as_float((__float_as_uint(accA[cb][r]) & ~15u) | (uint32_t)r);
+              const float v = __uint_as_float((__float_as_uint(accA[cb][r + 1]) & ~15u) | (uint32_t)(r + 1));
+              const float mid = __builtin_amdgcn_fmed3f(a1[cb], u, v);
+              a1[cb] = fmaxf(fmaxf(a1[cb], u), v);
+              a2[cb] = fmaxf(a2[cb], mid);
+            }
+          }
+          // the next step's fragment "depends" on this step's updates (an
+          // empty asm, no instruction): its products issue after them
+          if (s + 1 < S) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) asm volatile("" : "+v"(af[s + 1]) : "v"(a1[cb]), "v"(a2[cb]));
+          }
+        }
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) blk[cb] = a1[cb] != a1p[cb] ? g0 : blk[cb];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) t2_update(cb, accB[cb], g0 + 1);
+      } else
 #pragma unroll 1
       for (int rb = 0; rb < SCAN_BC / 32; ++rb) {
         const int jb = rb * 32;
@@ -436,6 +513,16 @@ __device__ __forceinline__ void scan_tiles(
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
               for (int r = 0; r < 16; ++r) acc[cb][r] += blk[cb][r];
+          }
+        } else if constexpr (PF) {
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = M::mma(af[s], xb[cb][s], acc[cb]);
+          }
+          if (rb + 1 < SCAN_BC / 32) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) af[s] = afrag_rb(rb + 1, s);
           }
         } else {
 #pragma unroll
