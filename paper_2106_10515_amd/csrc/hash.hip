@@ -243,13 +243,12 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     // integer lies within coef64 * (|a||x| + |b|) / w of it, its floor is the
     // reference floor, else the lane that owns the row evaluates the
     // reference sum itself.  The owner writes the code it stored before.
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      nfix += __popc(badv[half]);
-      uint32_t fl = badv[half] | __shfl_xor(badv[half], 32);
-      while (__any(fl != 0u)) {
-        const int bit = fl ? __ffs(fl) - 1 : 0;
-        const int row = half * 32 + bit;
+    {
+      nfix += __popc(badv[0]) + __popc(badv[1]);
+      unsigned long long fl = ((unsigned long long)(badv[1] | __shfl_xor(badv[1], 32)) << 32) |
+                              (unsigned long long)(badv[0] | __shfl_xor(badv[0], 32));
+      while (__any(fl != 0ull)) {
+        const int row = fl ? __ffsll((long long)fl) - 1 : 0;
         double part = 0.0;
         if (fl) {
           // four independent FMA chains (k mod 4), then summed pairwise
@@ -278,7 +277,7 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
           part = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         }
         part += __shfl_xor(part, 32);
-        if (fl && ((bit >> 2) & 1) == h) {
+        if (fl && ((row >> 2) & 1) == h) {
           const double bv = (double)lds_b[row];
           const double qf = (part + bv) * inv_wd;
           const double rad = coef64 * ((double)lds_an[row] * (double)xn + fabs(bv)) / (double)w;
@@ -293,7 +292,7 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
           if (!fits) set_status(st, GEEK_ERR_RANGE);
           lds_code[pl * H_CS + row] = fits ? (int)flo : 0;
         }
-        fl &= fl - 1u;
+        fl &= fl - 1ull;
       }
     }
     __syncthreads();
