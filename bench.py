@@ -46,6 +46,8 @@ def parse():
                     help="dense: bucketize the first half of the tables on a second stream while the second "
                          "half is hashed (0 = hash, bucketize and assign one after another)")
     ap.add_argument("--scaled", action="store_true", help="w * sqrt(d) instead of w")
+    ap.add_argument("--no-key-fp", action="store_true",
+                    help="dense: bucketize fingerprints the keys itself instead of taking the hash's")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
     ap.add_argument("--workload", default="dense_large", choices=["dense_large", "batched", "hetero", "sets", "silk", "refine", "quantile"],
@@ -172,9 +174,12 @@ def main():
             torch.cuda.current_stream().wait_event(done)
             buckets = (bza, bzb)
         else:
-            keys, _ = api.hash_dense(X, Ag, bg, m, Lt, w, status=status, check=False, n_fixup=nfix)
+            # the hash writes each key's bucketize fingerprint beside it, so
+            # bucketize does not read the keys back to fingerprint them
+            fp = torch.empty((Lt, n), dtype=torch.int32, device=dev) if not args.no_key_fp else None
+            keys, _ = api.hash_dense(X, Ag, bg, m, Lt, w, status=status, check=False, n_fixup=nfix, key_fp=fp)
             ev[1].record()
-            buckets = api.bucketize(keys, n, Lt, 4, n * 4, 4, status=status, check=False)
+            buckets = api.bucketize(keys, n, Lt, 4, n * 4, 4, status=status, check=False, key_fp=fp)
         ev[2].record()
         out = api.assign_euclid(X, sog, smg, k, prec, status=status, check=False)
         ev[3].record()
@@ -240,7 +245,10 @@ def main():
     hash_ms = prof_bf16["e2lsh"][0] * prof_bf16["e2lsh"][1] / args.steps
     hash_tf = 2.0 * n * d * m * Lt / (hash_ms * 1e-3) / 1e12
     bz_ms = prof_bf16["bucketize"][0] * prof_bf16["bucketize"][1] / args.steps
-    bz_gbs = 28.0 * n * Lt / (bz_ms * 1e-3) / 1e9
+    # per (table, object): the 16-byte key read (or a 4-byte fingerprint
+    # when the hash wrote them) + members, bucket_of and offsets written
+    bz_gbs = (16.0 if args.no_key_fp or args.pipeline else 4.0) + 12.0
+    bz_gbs = bz_gbs * n * Lt / (bz_ms * 1e-3) / 1e9
 
     cpu = None
     if not args.no_cpu:

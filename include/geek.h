@@ -156,6 +156,11 @@ typedef struct geek_hash_job {
   uint32_t* sig;            /* sets/hetero out: [n][F] */
   unsigned long long* n_fixup; /* optional out (device, accumulated):
                                   (i, p) pairs recomputed in float64 */
+  uint32_t* key_fp;         /* optional out (GEEK_HASH_DENSE only; NULL to skip):
+                               [L][n] the 32-bit fingerprint geek_bucketize
+                               takes of each packed key; hand it to
+                               geek_bucketize (key_fp) so that call need not
+                               read the keys to fingerprint them */
 } geek_hash_job;
 
 /* ---- geek_bucketize -----------------------------------------------------
@@ -180,6 +185,12 @@ typedef struct geek_bucketize_job {
   uint32_t* offsets;        /* out [T][n+1]; entries past nbuckets[t] unspecified */
   uint32_t* nbuckets;       /* out [T] */
   uint32_t* bucket_of;      /* optional out [T][n] */
+  const uint32_t* key_fp;   /* optional in [T][n]: the fingerprints of exactly
+                               these keys as geek_hash (key_fp) of this library
+                               writes them, or NULL (computed from the keys).
+                               Buckets stay exact-key groups (keys are still
+                               compared), but a bucket is only found whole
+                               if equal keys carry equal fingerprints */
 } geek_bucketize_job;
 
 /* ---- geek_silk_seeds ----------------------------------------------------

@@ -54,7 +54,7 @@ class HashJob(C.Structure):
         ("m", C.c_int32), ("L", C.c_int32), ("w", C.c_float), ("F", C.c_int32),
         ("keys", P), ("codes", P), ("offsets", P), ("tokens", P),
         ("cat", P), ("n_cat", C.c_int32), ("pad0", C.c_int32),
-        ("mh_keys", P), ("sig", P), ("n_fixup", P),
+        ("mh_keys", P), ("sig", P), ("n_fixup", P), ("key_fp", P),
     ]
 
 
@@ -62,7 +62,7 @@ class BucketizeJob(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("T", C.c_int32), ("key_words", C.c_int32),
         ("keys", P), ("table_stride", C.c_int64), ("row_stride", C.c_int64),
-        ("members", P), ("offsets", P), ("nbuckets", P), ("bucket_of", P),
+        ("members", P), ("offsets", P), ("nbuckets", P), ("bucket_of", P), ("key_fp", P),
     ]
 
 

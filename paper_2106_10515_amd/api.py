@@ -67,9 +67,11 @@ def _run(op, fn, jobs, device, status):
 
 # ---------------------------------------------------------------- geek_hash
 def hash_dense(X, A, b, m, L_tables, w, want_codes=False, status=None, check=True,
-               n_fixup=None):
+               n_fixup=None, key_fp=None):
     """E2LSH codes of every row of X packed into per-table 128-bit keys.
-    Returns ``(keys int32 [L, n, 4], codes int32 [n, m*L] or None)``."""
+    Returns ``(keys int32 [L, n, 4], codes int32 [n, m*L] or None)``.
+    ``key_fp``: optional int32 [L, n] output, the keys' bucketize
+    fingerprints (pass it to ``bucketize``)."""
     dev = _dev(X)
     n, d = X.shape
     assert X.dtype == torch.float32 and X.stride(1) == 1
@@ -81,7 +83,7 @@ def hash_dense(X, A, b, m, L_tables, w, want_codes=False, status=None, check=Tru
     status = new_status(dev) if status is None else status
     j = L.HashJob(kind=L.GEEK_HASH_DENSE, d=d, n=n, X=_p(X), ldx=X.stride(0), A=_p(A), b=_p(b),
                   m=m, L=L_tables, w=float(w), F=0, keys=_p(keys), codes=_p(codes),
-                  n_fixup=_p(n_fixup))
+                  n_fixup=_p(n_fixup), key_fp=_p(key_fp))
     _run(L.GEEK_OP_HASH, L.geek_hash, [j], dev, status)
     if check:
         check_status(status, "geek_hash")
@@ -163,10 +165,11 @@ def hash_hetero(X, cat, A, b, m, L_tables, w, mh_keys, status=None, check=True):
 
 # ---------------------------------------------------------------- geek_bucketize
 def bucketize(keys, n, T, key_words, table_stride, row_stride, want_bucket_of=True,
-              status=None, check=True):
+              status=None, check=True, key_fp=None):
     """Buckets of T tables.  ``keys`` is any int32 device tensor holding the
-    key words at the given strides (in words).  Returns ``(members [T, n],
-    offsets [T, n+1], nbuckets [T], bucket_of [T, n] or None)``."""
+    key words at the given strides (in words); ``key_fp`` optionally the
+    [T, n] fingerprints ``hash_dense`` wrote for them.  Returns ``(members
+    [T, n], offsets [T, n+1], nbuckets [T], bucket_of [T, n] or None)``."""
     dev = _dev(keys)
     members = torch.empty((T, n), dtype=torch.int32, device=dev)
     offsets = torch.empty((T, n + 1), dtype=torch.int32, device=dev)
@@ -175,7 +178,7 @@ def bucketize(keys, n, T, key_words, table_stride, row_stride, want_bucket_of=Tr
     status = new_status(dev) if status is None else status
     j = L.BucketizeJob(n=n, T=T, key_words=key_words, keys=_p(keys), table_stride=table_stride,
                        row_stride=row_stride, members=_p(members), offsets=_p(offsets),
-                       nbuckets=_p(nbuckets), bucket_of=_p(bucket_of))
+                       nbuckets=_p(nbuckets), bucket_of=_p(bucket_of), key_fp=_p(key_fp))
     _run(L.GEEK_OP_BUCKETIZE, L.geek_bucketize, [j], dev, status)
     if check:
         check_status(status, "geek_bucketize")

@@ -1,8 +1,9 @@
 // Buckets of every table (paper Algorithms 2 and 3: T[G(x_j)].push(j)) on
 // gfx950: group the objects whose table keys are identical.
 //
-//  1. k_fp_count: a 32-bit fingerprint f of every exact key (written once)
-//     and the histogram of its top bits per chunk of ids.
+//  1. k_fp_count: a 32-bit fingerprint f of every exact key (written once,
+//     or the caller's: geek_hash can write them beside the keys) and the
+//     histogram of its top bits per chunk of ids.
 //  2. A stable partition of (f, id) records into 2^nb bins per table by the
 //     top nb bits of f (equal keys always share a bin): up to 2^PT_B1 bins in
 //     one pass, else a second pass splits every first-pass bin by the next
@@ -74,9 +75,10 @@ GEEK_D bool key_eq(const uint4& a, const uint4& b) {
 
 // ---------------------------------------------------------------- partition
 // Fingerprint of every (table, id) and the per-chunk histogram of its top nb
-// bits.
+// bits.  With `given` (the caller's fingerprints of these keys) the keys are
+// not read and nothing is written but the histogram.
 __global__ __launch_bounds__(BZ_THREADS) void k_fp_count(BzArgs a, int nblk, int chunk, uint32_t* counts,
-                                                         uint32_t* fp) {
+                                                         uint32_t* fp, const uint32_t* given) {
   extern __shared__ uint32_t hist[];
   const int t = blockIdx.y, blk = blockIdx.x;
   const int nbins = 1 << a.nb;
@@ -85,8 +87,13 @@ __global__ __launch_bounds__(BZ_THREADS) void k_fp_count(BzArgs a, int nblk, int
   const int64_t s = (int64_t)blk * chunk;
   const int64_t e = s + chunk < a.n ? s + chunk : a.n;
   for (int64_t i = s + threadIdx.x; i < e; i += BZ_THREADS) {
-    const uint32_t f = fp_of(load_key(a, t, i));
-    fp[(int64_t)t * a.n + i] = f;
+    uint32_t f;
+    if (given) {
+      f = given[(int64_t)t * a.n + i];
+    } else {
+      f = fp_of(load_key(a, t, i));
+      fp[(int64_t)t * a.n + i] = f;
+    }
     atomicAdd(&hist[bin_bits_of(f, a.nb)], 1u);
   }
   __syncthreads();
@@ -1136,17 +1143,20 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   BzArgs a{J.keys, J.n, J.T, J.key_words, J.table_stride, J.row_stride, nb};
   GroupOut go{W.flag8, W.info, fw};
   prof_begin(GEEK_PROF_BUCKETIZE, s);
+  // the fingerprints: the caller's (geek_hash wrote them with the keys) or
+  // computed here into the workspace
+  const uint32_t* fps = J.key_fp ? J.key_fp : W.fp;
   hipLaunchKernelGGL(k_zero_u4, dim3(ceil_div((int64_t)J.T * fw / 16 + 1, 256)), dim3(256), 0, s,
                      reinterpret_cast<uint4*>(W.flag8), (int64_t)J.T * fw / 16 + 1);
   uint32_t* nhard = reinterpret_cast<uint32_t*>(W.flag8 + (size_t)J.T * fw);
   if (nb <= PT_B1) {
     hipLaunchKernelGGL(k_fp_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)nbins * 4, s, a, nblk, PT_SUPER,
-                       W.counts, W.fp);
+                       W.counts, W.fp, J.key_fp);
     hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div((int64_t)J.T * nbins, 256)), dim3(256), 0, s, J.T,
                        nblk, nbins, W.counts, W.bintot);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
     hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a, nb, nblk, W.counts, W.binstart,
-                       W.fp, W.st);
+                       fps, W.st);
   } else {
     // first pass into the alternate buffers by the top PT_B1 bits, second
     // pass by the next nb - PT_B1 bits into the staging buffers
@@ -1156,12 +1166,12 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
     const int F = 1 << (nb - PT_B1);
     const int maxchunks = (int)p2_max_chunks(J.n, J.T);
     hipLaunchKernelGGL(k_fp_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)4 << PT_B1, s, a1, nblk, PT_SUPER,
-                       W.counts, W.fp);
+                       W.counts, W.fp, J.key_fp);
     hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div(nb1bins, 256)), dim3(256), 0, s, J.T, nblk, 1 << PT_B1,
                        W.counts, W.bintot1);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, 1 << PT_B1, W.bintot1, W.binstart1);
     hipLaunchKernelGGL(k_p1_scatter, dim3(nblk, J.T), dim3(BZ_THREADS), 0, s, a1, PT_B1, nblk, W.counts,
-                       W.binstart1, W.fp, W.alt);
+                       W.binstart1, fps, W.alt);
     hipLaunchKernelGGL(k_p2_chunks, dim3(1), dim3(1024), 0, s, nb1bins, W.bintot1, W.cbase, W.cbin);
     hipLaunchKernelGGL(k_p2_count, dim3(maxchunks), dim3(BZ_THREADS), 0, s, J.n, nb, W.cbase, W.cbin, nb1bins,
                        W.bintot1,

@@ -35,7 +35,7 @@ template <int DP>
 __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n, const float* __restrict__ A,
     const float* __restrict__ bvec, const float* __restrict__ anorm, int m, int L, float w,
-    int tpc, uint32_t* __restrict__ keys, int32_t* __restrict__ codes_out,
+    int tpc, uint32_t* __restrict__ keys, uint32_t* __restrict__ key_fp, int32_t* __restrict__ codes_out,
     unsigned long long* __restrict__ n_fixup, int32_t* st) {
   constexpr int S = DP / 2;
   constexpr int STR = DP + 4;
@@ -322,6 +322,8 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       const int64_t ii = i0 + pp;
       *reinterpret_cast<uint4*>(keys + ((int64_t)(tb + t) * n + ii) * 4) =
           make_uint4(kw[0], kw[1], kw[2], kw[3]);
+      // the key's fingerprint as bucketize takes it (all four words)
+      if (key_fp) key_fp[(int64_t)(tb + t) * n + ii] = key_hash(kw, 4);
     }
     if (codes_out) {
       for (int q = tid; q < H_BN * rows_used; q += H_THREADS) {
@@ -500,8 +502,8 @@ size_t hash_ws(const geek_hash_job& J) {
   return c.used + 256;
 }
 
-static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys, int32_t* codes,
-                            unsigned long long* nfix, int32_t* st, hipStream_t s) {
+static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys, uint32_t* key_fp,
+                            int32_t* codes, unsigned long long* nfix, int32_t* st, hipStream_t s) {
   const int P = J.m * J.L;
   hipLaunchKernelGGL(k_rownorm, dim3(ceil_div(P, 128)), dim3(128), 0, s, J.A, P, J.d, anorm);
   const int tpc = H_BC / J.m;  // whole tables per 64-row chunk
@@ -512,7 +514,7 @@ static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys
 #define GEEK_H_CASE(DPV)                                                                        \
   case DPV:                                                                                     \
     hipLaunchKernelGGL((k_e2lsh<DPV>), dim3(grid), dim3(H_THREADS), 0, s, J.X, J.ldx, J.d, J.n, \
-                       J.A, J.b, anorm, J.m, J.L, J.w, tpc, keys, codes, nfix, st);             \
+                       J.A, J.b, anorm, J.m, J.L, J.w, tpc, keys, key_fp, codes, nfix, st);     \
     break;
     GEEK_H_CASE(32)
     GEEK_H_CASE(64)
@@ -544,7 +546,7 @@ int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st,
   if (ws_bytes < c.used + 256) return GEEK_ERR_WORKSPACE;
   int32_t rc = GEEK_OK;
   if (J.kind == GEEK_HASH_DENSE) {
-    rc = launch_e2lsh(J, anorm, J.keys, J.codes, J.n_fixup, st, s);
+    rc = launch_e2lsh(J, anorm, J.keys, J.key_fp, J.codes, J.n_fixup, st, s);
   } else if (J.kind == GEEK_HASH_DOPH) {
     if (J.n == 0) return GEEK_OK;
     const size_t lds = sizeof(uint32_t) * 4 * (size_t)(J.F + (J.F + 31) / 32);
@@ -566,7 +568,7 @@ int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st,
     uint32_t* no_keys = nullptr;
     geek_hash_job D = J;
     D.kind = GEEK_HASH_DENSE;
-    rc = launch_e2lsh(D, anorm, no_keys, hcodes, J.n_fixup, st, s);
+    rc = launch_e2lsh(D, anorm, no_keys, nullptr, hcodes, J.n_fixup, st, s);
     if (rc != GEEK_OK) return rc;
     if (J.n == 0) return GEEK_OK;
     const int P = J.m * J.L;

@@ -11,12 +11,13 @@ int main(void) {
   F(geek_hash_job, L); F(geek_hash_job, w); F(geek_hash_job, F); F(geek_hash_job, keys);
   F(geek_hash_job, codes); F(geek_hash_job, offsets); F(geek_hash_job, tokens);
   F(geek_hash_job, cat); F(geek_hash_job, n_cat); F(geek_hash_job, mh_keys);
-  F(geek_hash_job, sig); F(geek_hash_job, n_fixup);
+  F(geek_hash_job, sig); F(geek_hash_job, n_fixup); F(geek_hash_job, key_fp);
   printf("geek_bucketize_job sizeof %zu\n", sizeof(geek_bucketize_job));
   F(geek_bucketize_job, n); F(geek_bucketize_job, T); F(geek_bucketize_job, key_words);
   F(geek_bucketize_job, keys); F(geek_bucketize_job, table_stride);
   F(geek_bucketize_job, row_stride); F(geek_bucketize_job, members);
   F(geek_bucketize_job, offsets); F(geek_bucketize_job, nbuckets); F(geek_bucketize_job, bucket_of);
+  F(geek_bucketize_job, key_fp);
   printf("geek_silk_job sizeof %zu\n", sizeof(geek_silk_job));
   F(geek_silk_job, n); F(geek_silk_job, T); F(geek_silk_job, K); F(geek_silk_job, members);
   F(geek_silk_job, offsets); F(geek_silk_job, nbuckets); F(geek_silk_job, L);

@@ -6,6 +6,7 @@ import math
 
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from workloads import dense_mixture, e2lsh_params
@@ -238,3 +239,33 @@ def test_bucketize_full_table_with_fingerprint_collision():
     n = len(k0)
     keys = np.stack([k0, k0], axis=1)
     _compare(api, keys.reshape(-1), n, 1, 2, 0, 2, [keys], "full table, fingerprint collision")
+
+
+def test_bucketize_with_the_hash_fingerprints():
+    # geek_hash can write each key's bucketize fingerprint beside it; the
+    # buckets formed from those fingerprints equal the ones formed from the
+    # keys alone and the oracle's
+    api = gpu_api()
+    n, d, m, L = 50_000, 32, 8, 4
+    X, _, _ = dense_mixture(n, d, 40, -10, 10, 1.0, "equal", 3)
+    w = 4.0 * math.sqrt(d)
+    A, b = e2lsh_params(m * L, d, w, 3)
+    codes = oracle.e2lsh_codes(X, A, b, w)
+    fp = torch.empty((L, n), dtype=torch.int32, device="cuda")
+    keys, _ = api.hash_dense(cuda(X), cuda(A), cuda(b), m, L, w, key_fp=fp)
+    kh, fh = host_u32(keys), host_u32(fp)
+    g = np.random.default_rng(7)
+    for t in range(L):
+        for i in g.integers(0, n, 64):
+            assert int(fh[t, i]) == _bin_hash([int(x) for x in kh[t, i]]), (t, i)
+    announce("bucketize with and without the hash's fingerprints")
+    a = api.bucketize(keys, n, L, 4, n * 4, 4, key_fp=fp)
+    c = api.bucketize(keys, n, L, 4, n * 4, 4)
+    ma, oa, na, ba = (host_u32(x) for x in a)
+    mc, oc, nc, bc = (host_u32(x) for x in c)
+    for t in range(L):
+        rm, ro, rb = oracle.bucketize(codes[:, t * m:(t + 1) * m])
+        assert na[t] == nc[t] == len(ro) - 1
+        assert np.array_equal(oa[t, :na[t] + 1], ro) and np.array_equal(oc[t, :nc[t] + 1], ro)
+        assert np.array_equal(ma[t], rm) and np.array_equal(mc[t], rm)
+        assert np.array_equal(ba[t], rb) and np.array_equal(bc[t], rb)
