@@ -31,6 +31,63 @@ constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks
 constexpr int H_CS = H_BC + 1;  // LDS stride of a point's codes (odd: conflict-free stores)
 constexpr int H_KB = 16;        // products per accumulation block of the GEMM
 
+// The keys of point pk of a block for tables t0, t0 + step, ... < ntab
+// (table tb + t): code j + 2^(B-1) at bits j*B .. j*B+B-1 of four words,
+// little-endian.  M > 0 fixes m at compile time (shifts and words become
+// constants); M == 0 takes m at run time.  Returns the OR of the offset
+// codes (a code is in range when that OR has no bit at or above B).
+template <int M>
+__device__ __forceinline__ uint32_t pack_keys(const int* __restrict__ lds_code, int pk, int t0, int step,
+                                              int ntab, int tb, int m_rt, int B_rt, uint32_t code_off,
+                                              int64_t n, int64_t ii, uint32_t* __restrict__ keys,
+                                              uint32_t* __restrict__ key_fp) {
+  const int m = M > 0 ? M : m_rt;
+  const int B = M > 0 ? (128 / M < 32 ? 128 / M : 32) : B_rt;
+  uint32_t orr = 0u;
+  for (int t = t0; t < ntab; t += step) {
+    const int* cp = lds_code + pk * H_CS + t * m;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if constexpr (M > 0) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const uint32_t u = (uint32_t)cp[j] + code_off;
+        orr |= u;
+        const int bit = j * B, sh = bit & 31;
+        w[bit >> 5] |= u << sh;
+        if (sh + B > 32) w[(bit >> 5) + 1] |= u >> (32 - sh);
+      }
+    } else {
+      for (int j = 0; j < m; ++j) {
+        const uint32_t u = (uint32_t)cp[j] + code_off;
+        orr |= u;
+        const int bit = j * B, sh = bit & 31;
+        const bool spill = sh + B > 32;  // the code continues in the next word
+        switch (bit >> 5) {
+          case 0:
+            w[0] |= u << sh;
+            if (spill) w[1] |= u >> (32 - sh);
+            break;
+          case 1:
+            w[1] |= u << sh;
+            if (spill) w[2] |= u >> (32 - sh);
+            break;
+          case 2:
+            w[2] |= u << sh;
+            if (spill) w[3] |= u >> (32 - sh);
+            break;
+          default:
+            w[3] |= u << sh;
+        }
+      }
+    }
+    const int64_t at = (int64_t)(tb + t) * n + ii;
+    *reinterpret_cast<uint4*>(keys + at * 4) = make_uint4(w[0], w[1], w[2], w[3]);
+    // the key's fingerprint as bucketize takes it (all four words)
+    if (key_fp) key_fp[at] = key_hash(w, 4);
+  }
+  return orr;
+}
+
 template <int DP>
 __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n, const float* __restrict__ A,
@@ -46,6 +103,7 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   __shared__ __attribute__((aligned(16))) float lds_t1[H_BC];
   __shared__ __attribute__((aligned(16))) float lds_t0[H_BC];
   __shared__ float lds_an[H_BC];   // |a_p| (rounded up) per row of the chunk
+  __shared__ float lds_qb[2];      // the chunk's largest |a_p| and |b_p|
   // codes of a point are H_CS ints apart: the epilogue's stores (one row,
   // 32 points per instruction) then fall into distinct banks
   __shared__ int lds_code[H_BN * H_CS];
@@ -62,7 +120,6 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   const float inv_w = 1.0f / w;
   const int B = 128 / m < 32 ? 128 / m : 32;
   const uint32_t code_off = B == 32 ? 0x80000000u : (1u << (B - 1));
-  const uint32_t code_mask = B == 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
 
   // ---- x fragments (K index of step s for half h: h*DP/2 + s), exact |x|^2
   float xb[S];
@@ -96,10 +153,10 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   nrm += __shfl_xor(nrm, 32);
   const float xn = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
   // |q32 - q64| <= coef * (|a||x| + |b|) / w.  The GEMM sums blocks of
-  // H_KB products in fresh accumulators and then adds the block sums, so a
-  // product passes through at most H_KB + DP/H_KB + 1 roundings (2u each,
-  // b included); then * (1/w) with 1/w rounded, and the float64 reference's
-  // own rounding.
+  // H_KB products in fresh accumulators and then adds the block sums to
+  // accumulators that start at b, so a term passes through at most H_KB +
+  // DP/H_KB + 1 roundings (2u each); then * (1/w) with 1/w rounded, and the
+  // float64 reference's own rounding.
   const double u32 = 0x1p-24;
   constexpr int NR = H_KB + DP / H_KB + 1;
   const double coef_d = (NR * 2.0 * u32 / (1.0 - NR * 2.0 * u32) + 6.0 * u32 + (DP + 3) * 0x1p-53) * 1.01;
@@ -137,17 +194,36 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       }
       *reinterpret_cast<float4*>(lds_a + r * STR + c4) = v;
     }
-    if (tid < H_BC) {
+    if (tid < H_BC) {  // wavefront 0
       const bool live = tid < rows_used;
       const float bv = live ? bvec[p0 + tid] : 0.f;
+      const float an = live ? anorm[p0 + tid] : 0.f;
       lds_b[tid] = bv;
-      lds_t1[tid] = live ? tscale * anorm[p0 + tid] : 0.f;
-      lds_an[tid] = live ? anorm[p0 + tid] : 0.f;
+      lds_t1[tid] = tscale * an;
+      lds_an[tid] = an;
       lds_t0[tid] = live ? __builtin_fmaf(tscale, fabsf(bv), 0x1p-22f) : 0.f;
+      float am = an, bm = fabsf(bv);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        am = fmaxf(am, __shfl_xor(am, o));
+        bm = fmaxf(bm, __shfl_xor(bm, o));
+      }
+      if (tid == 0) {
+        lds_qb[0] = am;
+        lds_qb[1] = bm;
+      }
     }
     __syncthreads();
 
-    f32x16 acc0 = {}, acc1 = {};
+    // the accumulators start at b (b is one more term of the sum)
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+      const float4 b0 = *reinterpret_cast<const float4*>(lds_b + g4 * 8 + h * 4);
+      const float4 b1 = *reinterpret_cast<const float4*>(lds_b + 32 + g4 * 8 + h * 4);
+      acc0[g4 * 4] = b0.x, acc0[g4 * 4 + 1] = b0.y, acc0[g4 * 4 + 2] = b0.z, acc0[g4 * 4 + 3] = b0.w;
+      acc1[g4 * 4] = b1.x, acc1[g4 * 4 + 1] = b1.y, acc1[g4 * 4 + 2] = b1.z, acc1[g4 * 4 + 3] = b1.w;
+    }
     const float* a0p = lds_a + p * STR + h * S;
     const float* a1p = a0p + 32 * STR;
     // A fragments: four K steps per 16-byte LDS read (rows STR = DP + 4
@@ -196,6 +272,10 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     const int pl = wv * 32 + p;  // point within block
     // Register r of half hf holds row hf*32 + (r/4)*8 + h*4 + r%4; rows past
     // rows_used (zero A rows) are stored but never flagged or read.
+    // |q| < 2^22 for every row of the chunk when (max|a| |x| + max|b|) / w
+    // < 2^21: floor, the fraction and the int conversion are then exact.
+    // Otherwise (huge x) every row of the point goes to the float64 check.
+    const bool qsafe = __builtin_fmaf(lds_qb[0], xn, lds_qb[1]) * inv_w < 0x1p21f;
     uint32_t badv[2] = {0u, 0u};
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -213,26 +293,25 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
 #pragma unroll
       for (int g4 = 0; g4 < 4; ++g4) {
         const int rbase = half * 32 + g4 * 8 + h * 4;
-        const float4 bb = *reinterpret_cast<const float4*>(lds_b + rbase);
         const float4 t1 = *reinterpret_cast<const float4*>(lds_t1 + rbase);
         const float4 t0 = *reinterpret_cast<const float4*>(lds_t0 + rbase);
-        const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
         const float t1v[4] = {t1.x, t1.y, t1.z, t1.w};
         const float t0v[4] = {t0.x, t0.y, t0.z, t0.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int r = g4 * 4 + e;
-          const float v = acc[r] + bv[e];
-          const float q = v * inv_w;
+          const float q = acc[r] * inv_w;
           const float fq = floorf(q);
-          const float frac = q - fq;
+          const float frac = q - fq;  // exact
           const float tau = __builtin_fmaf(t1v[e], xn, t0v[e]);
-          const bool ok = frac > tau && frac < 1.0f - tau && fabsf(q) < 0x1p22f;
+          // distance to the nearest integer (exact: 1 - frac is exact when
+          // it is the smaller) less the radius; negative = not certified
+          const float marg = fminf(frac, 1.0f - frac) - tau;
           lds_code[pl * H_CS + rbase + e] = (int)fq;
-          const int bitpos = g4 * 8 + h * 4 + e;
-          bad |= (ok ? 0u : 1u) << bitpos;
+          bad |= (__float_as_uint(marg) >> 31) << (g4 * 8 + h * 4 + e);
         }
       }
+      bad = qsafe ? bad : 0xFFFFFFFFu;
       bad &= live;
       badv[half] = valid ? bad : 0u;
     }
@@ -264,14 +343,16 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const int k = k0 + 4 * u;
-              float xk[4] = {xb[k], xb[k + 1], xb[k + 2], xb[k + 3]};
-              // opaque copies: converting all of x to float64 once, outside
-              // the loop over flagged rows, would need 2*S more registers
-              asm volatile("" : "+v"(xk[0]), "+v"(xk[1]), "+v"(xk[2]), "+v"(xk[3]));
-              p4[0] = __fma_rn((double)av[u].x, (double)xk[0], p4[0]);
-              p4[1] = __fma_rn((double)av[u].y, (double)xk[1], p4[1]);
-              p4[2] = __fma_rn((double)av[u].z, (double)xk[2], p4[2]);
-              p4[3] = __fma_rn((double)av[u].w, (double)xk[3], p4[3]);
+              // x converted to float64 here, by an opaque instruction:
+              // converting all of x once, outside the loop over flagged
+              // rows, would need 2*S more registers
+              double xd[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) asm volatile("v_cvt_f64_f32 %0, %1" : "=v"(xd[c]) : "v"(xb[k + c]));
+              p4[0] = __fma_rn((double)av[u].x, xd[0], p4[0]);
+              p4[1] = __fma_rn((double)av[u].y, xd[1], p4[1]);
+              p4[2] = __fma_rn((double)av[u].z, xd[2], p4[2]);
+              p4[3] = __fma_rn((double)av[u].w, xd[3], p4[3]);
             }
           }
           part = (p4[0] + p4[1]) + (p4[2] + p4[3]);
@@ -296,34 +377,22 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       }
     }
     __syncthreads();
-    // ---- pack the m codes of every (table, point) into a 128-bit key
+    // ---- pack the m codes of every (table, point) into a 128-bit key (m = 10
+    // at compile time; more compile-time cases push the kernel past its
+    // register budget)
     const int64_t np = (n - i0) < H_BN ? (n - i0) : H_BN;
-    for (int q = tid; keys && q < ntab * H_BN; q += H_THREADS) {
-      const int t = q / H_BN, pp = q % H_BN;
-      if (pp >= np) continue;
-      // code + 2^(B-1) in B bits, code j at bit j*B of a 128-bit key
-      uint64_t lo = 0, hi = 0;
-      bool inr = true;
-      const int* cp = lds_code + pp * H_CS + t * m;
-      for (int j = 0; j < m; ++j) {
-        const uint32_t u = (uint32_t)cp[j] + code_off;
-        inr = inr && (B == 32 || u < (1u << B));
-        const uint64_t f = (uint64_t)(u & code_mask);
-        const int bit = j * B;
-        if (bit < 64) {
-          lo |= f << bit;
-          if (bit + B > 64) hi |= f >> (64 - bit);
-        } else {
-          hi |= f << (bit - 64);
-        }
-      }
-      const uint32_t kw[4] = {(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
-      if (!inr) set_status(st, GEEK_ERR_RANGE);
-      const int64_t ii = i0 + pp;
-      *reinterpret_cast<uint4*>(keys + ((int64_t)(tb + t) * n + ii) * 4) =
-          make_uint4(kw[0], kw[1], kw[2], kw[3]);
-      // the key's fingerprint as bucketize takes it (all four words)
-      if (key_fp) key_fp[(int64_t)(tb + t) * n + ii] = key_hash(kw, 4);
+    const int pk = tid % H_BN;  // this thread's point; tables tid / H_BN, + 2, ...
+    if (keys && pk < np) {
+      const int64_t ii = i0 + pk;
+      const int t0 = tid / H_BN, step = H_THREADS / H_BN;
+      uint32_t orr;
+#define GEEK_PACK(MM) pack_keys<MM>(lds_code, pk, t0, step, ntab, tb, m, B, code_off, n, ii, keys, key_fp)
+      if (m == 10)
+        orr = GEEK_PACK(10);
+      else
+        orr = GEEK_PACK(0);
+#undef GEEK_PACK
+      if (B < 32 && (orr >> B) != 0u) set_status(st, GEEK_ERR_RANGE);
     }
     if (codes_out) {
       for (int q = tid; q < H_BN * rows_used; q += H_THREADS) {

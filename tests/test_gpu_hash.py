@@ -62,6 +62,20 @@ def test_e2lsh_exact_bucket_edges_go_through_fixup():
     _dense_case(api, Xe.astype(np.float32), A, np.zeros(40, np.float32), 8, 5, 1.0, "edges-ulp")
 
 
+def test_e2lsh_large_quotients_take_float64():
+    # rows scaled by 1e5 or 2e6 put |a.x + b| / w far above 2^21, where the
+    # float32 quotient is no longer certified: every pair of such a row is
+    # recomputed in float64; the other rows keep the fast path
+    api = gpu_api()
+    X, _, _ = dense_mixture(1500, 16, 10, -10, 10, 1.0, "equal", 5)
+    X[::3] *= np.float32(1e5)
+    X[1::6] *= np.float32(2e6)
+    for m, L, w in ((2, 3, 1.0), (1, 5, 0.5), (4, 2, 7.0)):
+        A, b = e2lsh_params(m * L, 16, w, 5)
+        nf = _dense_case(api, X, A, b, m, L, w, "large-quotients")
+        assert nf >= (len(X) // 6) * m * L
+
+
 def test_e2lsh_errors_reported():
     api = gpu_api()
     from paper_2106_10515_amd import GeekError
@@ -76,6 +90,11 @@ def test_e2lsh_errors_reported():
     # m = 10 leaves 12 bits per code: a tiny width overflows them
     with pytest.raises(GeekError) as e:
         api.hash_dense(cuda(X), cuda(A), cuda(b), 10, 2, 1e-3)
+    assert e.value.code == 2
+    # m = 4 leaves 32 bits per code, m = 5 25 bits
+    A5, b5 = e2lsh_params(20, 8, 4.0, 1)
+    with pytest.raises(GeekError) as e:
+        api.hash_dense(cuda(X), cuda(A5), cuda(b5), 5, 4, 1e-6)
     assert e.value.code == 2
 
 
