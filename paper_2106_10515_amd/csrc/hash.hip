@@ -31,6 +31,82 @@ constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks
 constexpr int H_CS = H_BC + 1;  // LDS stride of a point's codes (odd: conflict-free stores)
 constexpr int H_KB = 16;        // products per accumulation block of the GEMM
 
+// Float32 certification constant of the projection: |q32 - q64| <= coef *
+// (|a||x| + |b|) / w.  The GEMM sums blocks of H_KB products in fresh
+// accumulators and then adds the block sums to accumulators that start at
+// b, so a term passes through at most H_KB + DP/H_KB + 1 roundings (2u
+// each); then * (1/w) with 1/w rounded, and the float64 reference's own
+// rounding.
+template <int DP>
+GEEK_HD double e2lsh_coef() {
+  const double u32 = 0x1p-24;
+  constexpr int NR = H_KB + DP / H_KB + 1;
+  return (NR * 2.0 * u32 / (1.0 - NR * 2.0 * u32) + 6.0 * u32 + (DP + 3) * 0x1p-53) * 1.01;
+}
+
+// One chunk of projection rows (whole tables, at most H_BC rows) in the
+// hash kernel's LDS: H_BC rows of a, zero-padded to DP attributes and to
+// H_BC rows, at a stride of DP + 4 floats; then per row b, t1 and t0 (the
+// radius tau = t1 * |x| + t0) and |a| rounded up, H_BC each; then the
+// chunk's largest |a| and |b| and two unused words.  `k_e2lsh_prep` writes
+// the same image to global memory without the 16-byte pad of each row, and
+// the hash kernel copies it to LDS with LDS DMA, one 16-byte piece per lane,
+// filling each row's pad with a duplicate piece.
+template <int DP>
+struct E2Chunk {
+  static constexpr int CH = DP / 4;                // 16-byte pieces of a row
+  static constexpr int STR = DP + 4;               // LDS row stride (floats)
+  static constexpr int INFO = 4 * H_BC + 4;        // b, t1, t0, |a|, maxima
+  static constexpr int G_FLOATS = H_BC * DP + INFO;   // per chunk in global memory
+  static constexpr int L_FLOATS = H_BC * STR + INFO;  // in LDS
+  static constexpr int PIECES = L_FLOATS / 4;
+  static constexpr int A_PIECES = H_BC * (CH + 1);
+  static constexpr int DMA_ROUNDS = (PIECES + H_THREADS - 1) / H_THREADS;
+};
+
+// Chunk c = blockIdx.x holds tables c*tpc .. c*tpc + tpc - 1 (rows
+// c*tpc*m ..).  |a| is the float64 norm in attribute order, rounded up.
+template <int DP>
+__global__ __launch_bounds__(H_THREADS) void k_e2lsh_prep(const float* __restrict__ A, const float* __restrict__ bvec,
+                                                          int d, int m, int L, float w, int tpc,
+                                                          float* __restrict__ out) {
+  using C = E2Chunk<DP>;
+  const int c = blockIdx.x, tid = threadIdx.x;
+  const int tb = c * tpc;
+  const int ntab = (L - tb) < tpc ? (L - tb) : tpc;
+  const int rows_used = ntab * m, p0 = tb * m;
+  float* o = out + (int64_t)c * C::G_FLOATS;
+  for (int q = tid; q < H_BC * DP; q += H_THREADS) {
+    const int r = q / DP, k = q % DP;
+    o[q] = (r < rows_used && k < d) ? A[(int64_t)(p0 + r) * d + k] : 0.f;
+  }
+  if (tid < H_BC) {  // wavefront 0: one row per lane
+    const bool live = tid < rows_used;
+    double ss = 0.0;
+    if (live)
+      for (int k = 0; k < d; ++k) {
+        const double v = (double)A[(int64_t)(p0 + tid) * d + k];
+        ss += v * v;
+      }
+    const float an = live ? (float)(sqrt(ss) * (1.0 + 0x1p-20)) : 0.f;
+    const float bv = live ? bvec[p0 + tid] : 0.f;
+    const float inv_w = 1.0f / w;
+    const float tscale = (float)e2lsh_coef<DP>() * inv_w;
+    float* info = o + H_BC * DP;
+    info[tid] = bv;
+    info[H_BC + tid] = tscale * an;
+    info[2 * H_BC + tid] = live ? __builtin_fmaf(tscale, fabsf(bv), 0x1p-22f) : 0.f;
+    info[3 * H_BC + tid] = an;
+    float am = an, bm = fabsf(bv);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      am = fmaxf(am, __shfl_xor(am, off));
+      bm = fmaxf(bm, __shfl_xor(bm, off));
+    }
+    if (tid < 4) info[4 * H_BC + tid] = tid == 0 ? am : tid == 1 ? bm : 0.f;
+  }
+}
+
 // The keys of point pk of a block for tables t0, t0 + step, ... < ntab
 // (table tb + t): code j + 2^(B-1) at bits j*B .. j*B+B-1 of four words,
 // little-endian.  M > 0 fixes m at compile time (shifts and words become
@@ -90,20 +166,22 @@ __device__ __forceinline__ uint32_t pack_keys(const int* __restrict__ lds_code, 
 
 template <int DP>
 __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
-    const float* __restrict__ X, int64_t ldx, int d, int64_t n, const float* __restrict__ A,
-    const float* __restrict__ bvec, const float* __restrict__ anorm, int m, int L, float w,
-    int tpc, uint32_t* __restrict__ keys, uint32_t* __restrict__ key_fp, int32_t* __restrict__ codes_out,
-    unsigned long long* __restrict__ n_fixup, int32_t* st) {
+    const float* __restrict__ X, int64_t ldx, int d, int64_t n, const float* __restrict__ chunks, int m,
+    int L, float w, int tpc, uint32_t* __restrict__ keys, uint32_t* __restrict__ key_fp,
+    int32_t* __restrict__ codes_out, unsigned long long* __restrict__ n_fixup, int32_t* st) {
+  using C = E2Chunk<DP>;
   constexpr int S = DP / 2;
-  constexpr int STR = DP + 4;
-  __shared__ __attribute__((aligned(16))) float lds_a[H_BC * STR];
-  // per row of the chunk: b, and the two factors of the certification
-  // radius tau = t1 * |x| + t0
-  __shared__ __attribute__((aligned(16))) float lds_b[H_BC];
-  __shared__ __attribute__((aligned(16))) float lds_t1[H_BC];
-  __shared__ __attribute__((aligned(16))) float lds_t0[H_BC];
-  __shared__ float lds_an[H_BC];   // |a_p| (rounded up) per row of the chunk
-  __shared__ float lds_qb[2];      // the chunk's largest |a_p| and |b_p|
+  constexpr int STR = C::STR;
+  // the chunk's rows of a, then per row b, the two factors of the
+  // certification radius tau = t1 * |x| + t0, |a_p| rounded up, and the
+  // chunk's largest |a_p| and |b_p| (layout of E2Chunk)
+  __shared__ __attribute__((aligned(16))) float lds_chunk[C::L_FLOATS];
+  float* const lds_a = lds_chunk;
+  float* const lds_b = lds_chunk + H_BC * STR;
+  float* const lds_t1 = lds_b + H_BC;
+  float* const lds_t0 = lds_t1 + H_BC;
+  float* const lds_an = lds_t0 + H_BC;
+  float* const lds_qb = lds_an + H_BC;
   // codes of a point are H_CS ints apart: the epilogue's stores (one row,
   // 32 points per instruction) then fall into distinct banks
   __shared__ int lds_code[H_BN * H_CS];
@@ -120,6 +198,31 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   const float inv_w = 1.0f / w;
   const int B = 128 / m < 32 ? 128 / m : 32;
   const uint32_t code_off = B == 32 ? 0x80000000u : (1u << (B - 1));
+  const int wu = __builtin_amdgcn_readfirstlane(wv);  // wave-uniform, for the LDS DMA bases
+
+  // Copy of chunk c into LDS: 16-byte piece q of the LDS image from its
+  // place in the global image (a row's pad piece takes the row's first
+  // piece).  Lane-contiguous pieces, one DMA instruction per wave and round.
+  auto issue_chunk = [&](int c) {
+    const float* g = chunks + (int64_t)c * C::G_FLOATS;
+#pragma unroll
+    for (int u = 0; u < C::DMA_ROUNDS; ++u) {
+      const int q0 = u * H_THREADS + wu * 64;  // wave-uniform first piece
+      const int q = q0 + lane;
+      if (q0 < C::PIECES && q < C::PIECES) {
+        int src;
+        if (q < C::A_PIECES) {
+          const int r = q / (C::CH + 1), pc = q % (C::CH + 1);
+          src = r * DP + (pc < C::CH ? pc * 4 : 0);
+        } else {
+          src = H_BC * DP + (q - C::A_PIECES) * 4;
+        }
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g + src),
+                                         reinterpret_cast<void*>(lds_chunk + q0 * 4), 16, 0, 0);
+      }
+    }
+  };
+  issue_chunk(0);
 
   // ---- x fragments (K index of step s for half h: h*DP/2 + s), exact |x|^2
   float xb[S];
@@ -152,67 +255,21 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   if (!finite) set_status(st, GEEK_ERR_NONFINITE);
   nrm += __shfl_xor(nrm, 32);
   const float xn = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
-  // |q32 - q64| <= coef * (|a||x| + |b|) / w.  The GEMM sums blocks of
-  // H_KB products in fresh accumulators and then adds the block sums to
-  // accumulators that start at b, so a term passes through at most H_KB +
-  // DP/H_KB + 1 roundings (2u each); then * (1/w) with 1/w rounded, and the
-  // float64 reference's own rounding.
-  const double u32 = 0x1p-24;
-  constexpr int NR = H_KB + DP / H_KB + 1;
-  const double coef_d = (NR * 2.0 * u32 / (1.0 - NR * 2.0 * u32) + 6.0 * u32 + (DP + 3) * 0x1p-53) * 1.01;
-  const float coef = (float)coef_d;
   // second stage (float64 dot: four FMA chains per K half, summed pairwise,
   // then across the halves; + b; * (1/w) with 1/w rounded): |q_fast - q64|
   // <= coef64 * (|a||x| + |b|) / w, covering both float64 evaluations
   const double coef64 = ((DP / 8 + 8) + (DP + 3)) * 0x1p-53 * 1.02;
   const double inv_wd = 1.0 / (double)w;
 
-  const float tscale = coef * inv_w;
-  const bool a_vec = ((d & 3) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
 
   unsigned long long nfix = 0;  // uncertified pairs owned by this lane
   for (int tb = 0; tb < L; tb += tpc) {
     const int ntab = (L - tb) < tpc ? (L - tb) : tpc;
     const int rows_used = ntab * m;
     const int p0 = tb * m;
-    // A tile of the chunk (rows p0.., zero-padded to H_BC x DP) and the
-    // per-row b and certification factors
-    __syncthreads();
-    for (int q = tid; q < H_BC * (DP / 4); q += H_THREADS) {
-      const int r = q / (DP / 4), c4 = (q % (DP / 4)) * 4;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < rows_used) {
-        const float* ar = A + (int64_t)(p0 + r) * d;
-        if (a_vec && c4 + 3 < d) {
-          v = *reinterpret_cast<const float4*>(ar + c4);
-        } else {
-          v.x = c4 < d ? ar[c4] : 0.f;
-          v.y = c4 + 1 < d ? ar[c4 + 1] : 0.f;
-          v.z = c4 + 2 < d ? ar[c4 + 2] : 0.f;
-          v.w = c4 + 3 < d ? ar[c4 + 3] : 0.f;
-        }
-      }
-      *reinterpret_cast<float4*>(lds_a + r * STR + c4) = v;
-    }
-    if (tid < H_BC) {  // wavefront 0
-      const bool live = tid < rows_used;
-      const float bv = live ? bvec[p0 + tid] : 0.f;
-      const float an = live ? anorm[p0 + tid] : 0.f;
-      lds_b[tid] = bv;
-      lds_t1[tid] = tscale * an;
-      lds_an[tid] = an;
-      lds_t0[tid] = live ? __builtin_fmaf(tscale, fabsf(bv), 0x1p-22f) : 0.f;
-      float am = an, bm = fabsf(bv);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        am = fmaxf(am, __shfl_xor(am, o));
-        bm = fmaxf(bm, __shfl_xor(bm, o));
-      }
-      if (tid == 0) {
-        lds_qb[0] = am;
-        lds_qb[1] = bm;
-      }
-    }
+    const int c = tb / tpc;
+    // this wave's pieces of the chunk have landed; then everyone's
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
     // the accumulators start at b (b is one more term of the sum)
@@ -377,6 +434,9 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       }
     }
     __syncthreads();
+    // every wave is done with this chunk's LDS rows: the next chunk's copy
+    // runs during the packing
+    if (tb + tpc < L) issue_chunk(c + 1);
     // ---- pack the m codes of every (table, point) into a 128-bit key (m = 10
     // at compile time; more compile-time cases push the kernel past its
     // register budget)
@@ -405,15 +465,6 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     for (int o = 32; o > 0; o >>= 1) nfix += __shfl_xor(nfix, o);
     if (lane == 0 && nfix) atomicAdd(n_fixup, nfix);
   }
-}
-
-// |a_p| rounded up (float64 sum of squares), per projection.
-__global__ void k_rownorm(const float* __restrict__ A, int P, int d, float* __restrict__ out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= P) return;
-  double s = 0.0;
-  for (int t = 0; t < d; ++t) s += (double)A[(int64_t)r * d + t] * (double)A[(int64_t)r * d + t];
-  out[r] = (float)(sqrt(s) * (1.0 + 0x1p-20));
 }
 
 __global__ void k_check_finite(const float* __restrict__ v, int64_t n, int32_t* st) {
@@ -563,27 +614,42 @@ __global__ __launch_bounds__(256) void k_doph(const int64_t* __restrict__ offset
 // ---------------------------------------------------------------- host side
 static int pick_dp_h(int d) { return d <= 32 ? 32 : d <= 64 ? 64 : d <= 128 ? 128 : d <= 256 ? 256 : 0; }
 
+// Floats of the projection-row chunks that k_e2lsh_prep writes.
+static size_t e2lsh_chunk_floats(const geek_hash_job& J) {
+  if (J.kind != GEEK_HASH_DENSE && J.kind != GEEK_HASH_HETERO) return 0;
+  if (J.m < 1 || J.m > H_BC) return 0;
+  const int nchunks = ceil_div(J.L, H_BC / J.m);
+  switch (pick_dp_h(J.d)) {
+    case 32: return (size_t)nchunks * E2Chunk<32>::G_FLOATS;
+    case 64: return (size_t)nchunks * E2Chunk<64>::G_FLOATS;
+    case 128: return (size_t)nchunks * E2Chunk<128>::G_FLOATS;
+    default: return (size_t)nchunks * E2Chunk<256>::G_FLOATS;
+  }
+}
+
 size_t hash_ws(const geek_hash_job& J) {
   Carver c(nullptr);
-  c.take<float>((size_t)J.m * J.L + 64);
+  c.take<float>(e2lsh_chunk_floats(J) + 64);
   if (J.kind == GEEK_HASH_HETERO) c.take<int32_t>((size_t)J.n * J.m * J.L);
   c.take<unsigned long long>(1);
   return c.used + 256;
 }
 
-static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys, uint32_t* key_fp,
+static int32_t launch_e2lsh(const geek_hash_job& J, float* chunks, uint32_t* keys, uint32_t* key_fp,
                             int32_t* codes, unsigned long long* nfix, int32_t* st, hipStream_t s) {
-  const int P = J.m * J.L;
-  hipLaunchKernelGGL(k_rownorm, dim3(ceil_div(P, 128)), dim3(128), 0, s, J.A, P, J.d, anorm);
   const int tpc = H_BC / J.m;  // whole tables per 64-row chunk
+  const int nchunks = ceil_div(J.L, tpc);
   const int grid = ceil_div(J.n, H_BN);
-  if (grid == 0) return GEEK_OK;
-  prof_begin(GEEK_PROF_E2LSH, s);
   switch (pick_dp_h(J.d)) {
-#define GEEK_H_CASE(DPV)                                                                        \
-  case DPV:                                                                                     \
-    hipLaunchKernelGGL((k_e2lsh<DPV>), dim3(grid), dim3(H_THREADS), 0, s, J.X, J.ldx, J.d, J.n, \
-                       J.A, J.b, anorm, J.m, J.L, J.w, tpc, keys, key_fp, codes, nfix, st);     \
+#define GEEK_H_CASE(DPV)                                                                                   \
+  case DPV:                                                                                                \
+    hipLaunchKernelGGL((k_e2lsh_prep<DPV>), dim3(nchunks), dim3(H_THREADS), 0, s, J.A, J.b, J.d, J.m, J.L, \
+                       J.w, tpc, chunks);                                                                  \
+    if (grid == 0) return GEEK_OK;                                                                         \
+    prof_begin(GEEK_PROF_E2LSH, s);                                                                        \
+    hipLaunchKernelGGL((k_e2lsh<DPV>), dim3(grid), dim3(H_THREADS), 0, s, J.X, J.ldx, J.d, J.n, chunks,    \
+                       J.m, J.L, J.w, tpc, keys, key_fp, codes, nfix, st);                                 \
+    prof_end(GEEK_PROF_E2LSH, s);                                                                          \
     break;
     GEEK_H_CASE(32)
     GEEK_H_CASE(64)
@@ -593,7 +659,6 @@ static int32_t launch_e2lsh(const geek_hash_job& J, float* anorm, uint32_t* keys
     default:
       return GEEK_ERR_UNSUPPORTED;
   }
-  prof_end(GEEK_PROF_E2LSH, s);
   return GEEK_OK;
 }
 
@@ -608,14 +673,14 @@ static int32_t dispatch_fpl(int F, Fn&& fn) {
 
 int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st, hipStream_t s) {
   Carver c(ws);
-  float* anorm = c.take<float>((size_t)J.m * J.L + 64);
+  float* chunks = c.take<float>(e2lsh_chunk_floats(J) + 64);
   int32_t* hcodes = (J.kind == GEEK_HASH_HETERO) ? c.take<int32_t>((size_t)J.n * J.m * J.L) : nullptr;
   unsigned long long* dummy = c.take<unsigned long long>(1);
   (void)dummy;
   if (ws_bytes < c.used + 256) return GEEK_ERR_WORKSPACE;
   int32_t rc = GEEK_OK;
   if (J.kind == GEEK_HASH_DENSE) {
-    rc = launch_e2lsh(J, anorm, J.keys, J.key_fp, J.codes, J.n_fixup, st, s);
+    rc = launch_e2lsh(J, chunks, J.keys, J.key_fp, J.codes, J.n_fixup, st, s);
   } else if (J.kind == GEEK_HASH_DOPH) {
     if (J.n == 0) return GEEK_OK;
     const size_t lds = sizeof(uint32_t) * 4 * (size_t)(J.F + (J.F + 31) / 32);
@@ -637,7 +702,7 @@ int32_t hash_run(const geek_hash_job& J, void* ws, size_t ws_bytes, int32_t* st,
     uint32_t* no_keys = nullptr;
     geek_hash_job D = J;
     D.kind = GEEK_HASH_DENSE;
-    rc = launch_e2lsh(D, anorm, no_keys, nullptr, hcodes, J.n_fixup, st, s);
+    rc = launch_e2lsh(D, chunks, no_keys, nullptr, hcodes, J.n_fixup, st, s);
     if (rc != GEEK_OK) return rc;
     if (J.n == 0) return GEEK_OK;
     const int P = J.m * J.L;
