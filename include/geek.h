@@ -396,8 +396,8 @@ int32_t geek_bucketize(const geek_bucketize_job* jobs, int32_t njobs, void* ws,
  * of GEEK_NOALLOC_SCRATCH_BYTES per GPU (each GPU the call runs on holds it
  * until the process ends).  A job whose workspace (geek_workspace_size)
  * exceeds it -- e.g. heterogeneous rows with n * m * L above about 2^18, or
- * dense rows with more than about 1,900 projections (about 950 for d > 128)
- * -- returns GEEK_ERR_WORKSPACE before any work is enqueued.  The jobs run one
+ * dense rows with more than about 750 projections (d <= 128; about 950 for
+ * d > 128) -- returns GEEK_ERR_WORKSPACE before any work is enqueued.  The jobs run one
  * after another on `stream`.  The call allocates nothing (no hipMalloc,
  * hipFree or allocating library routine).  Every call on one GPU shares that
  * GPU's array: calls that overlap on one GPU (other streams, other host

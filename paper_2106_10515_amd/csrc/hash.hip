@@ -1,7 +1,8 @@
 // LSH values of the data transformation (paper Section 3.1) on gfx950.
 //
 // Dense E2LSH: code[i][p] = floor((a_p . x_i + b_p) / w).  The projection is
-// a GEMM X[n x d] . A^T[d x P] on the float32 matrix cores; the epilogue adds
+// a GEMM X[n x d] . A^T[d x P] on the matrix cores (for d <= 128 from exact
+// three-piece bf16 splits of a and x, else in float32); the epilogue adds
 // b, scales by 1/w, floors and certifies the result: the float32 quotient q
 // differs from the float64 reference quotient (sum over t in order, + b, / w)
 // by at most tau = c * (|a_p| |x_i| + |b_p|) / w, so when [q - tau, q + tau]
@@ -31,54 +32,87 @@ constexpr int H_BC = 64;    // projection rows per chunk (two 32-row MFMA blocks
 constexpr int H_CS = H_BC + 1;  // LDS stride of a point's codes (odd: conflict-free stores)
 constexpr int H_KB = 16;        // products per accumulation block of the GEMM
 
-// Float32 certification constant of the projection: |q32 - q64| <= coef *
-// (|a||x| + |b|) / w.  The GEMM sums blocks of H_KB products in fresh
-// accumulators and then adds the block sums to accumulators that start at
-// b, so a term passes through at most H_KB + DP/H_KB + 1 roundings (2u
-// each); then * (1/w) with 1/w rounded, and the float64 reference's own
-// rounding.
-template <int DP>
+// Certification constant of the projection: |q_fast - q64| <= coef *
+// (|a||x| + |b|) / w.  Float32 products (B3 false): the GEMM sums blocks of
+// H_KB products in fresh accumulators and then adds the block sums to
+// accumulators that start at b, so a term passes through at most H_KB +
+// DP/H_KB + 1 roundings (2u each); then * (1/w) with 1/w rounded, and the
+// float64 reference's own rounding.  Bfloat16 pieces (B3 true): a and x are
+// each the exact sum of three bf16 pieces (hi, mid, lo; round-to-nearest
+// splits, so |mid| <= 2^-8 |v| and |lo| <= 2^-16 |v|); a K step of 16 sums
+// mid*mid, hi*lo, lo*hi, hi*mid, mid*hi and last hi*hi in one fresh
+// accumulator (every bf16 product is exact in float32), which is then added
+// to the running sums: the hi*hi terms (at most (1 + 2^-8)^2 |a_t x_t|)
+// see the same 16 + DP/16 + 1 roundings, the smaller terms (at most
+// (2^-7 + 3 * 2^-16)(1 + 2^-8)^2 |a_t x_t| together) up to 6 * 16 + DP/16
+// + 1, and the dropped mid*lo, lo*mid, lo*lo are at most 2^-23 |a_t x_t| +
+// 2^-32 |a_t x_t|.
+template <int DP, bool B3>
 GEEK_HD double e2lsh_coef() {
   const double u32 = 0x1p-24;
   constexpr int NR = H_KB + DP / H_KB + 1;
-  return (NR * 2.0 * u32 / (1.0 - NR * 2.0 * u32) + 6.0 * u32 + (DP + 3) * 0x1p-53) * 1.01;
+  const double main = NR * 2.0 * u32 / (1.0 - NR * 2.0 * u32) * (B3 ? 1.0079 : 1.0);
+  constexpr int NRS = 6 * H_KB + DP / H_KB + 1;
+  const double small =
+      B3 ? (NRS * 2.0 * u32 / (1.0 - NRS * 2.0 * u32)) * 0x1.06p-7 + 0x1p-23 + 0x1p-32 : 0.0;
+  return (main + small + 6.0 * u32 + (DP + 3) * 0x1p-53) * 1.01;
 }
 
 // One chunk of projection rows (whole tables, at most H_BC rows) in the
-// hash kernel's LDS: H_BC rows of a, zero-padded to DP attributes and to
-// H_BC rows, at a stride of DP + 4 floats; then per row b, t1 and t0 (the
+// hash kernel's LDS: H_BC rows of a in float32, zero-padded to DP
+// attributes and to H_BC rows, at a stride of DP + 4 floats; with B3 the
+// three bf16 pieces of the same rows (hi, mid, lo; a = hi + mid + lo
+// exactly), each at a stride of DP + 8 bf16; then per row b, t1 and t0 (the
 // radius tau = t1 * |x| + t0) and |a| rounded up, H_BC each; then the
 // chunk's largest |a| and |b| and two unused words.  `k_e2lsh_prep` writes
 // the same image to global memory without the 16-byte pad of each row, and
 // the hash kernel copies it to LDS with LDS DMA, one 16-byte piece per lane,
 // filling each row's pad with a duplicate piece.
-template <int DP>
+template <int DP, bool B3>
 struct E2Chunk {
-  static constexpr int CH = DP / 4;                // 16-byte pieces of a row
-  static constexpr int STR = DP + 4;               // LDS row stride (floats)
+  static constexpr int CH = DP / 4;                // 16-byte pieces of a float32 row
+  static constexpr int STR = DP + 4;               // LDS float32 row stride (floats)
+  static constexpr int NPC = B3 ? 3 : 0;           // bf16 pieces per row
+  static constexpr int PCH = DP / 8;               // 16-byte pieces of a bf16 row
+  static constexpr int PSTR = DP / 2 + 4;          // LDS bf16 row stride (floats)
   static constexpr int INFO = 4 * H_BC + 4;        // b, t1, t0, |a|, maxima
-  static constexpr int G_FLOATS = H_BC * DP + INFO;   // per chunk in global memory
-  static constexpr int L_FLOATS = H_BC * STR + INFO;  // in LDS
+  static constexpr int G_A = H_BC * DP;            // global: float32 rows (floats)
+  static constexpr int G_P = H_BC * DP / 2;        // global: one bf16 piece of the rows (floats)
+  static constexpr int G_FLOATS = G_A + NPC * G_P + INFO;  // per chunk in global memory
+  static constexpr int L_A = H_BC * STR;
+  static constexpr int L_P = H_BC * PSTR;
+  static constexpr int L_INFO = L_A + NPC * L_P;   // LDS offset of the per-row data (floats)
+  static constexpr int L_FLOATS = L_INFO + INFO;
   static constexpr int PIECES = L_FLOATS / 4;
   static constexpr int A_PIECES = H_BC * (CH + 1);
-  static constexpr int DMA_ROUNDS = (PIECES + H_THREADS - 1) / H_THREADS;
+  static constexpr int P_PIECES = H_BC * (PCH + 1);
 };
 
 // Chunk c = blockIdx.x holds tables c*tpc .. c*tpc + tpc - 1 (rows
 // c*tpc*m ..).  |a| is the float64 norm in attribute order, rounded up.
-template <int DP>
+template <int DP, bool B3>
 __global__ __launch_bounds__(H_THREADS) void k_e2lsh_prep(const float* __restrict__ A, const float* __restrict__ bvec,
                                                           int d, int m, int L, float w, int tpc,
                                                           float* __restrict__ out) {
-  using C = E2Chunk<DP>;
+  using C = E2Chunk<DP, B3>;
   const int c = blockIdx.x, tid = threadIdx.x;
   const int tb = c * tpc;
   const int ntab = (L - tb) < tpc ? (L - tb) : tpc;
   const int rows_used = ntab * m, p0 = tb * m;
   float* o = out + (int64_t)c * C::G_FLOATS;
+  __bf16* pc = reinterpret_cast<__bf16*>(o + C::G_A);
   for (int q = tid; q < H_BC * DP; q += H_THREADS) {
     const int r = q / DP, k = q % DP;
-    o[q] = (r < rows_used && k < d) ? A[(int64_t)(p0 + r) * d + k] : 0.f;
+    const float v = (r < rows_used && k < d) ? A[(int64_t)(p0 + r) * d + k] : 0.f;
+    o[q] = v;
+    if constexpr (B3) {
+      const __bf16 hi = (__bf16)v;
+      const float r1 = v - (float)hi;
+      const __bf16 mid = (__bf16)r1;
+      pc[q] = hi;
+      pc[2 * C::G_P + q] = mid;
+      pc[4 * C::G_P + q] = (__bf16)(r1 - (float)mid);
+    }
   }
   if (tid < H_BC) {  // wavefront 0: one row per lane
     const bool live = tid < rows_used;
@@ -91,8 +125,8 @@ __global__ __launch_bounds__(H_THREADS) void k_e2lsh_prep(const float* __restric
     const float an = live ? (float)(sqrt(ss) * (1.0 + 0x1p-20)) : 0.f;
     const float bv = live ? bvec[p0 + tid] : 0.f;
     const float inv_w = 1.0f / w;
-    const float tscale = (float)e2lsh_coef<DP>() * inv_w;
-    float* info = o + H_BC * DP;
+    const float tscale = (float)e2lsh_coef<DP, B3>() * inv_w;
+    float* info = o + C::G_A + C::NPC * C::G_P;
     info[tid] = bv;
     info[H_BC + tid] = tscale * an;
     info[2 * H_BC + tid] = live ? __builtin_fmaf(tscale, fabsf(bv), 0x1p-22f) : 0.f;
@@ -164,33 +198,77 @@ __device__ __forceinline__ uint32_t pack_keys(const int* __restrict__ lds_code, 
   return orr;
 }
 
-template <int DP>
-__global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
+// Two floats to packed bf16 (round to nearest even -- the instruction the
+// compiler itself emits for a float-to-bf16 conversion; the first in the
+// low half).  An opaque instruction: the split of x is loop-invariant, and
+// hoisted out of the chunk loop it would hold 96 more VGPRs.
+GEEK_D uint32_t cvt_pk_bf16(float a, float b) {
+  uint32_t r;
+  asm volatile("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+
+// The three bf16 pieces of eight floats: v = hi + mid + lo exactly (each
+// remainder is exact in float32).
+GEEK_D void split3_bf16(const float* v, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+  u32x4v H, M, O;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float v0 = v[2 * q], v1 = v[2 * q + 1];
+    const uint32_t h = cvt_pk_bf16(v0, v1);
+    const float r0 = v0 - __uint_as_float(h << 16), r1 = v1 - __uint_as_float(h & 0xFFFF0000u);
+    const uint32_t mm = cvt_pk_bf16(r0, r1);
+    const float s0 = r0 - __uint_as_float(mm << 16), s1 = r1 - __uint_as_float(mm & 0xFFFF0000u);
+    H[q] = h;
+    M[q] = mm;
+    O[q] = cvt_pk_bf16(s0, s1);
+  }
+  hi = __builtin_bit_cast(bf16x8, H);
+  mid = __builtin_bit_cast(bf16x8, M);
+  lo = __builtin_bit_cast(bf16x8, O);
+}
+
+// Wavefront wv owns 32 points; lane (p, h) holds point p's x at the K
+// indices kidx(h, s), s < DP/2: the K half h (float32 products, 32x32x2
+// fragments) or, with B3, the 8-wide half h of every 16-wide K step
+// (32x32x16 bf16 fragments).  B3 blocks have eight wavefronts (the chunk
+// image with its bf16 pieces leaves LDS for one block per CU).
+template <int DP, bool B3>
+GEEK_D constexpr int e2lsh_kidx(int h, int s) {
+  return B3 ? (s / 8) * 16 + h * 8 + (s % 8) : h * (DP / 2) + s;
+}
+
+template <int DP, bool B3>
+__global__ __launch_bounds__(B3 ? 2 * H_THREADS : H_THREADS, B3 ? 1 : 2) void k_e2lsh(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n, const float* __restrict__ chunks, int m,
     int L, float w, int tpc, uint32_t* __restrict__ keys, uint32_t* __restrict__ key_fp,
     int32_t* __restrict__ codes_out, unsigned long long* __restrict__ n_fixup, int32_t* st) {
-  using C = E2Chunk<DP>;
+  using C = E2Chunk<DP, B3>;
   constexpr int S = DP / 2;
   constexpr int STR = C::STR;
-  // the chunk's rows of a, then per row b, the two factors of the
-  // certification radius tau = t1 * |x| + t0, |a_p| rounded up, and the
-  // chunk's largest |a_p| and |b_p| (layout of E2Chunk)
+  constexpr int NT = B3 ? 2 * H_THREADS : H_THREADS;  // threads per block
+  constexpr int BPTS = NT / 2;                        // points per block
+  constexpr int DMA_ROUNDS = (C::PIECES + NT - 1) / NT;
+  // the chunk's rows of a (and their bf16 pieces), then per row b, the two
+  // factors of the certification radius tau = t1 * |x| + t0, |a_p| rounded
+  // up, and the chunk's largest |a_p| and |b_p| (layout of E2Chunk)
   __shared__ __attribute__((aligned(16))) float lds_chunk[C::L_FLOATS];
   float* const lds_a = lds_chunk;
-  float* const lds_b = lds_chunk + H_BC * STR;
+  float* const lds_b = lds_chunk + C::L_INFO;
   float* const lds_t1 = lds_b + H_BC;
   float* const lds_t0 = lds_t1 + H_BC;
   float* const lds_an = lds_t0 + H_BC;
   float* const lds_qb = lds_an + H_BC;
   // codes of a point are H_CS ints apart: the epilogue's stores (one row,
   // 32 points per instruction) then fall into distinct banks
-  __shared__ int lds_code[H_BN * H_CS];
+  __shared__ int lds_code[BPTS * H_CS];
 
   const int P = m * L;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int p = lane & 31, h = lane >> 5;
-  const int64_t i0 = (int64_t)blockIdx.x * H_BN;
+  const int64_t i0 = (int64_t)blockIdx.x * BPTS;
   const int64_t i = i0 + wv * 32 + p;
   const bool valid = i < n;
   const float* xr = X + (valid ? i : 0) * ldx;
@@ -206,16 +284,20 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   auto issue_chunk = [&](int c) {
     const float* g = chunks + (int64_t)c * C::G_FLOATS;
 #pragma unroll
-    for (int u = 0; u < C::DMA_ROUNDS; ++u) {
-      const int q0 = u * H_THREADS + wu * 64;  // wave-uniform first piece
+    for (int u = 0; u < DMA_ROUNDS; ++u) {
+      const int q0 = u * NT + wu * 64;  // wave-uniform first piece
       const int q = q0 + lane;
       if (q0 < C::PIECES && q < C::PIECES) {
         int src;
         if (q < C::A_PIECES) {
           const int r = q / (C::CH + 1), pc = q % (C::CH + 1);
           src = r * DP + (pc < C::CH ? pc * 4 : 0);
+        } else if (q < C::A_PIECES + C::NPC * C::P_PIECES) {
+          const int qq = q - C::A_PIECES, seg = qq / C::P_PIECES, rr = qq % C::P_PIECES;
+          const int r = rr / (C::PCH + 1), pc = rr % (C::PCH + 1);
+          src = C::G_A + seg * C::G_P + r * (DP / 2) + (pc < C::PCH ? pc * 4 : 0);
         } else {
-          src = H_BC * DP + (q - C::A_PIECES) * 4;
+          src = C::G_A + C::NPC * C::G_P + (q - C::A_PIECES - C::NPC * C::P_PIECES) * 4;
         }
         __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(g + src),
                                          reinterpret_cast<void*>(lds_chunk + q0 * 4), 16, 0, 0);
@@ -228,7 +310,7 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
   float xb[S];
 #pragma unroll
   for (int q = 0; q < S; q += 4) {
-    const int t0 = h * S + q;
+    const int t0 = e2lsh_kidx<DP, B3>(h, q);
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
     if (valid) {
       if (vec4 && t0 + 3 < d) {
@@ -281,49 +363,110 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       acc0[g4 * 4] = b0.x, acc0[g4 * 4 + 1] = b0.y, acc0[g4 * 4 + 2] = b0.z, acc0[g4 * 4 + 3] = b0.w;
       acc1[g4 * 4] = b1.x, acc1[g4 * 4 + 1] = b1.y, acc1[g4 * 4 + 2] = b1.z, acc1[g4 * 4 + 3] = b1.w;
     }
-    const float* a0p = lds_a + p * STR + h * S;
-    const float* a1p = a0p + 32 * STR;
-    // A fragments: four K steps per 16-byte LDS read (rows STR = DP + 4
-    // floats apart, so eight consecutive lanes cover all banks)
-    // blocks of H_KB / 2 steps (H_KB products per output) accumulate from
-    // zero and are then added to the running sums
-    if (rows_used > 32) {
+    if constexpr (B3) {
+      // K step ks: x's three bf16 pieces for this lane's 8 K indices, split
+      // here from the float32 copy (kept for the float64 checks), and a's
+      // pieces from LDS; the small products first, hi*hi last, in a fresh
+      // accumulator that is then added to the running sums
+      const __bf16* pa = reinterpret_cast<const __bf16*>(lds_chunk + C::L_A);
+      auto afrag = [&](int seg, int row, int ks) -> bf16x8 {
+        return *reinterpret_cast<const bf16x8*>(pa + (seg * C::L_P + row * C::PSTR) * 2 + ks * 16 + h * 8);
+      };
+      const f32x16 zero = {};
+      if (rows_used > 32) {
 #pragma unroll
-      for (int s0 = 0; s0 < S; s0 += H_KB / 2) {
-        f32x16 b0 = {}, b1 = {};
+        for (int ks = 0; ks < DP / 16; ++ks) {
+          bf16x8 xh, xm, xl;
+          split3_bf16(xb + ks * 8, xh, xm, xl);
+          // one row block's chain after the other: a dependent MFMA takes its
+          // accumulator from the previous one without a stall, and only one
+          // block's pieces are live at a time
+          f32x16 b0, b1;
+          {
+            const bf16x8 ah = afrag(0, p, ks), am = afrag(1, p, ks), al = afrag(2, p, ks);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, xm, zero, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl, b0, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh, b0, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xm, b0, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, xh, b0, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh, b0, 0, 0, 0);
+          }
+          {
+            const bf16x8 ah = afrag(0, p + 32, ks), am = afrag(1, p + 32, ks), al = afrag(2, p + 32, ks);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, xm, zero, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xl, b1, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, xh, b1, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xm, b1, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, xh, b1, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, xh, b1, 0, 0, 0);
+          }
 #pragma unroll
-        for (int s = s0; s < s0 + H_KB / 2; s += 4) {
-          const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
-          const float4 a1 = *reinterpret_cast<const float4*>(a1p + s);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], b0, 0, 0, 0);
-          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, xb[s], b1, 0, 0, 0);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], b0, 0, 0, 0);
-          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, xb[s + 1], b1, 0, 0, 0);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], b0, 0, 0, 0);
-          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, xb[s + 2], b1, 0, 0, 0);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], b0, 0, 0, 0);
-          b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, xb[s + 3], b1, 0, 0, 0);
+          for (int r = 0; r < 16; ++r) {
+            acc0[r] += b0[r];
+            acc1[r] += b1[r];
+          }
         }
+      } else {  // the second 32-row block holds no projection of this chunk
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          acc0[r] += b0[r];
-          acc1[r] += b1[r];
+        for (int ks = 0; ks < DP / 16; ++ks) {
+          bf16x8 xh, xm, xl;
+          split3_bf16(xb + ks * 8, xh, xm, xl);
+          const bf16x8 ah0 = afrag(0, p, ks), am0 = afrag(1, p, ks), al0 = afrag(2, p, ks);
+          f32x16 b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am0, xm, zero, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, xl, b0, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, xh, b0, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, xm, b0, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am0, xh, b0, 0, 0, 0);
+          b0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah0, xh, b0, 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc0[r] += b0[r];
         }
       }
-    } else {  // the second 32-row block holds no projection of this chunk
-#pragma unroll
-      for (int s0 = 0; s0 < S; s0 += H_KB / 2) {
-        f32x16 b0 = {};
-#pragma unroll
-        for (int s = s0; s < s0 + H_KB / 2; s += 4) {
-          const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], b0, 0, 0, 0);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], b0, 0, 0, 0);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], b0, 0, 0, 0);
-          b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], b0, 0, 0, 0);
+    } else {
+      const float* a0p = lds_a + p * STR + h * S;
+      const float* a1p = a0p + 32 * STR;
+      // A fragments: four K steps per 16-byte LDS read (rows STR = DP + 4
+      // floats apart, so eight consecutive lanes cover all banks)
+      // blocks of H_KB / 2 steps (H_KB products per output) accumulate from
+      // zero and are then added to the running sums
+      if (rows_used > 32) {
+  #pragma unroll
+        for (int s0 = 0; s0 < S; s0 += H_KB / 2) {
+          f32x16 b0 = {}, b1 = {};
+  #pragma unroll
+          for (int s = s0; s < s0 + H_KB / 2; s += 4) {
+            const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
+            const float4 a1 = *reinterpret_cast<const float4*>(a1p + s);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], b0, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.x, xb[s], b1, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], b0, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.y, xb[s + 1], b1, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], b0, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.z, xb[s + 2], b1, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], b0, 0, 0, 0);
+            b1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1.w, xb[s + 3], b1, 0, 0, 0);
+          }
+  #pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            acc0[r] += b0[r];
+            acc1[r] += b1[r];
+          }
         }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc0[r] += b0[r];
+      } else {  // the second 32-row block holds no projection of this chunk
+  #pragma unroll
+        for (int s0 = 0; s0 < S; s0 += H_KB / 2) {
+          f32x16 b0 = {};
+  #pragma unroll
+          for (int s = s0; s < s0 + H_KB / 2; s += 4) {
+            const float4 a0 = *reinterpret_cast<const float4*>(a0p + s);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.x, xb[s], b0, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.y, xb[s + 1], b0, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.z, xb[s + 2], b0, 0, 0, 0);
+            b0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0.w, xb[s + 3], b0, 0, 0, 0);
+          }
+  #pragma unroll
+          for (int r = 0; r < 16; ++r) acc0[r] += b0[r];
+        }
       }
     }
     const int pl = wv * 32 + p;  // point within block
@@ -388,7 +531,7 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
         double part = 0.0;
         if (fl) {
           // four independent FMA chains (k mod 4), then summed pairwise
-          const float* ap = lds_a + row * STR + h * S;
+          const float* ap = lds_a + row * STR;
           double p4[4] = {0.0, 0.0, 0.0, 0.0};
           // the row is read sixteen attributes at a time: four LDS reads in
           // flight per wait
@@ -396,7 +539,8 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
           for (int k0 = 0; k0 < S; k0 += 16) {
             float4 av[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) av[u] = *reinterpret_cast<const float4*>(ap + k0 + 4 * u);
+            for (int u = 0; u < 4; ++u)
+              av[u] = *reinterpret_cast<const float4*>(ap + e2lsh_kidx<DP, B3>(h, k0 + 4 * u));
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const int k = k0 + 4 * u;
@@ -440,11 +584,11 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
     // ---- pack the m codes of every (table, point) into a 128-bit key (m = 10
     // at compile time; more compile-time cases push the kernel past its
     // register budget)
-    const int64_t np = (n - i0) < H_BN ? (n - i0) : H_BN;
-    const int pk = tid % H_BN;  // this thread's point; tables tid / H_BN, + 2, ...
+    const int64_t np = (n - i0) < BPTS ? (n - i0) : BPTS;
+    const int pk = tid % BPTS;  // this thread's point; tables tid / BPTS, + 2, ...
     if (keys && pk < np) {
       const int64_t ii = i0 + pk;
-      const int t0 = tid / H_BN, step = H_THREADS / H_BN;
+      const int t0 = tid / BPTS, step = NT / BPTS;
       uint32_t orr;
 #define GEEK_PACK(MM) pack_keys<MM>(lds_code, pk, t0, step, ntab, tb, m, B, code_off, n, ii, keys, key_fp)
       if (m == 10)
@@ -455,7 +599,7 @@ __global__ __launch_bounds__(H_THREADS, 2) void k_e2lsh(
       if (B < 32 && (orr >> B) != 0u) set_status(st, GEEK_ERR_RANGE);
     }
     if (codes_out) {
-      for (int q = tid; q < H_BN * rows_used; q += H_THREADS) {
+      for (int q = tid; q < BPTS * rows_used; q += NT) {
         const int pp = q / rows_used, row = q % rows_used;
         if (pp < np) codes_out[(i0 + pp) * P + p0 + row] = lds_code[pp * H_CS + row];
       }
@@ -620,10 +764,10 @@ static size_t e2lsh_chunk_floats(const geek_hash_job& J) {
   if (J.m < 1 || J.m > H_BC) return 0;
   const int nchunks = ceil_div(J.L, H_BC / J.m);
   switch (pick_dp_h(J.d)) {
-    case 32: return (size_t)nchunks * E2Chunk<32>::G_FLOATS;
-    case 64: return (size_t)nchunks * E2Chunk<64>::G_FLOATS;
-    case 128: return (size_t)nchunks * E2Chunk<128>::G_FLOATS;
-    default: return (size_t)nchunks * E2Chunk<256>::G_FLOATS;
+    case 32: return (size_t)nchunks * E2Chunk<32, true>::G_FLOATS;
+    case 64: return (size_t)nchunks * E2Chunk<64, true>::G_FLOATS;
+    case 128: return (size_t)nchunks * E2Chunk<128, true>::G_FLOATS;
+    default: return (size_t)nchunks * E2Chunk<256, false>::G_FLOATS;
   }
 }
 
@@ -639,22 +783,26 @@ static int32_t launch_e2lsh(const geek_hash_job& J, float* chunks, uint32_t* key
                             int32_t* codes, unsigned long long* nfix, int32_t* st, hipStream_t s) {
   const int tpc = H_BC / J.m;  // whole tables per 64-row chunk
   const int nchunks = ceil_div(J.L, tpc);
-  const int grid = ceil_div(J.n, H_BN);
   switch (pick_dp_h(J.d)) {
-#define GEEK_H_CASE(DPV)                                                                                   \
-  case DPV:                                                                                                \
-    hipLaunchKernelGGL((k_e2lsh_prep<DPV>), dim3(nchunks), dim3(H_THREADS), 0, s, J.A, J.b, J.d, J.m, J.L, \
-                       J.w, tpc, chunks);                                                                  \
+#define GEEK_H_CASE(DPV, B3V)                                                                              \
+  case DPV: {                                                                                              \
+    constexpr int nt = B3V ? 2 * H_THREADS : H_THREADS;                                                    \
+    hipLaunchKernelGGL((k_e2lsh_prep<DPV, B3V>), dim3(nchunks), dim3(H_THREADS), 0, s, J.A, J.b, J.d, J.m, \
+                       J.L, J.w, tpc, chunks);                                                             \
+    const int64_t grid = ceil_div(J.n, (int64_t)nt / 2);                                                   \
     if (grid == 0) return GEEK_OK;                                                                         \
     prof_begin(GEEK_PROF_E2LSH, s);                                                                        \
-    hipLaunchKernelGGL((k_e2lsh<DPV>), dim3(grid), dim3(H_THREADS), 0, s, J.X, J.ldx, J.d, J.n, chunks,    \
-                       J.m, J.L, J.w, tpc, keys, key_fp, codes, nfix, st);                                 \
+    hipLaunchKernelGGL((k_e2lsh<DPV, B3V>), dim3(grid), dim3(nt), 0, s, J.X, J.ldx, J.d, J.n, chunks, J.m, \
+                       J.L, J.w, tpc, keys, key_fp, codes, nfix, st);                                      \
     prof_end(GEEK_PROF_E2LSH, s);                                                                          \
-    break;
-    GEEK_H_CASE(32)
-    GEEK_H_CASE(64)
-    GEEK_H_CASE(128)
-    GEEK_H_CASE(256)
+    break;                                                                                                 \
+  }
+    // d <= 128: products from bf16 pieces; d = 256: float32 products (the
+    // chunk image with bf16 pieces would not fit in LDS)
+    GEEK_H_CASE(32, true)
+    GEEK_H_CASE(64, true)
+    GEEK_H_CASE(128, true)
+    GEEK_H_CASE(256, false)
 #undef GEEK_H_CASE
     default:
       return GEEK_ERR_UNSUPPORTED;
