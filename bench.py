@@ -231,15 +231,18 @@ def main():
     ctr_bf16 = out_bf16["counters"].cpu().numpy().tolist()
     a_bf16 = out_bf16["assign"]
     sse_bf16 = float(out_bf16["sse"].item())
-    ms_fp32, st_fp32, out_fp32, prof_fp32 = run(L.GEEK_PREC_FP32, args.fp32_steps, 1, True)
-    log(f"fp32 path {ms_fp32:.2f} ms/step stages {np.round(st_fp32, 2)}")
-    same = bool(torch.equal(a_bf16, out_fp32["assign"])) and sse_bf16 == float(out_fp32["sse"].item())
-
     flops = 2.0 * n * d * k
     scan_ms = prof_bf16["assign_scan"][0]
     ach = flops / (scan_ms * 1e-3) / 1e12
-    scan32_ms = prof_fp32["assign_scan"][0]
-    ach32 = flops / (scan32_ms * 1e-3) / 1e12
+    fp32 = None  # the float32 path for comparison (--fp32-steps 0 skips it)
+    same = None
+    if args.fp32_steps > 0:
+        ms_fp32, st_fp32, out_fp32, prof_fp32 = run(L.GEEK_PREC_FP32, args.fp32_steps, 1, True)
+        log(f"fp32 path {ms_fp32:.2f} ms/step stages {np.round(st_fp32, 2)}")
+        same = bool(torch.equal(a_bf16, out_fp32["assign"])) and sse_bf16 == float(out_fp32["sse"].item())
+        scan32_ms = prof_fp32["assign_scan"][0]
+        ach32 = flops / (scan32_ms * 1e-3) / 1e12
+        fp32 = (ms_fp32, st_fp32, scan32_ms, ach32)
     # per step: launch average x launches per step (two each when pipelined);
     # the rates use each kernel's own busy time (overlapped work counted once)
     hash_ms = prof_bf16["e2lsh"][0] * prof_bf16["e2lsh"][1] / args.steps
@@ -277,10 +280,11 @@ def main():
                      "frac": ach / PEAK_BF16, "traffic": measured_traffic(),
                      "kernel": "k_scan<ModeBF16,128>", "avg_launch_ms": scan_ms,
                      "flop_per_launch": flops},
-        "fp32_path": {"value": n / (ms_fp32 * 1e-3), "ms_per_step": ms_fp32,
-                      "stages_ms": dict(zip(stage_names, st_fp32.round(3).tolist())),
-                      "scan_ms": scan32_ms, "scan_tflops": ach32, "scan_frac": ach32 / PEAK_FP32},
-        "speedup_bf16_over_fp32": ms_fp32 / ms_bf16,
+        "fp32_path": None if fp32 is None else {
+            "value": n / (fp32[0] * 1e-3), "ms_per_step": fp32[0],
+            "stages_ms": dict(zip(stage_names, fp32[1].round(3).tolist())),
+            "scan_ms": fp32[2], "scan_tflops": fp32[3], "scan_frac": fp32[3] / PEAK_FP32},
+        "speedup_bf16_over_fp32": None if fp32 is None else fp32[0] / ms_bf16,
         "stages_ms": dict(zip(stage_names, st_bf16.round(3).tolist())),
         "pipelined_tables": bool(args.pipeline),
         "kernels": {"e2lsh_ms": hash_ms, "e2lsh_tflops": hash_tf, "e2lsh_frac_fp32": hash_tf / PEAK_FP32,
