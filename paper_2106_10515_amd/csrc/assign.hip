@@ -268,47 +268,12 @@ __global__ void k_clock_now(unsigned long long* dst) {
 }
 
 // ---------------------------------------------------------------- float64 checks
-GEEK_D double d64(const float* __restrict__ xr, const double* __restrict__ cr, int d) {
-  double acc = 0.0;
-  int t = 0;
-  // 16-byte loads when both rows are aligned (whole cache lines per lane
-  // instead of one scalar per iteration); the summation order is unchanged
-  if (((reinterpret_cast<uintptr_t>(xr) | reinterpret_cast<uintptr_t>(cr)) & 15) == 0) {
-    for (; t + 4 <= d; t += 4) {
-      const float4 xv = *reinterpret_cast<const float4*>(xr + t);
-      const double2 c0 = *reinterpret_cast<const double2*>(cr + t);
-      const double2 c1 = *reinterpret_cast<const double2*>(cr + t + 2);
-      double delta = __dadd_rn((double)xv.x, -c0.x);
-      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
-      delta = __dadd_rn((double)xv.y, -c0.y);
-      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
-      delta = __dadd_rn((double)xv.z, -c1.x);
-      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
-      delta = __dadd_rn((double)xv.w, -c1.y);
-      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
-    }
-  }
-  for (; t < d; ++t) {
-    const double delta = __dadd_rn((double)xr[t], -cr[t]);
-    acc = __dadd_rn(acc, __dmul_rn(delta, delta));
-  }
-  return acc;
-}
-
 // Categorical attributes of row i that differ from seed j's modes.
 GEEK_D int mismatches(const Het& het, int64_t i, int j) {
   int mm = 0;
   for (int a = 0; a < het.n_cat; ++a)
     mm += ((uint32_t)het.cat[i * het.n_cat + a] != het.mode[(int64_t)j * het.n_cat + a]) ? 1 : 0;
   return mm;
-}
-
-// D_num + gamma * mismatches, in that float64 order (reference formula).
-GEEK_D double d64h(const float* __restrict__ xr, const double* __restrict__ cr, int d, const Het& het,
-                   int64_t i, int j) {
-  const double dn = d64(xr, cr, d);
-  if (!het.cat) return dn;
-  return __dadd_rn(dn, __dmul_rn(het.gamma, (double)mismatches(het, i, j)));
 }
 
 __device__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
@@ -318,47 +283,104 @@ __device__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
 }
 
 // Candidate records: rstride int32 per row (count, then seed indices); the
-// BF16 first pass writes 2 per row, the windows RECW.
-__global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
-                           const double* __restrict__ C, int k, Het het, int64_t n_rows,
-                           const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
-                           const int32_t* __restrict__ rec, int rstride, int32_t* __restrict__ assign,
-                           double* __restrict__ dist, uint32_t* __restrict__ esc,
-                           uint32_t* __restrict__ esc_count, unsigned long long* __restrict__ ctr,
-                           int ctr_rows) {
+// BF16 first pass writes 2 per row, the windows RECW.  Eight lanes per row:
+// lane e loads attributes t0 + 4e .. t0 + 4e + 3 of the row and of the
+// candidate centroid for t0 = 0, 32, ... (one x cache line and two centroid
+// lines per step, coalesced over the eight lanes), forms the rounded
+// squared differences, and lane 0 of the eight adds the 32 squares of a step
+// in attribute order from LDS: D = sum over t = 0..d-1 in order of
+// (x_t - c_t)^2, each difference, square and sum rounded to float64 (plus
+// gamma * mismatches for heterogeneous rows).  With a lane per row, every
+// load touched 64 cache lines and the lines were evicted between the row's
+// steps.
+constexpr int FZ_ROWS = 8;   // rows per wavefront and step
+constexpr int FZ_STEP = 32;  // attributes per step
+__global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
+                                                  const double* __restrict__ C, int k, Het het, int64_t n_rows,
+                                                  const uint32_t* __restrict__ rows,
+                                                  const uint32_t* __restrict__ rows_count,
+                                                  const int32_t* __restrict__ rec, int rstride,
+                                                  int32_t* __restrict__ assign, double* __restrict__ dist,
+                                                  uint32_t* __restrict__ esc, uint32_t* __restrict__ esc_count,
+                                                  unsigned long long* __restrict__ ctr, int ctr_rows) {
+  __shared__ double sq[4][FZ_ROWS][FZ_STEP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 3, e = lane & 7;  // row slot, lane within the row
   const int64_t count = rows ? (int64_t)*rows_count : n_rows;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t start = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t iters = (count + stride - 1) / stride;
+  const int64_t stride = (int64_t)gridDim.x * 4 * FZ_ROWS;
+  const bool xal = ((reinterpret_cast<uintptr_t>(X) | (uintptr_t)(ldx * 4)) & 15) == 0;
+  const bool cal = ((reinterpret_cast<uintptr_t>(C) | (uintptr_t)(d * 8)) & 15) == 0;
   unsigned long long nrow = 0, ncand = 0;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t pos = start + it * stride;
-    if (pos >= count) continue;
-    const int64_t i = rows ? (int64_t)rows[pos] : pos;
-    const int32_t* rr = rec + pos * rstride;
-    const int c = rr[0];
-    if (c <= 0) {  // window overflow (or no finite candidate): escalate
-      const uint32_t q = atomicAdd(esc_count, 1u);
-      esc[q] = (uint32_t)i;
-      continue;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wv) * FZ_ROWS; base < count; base += stride) {
+    const int64_t pos = base + g;
+    const bool live = pos < count;
+    const int64_t i = live ? (rows ? (int64_t)rows[pos] : pos) : 0;
+    const int32_t* rr = rec + (live ? pos : 0) * rstride;
+    int c = live ? rr[0] : 0;
+    if (live && c <= 0) {  // window overflow (or no finite candidate): escalate
+      if (e == 0) esc[atomicAdd(esc_count, 1u)] = (uint32_t)i;
+      c = 0;
     }
+    int maxc = c;  // the wavefront walks the largest candidate count of its rows
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o));
     double best = INFINITY;
     int bj = 0x7fffffff;
     const float* xr = X + i * ldx;
-    for (int q = 0; q < c; ++q) {
-      const int j = rr[1 + q];
-      if ((unsigned)j >= (unsigned)k) continue;
-      const double D = d64h(xr, C + (int64_t)j * d, d, het, i, j);
-      if (D < best || (D == best && j < bj)) {
-        best = D;
-        bj = j;
+    for (int q = 0; q < maxc; ++q) {
+      const int j = q < c ? rr[1 + q] : -1;
+      const bool act = j >= 0 && j < k;
+      const double* cr = C + (int64_t)(act ? j : 0) * d;
+      double acc = 0.0;
+      for (int t0 = 0; t0 < d; t0 += FZ_STEP) {
+        const int t = t0 + 4 * e;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (act && t < d) {
+          float xs[4];
+          double cs[4];
+          if (xal && cal && t + 4 <= d) {
+            const float4 xv = *reinterpret_cast<const float4*>(xr + t);
+            const double2 c0 = *reinterpret_cast<const double2*>(cr + t);
+            const double2 c1 = *reinterpret_cast<const double2*>(cr + t + 2);
+            xs[0] = xv.x, xs[1] = xv.y, xs[2] = xv.z, xs[3] = xv.w;
+            cs[0] = c0.x, cs[1] = c0.y, cs[2] = c1.x, cs[3] = c1.y;
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              xs[u] = t + u < d ? xr[t + u] : 0.f;
+              cs[u] = t + u < d ? cr[t + u] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double delta = __dadd_rn((double)xs[u], -cs[u]);
+            s4[u] = __dmul_rn(delta, delta);
+          }
+        }
+        *reinterpret_cast<double2*>(&sq[wv][g][4 * e]) = make_double2(s4[0], s4[1]);
+        *reinterpret_cast<double2*>(&sq[wv][g][4 * e + 2]) = make_double2(s4[2], s4[3]);
+        // the row's squares in attribute order (a wavefront's LDS accesses
+        // complete in order, so the eight lanes' stores are visible here)
+        if (e == 0 && act) {
+          const int lim = d - t0 < FZ_STEP ? d - t0 : FZ_STEP;
+          for (int u = 0; u < lim; ++u) acc = __dadd_rn(acc, sq[wv][g][u]);
+        }
+      }
+      if (e == 0 && act) {
+        const double D = het.cat ? __dadd_rn(acc, __dmul_rn(het.gamma, (double)mismatches(het, i, j))) : acc;
+        if (D < best || (D == best && j < bj)) {
+          best = D;
+          bj = j;
+        }
       }
     }
-    if (bj == 0x7fffffff) bj = 0;
-    assign[i] = bj;
-    dist[i] = best;
-    nrow += 1;
-    ncand += (unsigned long long)c;
+    if (e == 0 && live && c > 0) {
+      if (bj == 0x7fffffff) bj = 0;
+      assign[i] = bj;
+      dist[i] = best;
+      nrow += 1;
+      ncand += (unsigned long long)c;
+    }
   }
   if (ctr) {
     block_add_u64(ctr + ctr_rows, nrow);
@@ -370,7 +392,7 @@ __global__ void k_finalize(const float* __restrict__ X, int64_t ldx, int d,
 // ties.  A workgroup takes FB_R rows and a range of FB_C-seed tiles; each
 // thread holds a 4 x 4 block of (row, seed) sums with both operands staged in
 // LDS, so one read of a seed row from L2 serves FB_R rows.  Every sum runs
-// over t = 0..d-1 in order with the operations of d64 (the zero padding of
+// over t = 0..d-1 in order with the operations of k_finalize (the zero padding of
 // t >= d adds +0.0, which leaves a sum of squares unchanged), so the values
 // are those of the reference formula.  With fewer row groups than workgroups
 // the seed tiles of a group are split over up to FB_SPLIT workgroups, whose
@@ -879,9 +901,9 @@ static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, h
                           const unsigned long long* t0) {
   AssignWs& W = C.W;
   unsigned long long* ctr = W.ctr;
-  const int nb_rows = ceil_div(J.n, 256);
+  const int fz_grid = (int)std::min<int64_t>(ceil_div(J.n, 4 * FZ_ROWS), 8192);
   const int rstride = J.precision == GEEK_PREC_BF16 ? RECW_T2 : RECW;
-  hipLaunchKernelGGL(k_finalize, dim3(nb_rows), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
+  hipLaunchKernelGGL(k_finalize, dim3(fz_grid), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
                      nullptr, nullptr, W.rec, rstride, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
   // rows with several first-pass candidates: float32 rescan of those rows with
   // a wider window (persistent grids, at most one row tile / block per group)
