@@ -241,12 +241,14 @@ def test_bucketize_full_table_with_fingerprint_collision():
     _compare(api, keys.reshape(-1), n, 1, 2, 0, 2, [keys], "full table, fingerprint collision")
 
 
-def test_bucketize_with_the_hash_fingerprints():
+@pytest.mark.parametrize("m", [8, 10])
+def test_bucketize_with_the_hash_fingerprints(m):
     # geek_hash can write each key's bucketize fingerprint beside it; the
     # buckets formed from those fingerprints equal the ones formed from the
-    # keys alone and the oracle's
+    # keys alone and the oracle's (m = 10 takes the compile-time packing,
+    # other m the run-time one)
     api = gpu_api()
-    n, d, m, L = 50_000, 32, 8, 4
+    n, d, L = 50_000, 32, 4
     X, _, _ = dense_mixture(n, d, 40, -10, 10, 1.0, "equal", 3)
     w = 4.0 * math.sqrt(d)
     A, b = e2lsh_params(m * L, d, w, 3)
@@ -258,6 +260,12 @@ def test_bucketize_with_the_hash_fingerprints():
     for t in range(L):
         for i in g.integers(0, n, 64):
             assert int(fh[t, i]) == _bin_hash([int(x) for x in kh[t, i]]), (t, i)
+        # equal keys carry equal fingerprints
+        _, inv = np.unique(kh[t], axis=0, return_inverse=True)
+        inv = inv.ravel()
+        first = np.full(inv.max() + 1, -1, np.int64)
+        first[inv[::-1]] = np.arange(n)[::-1]
+        assert np.array_equal(fh[t], fh[t][first[inv]]), t
     announce("bucketize with and without the hash's fingerprints")
     a = api.bucketize(keys, n, L, 4, n * 4, 4, key_fp=fp)
     c = api.bucketize(keys, n, L, 4, n * 4, 4)
