@@ -239,8 +239,17 @@ __global__ void k_cprep(const double* __restrict__ C, int k, int d, int k_pad, i
   }
 }
 
+// Two workgroups per CU (at most 256 registers a wavefront) for the BF16
+// first pass of point rows up to 128 attributes, whose stage pipeline keeps
+// two blocks' accumulators live; the compiler would otherwise go just past
+// 256 and halve the occupancy.
+template <class M, int DP, bool HET, int NCB>
+constexpr int scan_min_blocks() {
+  return (std::is_same<M, ModeBF16>::value && !HET && NCB == 2 && DP <= 128) ? 2 : 1;
+}
+
 template <class M, int DP, bool HET, int NCB, int NBUF, bool T2, bool WIDE>
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan(
+__global__ __launch_bounds__(SCAN_THREADS, (scan_min_blocks<M, DP, HET, NCB>())) void k_scan(
     const float* __restrict__ X, int64_t ldx, int d, int64_t n_rows,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
     const typename M::ce* __restrict__ cl, const float* __restrict__ nc, int k_pad,

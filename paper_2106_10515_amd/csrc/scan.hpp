@@ -383,6 +383,11 @@ __device__ __forceinline__ void scan_tiles(
       }
       blk[cb] = a1[cb] != a1_prev ? gb : blk[cb];
     };
+    // T2 fast path: the second block's accumulators of a stage are carried
+    // into the next stage, whose first block's products run while their
+    // values enter the running best two (the same order of updates)
+    f32x16 pendB[T2 ? NCB : 1];
+    int pend_g = -1;
     // one stage of SCAN_BC centroids from buffer `cur` (a compile-time
     // constant), with the next stage loading into the other buffer
     auto stage = [&](auto curc, const int c0, const int it) {
@@ -420,23 +425,57 @@ __device__ __forceinline__ void scan_tiles(
       // second block's products are still in the matrix pipe
       if constexpr (T2 && PF && !HET && SCAN_BC == 64) {
         f32x16 accA[NCB], accB[NCB];
-        f32x16 initA, initB;
+        {
+          f32x16 initA;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          initA[r] = lds_nc[cur][(r >> 2) * 8 + h * 4 + (r & 3)];
-          initB[r] = lds_nc[cur][32 + (r >> 2) * 8 + h * 4 + (r & 3)];
+          for (int r = 0; r < 16; ++r) initA[r] = lds_nc[cur][(r >> 2) * 8 + h * 4 + (r & 3)];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) accA[cb] = initA;
         }
+        if (pend_g >= 0) {
+          // block A's products step by step, each followed by its share of
+          // the previous stage's block B values
+          float a1q[NCB];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          accA[cb] = initA;
-          accB[cb] = initB;
+          for (int cb = 0; cb < NCB; ++cb) a1q[cb] = a1[cb];
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) accA[cb] = M::mma(af[s], xb[cb][s], accA[cb]);
+#pragma unroll
+            for (int q = 8 * s / S; q < 8 * (s + 1) / S; ++q) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) {
+                const int r = 2 * q;
+                const float u = __uint_as_float((__float_as_uint(pendB[cb][r]) & ~15u) | (uint32_t)r);
+                const float v = __uint_as_float((__float_as_uint(pendB[cb][r + 1]) & ~15u) | (uint32_t)(r + 1));
+                const float mid = __builtin_amdgcn_fmed3f(a1[cb], u, v);
+                a1[cb] = fmaxf(fmaxf(a1[cb], u), v);
+                a2[cb] = fmaxf(a2[cb], mid);
+              }
+            }
+            if (s + 1 < S) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) asm volatile("" : "+v"(af[s + 1]) : "v"(a1[cb]), "v"(a2[cb]));
+            }
+          }
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) blk[cb] = a1[cb] != a1q[cb] ? pend_g : blk[cb];
+        } else {
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) accA[cb] = M::mma(af[s], xb[cb][s], accA[cb]);
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) accA[cb] = M::mma(af[s], xb[cb][s], accA[cb]);
 #pragma unroll
         for (int s = 0; s < S; ++s) af[s] = afrag_rb(1, s);
+        {
+          f32x16 initB;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) initB[r] = lds_nc[cur][32 + (r >> 2) * 8 + h * 4 + (r & 3)];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) accB[cb] = initB;
+        }
         const int g0 = it * (SCAN_BC / 32);
         // block B's products step by step, each step followed by its share
         // of block A's eight value pairs per column block: the vector
@@ -470,7 +509,8 @@ __device__ __forceinline__ void scan_tiles(
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) blk[cb] = a1[cb] != a1p[cb] ? g0 : blk[cb];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) t2_update(cb, accB[cb], g0 + 1);
+        for (int cb = 0; cb < NCB; ++cb) pendB[cb] = accB[cb];
+        pend_g = g0 + 1;
       } else
 #pragma unroll 1
       for (int rb = 0; rb < SCAN_BC / 32; ++rb) {
@@ -637,6 +677,13 @@ __device__ __forceinline__ void scan_tiles(
           c0 += SCAN_BC;
           ++it;
         }
+      }
+    }
+
+    if constexpr (T2) {  // the last stage's second block
+      if (pend_g >= 0) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) t2_update(cb, pendB[cb], pend_g);
       }
     }
 
