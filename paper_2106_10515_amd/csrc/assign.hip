@@ -285,14 +285,118 @@ GEEK_D int mismatches(const Het& het, int64_t i, int j) {
   return mm;
 }
 
+GEEK_D double d64(const float* __restrict__ xr, const double* __restrict__ cr, int d) {
+  double acc = 0.0;
+  int t = 0;
+  // 16-byte loads when both rows are aligned; the summation order is
+  // unchanged.  32 attributes at a time: the 24 loads of one x cache line
+  // and two centroid lines are issued before the first use, one memory round
+  // trip per 32 attributes
+  if (((reinterpret_cast<uintptr_t>(xr) | reinterpret_cast<uintptr_t>(cr)) & 15) == 0) {
+    for (; t + 32 <= d; t += 32) {
+      float4 xv[8];
+      double2 cv[16];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = *reinterpret_cast<const float4*>(xr + t + 4 * u);
+#pragma unroll
+      for (int u = 0; u < 16; ++u) cv[u] = *reinterpret_cast<const double2*>(cr + t + 2 * u);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float xs[4] = {xv[u].x, xv[u].y, xv[u].z, xv[u].w};
+        const double cs[4] = {cv[2 * u].x, cv[2 * u].y, cv[2 * u + 1].x, cv[2 * u + 1].y};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double delta = __dadd_rn((double)xs[e], -cs[e]);
+          acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+        }
+      }
+    }
+    for (; t + 4 <= d; t += 4) {
+      const float4 xv = *reinterpret_cast<const float4*>(xr + t);
+      const double2 c0 = *reinterpret_cast<const double2*>(cr + t);
+      const double2 c1 = *reinterpret_cast<const double2*>(cr + t + 2);
+      double delta = __dadd_rn((double)xv.x, -c0.x);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+      delta = __dadd_rn((double)xv.y, -c0.y);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+      delta = __dadd_rn((double)xv.z, -c1.x);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+      delta = __dadd_rn((double)xv.w, -c1.y);
+      acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+    }
+  }
+  for (; t < d; ++t) {
+    const double delta = __dadd_rn((double)xr[t], -cr[t]);
+    acc = __dadd_rn(acc, __dmul_rn(delta, delta));
+  }
+  return acc;
+}
+
+// D_num + gamma * mismatches, in that float64 order (reference formula).
+GEEK_D double d64h(const float* __restrict__ xr, const double* __restrict__ cr, int d, const Het& het,
+                   int64_t i, int j) {
+  const double dn = d64(xr, cr, d);
+  if (!het.cat) return dn;
+  return __dadd_rn(dn, __dmul_rn(het.gamma, (double)mismatches(het, i, j)));
+}
+
 __device__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
   // one atomic per wave
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(dst, v);
 }
 
-// Candidate records: rstride int32 per row (count, then seed indices); the
-// BF16 first pass writes 2 per row, the windows RECW.  Eight lanes per row:
+// Candidate windows (RECW records: the FP8 and float32 first passes, the
+// rescans): a lane per row, each lane walking its own row's candidates.
+__global__ void k_finalize_win(const float* __restrict__ X, int64_t ldx, int d,
+                           const double* __restrict__ C, int k, Het het, int64_t n_rows,
+                           const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count,
+                           const int32_t* __restrict__ rec, int rstride, int32_t* __restrict__ assign,
+                           double* __restrict__ dist, uint32_t* __restrict__ esc,
+                           uint32_t* __restrict__ esc_count, unsigned long long* __restrict__ ctr,
+                           int ctr_rows) {
+  const int64_t count = rows ? (int64_t)*rows_count : n_rows;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t iters = (count + stride - 1) / stride;
+  unsigned long long nrow = 0, ncand = 0;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t pos = start + it * stride;
+    if (pos >= count) continue;
+    const int64_t i = rows ? (int64_t)rows[pos] : pos;
+    const int32_t* rr = rec + pos * rstride;
+    const int c = rr[0];
+    if (c <= 0) {  // window overflow (or no finite candidate): escalate
+      const uint32_t q = atomicAdd(esc_count, 1u);
+      esc[q] = (uint32_t)i;
+      continue;
+    }
+    double best = INFINITY;
+    int bj = 0x7fffffff;
+    const float* xr = X + i * ldx;
+    for (int q = 0; q < c; ++q) {
+      const int j = rr[1 + q];
+      if ((unsigned)j >= (unsigned)k) continue;
+      const double D = d64h(xr, C + (int64_t)j * d, d, het, i, j);
+      if (D < best || (D == best && j < bj)) {
+        best = D;
+        bj = j;
+      }
+    }
+    if (bj == 0x7fffffff) bj = 0;
+    assign[i] = bj;
+    dist[i] = best;
+    nrow += 1;
+    ncand += (unsigned long long)c;
+  }
+  if (ctr) {
+    block_add_u64(ctr + ctr_rows, nrow);
+    block_add_u64(ctr + 3, ncand);
+  }
+}
+
+// The BF16 first pass's records (RECW_T2: at most one candidate).  Eight
+// lanes per row:
 // lane e loads attributes t0 + 4e .. t0 + 4e + 3 of the row and of the
 // candidate centroid for t0 = 0, 32, ... (one x cache line and two centroid
 // lines per step, coalesced over the eight lanes), forms the rounded
@@ -312,7 +416,7 @@ __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ X, i
                                                   int32_t* __restrict__ assign, double* __restrict__ dist,
                                                   uint32_t* __restrict__ esc, uint32_t* __restrict__ esc_count,
                                                   unsigned long long* __restrict__ ctr, int ctr_rows) {
-  __shared__ double sq[4][FZ_ROWS][FZ_STEP];
+  __shared__ double sq[4][FZ_ROWS][FZ_STEP + 2];  // + 2: the eight row leaders read distinct banks
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 3, e = lane & 7;  // row slot, lane within the row
   const int64_t count = rows ? (int64_t)*rows_count : n_rows;
@@ -401,7 +505,7 @@ __global__ __launch_bounds__(256) void k_finalize(const float* __restrict__ X, i
 // ties.  A workgroup takes FB_R rows and a range of FB_C-seed tiles; each
 // thread holds a 4 x 4 block of (row, seed) sums with both operands staged in
 // LDS, so one read of a seed row from L2 serves FB_R rows.  Every sum runs
-// over t = 0..d-1 in order with the operations of k_finalize (the zero padding of
+// over t = 0..d-1 in order with the operations of d64 (the zero padding of
 // t >= d adds +0.0, which leaves a sum of squares unchanged), so the values
 // are those of the reference formula.  With fewer row groups than workgroups
 // the seed tiles of a group are split over up to FB_SPLIT workgroups, whose
@@ -912,15 +1016,23 @@ static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, h
   unsigned long long* ctr = W.ctr;
   const int fz_grid = (int)std::min<int64_t>(ceil_div(J.n, 4 * FZ_ROWS), 8192);
   const int rstride = J.precision == GEEK_PREC_BF16 ? RECW_T2 : RECW;
-  hipLaunchKernelGGL(k_finalize, dim3(fz_grid), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
-                     nullptr, nullptr, W.rec, rstride, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
+  // eight lanes per row for the BF16 records of large jobs (10^7 rows at
+  // d = 128: 3.3 against 4.0 ms); the batched workload's jobs (10^3 .. 10^6
+  // rows on four streams) ran 36 ms slower in all with it than with a lane
+  // per row, for reasons not yet found, so smaller jobs keep a lane per row
+  if (rstride == RECW_T2 && J.n >= ((int64_t)1 << 20))
+    hipLaunchKernelGGL(k_finalize, dim3(fz_grid), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, C.het, J.n,
+                       nullptr, nullptr, W.rec, rstride, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
+  else
+    hipLaunchKernelGGL(k_finalize_win, dim3(ceil_div(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
+                       C.het, J.n, nullptr, nullptr, W.rec, rstride, J.assign, C.dist, W.esc, W.counts + 0, ctr, 0);
   // rows with several first-pass candidates: float32 rescan of those rows with
   // a wider window (persistent grids, at most one row tile / block per group)
   scan_any<ModeF32, true>(C.het_on, C.DP, esc_grid(J.n, 128), s, J, 0, W.esc, W.counts + 0, W.cl32, W, C.k_pad,
                           C.het, st);
-  hipLaunchKernelGGL(k_finalize, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k,
-                     C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, RECW, J.assign, C.dist, W.fb, W.counts + 1, ctr,
-                     1);
+  hipLaunchKernelGGL(k_finalize_win, dim3(esc_grid(J.n, 256)), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids,
+                     J.k, C.het, (int64_t)0, W.esc, W.counts + 0, W.rec, RECW, J.assign, C.dist, W.fb, W.counts + 1,
+                     ctr, 1);
   const int fb_grid = (int)std::min<int64_t>(FB_GRID, ceil_div(J.n, FB_R) * FB_SPLIT);
   switch (C.DP) {
 #define GEEK_FB_CASE(DPV)                                                                                  \
