@@ -7,7 +7,7 @@
 // differs from the float64 reference quotient (sum over t in order, + b, / w)
 // by at most tau = c * (|a_p| |x_i| + |b_p|) / w, so when [q - tau, q + tau]
 // holds no integer the float32 floor equals the reference floor.  Otherwise
-// the pair gets a float64 dot product (16 lanes, FMA), certified the same way
+// the pair gets a float64 dot product (FMA, by the two lanes that hold x), certified the same way
 // with a radius of a few float64 ulps, and only the pairs that this leaves
 // open are summed in exactly the reference order.  The m codes of each table
 // are then packed into a 128-bit exact key.
@@ -328,14 +328,13 @@ __global__ __launch_bounds__(B3 ? 2 * H_THREADS : H_THREADS, B3 ? 1 : 2) void k_
     xb[q + 3] = v.w;
   }
   double nrm = 0.0;
-  bool finite = true;
 #pragma unroll
-  for (int q = 0; q < S; ++q) {
-    finite = finite && isfinite(xb[q]);
-    nrm += (double)xb[q] * (double)xb[q];
-  }
-  if (!finite) set_status(st, GEEK_ERR_NONFINITE);
+  for (int q = 0; q < S; ++q) nrm += (double)xb[q] * (double)xb[q];
   nrm += __shfl_xor(nrm, 32);
+  // a NaN or infinite attribute makes the float64 sum of squares NaN or
+  // infinite; finite float32 values cannot overflow it (d * FLT_MAX^2 is far
+  // below DBL_MAX)
+  if (!isfinite(nrm)) set_status(st, GEEK_ERR_NONFINITE);
   const float xn = (float)(sqrt(nrm) * (1.0 + 0x1p-20));
   // second stage (float64 dot: four FMA chains per K half, summed pairwise,
   // then across the halves; + b; * (1/w) with 1/w rounded): |q_fast - q64|
@@ -470,35 +469,30 @@ __global__ __launch_bounds__(B3 ? 2 * H_THREADS : H_THREADS, B3 ? 1 : 2) void k_
       }
     }
     const int pl = wv * 32 + p;  // point within block
-    // Register r of half hf holds row hf*32 + (r/4)*8 + h*4 + r%4; rows past
-    // rows_used (zero A rows) are stored but never flagged or read.
+    // Register r of half hf holds row hf*32 + (r/4)*8 + h*4 + r%4.  The
+    // lane's uncertified rows collect in `own`, bit hf*16 + r for that row;
+    // rows past rows_used (zero A rows) are stored but never flagged or read.
     // |q| < 2^22 for every row of the chunk when (max|a| |x| + max|b|) / w
     // < 2^21: floor, the fraction and the int conversion are then exact.
     // Otherwise (huge x) every row of the point goes to the float64 check.
     const bool qsafe = __builtin_fmaf(lds_qb[0], xn, lds_qb[1]) * inv_w < 0x1p21f;
-    uint32_t badv[2] = {0u, 0u};
+    uint32_t own = 0u;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       if (half == 1 && rows_used <= 32) break;
       const f32x16& acc = half ? acc1 : acc0;
-      uint32_t bad = 0u, live = 0xFFFFFFFFu;
-      if (half * 32 + 32 > rows_used) {  // the chunk's last rows are padding
-        live = 0u;
+      uint32_t bad = 0u;
+      // registers from the last to the first: each value's sign bit enters
+      // at bit 0 as the earlier ones move up (one funnel shift per value)
 #pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4)
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            live |= (half * 32 + g4 * 8 + h * 4 + e < rows_used ? 1u : 0u) << (g4 * 8 + h * 4 + e);
-      }
-#pragma unroll
-      for (int g4 = 0; g4 < 4; ++g4) {
+      for (int g4 = 3; g4 >= 0; --g4) {
         const int rbase = half * 32 + g4 * 8 + h * 4;
         const float4 t1 = *reinterpret_cast<const float4*>(lds_t1 + rbase);
         const float4 t0 = *reinterpret_cast<const float4*>(lds_t0 + rbase);
         const float t1v[4] = {t1.x, t1.y, t1.z, t1.w};
         const float t0v[4] = {t0.x, t0.y, t0.z, t0.w};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 3; e >= 0; --e) {
           const int r = g4 * 4 + e;
           const float q = acc[r] * inv_w;
           const float fq = floorf(q);
@@ -508,12 +502,21 @@ __global__ __launch_bounds__(B3 ? 2 * H_THREADS : H_THREADS, B3 ? 1 : 2) void k_
           // it is the smaller) less the radius; negative = not certified
           const float marg = fminf(frac, 1.0f - frac) - tau;
           lds_code[pl * H_CS + rbase + e] = (int)fq;
-          bad |= (__float_as_uint(marg) >> 31) << (g4 * 8 + h * 4 + e);
+          bad = __builtin_amdgcn_alignbit(bad, __float_as_uint(marg), 31);
         }
       }
-      bad = qsafe ? bad : 0xFFFFFFFFu;
-      bad &= live;
-      badv[half] = valid ? bad : 0u;
+      uint32_t live = 0xFFFFu;
+      const int rem = rows_used - half * 32;  // rows of this half in use
+      if (rem < 32) {  // the chunk's last rows are padding
+        live = 0u;
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+          const int k = rem - g4 * 8 - h * 4;
+          live |= ((1u << (k < 0 ? 0 : k > 4 ? 4 : k)) - 1u) << (g4 * 4);
+        }
+      }
+      bad = (qsafe ? bad : 0xFFFFu) & live;
+      own |= (valid ? bad : 0u) << (half * 16);
     }
     // ---- float64 check of the uncertified pairs, by the two lanes that hold
     // the point's x (each its half of the K range, in registers).  Both lanes
@@ -523,11 +526,14 @@ __global__ __launch_bounds__(B3 ? 2 * H_THREADS : H_THREADS, B3 ? 1 : 2) void k_
     // reference floor, else the lane that owns the row evaluates the
     // reference sum itself.  The owner writes the code it stored before.
     {
-      nfix += __popc(badv[0]) + __popc(badv[1]);
-      unsigned long long fl = ((unsigned long long)(badv[1] | __shfl_xor(badv[1], 32)) << 32) |
-                              (unsigned long long)(badv[0] | __shfl_xor(badv[0], 32));
+      nfix += __popc(own);
+      // the pair's union, bit hk*32 + hf*16 + r: lane hk's register r of half hf
+      const uint32_t oth = __shfl_xor(own, 32);
+      unsigned long long fl = h ? (((unsigned long long)own << 32) | oth) : (((unsigned long long)oth << 32) | own);
       while (__any(fl != 0ull)) {
-        const int row = fl ? __ffsll((long long)fl) - 1 : 0;
+        const int kb = fl ? __ffsll((long long)fl) - 1 : 0;
+        const int hk = kb >> 5;
+        const int row = ((kb >> 4) & 1) * 32 + ((kb >> 2) & 3) * 8 + hk * 4 + (kb & 3);
         double part = 0.0;
         if (fl) {
           // four independent FMA chains (k mod 4), then summed pairwise
@@ -559,7 +565,7 @@ __global__ __launch_bounds__(B3 ? 2 * H_THREADS : H_THREADS, B3 ? 1 : 2) void k_
           part = (p4[0] + p4[1]) + (p4[2] + p4[3]);
         }
         part += __shfl_xor(part, 32);
-        if (fl && ((row >> 2) & 1) == h) {
+        if (fl && hk == h) {
           const double bv = (double)lds_b[row];
           const double qf = (part + bv) * inv_wd;
           const double rad = coef64 * ((double)lds_an[row] * (double)xn + fabs(bv)) / (double)w;
