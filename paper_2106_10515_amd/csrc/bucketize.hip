@@ -747,8 +747,9 @@ struct FastLds {
   uint32_t twice[GF_BITS / 32];
   uint32_t lid[GB_LIST], lf[GB_LIST];
   uint4 lkey[GB_LIST];
-  uint32_t nlist;
+  uint32_t nlist[2];  // list lengths, used by alternate bins
 };
+static_assert(GB_LIST % 8 == 0, "the list is read eight fingerprints at a time");
 
 __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* bintot, const uint32_t* binstart,
                                                       const BzRec* recs, GroupOut go, uint32_t* hard,
@@ -784,6 +785,12 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
   extent(w + step, sz1, b1);
   uint32_t f0[GF_RPL], i0[GF_RPL];
   records(w, sz0, b0, f0, i0);
+  // bins that reach the bitmaps alternate between the two list counters: a
+  // bin's counter was last read by the bin before the previous one, so it is
+  // reset after the first barrier of the previous bin without a barrier of
+  // its own
+  uint32_t par = 0u;
+  if (tid == 0) S.nlist[0] = S.nlist[1] = 0u;
   for (; w < nwork; w += step) {
     const uint32_t size = sz0;
     uint32_t f[GF_RPL], id[GF_RPL];
@@ -812,8 +819,8 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
       uint4* s4 = reinterpret_cast<uint4*>(S.seen);  // seen and twice are adjacent
       for (int i = tid; i < GF_BITS / 64; i += BZ_THREADS) s4[i] = make_uint4(0u, 0u, 0u, 0u);
     }
-    if (tid == 0) S.nlist = 0u;
     __syncthreads();
+    if (tid == 0) S.nlist[par ^ 1u] = 0u;  // the next bin's counter
 #pragma unroll
     for (int u = 0; u < GF_RPL; ++u) {
       if (!in[u]) continue;
@@ -825,7 +832,7 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
     for (int u = 0; u < GF_RPL; ++u) {
       const uint32_t b = f[u] & (GF_BITS - 1);
       if (in[u] && ((S.twice[b >> 5] >> (b & 31)) & 1u)) {
-        const uint32_t p = atomicAdd(&S.nlist, 1u);
+        const uint32_t p = atomicAdd(&S.nlist[par], 1u);
         if (p < (uint32_t)GB_LIST) {
           S.lid[p] = id[u];
           S.lf[p] = f[u];
@@ -833,8 +840,8 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
       }
     }
     __syncthreads();
-    const uint32_t k = S.nlist;
-    __syncthreads();        // read by every thread before the next item resets it
+    const uint32_t k = S.nlist[par];
+    par ^= 1u;
     if (k == 0u) continue;  // every key alone
     if (k > (uint32_t)GB_LIST) {
       if (tid == 0) hard[atomicAdd(nhard, 1u)] = (uint32_t)w;
@@ -842,21 +849,32 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
     }
     if ((uint32_t)tid < k) S.lkey[tid] = load_key(a, t, S.lid[tid]);
     __syncthreads();
+    // (no barrier after this pass: the next bin writes the list only after
+    // two barriers that every thread reaches once done here)
     if ((uint32_t)tid < k) {
       const uint32_t me = S.lid[tid], mf = S.lf[tid];
       const uint4 mk = S.lkey[tid];
       uint32_t rank = 0u, cnt = 0u, head = me;
-      for (uint32_t j = 0; j < k; ++j) {
-        if (S.lf[j] == mf && key_eq(S.lkey[j], mk)) {
-          const uint32_t ij = S.lid[j];
-          ++cnt;
-          rank += ij < me;
-          head = min(head, ij);
+      // eight fingerprints per two broadcast reads; an exact key is read only
+      // on a fingerprint match (entries past k are stale and skipped; the list
+      // holds GB_LIST, a multiple of eight)
+      for (uint32_t j0 = 0; j0 < k; j0 += 8) {
+        const uint4 fa = *reinterpret_cast<const uint4*>(S.lf + j0);
+        const uint4 fb = *reinterpret_cast<const uint4*>(S.lf + j0 + 4);
+        const uint32_t fv[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t j = j0 + (uint32_t)e;
+          if (j < k && fv[e] == mf && key_eq(S.lkey[j], mk)) {
+            const uint32_t ij = S.lid[j];
+            ++cnt;
+            rank += ij < me;
+            head = min(head, ij);
+          }
         }
       }
       if (cnt >= 2u) group_record(go, t, n, me, head, rank ? rank : cnt);
     }
-    __syncthreads();
   }
 }
 
