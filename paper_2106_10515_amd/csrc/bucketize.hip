@@ -732,10 +732,11 @@ __device__ void gb_large_bin(GroupLds& G, const BzArgs& a, int t, uint32_t size,
 // the current one is grouped.  A record sets bit (f mod 2^16) of a "seen"
 // bitmap; a bit that was already set also goes into "seen twice".  Records
 // whose bit is in "seen twice" -- every record of a key shared in the bin,
-// plus a few whose 16 bits merely coincide -- are listed with their exact
-// keys, and each listed record's rank (number of smaller listed ids with
-// the same key), bucket size and head come from one pass over the list.
-// Every other record is alone in its bucket.  Bins larger than GF_MAXREC or
+// plus a few whose 16 bits merely coincide -- are listed; listed records
+// that share their full fingerprint with another listed one get their exact
+// keys, and their rank (number of smaller listed ids with the same key),
+// bucket size and head come from one pass over the list.  Every other
+// record is alone in its bucket.  Bins larger than GF_MAXREC or
 // with more than GB_LIST listed records go to a list of hard items for
 // k_group_hard.
 constexpr int GF_BITS = 1 << 16;
@@ -847,17 +848,32 @@ __global__ __launch_bounds__(BZ_THREADS) void k_group(BzArgs a, const uint32_t* 
       if (tid == 0) hard[atomicAdd(nhard, 1u)] = (uint32_t)w;
       continue;
     }
-    if ((uint32_t)tid < k) S.lkey[tid] = load_key(a, t, S.lid[tid]);
+    // a listed record whose full fingerprint no other listed record shares is
+    // alone (equal keys have equal fingerprints): only the others need their
+    // exact keys.  Eight fingerprints per two broadcast reads (entries past k
+    // are stale and skipped; the list holds GB_LIST, a multiple of eight).
+    bool twin = false;
+    if ((uint32_t)tid < k) {
+      const uint32_t mf = S.lf[tid];
+      uint32_t nf = 0u;
+      for (uint32_t j0 = 0; j0 < k; j0 += 8) {
+        const uint4 fa = *reinterpret_cast<const uint4*>(S.lf + j0);
+        const uint4 fb = *reinterpret_cast<const uint4*>(S.lf + j0 + 4);
+        const uint32_t fv[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) nf += (j0 + (uint32_t)e < k && fv[e] == mf) ? 1u : 0u;
+      }
+      twin = nf >= 2u;
+      if (twin) S.lkey[tid] = load_key(a, t, S.lid[tid]);
+    }
     __syncthreads();
     // (no barrier after this pass: the next bin writes the list only after
     // two barriers that every thread reaches once done here)
-    if ((uint32_t)tid < k) {
+    if (twin) {
       const uint32_t me = S.lid[tid], mf = S.lf[tid];
       const uint4 mk = S.lkey[tid];
       uint32_t rank = 0u, cnt = 0u, head = me;
-      // eight fingerprints per two broadcast reads; an exact key is read only
-      // on a fingerprint match (entries past k are stale and skipped; the list
-      // holds GB_LIST, a multiple of eight)
+      // an exact key is read only on a fingerprint match (whose key is loaded)
       for (uint32_t j0 = 0; j0 < k; j0 += 8) {
         const uint4 fa = *reinterpret_cast<const uint4*>(S.lf + j0);
         const uint4 fb = *reinterpret_cast<const uint4*>(S.lf + j0 + 4);
