@@ -175,7 +175,7 @@ __global__ __launch_bounds__(1024) void k_bin_rowscan(int nbins, const uint32_t*
   }
 }
 constexpr int PT_B1 = 6;          // bits of the first partition pass (64 bins)
-constexpr int PT_ROUND = 2048;    // records placed in LDS per round
+constexpr int PT_ROUND = 4096;    // records placed in LDS per round (longer runs per bin)
 constexpr int PT_SUPER = 16384;   // records per workgroup of a partition pass
 constexpr int PT_RPT = PT_ROUND / BZ_THREADS;
 constexpr int PT_SEG = PT_ROUND / (BZ_THREADS / 64);  // records of one wavefront per round
