@@ -343,6 +343,10 @@ __device__ __forceinline__ void scan_tiles(
     // the lane's 16 values of a 32-centroid block in its low 4 mantissa bits;
     // blk is the block where a1 last changed.
     float b0[NCB], thr[NCB], lost[NCB];
+    // thr at the window's last compaction: while thr has not dropped below
+    // it, every stored value is still within thr and a compaction of a full
+    // window would keep all of them, so it is skipped
+    float cthr[NCB];
     int cnt[NCB];
     float a1[NCB], a2[NCB];
     int blk[NCB];
@@ -351,6 +355,7 @@ __device__ __forceinline__ void scan_tiles(
       b0[cb] = INFINITY;
       thr[cb] = 3.402823466e38f;
       lost[cb] = INFINITY;
+      cthr[cb] = INFINITY;
       cnt[cb] = 0;
       a1[cb] = -3.402823466e38f;
       a2[cb] = -3.402823466e38f;
@@ -626,7 +631,8 @@ __device__ __forceinline__ void scan_tiles(
                   b0[cb] = v[r];
                   thr[cb] = b0[cb] + twoeps[cb];
                 }
-                if (cnt[cb] == TC) {
+                if (cnt[cb] == TC && thr[cb] < cthr[cb]) {
+                  cthr[cb] = thr[cb];
                   int kept = 0;
 #pragma unroll 1
                   for (int q = 0; q < TC; ++q) {
