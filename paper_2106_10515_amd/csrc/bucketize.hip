@@ -101,6 +101,18 @@ __global__ __launch_bounds__(BZ_THREADS) void k_fp_count(BzArgs a, int nblk, int
   for (int b = threadIdx.x; b < nbins; b += BZ_THREADS) out[b] = hist[b];
 }
 
+// Fingerprints of every (table, id) when each object's T keys lie within its
+// row (the bands of a signature row): FR_LANES lanes share an object and lane
+// q takes tables q, q + FR_LANES, ..., so consecutive lanes read consecutive
+// keys of one row, where the pass per table reads one key out of every row.
+constexpr int FR_LANES = 16;
+__global__ __launch_bounds__(BZ_THREADS) void k_fp_rows(BzArgs a, uint32_t* fp) {
+  const int64_t i = ((int64_t)blockIdx.x * BZ_THREADS + threadIdx.x) / FR_LANES;
+  const int q = (int)(threadIdx.x % FR_LANES);
+  if (i >= a.n) return;
+  for (int t = q; t < a.T; t += FR_LANES) fp[(int64_t)t * a.n + i] = fp_of(load_key(a, t, i));
+}
+
 // Per (table, bin): exclusive scan over blocks; bin totals.
 __global__ void k_bin_colscan(int T, int nblk, int nbins, uint32_t* counts, uint32_t* bintot) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1178,14 +1190,20 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
   GroupOut go{W.flag8, W.info, fw};
   prof_begin(GEEK_PROF_BUCKETIZE, s);
   // the fingerprints: the caller's (geek_hash wrote them with the keys) or
-  // computed here into the workspace
+  // computed here into the workspace -- row by row first when every table's
+  // key of an object lies in the object's row, else by the count pass
   const uint32_t* fps = J.key_fp ? J.key_fp : W.fp;
+  const uint32_t* given = J.key_fp;
+  if (!J.key_fp && J.T > 1 && J.table_stride * J.T <= J.row_stride) {
+    hipLaunchKernelGGL(k_fp_rows, dim3(ceil_div(J.n * FR_LANES, BZ_THREADS)), dim3(BZ_THREADS), 0, s, a, W.fp);
+    given = W.fp;
+  }
   hipLaunchKernelGGL(k_zero_u4, dim3(ceil_div((int64_t)J.T * fw / 16 + 1, 256)), dim3(256), 0, s,
                      reinterpret_cast<uint4*>(W.flag8), (int64_t)J.T * fw / 16 + 1);
   uint32_t* nhard = reinterpret_cast<uint32_t*>(W.flag8 + (size_t)J.T * fw);
   if (nb <= PT_B1) {
     hipLaunchKernelGGL(k_fp_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)nbins * 4, s, a, nblk, PT_SUPER,
-                       W.counts, W.fp, J.key_fp);
+                       W.counts, W.fp, given);
     hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div((int64_t)J.T * nbins, 256)), dim3(256), 0, s, J.T,
                        nblk, nbins, W.counts, W.bintot);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, nbins, W.bintot, W.binstart);
@@ -1200,7 +1218,7 @@ int32_t bucketize_run(const geek_bucketize_job& J, void* ws, size_t ws_bytes, in
     const int F = 1 << (nb - PT_B1);
     const int maxchunks = (int)p2_max_chunks(J.n, J.T);
     hipLaunchKernelGGL(k_fp_count, dim3(nblk, J.T), dim3(BZ_THREADS), (size_t)4 << PT_B1, s, a1, nblk, PT_SUPER,
-                       W.counts, W.fp, J.key_fp);
+                       W.counts, W.fp, given);
     hipLaunchKernelGGL(k_bin_colscan, dim3(ceil_div(nb1bins, 256)), dim3(256), 0, s, J.T, nblk, 1 << PT_B1,
                        W.counts, W.bintot1);
     hipLaunchKernelGGL(k_bin_rowscan, dim3(J.T), dim3(1024), 0, s, 1 << PT_B1, W.bintot1, W.binstart1);
