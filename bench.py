@@ -425,6 +425,42 @@ def _timed_graph(step, steps, warmup):
     return e0.elapsed_time(e1) / steps, out
 
 
+def _oracle_euclid_sample(jobs, rows_per_job):
+    """The oracle (numpy float64, one thread) on sampled rows of dense jobs
+    already assigned on the GPU: for each (X, seed_offsets, seed_members,
+    gpu_out) it computes every centroid, then assigns the first rows to all
+    of them.  Returns the cpu_baseline object: points/s with the centroid
+    time prorated by sample / n, whether the sampled assignments equal the
+    GPU's, and the sampled SSE's relative error against the oracle."""
+    import numpy as np
+
+    import oracle
+
+    t_tot, rows_tot, agree, s_gpu, s_ref = 0.0, 0, True, 0.0, 0.0
+    for X, so, sm, out in jobs:
+        Xh = X.cpu().numpy()
+        soh, smh = so.cpu().numpy().view(np.uint32), sm.cpu().numpy().view(np.uint32)
+        n = Xh.shape[0]
+        rows = min(rows_per_job, n)
+        t0 = time.perf_counter()
+        C = oracle.centroids(Xh, soh, smh)
+        t_c = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        a_ref, d_ref = oracle.assign_euclid(Xh[:rows], C)
+        t_a = time.perf_counter() - t0
+        t_tot += t_a + t_c * rows / n
+        rows_tot += rows
+        agree = agree and bool(np.array_equal(a_ref, out["assign"][:rows].cpu().numpy()))
+        s_gpu += float(out["dist"][:rows].double().sum())
+        s_ref += float(d_ref.sum())
+    return {"value": rows_tot / t_tot, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {rows_per_job} rows of each of {len(jobs)} job(s) assigned to all of the job's "
+                      "seeds (numpy float64, one thread; centroid time prorated by sample / n); hashing, "
+                      "bucketing and seeding not included",
+            "sample_assign_matches_gpu": agree,
+            "sample_sse_rel_err_vs_oracle": abs(s_gpu - s_ref) / max(s_ref, 1e-300)}
+
+
 def bench_batched(args):
     """Many independent dense jobs (n log-uniform in [1e3, 1e6], d over
     {16, 32, 64, 128, 256}, 10..5000 planted clusters): one geek_hash, one
@@ -507,6 +543,8 @@ def bench_batched(args):
         "assign_one_call_per_job_ms": single_ms,
         "batched_equals_single_calls": bool(same),
     }
+    line["cpu_baseline"] = _oracle_euclid_sample(
+        [(X, so, sm, o) for (X, so, sm, _), o in list(zip(probs, outs))[:4]], 128)
     if tiles:
         # the persistent first pass of every padded depth, timed by the
         # autotuner with its chosen shape: 2 n d k flops per job
@@ -706,7 +744,56 @@ def bench_sets(args):
     }
     if not doph:
         line["minhash_evals_per_s"] = nnz * K * Lb / (t_hash * 1e-3)
+    if not args.no_cpu:
+        line["cpu_baseline"] = _oracle_sets_sample(off, tok, mh, so, sm, F if doph else None, sig, out, 512)
     print(json.dumps(line), flush=True)
+
+
+def _oracle_sets_sample(off, tok, mh, so, sm, doph_dims, sig, out, rows):
+    """The oracle (numpy, one thread) on a sample of the sets workload: the
+    signatures (MinHash, or DOPH when doph_dims is given) of every planted
+    seed member and of the first rows, the seeds' modes, and the assignment
+    of those rows.  Returns the cpu_baseline object (sets/s, seed work
+    prorated by rows / n) with the sampled checks against the GPU."""
+    import numpy as np
+
+    import oracle
+
+    offh, tokh = off.cpu().numpy().astype(np.int64), tok.cpu().numpy().view(np.uint32)
+    keys = mh.cpu().numpy().view(np.uint32)
+    n = len(offh) - 1
+    rows = min(rows, n)
+
+    def sub(ids):  # the CSR of the sets ids, in that order
+        lens = offh[ids + 1] - offh[ids]
+        o = np.zeros(len(ids) + 1, np.int64)
+        np.cumsum(lens, out=o[1:])
+        idx = np.repeat(offh[ids] - o[:-1], lens) + np.arange(o[-1])
+        return o, tokh[idx]
+
+    def sigs(ids):
+        o, t = sub(ids)
+        if doph_dims:
+            return oracle.doph_sets(o, t, keys.reshape(-1, 2)[0], doph_dims)
+        return oracle.minhash_sets(o, t, keys)
+
+    t0 = time.perf_counter()
+    S_mem = sigs(np.asarray(sm, dtype=np.int64))
+    M = oracle.modes(S_mem, so, np.arange(len(sm), dtype=np.uint32))
+    t_seed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    S_rows = sigs(np.arange(rows, dtype=np.int64))
+    a_ref, d_ref = oracle.assign_sig(S_rows, M)
+    t_rows = time.perf_counter() - t0
+    s_gpu = float(out["dist"][:rows].double().sum())
+    return {"value": rows / (t_rows + t_seed * rows / n), "unit": "sets/s", "cores": 1, "kind": "oracle",
+            "sample": f"signatures of the first {rows} of {n} sets and of all {len(sm)} planted seed members, "
+                      "the seeds' modes and the rows' assignment (numpy, one thread; seed work prorated by "
+                      "rows / n); bucketing not included",
+            "sample_signatures_match_gpu": bool(np.array_equal(S_rows.astype(np.uint32),
+                                                               sig[:rows].cpu().numpy().view(np.uint32))),
+            "sample_assign_matches_gpu": bool(np.array_equal(a_ref, out["assign"][:rows].cpu().numpy())),
+            "sample_sse_rel_err_vs_oracle": abs(s_gpu - float(d_ref.sum())) / max(float(d_ref.sum()), 1e-300)}
 
 
 def bench_silk(args):
@@ -750,7 +837,7 @@ def bench_silk(args):
         out = api.assign_euclid(X, so, sm, k, L.GEEK_PREC_BF16, status=status, check=False) if k > 0 else None
         ev[4].record()
         torch.cuda.synchronize()
-        return [ev[i].elapsed_time(ev[i + 1]) for i in range(4)], k, ctr, out
+        return [ev[i].elapsed_time(ev[i + 1]) for i in range(4)], k, ctr, out, (so, sm)
 
     for _ in range(args.warmup):
         one()
@@ -758,7 +845,7 @@ def bench_silk(args):
     runs = [one() for _ in range(args.steps)]
     api.check_status(status, "timed")
     st = np.median(np.array([r[0] for r in runs]), axis=0)
-    _, k, ctr, out = runs[-1]
+    _, k, ctr, out, _ = runs[-1]
     total = float(st.sum())
     line = {
         "metric": "points/s (hash+bucketize+SILK+assign), whole GEEK pass",
@@ -782,6 +869,9 @@ def bench_silk(args):
         "assign_counters": out["counters"].cpu().numpy().tolist() if out is not None else None,
         "sse": float(out["sse"].item()) if out is not None else None,
     }
+    if out is not None and not args.no_cpu:
+        so, sm = runs[-1][4]
+        line["cpu_baseline"] = _oracle_euclid_sample([(X, so, sm, out)], 64)
     print(json.dumps(line), flush=True)
 
 
