@@ -800,9 +800,11 @@ def bench_silk(args):
     """The whole GEEK pass on the dense mixture (d = 128, Zipf cluster sizes,
     clusters scaled with n) at the scaled E2LSH width w * sqrt(d): hash,
     buckets of 32 tables, SILK seeds (K_S = 3, L_S = 20, delta = 10), then the
-    BF16 assignment to the SILK seeds.  The binding reads the seed count k
-    back to the host between SILK and the assignment (geek_assign takes k on
-    the host), so the pass is timed eagerly with events."""
+    BF16 assignment to the SILK seeds.  The pass is timed eagerly with
+    events per stage.  The binding reads the seed count k back to the host
+    between SILK and the assignment, so the assignment costs what k seeds
+    cost rather than SILK's capacity (geek_assign's k_dev avoids the
+    read-back, at the capacity's cost)."""
     import numpy as np
     import torch
 

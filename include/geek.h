@@ -316,6 +316,18 @@ typedef struct geek_assign_job {
                                were complete (batched calls; jobs finish in
                                any order), or the absolute tick count at that
                                moment (njobs = 1) */
+  const uint32_t* k_dev;    /* optional [1], device (EUCLID, njobs = 1): the
+                               number of seeds as the device knows it, for
+                               seeds made earlier in the same stream (such as
+                               geek_silk_seeds' *k_out) without reading the
+                               count back to the host, so a whole pass can be
+                               captured in one graph.  k is then the host
+                               capacity: seeds j >= min(*k_dev, k) take no
+                               part (their seed_offsets entries are not read;
+                               centroids rows and radius entries of such j are
+                               written as 0), and the call costs what k
+                               seeds cost.  *k_dev = 0 sets GEEK_ERR_NO_SEEDS.
+                               NULL: k seeds. */
 } geek_assign_job;
 
 /* ---- geek_regroup ---------------------------------------------------------

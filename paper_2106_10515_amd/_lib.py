@@ -84,7 +84,7 @@ class AssignJob(C.Structure):
         ("sig", P), ("F", C.c_int32), ("n_cat", C.c_int32), ("cat", P), ("gamma", C.c_double),
         ("seed_offsets", P), ("seed_members", P), ("assign", P), ("centroids", P),
         ("modes", P), ("dist", P), ("sse", P), ("radius", P), ("counters", P),
-        ("n_members", C.c_int64), ("t_done", P),
+        ("n_members", C.c_int64), ("t_done", P), ("k_dev", P),
     ]
 
 

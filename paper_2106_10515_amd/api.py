@@ -261,9 +261,11 @@ def silk_seeds(members, offsets, nbuckets, n, T, K, L_silk, delta, silk_keys,
 
 # ---------------------------------------------------------------- geek_assign
 def assign_euclid(X, seed_offsets, seed_members, k, precision=L.GEEK_PREC_FP32,
-                  want_dist=True, want_radius=True, status=None, check=True):
+                  want_dist=True, want_radius=True, status=None, check=True, k_dev=None):
     """Central vectors and one-pass Euclidean assignment.  Returns a dict with
-    assign, centroids, dist, sse, radius and counters."""
+    assign, centroids, dist, sse, radius and counters.  ``k_dev`` (optional,
+    a one-element int32 device tensor such as silk_seeds_async's k_out):
+    the seed count as the device knows it, k then being the capacity."""
     dev = _dev(X)
     n, d = X.shape
     out = dict(
@@ -279,7 +281,8 @@ def assign_euclid(X, seed_offsets, seed_members, k, precision=L.GEEK_PREC_FP32,
                     ldx=X.stride(0), n_members=seed_members.numel(),
                     seed_offsets=_p(seed_offsets), seed_members=_p(seed_members),
                     assign=_p(out["assign"]), centroids=_p(out["centroids"]), dist=_p(out["dist"]),
-                    sse=_p(out["sse"]), radius=_p(out["radius"]), counters=_p(out["counters"]))
+                    sse=_p(out["sse"]), radius=_p(out["radius"]), counters=_p(out["counters"]),
+                    k_dev=_p(k_dev))
     _run(L.GEEK_OP_ASSIGN, L.geek_assign, [j], dev, status)
     if check:
         check_status(status, "geek_assign")

@@ -170,6 +170,7 @@ static int32_t check_bz(const geek_bucketize_job& J) {
 static int32_t check_assign(const geek_assign_job& J) {
   if (J.n < 1 || J.n >= (1ll << 31) || J.k < 1) return GEEK_ERR_ARG;
   if (!J.seed_offsets || !J.seed_members || !J.assign || !J.sse) return GEEK_ERR_ARG;
+  if (J.k_dev && J.metric != GEEK_METRIC_EUCLID) return GEEK_ERR_ARG;
   if (J.metric == GEEK_METRIC_EUCLID || J.metric == GEEK_METRIC_HETERO) {
     if (!J.X || !al4(J.X) || J.d < 1 || J.ldx < J.d || !J.centroids) return GEEK_ERR_ARG;
     if (J.d > 256) return GEEK_ERR_UNSUPPORTED;
@@ -393,8 +394,10 @@ int32_t geek_silk_seeds(const geek_silk_job* jobs, int32_t njobs, void* ws, size
 int32_t geek_assign(const geek_assign_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
                     int32_t* d_status, void* stream) {
   if (!jobs || njobs < 1) return GEEK_ERR_ARG;
-  for (int j = 0; j < njobs; ++j)
+  for (int j = 0; j < njobs; ++j) {
     if (int32_t rc = check_assign(jobs[j])) return rc;
+    if (njobs > 1 && jobs[j].k_dev) return GEEK_ERR_ARG;  // a device seed count: one job per call
+  }
   if (!ws) return GEEK_ERR_ARG;
   if (assign_batchable(jobs, njobs)) {
     if (ws_bytes < assign_batch_ws(jobs, njobs)) return GEEK_ERR_WORKSPACE;

@@ -46,10 +46,17 @@ constexpr int SSE_BLOCK = 4096;
 constexpr int CB = 32;
 __global__ void k_centroids(const float* __restrict__ X, int64_t ldx, int64_t n, int d,
                             const uint32_t* __restrict__ offs, const uint32_t* __restrict__ mem,
-                            int k, double* __restrict__ C, int32_t* st) {
+                            int k, const uint32_t* __restrict__ kdev, double* __restrict__ C, int32_t* st) {
   int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (gid >= (int64_t)k * d) return;
   int j = (int)(gid / d), t = (int)(gid % d);
+  // seeds counted on the device: those past the count take no part
+  const int kv = kdev ? (int)min(*kdev, (uint32_t)k) : k;
+  if (j >= kv) {
+    if (kv == 0 && gid == 0) set_status(st, GEEK_ERR_NO_SEEDS);
+    C[gid] = 0.0;
+    return;
+  }
   uint32_t s = offs[j], e = offs[j + 1];
   if (e <= s) {
     set_status(st, GEEK_ERR_EMPTY_SET);
@@ -168,7 +175,7 @@ __global__ void k_centroids_t(const float* __restrict__ Xt, int64_t nm, int d,
 // Whether the centroids go through the dimension-major copy: seeds of 64
 // members or more on average, with the member count known.
 static bool centroids_transposed(const geek_assign_job& J) {
-  return J.n_members > 0 && J.n_members >= 64 * (int64_t)J.k;
+  return !J.k_dev && J.n_members > 0 && J.n_members >= 64 * (int64_t)J.k;
 }
 static int64_t members_pad(const geek_assign_job& J) { return (J.n_members + 3) / 4 * 4; }
 
@@ -213,11 +220,12 @@ __global__ void k_fp8_scale(const float* __restrict__ mx, const float* __restric
 template <class M>
 __global__ void k_cprep(const double* __restrict__ C, int k, int d, int k_pad, int DP,
                         typename M::ce* __restrict__ cl, float* __restrict__ nc, float* __restrict__ cmax,
-                        const float* __restrict__ scale_p) {
+                        const float* __restrict__ scale_p, const uint32_t* __restrict__ kdev) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k_pad) return;
   const float sc = M::SCALED ? *scale_p : 1.0f;
-  if (j >= k) {
+  // seeds past a device-side count are padding too
+  if (j >= (kdev ? (int)min(*kdev, (uint32_t)k) : k)) {
     for (int t = 0; t < DP; t += M::KPER) M::store_zero(cl + (int64_t)j * DP + t);
     if (nc) nc[j] = INFINITY;
     return;
@@ -535,7 +543,8 @@ inline int64_t fb_part_cap(int64_t n) {
 
 template <int DP>
 __global__ __launch_bounds__(256) void k_fallback64(
-    const float* __restrict__ X, int64_t ldx, int d, const double* __restrict__ C, int k, Het het,
+    const float* __restrict__ X, int64_t ldx, int d, const double* __restrict__ C, int k,
+    const uint32_t* __restrict__ kdev, Het het,
     const uint32_t* __restrict__ rows, const uint32_t* __restrict__ rows_count, int32_t* __restrict__ assign,
     double* __restrict__ dist, double* __restrict__ part_d, int32_t* __restrict__ part_j,
     unsigned long long* __restrict__ ctr) {
@@ -550,6 +559,7 @@ __global__ __launch_bounds__(256) void k_fallback64(
   int S;
   fb_shape(count, k, &R, &S);
   const int T = (k + FB_C - 1) / FB_C;
+  const int kv = kdev ? (int)min(*kdev, (uint32_t)k) : k;  // seeds that take part
   const int dp16 = (d + FB_TK - 1) / FB_TK * FB_TK;
   const int nch = dp16 / FB_TK;
   for (int64_t q = blockIdx.x; q < R * S; q += gridDim.x) {
@@ -582,7 +592,7 @@ __global__ __launch_bounds__(256) void k_fallback64(
         const int idx = tid + u * 256;
         const int jj = idx >> 4, tt = idx & 15;
         const int j = tile * FB_C + jj, t = ch * FB_TK + tt;
-        pre[u] = (j < k && t < d) ? C[(int64_t)j * d + t] : 0.0;
+        pre[u] = (j < kv && t < d) ? C[(int64_t)j * d + t] : 0.0;
       }
     };
     if (tile0 < tile1) fetch(tile0, 0);
@@ -627,7 +637,7 @@ __global__ __launch_bounds__(256) void k_fallback64(
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int j = tile * FB_C + tc * 4 + b;
-          if (j >= k) continue;
+          if (j >= kv) continue;
           double D = acc[a][b];
           if (het.cat && i >= 0) D = __dadd_rn(D, __dmul_rn(het.gamma, (double)mismatches(het, i, j)));
           if (D < best[a]) {
@@ -961,7 +971,7 @@ static int32_t assign_prep(const geek_assign_job& J, void* ws, AssignCtx& C, int
                        J.n_members, J.d, J.seed_offsets, J.k, J.centroids, st);
   } else {
     hipLaunchKernelGGL(k_centroids, dim3(ceil_div((int64_t)J.k * J.d, 256)), dim3(256), 0, s, J.X,
-                       J.ldx, J.n, J.d, J.seed_offsets, J.seed_members, J.k, J.centroids, st);
+                       J.ldx, J.n, J.d, J.seed_offsets, J.seed_members, J.k, J.k_dev, J.centroids, st);
   }
   if (C.het_on) {
     if (int32_t rc = modes_compute(reinterpret_cast<const uint32_t*>(J.cat), J.n_cat, J.n_cat, J.n,
@@ -971,16 +981,16 @@ static int32_t assign_prep(const geek_assign_job& J, void* ws, AssignCtx& C, int
                        J.n_cat, k_pad, W.mode16);
   }
   hipLaunchKernelGGL(k_cprep<ModeF32>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k, J.d, k_pad,
-                     DP, W.cl32, W.nc, W.cmax, W.cmax + 3);
+                     DP, W.cl32, W.nc, W.cmax, W.cmax + 3, J.k_dev);
   if (J.precision == GEEK_PREC_BF16) {
     hipLaunchKernelGGL(k_cprep<ModeBF16>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k, J.d,
-                       k_pad, DP, static_cast<__bf16*>(W.cllow), nullptr, nullptr, W.cmax + 3);
+                       k_pad, DP, static_cast<__bf16*>(W.cllow), nullptr, nullptr, W.cmax + 3, J.k_dev);
   } else if (J.precision == GEEK_PREC_FP8) {
     hipLaunchKernelGGL(k_absmax_x, dim3(1024), dim3(256), 0, s, J.X, J.ldx, J.n, J.d, W.cmax + 1);
     hipLaunchKernelGGL(k_absmax_c, dim3(256), dim3(256), 0, s, J.centroids, (int64_t)J.k * J.d, W.cmax + 2);
     hipLaunchKernelGGL(k_fp8_scale, dim3(1), dim3(1), 0, s, W.cmax + 1, W.cmax + 2, W.cmax + 3);
     hipLaunchKernelGGL(k_cprep<ModeFP8>, dim3(ceil_div(k_pad, 128)), dim3(128), 0, s, J.centroids, J.k, J.d,
-                       k_pad, DP, static_cast<uint8_t*>(W.cllow), nullptr, nullptr, W.cmax + 3);
+                       k_pad, DP, static_cast<uint8_t*>(W.cllow), nullptr, nullptr, W.cmax + 3, J.k_dev);
   }
   GEEK_LAUNCH_CHECK();
   return GEEK_OK;
@@ -1038,7 +1048,7 @@ static void assign_finish(const geek_assign_job& J, AssignCtx& C, int32_t* st, h
 #define GEEK_FB_CASE(DPV)                                                                                  \
   case DPV:                                                                                                \
     hipLaunchKernelGGL(k_fallback64<DPV>, dim3(fb_grid), dim3(256), 0, s, J.X, J.ldx, J.d, J.centroids, J.k, \
-                       C.het, W.fb, W.counts + 1, J.assign, C.dist, W.part_d, W.part_j, ctr);               \
+                       J.k_dev, C.het, W.fb, W.counts + 1, J.assign, C.dist, W.part_d, W.part_j, ctr);               \
     break;
     GEEK_FB_CASE(32)
     GEEK_FB_CASE(64)
@@ -1077,7 +1087,8 @@ int32_t assign_euclid(const geek_assign_job& J, void* ws, size_t ws_bytes, int32
 bool assign_batchable(const geek_assign_job* jobs, int njobs) {
   if (njobs < 2) return false;
   for (int j = 0; j < njobs; ++j)
-    if (jobs[j].metric != GEEK_METRIC_EUCLID || jobs[j].precision != jobs[0].precision) return false;
+    if (jobs[j].metric != GEEK_METRIC_EUCLID || jobs[j].precision != jobs[0].precision || jobs[j].k_dev)
+      return false;
   return true;
 }
 

@@ -33,7 +33,7 @@ int main(void) {
   F(geek_assign_job, seed_members); F(geek_assign_job, assign); F(geek_assign_job, centroids);
   F(geek_assign_job, modes); F(geek_assign_job, dist); F(geek_assign_job, sse);
   F(geek_assign_job, radius); F(geek_assign_job, counters); F(geek_assign_job, n_members);
-  F(geek_assign_job, t_done);
+  F(geek_assign_job, t_done); F(geek_assign_job, k_dev);
   printf("geek_regroup_job sizeof %zu\n", sizeof(geek_regroup_job));
   F(geek_regroup_job, n); F(geek_regroup_job, k); F(geek_regroup_job, assign);
   F(geek_regroup_job, seed_offsets); F(geek_regroup_job, seed_members); F(geek_regroup_job, k_out);

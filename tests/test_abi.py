@@ -69,6 +69,14 @@ def test_argument_errors_need_no_gpu():
     assert lib.geek_hash(C.byref(bad), 1, None, 0, None, None) == L.GEEK_ERR_ARG
     bad = L.HashJob(kind=7, n=10, F=400, offsets=16, tokens=16, mh_keys=16, sig=16)
     assert lib.geek_hash(C.byref(bad), 1, None, 0, None, None) == L.GEEK_ERR_ARG
+    # a device-side seed count: Euclidean jobs only, one job per call
+    bad = L.AssignJob(metric=L.GEEK_METRIC_SIG, n=10, k=2, sig=16, F=8, modes=16, n_members=2,
+                      seed_offsets=16, seed_members=16, assign=16, sse=16, k_dev=16)
+    assert lib.geek_assign(C.byref(bad), 1, C.c_void_p(256), 1 << 20, None, None) == L.GEEK_ERR_ARG
+    two = (L.AssignJob * 2)(*[L.AssignJob(metric=L.GEEK_METRIC_EUCLID, n=10, d=4, k=2, X=16, ldx=4,
+                                          seed_offsets=16, seed_members=16, assign=16, sse=16,
+                                          centroids=16, k_dev=16) for _ in range(2)])
+    assert lib.geek_assign(two, 2, C.c_void_p(256), 1 << 20, None, None) == L.GEEK_ERR_ARG
     assert lib.geek_status_string(L.GEEK_ERR_RANGE).decode() == "value outside the packable range"
     ok = L.BucketizeJob(n=1000, T=3, key_words=4, keys=16, table_stride=4000, row_stride=4,
                         members=16, offsets=16, nbuckets=16)

@@ -108,6 +108,47 @@ def test_assign_full_scan_rows(prec, n, d, clusters, copies, seed):
     assert ctr[2] == n
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,d,clusters,copies,seed", [
+    (3000, 32, 10, 36, 8),    # every row takes the float64 scan (seed tiles split)
+    (5000, 128, 300, 1, 1),   # rows settled by the first pass
+])
+def test_assign_device_seed_count(prec, n, d, clusters, copies, seed):
+    # the seed count read by the kernels from device memory (k_dev); the host
+    # k is a capacity with 200 further seeds behind the count, each a single
+    # row (at distance 0 from that row, were it to take part).  The result is
+    # the oracle's on the counted seeds; centroid and radius rows past the
+    # count are zero.
+    import torch
+
+    api = gpu_api()
+    X, lab, _ = dense_mixture(n, d, clusters, -10, 10, 1.0, "equal", seed)
+    so1, sm1 = planted_seeds(lab, clusters, 6)
+    offs, mem = [0], []
+    for c in range(len(so1) - 1):
+        for _ in range(copies):
+            mem.append(sm1[so1[c]:so1[c + 1]])
+            offs.append(offs[-1] + len(mem[-1]))
+    k, extra = len(offs) - 1, 200
+    for i in range(extra):
+        mem.append(np.array([i], np.uint32))
+        offs.append(offs[-1] + 1)
+    so, sm = np.asarray(offs, np.uint32), np.concatenate(mem).astype(np.uint32)
+    announce(f"assign device count n={n} d={d} k={k} capacity={k + extra} prec={prec}")
+    C = oracle.centroids(X, so[:k + 1], sm[:so[k]])
+    a, dist = oracle.assign_euclid(X, C)
+    kd = torch.tensor([k], dtype=torch.int32, device="cuda")
+    out = api.assign_euclid(cuda(X), cuda(so), cuda(sm), k + extra, PRECS[prec], k_dev=kd)
+    cen = out["centroids"].cpu().numpy()
+    assert np.array_equal(cen[:k], C) and not cen[k:].any()
+    assert np.array_equal(out["assign"].cpu().numpy(), a)
+    assert np.array_equal(out["dist"].cpu().numpy(), dist)
+    assert out["sse"].item() == oracle.sse(dist)
+    rad = out["radius"].cpu().numpy()
+    np.testing.assert_allclose(rad[:k], oracle.radius(dist, a, k), rtol=1e-13, atol=0)
+    assert not rad[k:].any()
+
+
 @pytest.mark.parametrize("n,d,clusters", [
     (12000, 8, 6000),    # k = 6000: per-workgroup radius maxima in a 128 KB LDS table
     (30000, 4, 30000),   # k = 30000: radius by global atomics

@@ -104,32 +104,55 @@ def test_silk_over_minhash_bands():
 
 
 def test_silk_pass_captured_in_one_graph():
-    # hash -> bucketize -> SILK recorded in one HIP graph (the SILK call reads
-    # nothing back to the host); every replay, with eager work and
-    # synchronizations between replays, gives the eager seeds bit for bit
+    # hash -> bucketize -> SILK -> assignment recorded in one HIP graph: the
+    # SILK call reads nothing back to the host and the assignment takes the
+    # seed count from the device (k = the seed capacity).  Every replay,
+    # with eager work and synchronizations between replays, gives the eager
+    # seeds and assignment bit for bit, and that assignment equals a call
+    # with the count given on the host.
+    from paper_2106_10515_amd import _lib as L
+
     api = gpu_api()
-    n, d, m, L, K, LS, delta = 4000, 32, 8, 16, 3, 20, 10
+    n, d, m, Lt, K, LS, delta = 4000, 32, 8, 16, 3, 20, 10
     w = 4.0 * math.sqrt(d)
     X, _, _ = dense_mixture(n, d, 20, -10, 10, 1.0, "equal", 0)
-    A, b = e2lsh_params(m * L, d, w, 0)
+    A, b = e2lsh_params(m * Lt, d, w, 0)
     keys = cuda(key_words((LS + 1) * K, 0, STREAM_SILK))
     Xg, Ag, bg = cuda(X), cuda(A), cuda(b)
     cap_k, cap_m = 4096, 16000
-    announce(f"silk graph capture n={n}")
+    announce(f"silk + assign graph capture n={n}")
 
     def chain(status):
-        kg, _ = api.hash_dense(Xg, Ag, bg, m, L, w, status=status, check=False)
-        bm, bo, bn, _ = api.bucketize(kg, n, L, 4, n * 4, 4, want_bucket_of=False, status=status, check=False)
-        return api.silk_seeds_async(bm, bo, bn, n, L, K, LS, delta, keys, cap_k, cap_m, status)
+        kg, _ = api.hash_dense(Xg, Ag, bg, m, Lt, w, status=status, check=False)
+        bm, bo, bn, _ = api.bucketize(kg, n, Lt, 4, n * 4, 4, want_bucket_of=False, status=status, check=False)
+        out = api.silk_seeds_async(bm, bo, bn, n, Lt, K, LS, delta, keys, cap_k, cap_m, status)
+        asg = api.assign_euclid(Xg, out["seed_offsets"], out["seed_members"], cap_k, L.GEEK_PREC_BF16,
+                                status=status, check=False, k_dev=out["k_out"])
+        return out, asg
 
-    def seeds(out):
+    def result(res):
+        out, asg = res
         k = int(out["k_out"].item())
         so = host_u32(out["seed_offsets"][:k + 1])
-        return so, host_u32(out["seed_members"][:int(so[-1])]), out["counters"].cpu().numpy()
+        return (so, host_u32(out["seed_members"][:int(so[-1])]), out["counters"].cpu().numpy(),
+                asg["assign"].cpu().numpy(), asg["dist"].cpu().numpy(), asg["sse"].cpu().numpy(),
+                asg["centroids"].cpu().numpy(), asg["radius"].cpu().numpy())
 
     st_e = api.new_status("cuda")
-    ref = seeds(chain(st_e))
+    eager = chain(st_e)
+    ref = result(eager)
     assert int(st_e.item()) == 0 and len(ref[0]) > 2
+    # the device count against the host count, on the same seeds
+    k = len(ref[0]) - 1
+    host = api.assign_euclid(Xg, eager[0]["seed_offsets"][:k + 1].clone(),
+                             eager[0]["seed_members"][:int(ref[0][-1])].clone(), k, L.GEEK_PREC_BF16)
+    assert np.array_equal(ref[3], host["assign"].cpu().numpy())
+    assert np.array_equal(ref[4], host["dist"].cpu().numpy())
+    assert np.array_equal(ref[5], host["sse"].cpu().numpy())
+    assert np.array_equal(ref[6][:k], host["centroids"].cpu().numpy())
+    assert not ref[6][k:].any()
+    assert np.array_equal(ref[7][:k], host["radius"].cpu().numpy())
+    assert not ref[7][k:].any()
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     st_g = api.new_status("cuda")
@@ -139,11 +162,11 @@ def test_silk_pass_captured_in_one_graph():
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        out = chain(st_g)
+        res = chain(st_g)
     for rep in range(3):
         g.replay()
         torch.cuda.synchronize()
-        got = seeds(out)
+        got = result(res)
         assert int(st_g.item()) == 0, rep
         for a, r in zip(got, ref):
             assert np.array_equal(a, r), rep
