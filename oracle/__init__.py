@@ -29,10 +29,13 @@ plus Lloyd's monotone SSE and a hand-worked case, and for DOPH hand-worked
 bins and densification, a plain per-bin loop, special sets and the
 collision rate = Jaccard.
 
-Parity unpinned: SILK's end-to-end seed sets on hashed inputs.  The paper's
-figures carry no coordinates, so only the worked example (explicit bins) and
-invariants pin the vote / threshold / de-duplication logic; the binning of
-real buckets is checked for self-consistency only.
+Without a printed value: SILK's end-to-end seed sets on hashed inputs (the
+paper's figures carry no coordinates).  The pieces are pinned instead.  The
+worked example (explicit bins) and invariants pin the vote, threshold and
+de-duplication.  A brute-force per-bucket minimum of the permuted ids pins
+the bucket signatures.  A hand-worked case whose tuples tie in their leading
+word pins the seed order.  An independent dictionary version of Algorithm 4
+pins the whole pass.
 """
 
 from .lsh import (  # noqa: F401
