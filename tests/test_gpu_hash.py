@@ -122,6 +122,11 @@ def test_minhash_hetero_match_oracle():
     ref = oracle.minhash_sets(off, tok.reshape(-1), keys)
     sig = api.hash_hetero(cuda(X), cuda(cat), cuda(A), cuda(b), m, L, w, cuda(keys))
     assert np.array_equal(host_u32(sig), ref)
+    # A as a transposed (non-contiguous) view gives the same signatures
+    At = cuda(np.ascontiguousarray(A.T)).T
+    assert not At.is_contiguous()
+    sig = api.hash_hetero(cuda(X), cuda(cat), At, cuda(b), m, L, w, cuda(keys))
+    assert np.array_equal(host_u32(sig), ref)
 
 
 def test_minhash_empty_set_reported():

@@ -67,3 +67,19 @@ def test_quantile_buckets_strided_rows():
     gm, go, gb = api.quantile_buckets(Wg[:, :33], torch.from_numpy(A).cuda(), 50)
     assert np.array_equal(host_u32(gm), mem) and np.array_equal(host_u32(go), off)
     assert np.array_equal(host_u32(gb), bof)
+
+
+def test_quantile_buckets_transposed_projection_view():
+    # A handed over as a transposed (non-contiguous) view: the binding's
+    # contiguous copy must stay alive until the call has been enqueued
+    api = gpu_api()
+    X = dense_mixture(4000, 24, 5, -10, 10, 1.0, "equal", 7)[0]
+    A = np.random.default_rng(7).standard_normal((3, 24)).astype(np.float32)
+    At = cuda(np.ascontiguousarray(A.T)).T
+    assert not At.is_contiguous()
+    announce("quantile transposed A view n=4000 d=24 m=3 t=40")
+    mem, off, bof = oracle.quantile_buckets(X, A, 40)
+    gm, go, gb = api.quantile_buckets(cuda(X), At, 40)
+    assert np.array_equal(host_u32(go), off)
+    assert np.array_equal(host_u32(gb), bof)
+    assert np.array_equal(host_u32(gm), mem)
